@@ -1,0 +1,273 @@
+"""Pins of the CPU oracle against facts fixed by the method and by mathematics.
+
+The oracle implements Stone's SIP (the paper's linear solver, Sec. 1 and
+Sec. 4.1).  None of these checks re-types the oracle's formulas: they use the
+defining property of the factorisation (M = L U = A + N, with N the
+alpha-weighted linear-extrapolation cancellation of the six fill diagonals),
+a textbook ILU(0), dense triangular / full solves, closed forms and special
+cases.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests import dense
+from paper_1303_4538_amd import problems
+
+DIMS = [(3, 4, 5), (5, 3, 4), (4, 4, 4), (1, 1, 7), (1, 7, 1), (7, 1, 1), (1, 5, 6), (6, 1, 5),
+        (5, 6, 1), (2, 2, 2), (1, 1, 1)]
+
+
+def _scale(M):
+    return max(1.0, np.abs(M).max())
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("alpha", [0.0, 0.5, 0.92, 1.0])
+def test_factor_is_stone_partial_cancellation(ora, dims, alpha):
+    """L U - A equals Stone's N exactly: the fill entries plus their
+    alpha-weighted cancellation on the spanning neighbours and the diagonal,
+    and nothing else.  This fixes every term of the factorisation."""
+    ni, nj, nk = dims
+    rng = np.random.default_rng(hash((dims, alpha)) % 2**32)
+    A = dense.random_mmatrix(ni, nj, nk, rng)
+    LU = ora.factor(A, alpha)
+    L, U = dense.dense_LU(LU)
+    M = L @ U
+    Ad = dense.dense_A(A)
+    Nx = dense.stone_N(M, ni, nj, nk, alpha)
+    assert np.abs((M - Ad) - Nx).max() <= 1e-13 * _scale(M)
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 5), (4, 3, 2), (2, 5, 3)])
+def test_factor_nonsymmetric_cd(ora, dims):
+    ni, nj, nk = dims
+    A = problems.convection_diffusion(ni, nj, nk, np.random.default_rng(7))
+    LU = ora.factor(A, 0.92)
+    L, U = dense.dense_LU(LU)
+    M = L @ U
+    Nx = dense.stone_N(M, ni, nj, nk, 0.92)
+    assert np.abs((M - dense.dense_A(A)) - Nx).max() <= 1e-13 * _scale(M)
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 5), (4, 4, 3), (1, 3, 4), (5, 1, 3)])
+def test_alpha0_is_ilu0(ora, dims):
+    """With alpha = 0 nothing is cancelled: the factorisation is ILU(0) on the
+    pattern of A, as given by textbook Gaussian elimination with dropping."""
+    ni, nj, nk = dims
+    A = dense.random_mmatrix(ni, nj, nk, np.random.default_rng(3))
+    LU = ora.factor(A, 0.0)
+    L, U = dense.dense_LU(LU)
+    Lu, Uu = dense.ilu0(dense.dense_A(A))
+    D = np.diag(Uu)
+    # our L = Lunit * diag(pivots), U = diag(pivots)^-1 * Uupper
+    assert np.allclose(L, Lu * D[None, :], rtol=1e-14, atol=1e-14)
+    assert np.allclose(U, Uu / D[:, None], rtol=1e-14, atol=1e-14)
+
+
+def test_alpha1_annihilates_linear_fields(ora):
+    """alpha = 1: (L U - A) phi = 0 for every linear field phi (Stone's design
+    property: the cancellation is exact extrapolation of a linear function)."""
+    ni, nj, nk = 4, 5, 3
+    A = dense.random_mmatrix(ni, nj, nk, np.random.default_rng(11))
+    LU = ora.factor(A, 1.0)
+    L, U = dense.dense_LU(LU)
+    R = L @ U - dense.dense_A(A)
+    k, j, i = np.meshgrid(np.arange(nk), np.arange(nj), np.arange(ni), indexing="ij")
+    for c in ([1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1], [0.3, -1.2, 2.5, 0.7]):
+        phi = (c[0] + c[1] * i + c[2] * j + c[3] * k).ravel().astype(float)
+        assert np.abs(R @ phi).max() <= 1e-13 * max(1, np.abs(phi).max()) * _scale(R)
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 5), (5, 2, 3)])
+def test_row_sum_identity(ora, dims):
+    """Row sums of L U - A equal (1 - alpha) times the sum of that row's fill
+    entries (each fill entry e is cancelled by alpha e (1 + 1 - 1))."""
+    ni, nj, nk = dims
+    alpha = 0.92
+    A = dense.random_mmatrix(ni, nj, nk, np.random.default_rng(5))
+    LU = ora.factor(A, alpha)
+    L, U = dense.dense_LU(LU)
+    M = L @ U
+    Ad = dense.dense_A(A)
+    fill = np.where(Ad == 0.0, M, 0.0)
+    np.fill_diagonal(fill, 0.0)
+    lhs = (M - Ad).sum(axis=1)
+    rhs = (1 - alpha) * fill.sum(axis=1)
+    assert np.abs(lhs - rhs).max() <= 1e-13 * _scale(M)
+
+
+def test_boundary_factors_vanish(ora):
+    """U couplings that point out of the block are exactly zero, and so are L
+    couplings on the W, S, B walls."""
+    A = problems.convection_diffusion(6, 5, 4, np.random.default_rng(2))
+    LU = ora.factor(A, 0.92)
+    assert np.all(LU[dense.UE, :, :, -1] == 0)
+    assert np.all(LU[dense.UN, :, -1, :] == 0)
+    assert np.all(LU[dense.UT, -1, :, :] == 0)
+    assert np.all(LU[dense.LW, :, :, 0] == 0)
+    assert np.all(LU[dense.LS, :, 0, :] == 0)
+    assert np.all(LU[dense.LB, 0, :, :] == 0)
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 9), (1, 9, 1), (9, 1, 1)])
+def test_one_dimensional_is_exact(ora, dims):
+    """Two dims equal to 1: no fill exists, L U = A (Thomas algorithm), and one
+    SIP update solves the system to rounding."""
+    ni, nj, nk = dims
+    A = dense.random_mmatrix(ni, nj, nk, np.random.default_rng(9))
+    LU = ora.factor(A, 0.92)
+    L, U = dense.dense_LU(LU)
+    assert np.abs(L @ U - dense.dense_A(A)).max() <= 1e-14 * _scale(L)
+    b = np.random.default_rng(1).uniform(-1, 1, (nk, nj, ni))
+    x, hist = ora.iterate(A, LU, b, np.zeros_like(b), 1)
+    assert hist[1] <= 1e-14
+
+
+def test_two_dimensional_reduction(ora):
+    """nk = 1 reduces to Stone's 2D SIP: no B or T coupling appears."""
+    A = dense.random_mmatrix(6, 5, 1, np.random.default_rng(4))
+    LU = ora.factor(A, 0.92)
+    assert np.all(LU[dense.LB] == 0) and np.all(LU[dense.UT] == 0)
+    L, U = dense.dense_LU(LU)
+    M = L @ U
+    Nx = dense.stone_N(M, 6, 5, 1, 0.92)
+    assert np.abs((M - dense.dense_A(A)) - Nx).max() <= 1e-13 * _scale(M)
+
+
+def test_residual_matches_dense_product(ora):
+    A = problems.convection_diffusion(5, 4, 3, np.random.default_rng(8))
+    rng = np.random.default_rng(0)
+    b = rng.uniform(-1, 1, (3, 4, 5))
+    x = rng.uniform(-1, 1, (3, 4, 5))
+    r = ora.residual(A, b, x)
+    ref = b.ravel() - dense.dense_A(A) @ x.ravel()
+    assert np.abs(r.ravel() - ref).max() <= 1e-14 * 10
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 5), (4, 1, 3), (6, 5, 1)])
+def test_sweeps_are_triangular_solves(ora, dims):
+    """Forward = L^-1 r and backward = U^-1 y (dense triangular solves)."""
+    ni, nj, nk = dims
+    A = problems.convection_diffusion(ni, nj, nk, np.random.default_rng(6))
+    LU = ora.factor(A, 0.92)
+    L, U = dense.dense_LU(LU)
+    r = np.random.default_rng(2).uniform(-1, 1, (nk, nj, ni))
+    y = ora.forward(LU, r)
+    d = ora.backward(LU, y)
+    y_ref = np.linalg.solve(L, r.ravel())
+    d_ref = np.linalg.solve(U, y.ravel())
+    assert np.abs(y.ravel() - y_ref).max() <= 1e-13 * max(1, np.abs(y_ref).max())
+    assert np.abs(d.ravel() - d_ref).max() <= 1e-13 * max(1, np.abs(d_ref).max())
+
+
+def test_fp32_sweeps_are_triangular_solves(ora):
+    ni, nj, nk = 4, 3, 5
+    A = problems.convection_diffusion(ni, nj, nk, np.random.default_rng(6))
+    LU32 = ora.factor(A, 0.92).astype(np.float32)
+    L, U = dense.dense_LU(LU32.astype(np.float64))
+    r = np.random.default_rng(2).uniform(-1, 1, (nk, nj, ni)).astype(np.float32)
+    y = ora.forward_f32(LU32, r)
+    d = ora.backward_f32(LU32, y)
+    assert y.dtype == np.float32 and d.dtype == np.float32
+    y_ref = np.linalg.solve(L, r.ravel().astype(np.float64))
+    d_ref = np.linalg.solve(U, y.ravel().astype(np.float64))
+    assert np.abs(y.ravel() - y_ref).max() <= 1e-5 * max(1, np.abs(y_ref).max())
+    assert np.abs(d.ravel() - d_ref).max() <= 1e-5 * max(1, np.abs(d_ref).max())
+
+
+def test_iteration_is_dense_defect_correction(ora):
+    """x_{n+1} = x_n + (L U)^-1 (b - A x_n), computed densely, for 6 updates;
+    rho_n = ||b - A x_n|| / ||b||."""
+    ni, nj, nk = 4, 5, 3
+    A = problems.convection_diffusion(ni, nj, nk, np.random.default_rng(12))
+    LU = ora.factor(A, 0.92)
+    L, U = dense.dense_LU(LU)
+    Ad = dense.dense_A(A)
+    b = np.random.default_rng(13).uniform(-1, 1, (nk, nj, ni))
+    x, hist = ora.iterate(A, LU, b, np.zeros_like(b), 6)
+    xr = np.zeros(b.size)
+    nb = np.linalg.norm(b.ravel())
+    for n in range(7):
+        r = b.ravel() - Ad @ xr
+        assert abs(hist[n] - np.linalg.norm(r) / nb) <= 1e-14
+        if n < 6:
+            xr = xr + np.linalg.solve(L @ U, r)
+    assert np.abs(x.ravel() - xr).max() <= 1e-12 * np.abs(xr).max()
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16), (12, 10, 9)])
+def test_manufactured_poisson_solution(ora, dims):
+    """x*(i,j,k) = prod sin(pi (m+1)/(N_m+1)) is an eigenvector of the
+    Dirichlet Poisson stencil with eigenvalue 6 - 2 sum cos(pi/(N_m+1)).
+    With b = lambda x*, SIP converges to x*."""
+    ni, nj, nk = dims
+    A = problems.poisson(ni, nj, nk)
+    k, j, i = np.meshgrid(np.arange(nk), np.arange(nj), np.arange(ni), indexing="ij")
+    xs = (np.sin(math.pi * (i + 1) / (ni + 1)) * np.sin(math.pi * (j + 1) / (nj + 1))
+          * np.sin(math.pi * (k + 1) / (nk + 1)))
+    lam = 6 - 2 * (math.cos(math.pi / (ni + 1)) + math.cos(math.pi / (nj + 1)) + math.cos(math.pi / (nk + 1)))
+    b = lam * xs
+    # the right-hand side really is A x*
+    assert np.abs(ora.residual(A, b, xs)).max() <= 2e-15 * 8
+    LU = ora.factor(A, 0.92)
+    x, it, rr, hist = ora.solve(A, LU, b, np.zeros_like(b), 1e-12, 500)
+    assert rr <= 1e-12 and it < 500
+    assert np.abs(x - xs).max() <= 1e-10
+    # the residual history decreases overall
+    assert hist[-1] < hist[0] * 1e-11
+
+
+def test_fixed_point_is_dense_solution(ora):
+    ni, nj, nk = 5, 4, 6
+    A = problems.convection_diffusion(ni, nj, nk, np.random.default_rng(21))
+    b = np.random.default_rng(22).uniform(-1, 1, (nk, nj, ni))
+    LU = ora.factor(A, 0.92)
+    x, it, rr, _ = ora.solve(A, LU, b, np.zeros_like(b), 1e-14, 2000)
+    xd = np.linalg.solve(dense.dense_A(A), b.ravel())
+    assert np.abs(x.ravel() - xd).max() <= 1e-12 * np.abs(xd).max()
+
+
+def test_mixed_form_reaches_fp64_accuracy(ora):
+    """Defect correction with FP32 sweeps keeps the FP64 residual, so it reaches
+    1e-8 with about the FP64 iteration count and its fixed point is A^-1 b."""
+    ni, nj, nk = 16, 16, 16
+    A = problems.convection_diffusion(ni, nj, nk, np.random.default_rng(31))
+    b = np.random.default_rng(32).uniform(-1, 1, (nk, nj, ni))
+    LU = ora.factor(A, 0.92)
+    x64, it64, rr64, _ = ora.solve(A, LU, b, np.zeros_like(b), 1e-8, 1000)
+    x32, it32, rr32, _ = ora.solve(A, LU, b, np.zeros_like(b), 1e-8, 1000, mixed=True)
+    assert rr64 <= 1e-8 and rr32 <= 1e-8
+    assert abs(it32 - it64) <= 3
+    # an independent FP64 residual of the mixed result
+    r = b.ravel() - dense.dense_A(A) @ x32.ravel()
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-8
+    x, _, rr, _ = ora.solve(A, LU, b, np.zeros_like(b), 1e-13, 3000, mixed=True)
+    xd = np.linalg.solve(dense.dense_A(A), b.ravel())
+    assert rr <= 1e-13
+    assert np.abs(x.ravel() - xd).max() <= 1e-11 * np.abs(xd).max()
+
+
+def test_zero_rhs_returns_zero(ora):
+    A = problems.poisson(4, 4, 4)
+    LU = ora.factor(A, 0.92)
+    b = np.zeros((4, 4, 4))
+    x, it, rr, _ = ora.solve(A, LU, b, np.ones_like(b), 1e-8, 10)
+    assert it == 0 and rr == 0.0 and np.all(x == 0)
+
+
+def test_breakdown_is_reported(ora):
+    A = problems.poisson(3, 3, 3)
+    A[0, 0, 0, 0] = 0.0            # zero pivot at the first cell
+    with pytest.raises(FloatingPointError):
+        ora.factor(A, 0.92)
+
+
+def test_config1_runs_and_converges(ora):
+    c = problems.config1()
+    LU = ora.factor(c["A"], c["alpha"])
+    x, hist = ora.iterate(c["A"], LU, c["b"], np.zeros_like(c["b"]), c["n_iter"])
+    assert hist[0] == pytest.approx(1.0)
+    assert np.all(np.diff(hist) < 0)
+    assert hist[-1] < 1e-9
