@@ -1,0 +1,180 @@
+/*
+ * sip.h -- C ABI of the MI355X (gfx950) implementation of Stone's strongly
+ * implicit procedure (SIP) on structured 3D blocks with the 7-point stencil.
+ *
+ * The method is the linear solver of FASTEST-3D in arXiv:1303.4538: an
+ * incomplete-LU (Stone) factorisation followed by relaxation sweeps (Sec. 1),
+ * redesigned in Sec. 4.1 as a modular solver that owns its coefficient
+ * memory, computes the factorisation once in advance, reuses it for all
+ * later iterations and time steps, and relaxes with single-precision sweeps.
+ *
+ * Conventions shared by every entry point:
+ *   - A block has ni x nj x nk cells.  Every grid array is C-contiguous
+ *     [nk][nj][ni] FP64 (i fastest) in DEVICE memory of the current HIP device.
+ *   - Row P of the system reads  A_P x_P + sum_nb A_nb x_nb = b_P  with signed
+ *     coefficients (the paper's listing in Sec. 4.1 stores a_nb = -A_nb).
+ *     Couplings that point out of the block are ignored.
+ *   - Streams are hipStream_t passed as void* (NULL = the legacy default
+ *     stream).  Work is stream-ordered on the caller's stream.
+ *   - Errors come back as sip_status; no call aborts or throws.  Detail text
+ *     for the calling thread is available from sip_last_error().
+ *   - The library never frees caller memory.  Handles are freed only by the
+ *     matching *_destroy call.
+ */
+#ifndef SIP_H
+#define SIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SIP_OK = 0,
+    SIP_PENDING = 1,        /* sip_batch_poll: request not finished yet            */
+    SIP_EINVAL = -1,        /* bad argument (dims < 1, alpha outside [0,1], NULL)  */
+    SIP_ENOMEM = -2,        /* device allocation or HBM budget exhausted           */
+    SIP_EBREAKDOWN = -3,    /* zero/non-finite pivot or zero denominator           */
+    SIP_ENOTCONV = -4,      /* iteration limit reached before the tolerance        */
+    SIP_EDEVICE = -5,       /* HIP error or a device-side wait timed out           */
+    SIP_EBUSY = -6,         /* server queue full                                   */
+    SIP_ECANCELLED = -7     /* request cancelled / server shut down                */
+} sip_status;
+
+typedef enum {
+    SIP_FP64 = 0,           /* factors and sweeps in FP64                          */
+    SIP_MIXED = 1           /* factors and sweeps in FP32; residual, norm and the
+                               solution update in FP64 (defect correction)         */
+} sip_precision;
+
+typedef struct sip_system_s *sip_system;   /* factorised system resident on a GPU */
+typedef struct sip_server_s *sip_server;   /* continuous-batching solve server    */
+
+/* One block.  a[d] are device pointers in the order P, W, E, S, N, B, T, each
+ * ni*nj*nk FP64 values.  alpha is Stone's cancellation parameter in [0, 1]. */
+typedef struct {
+    int32_t ni, nj, nk;
+    const double *a[7];
+    double alpha;
+    int32_t precision;      /* sip_precision */
+} sip_problem;
+
+typedef struct {
+    int32_t iters;          /* updates applied                                     */
+    double rel_res;         /* ||b - A x||_2 / ||b||_2 of the returned x (FP64)    */
+    double seconds;         /* host wall time of the call                          */
+} sip_info;
+
+/* sip_factor -- copy A into the library's own layout and compute the SIP
+ * factorisation (Sec. 4.1: the solver owns the coefficient memory and
+ * computes the incomplete factorisation in advance, once).
+ *   p       problem description; p->a are read during the call only (the
+ *           caller may free them afterwards).
+ *   stream  HIP stream; the call synchronises it before returning so that a
+ *           breakdown can be reported.
+ *   out     receives the new handle (unchanged on error).
+ * Errors: SIP_EINVAL (dims < 1, NULL pointers, alpha outside [0,1], unknown
+ * precision), SIP_ENOMEM, SIP_EBREAKDOWN (zero or non-finite pivot),
+ * SIP_EDEVICE. */
+sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out);
+
+/* sip_iterate -- apply exactly n_iter SIP updates to x (Sec. 4.1: the
+ * original driver relaxes a fixed number of iterations):
+ *   r = b - A x (FP64), forward sweep L y = r, backward sweep U d = y,
+ *   x += d.
+ *   b        device, read only.
+ *   x        device, read as the start vector and overwritten.
+ *   n_iter   >= 0.
+ *   rel_res_hist  NULL, or HOST memory of n_iter+1 doubles that receives
+ *           rho_n = ||b - A x_n|| / ||b|| for n = 0..n_iter.  With NULL the
+ *           call only enqueues work and does not synchronise the stream.
+ * b == 0 everywhere gives x = 0.  Errors: SIP_EINVAL, SIP_EDEVICE. */
+sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
+                       double *rel_res_hist, void *stream);
+
+/* sip_solve -- iterate until rho_n <= rtol and return that x_n (the paper
+ * evaluates residuals through a global reduction and keeps such evaluations
+ * cheap, Sec. 3.2; here the norm and the stop test run on the device).
+ *   rtol > 0, max_iter >= 0; info (nullable, host) receives iterations,
+ *   final relative residual and wall time.  Synchronises the stream.
+ * Errors: SIP_EINVAL, SIP_ENOTCONV (x holds x_max_iter), SIP_EDEVICE. */
+sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int32_t max_iter,
+                     sip_info *info, void *stream);
+
+/* sip_export_factors -- write the factors in natural [nk][nj][ni] order as
+ * FP64 into seven device arrays of ni*nj*nk doubles, in the order
+ * Lb, Lw, Ls, Lp, Un, Ue, Ut (Lp is the pivot, U has a unit diagonal).
+ * In the mixed precision the FP32 factors are widened.  Stream-ordered. */
+sip_status sip_export_factors(sip_system h, double *const out[7], void *stream);
+
+/* sip_system_info -- dims, precision and device bytes held by a handle. */
+sip_status sip_system_info(sip_system h, int32_t dims[3], int32_t *precision, size_t *device_bytes);
+
+/* sip_system_destroy -- free every device buffer of the handle.  The caller
+ * must not have work in flight on it. */
+sip_status sip_system_destroy(sip_system h);
+
+/* ------------------------------------------------------------------------
+ * Batched and served solves.  A server owns a scheduler thread that admits
+ * requests while device memory (the HBM budget) and slots allow, keeps SIP
+ * factors resident across requests of the same system, and advances all
+ * admitted requests together in epochs of device launches (continuous
+ * batching).  Requests that arrive while others run join the next epoch.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    size_t hbm_budget_bytes;    /* device bytes the server may hold (0 = 3/4 of free memory) */
+    int32_t max_slots;          /* requests advanced together (<= 4096)      */
+    int32_t epoch_iters;        /* iterations per epoch before re-admission  */
+    int32_t max_queue;          /* pending requests before SIP_EBUSY         */
+} sip_server_config;
+
+typedef struct {
+    uint64_t system_id;         /* caller's key: requests with the same id share factors */
+    sip_problem problem;        /* coefficients (device); read when the system is first factorised */
+    const double *b;            /* device right-hand side, read at admission  */
+    double *x;                  /* device solution; written when done         */
+    const double *x0;           /* device start vector or NULL (zeros)        */
+    double rtol;
+    int32_t max_iter;
+    int32_t retain;             /* 1: keep this system's factors resident after the request */
+} sip_request;
+
+typedef struct {
+    sip_status status;          /* SIP_OK, SIP_ENOTCONV, SIP_EBREAKDOWN ...   */
+    sip_info info;
+    double t_submit, t_admit, t_done;   /* seconds on the server's clock     */
+    int32_t factorised;         /* 1 if this request triggered a factorisation */
+} sip_result;
+
+sip_status sip_server_create(const sip_server_config *c, sip_server *out);
+
+/* Never blocks.  On success *ticket identifies the request.  The request's
+ * device arrays must stay valid until sip_batch_poll reports it done.
+ * Errors: SIP_EINVAL, SIP_EBUSY (queue full), SIP_ENOMEM (the request alone
+ * exceeds the HBM budget). */
+sip_status sip_batch_submit(sip_server s, const sip_request *r, uint64_t *ticket);
+
+/* Returns SIP_PENDING while the request runs (waits up to wait_ms
+ * milliseconds; 0 = do not wait, < 0 = wait until done), else SIP_OK and
+ * fills *out (whose status field carries the solve outcome). */
+sip_status sip_batch_poll(sip_server s, uint64_t ticket, int32_t wait_ms, sip_result *out);
+
+/* Drops a resident system's factors (no effect while requests use it). */
+sip_status sip_server_release(sip_server s, uint64_t system_id);
+
+/* Server counters: factorisations, evictions, epochs, resident bytes. */
+sip_status sip_server_stats(sip_server s, uint64_t out[8]);
+
+/* Stops the scheduler; pending requests complete with SIP_ECANCELLED. */
+sip_status sip_server_destroy(sip_server s);
+
+const char *sip_status_str(sip_status st);
+const char *sip_last_error(void);      /* thread-local detail of the last error */
+int32_t sip_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIP_H */

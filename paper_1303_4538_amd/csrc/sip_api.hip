@@ -1,0 +1,434 @@
+// Host runtime and C ABI of the SIP library (include/sip.h).
+//
+// A sip_system owns, in device memory and in the tile-sheared layout of
+// sip_internal.h: the coefficients (FP64), the factors (FP64 or FP32), b, x
+// (FP64), the forward-sweep result y, the tagged face words, per-tile
+// partial sums, the residual history and a control block.  A solve is a
+// stream-ordered sequence of launches: reorder b and x in, (forward sweep,
+// backward sweep) per iteration, reorder x out.  The stop test runs on the
+// device; the host replays graph-captured chunks of iterations and reads the
+// control block back one chunk behind, so the GPU never waits for the host.
+#include "sip_internal.h"
+#include "sip_runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace sipk;
+
+namespace sipk {
+
+thread_local std::string g_last_error;
+
+sip_status set_error(sip_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+uint64_t timeout_ticks_for(int device, double seconds)
+{
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || rate_khz <= 0)
+        rate_khz = 100000;
+    return (uint64_t)(seconds * rate_khz * 1000.0);
+}
+
+std::vector<int2> topo_order(const std::vector<Geom> &gs, bool backward)
+{
+    struct Item {
+        long long key;
+        int job, tile;
+    };
+    std::vector<Item> items;
+    for (size_t jb = 0; jb < gs.size(); jb++) {
+        const Geom &g = gs[jb];
+        const int dmax = g.nti + g.ntj - 2;
+        for (int t = 0; t < g.ntiles; t++) {
+            const int ti = t % g.nti, tj = t / g.nti;
+            const int d = backward ? dmax - (ti + tj) : ti + tj;
+            const int tjk = backward ? g.ntj - 1 - tj : tj;
+            items.push_back({((long long)d << 40) | ((long long)jb << 20) | tjk, (int)jb, t});
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.key < b.key; });
+    std::vector<int2> out(items.size());
+    for (size_t q = 0; q < items.size(); q++) out[q] = make_int2(items[q].job, items[q].tile);
+    return out;
+}
+
+size_t system_bytes(const Geom &g, int fp32)
+{
+    const size_t E = (size_t)g.elems, fs = fp32 ? 4 : 8;
+    return E * (7 * 8 + 7 * fs + 2 * 8 + fs) + (size_t)g.ntiles * g.steps * FACE_WORDS * 8 +
+           (size_t)g.ntiles * 2 * 8 + sizeof(Ctl) + 2 * (size_t)g.ntiles * sizeof(int2);
+}
+
+// ---------------------------------------------------------------- System
+
+static void free_system(sip_system_s *h)
+{
+    if (!h) return;
+    if (h->chunk_exec) hipGraphExecDestroy(h->chunk_exec);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    for (void *p : {(void *)h->A, h->LU, (void *)h->bx, h->y, (void *)h->face, (void *)h->part, (void *)h->ctl,
+                    (void *)h->hist, (void *)h->d_job, (void *)h->d_job_factor, (void *)h->order_f, (void *)h->order_b, (void *)h->lc})
+        if (p) hipFree(p);
+    if (h->h_ctl) hipHostFree(h->h_ctl);
+    if (h->h_hist) hipHostFree(h->h_hist);
+    delete h;
+}
+
+static sip_status alloc_dev(void **p, size_t n, const char *what)
+{
+    hipError_t e = hipMalloc(p, n ? n : 1);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_error(SIP_ENOMEM, "hipMalloc(%zu) for %s failed: %s", n, what, hipGetErrorString(e));
+    }
+    return SIP_OK;
+}
+
+#define TRY(x)                                  \
+    do {                                        \
+        sip_status st_ = (x);                   \
+        if (st_ != SIP_OK) return st_;          \
+    } while (0)
+#define HIPTRY(x)                                                                                 \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess) return set_error(SIP_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+sip_status system_alloc(sip_system_s *h, hipStream_t s)
+{
+    const Geom &g = h->g;
+    const size_t E = (size_t)g.elems, fs = h->fp32 ? 4 : 8;
+    TRY(alloc_dev((void **)&h->A, 7 * E * 8, "coefficients"));
+    TRY(alloc_dev(&h->LU, 7 * E * fs, "factors"));
+    TRY(alloc_dev((void **)&h->bx, 2 * E * 8, "b and x"));
+    TRY(alloc_dev(&h->y, E * fs, "y"));
+    const size_t fbytes = (size_t)g.ntiles * g.steps * FACE_WORDS * 8;
+    TRY(alloc_dev((void **)&h->face, fbytes, "face words"));
+    TRY(alloc_dev((void **)&h->part, (size_t)g.ntiles * 2 * 8, "partials"));
+    TRY(alloc_dev((void **)&h->ctl, sizeof(Ctl), "control"));
+    TRY(alloc_dev((void **)&h->d_job, sizeof(Job), "job"));
+    TRY(alloc_dev((void **)&h->d_job_factor, sizeof(Job), "job"));
+    TRY(alloc_dev((void **)&h->order_f, g.ntiles * sizeof(int2), "order"));
+    TRY(alloc_dev((void **)&h->order_b, g.ntiles * sizeof(int2), "order"));
+    TRY(alloc_dev((void **)&h->lc, sizeof(LaunchCtl), "launch control"));
+    HIPTRY(hipHostMalloc((void **)&h->h_ctl, 4 * sizeof(Ctl), hipHostMallocDefault));
+    HIPTRY(hipMemsetAsync(h->LU, 0, 7 * E * fs, s));
+    HIPTRY(hipMemsetAsync(h->y, 0, E * fs, s));
+    HIPTRY(hipMemsetAsync(h->face, 0, fbytes, s));
+    HIPTRY(hipMemsetAsync(h->lc, 0, sizeof(LaunchCtl), s));
+    h->bytes = system_bytes(g, h->fp32);
+    return SIP_OK;
+}
+
+sip_status ensure_hist(sip_system_s *h, int n, hipStream_t s)
+{
+    if (n <= h->hist_cap) return SIP_OK;
+    HIPTRY(hipStreamSynchronize(s));
+    if (h->hist) hipFree(h->hist);
+    if (h->h_hist) hipHostFree(h->h_hist);
+    h->hist = nullptr;
+    h->h_hist = nullptr;
+    h->hist_cap = 0;
+    const int cap = std::max(n, 64);
+    TRY(alloc_dev((void **)&h->hist, (size_t)cap * 8, "history"));
+    HIPTRY(hipHostMalloc((void **)&h->h_hist, (size_t)cap * 8, hipHostMallocDefault));
+    h->hist_cap = cap;
+    // the job descriptor holds the history pointer
+    h->job.hist = h->hist;
+    HIPTRY(hipMemcpyAsync(h->d_job, &h->job, sizeof(Job), hipMemcpyHostToDevice, s));
+    HIPTRY(hipStreamSynchronize(s));
+    if (h->chunk_exec) {
+        hipGraphExecDestroy(h->chunk_exec);
+        h->chunk_exec = nullptr;
+    }
+    return SIP_OK;
+}
+
+LaunchArgs fwd_args(const sip_system_s *h)
+{
+    return LaunchArgs{h->d_job, h->order_f, h->lc, h->g.ntiles, h->timeout_ticks};
+}
+LaunchArgs bwd_args(const sip_system_s *h)
+{
+    return LaunchArgs{h->d_job, h->order_b, h->lc, h->g.ntiles, h->timeout_ticks};
+}
+
+static sip_status launch_iterations(sip_system_s *h, int n, hipStream_t s)
+{
+    const LaunchArgs fa = fwd_args(h), ba = bwd_args(h);
+    for (int q = 0; q < n; q++) {
+        HIPTRY(launch_forward(fa, h->fp32, s));
+        HIPTRY(launch_backward(ba, h->fp32, s));
+    }
+    return SIP_OK;
+}
+
+// Replays CHUNK iterations as one captured graph.
+static sip_status launch_chunk(sip_system_s *h, hipStream_t s)
+{
+    if (!h->chunk_exec) {
+        if (!h->cap_stream) HIPTRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        HIPTRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        sip_status st = launch_iterations(h, CHUNK, h->cap_stream);
+        hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+        if (st != SIP_OK) return st;
+        if (e != hipSuccess) return set_error(SIP_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&h->chunk_exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return set_error(SIP_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    HIPTRY(hipGraphLaunch(h->chunk_exec, s));
+    return SIP_OK;
+}
+
+static sip_status stop_status(uint32_t stop)
+{
+    switch (stop) {
+    case RUN:
+    case CONVERGED:
+    case ZERO_RHS:
+        return SIP_OK;
+    case MAXITER:
+        return SIP_ENOTCONV;
+    case BREAKDOWN:
+        return set_error(SIP_EBREAKDOWN, "SIP factorisation breakdown (zero or non-finite pivot)");
+    case TIMEOUT:
+    default:
+        return set_error(SIP_EDEVICE, "a device-side wait timed out");
+    }
+}
+
+}  // namespace sipk
+
+// ================================================================= C ABI
+
+extern "C" {
+
+int32_t sip_abi_version(void) { return 1; }
+
+const char *sip_last_error(void) { return sipk::g_last_error.c_str(); }
+
+const char *sip_status_str(sip_status st)
+{
+    switch (st) {
+    case SIP_OK: return "SIP_OK";
+    case SIP_PENDING: return "SIP_PENDING";
+    case SIP_EINVAL: return "SIP_EINVAL";
+    case SIP_ENOMEM: return "SIP_ENOMEM";
+    case SIP_EBREAKDOWN: return "SIP_EBREAKDOWN";
+    case SIP_ENOTCONV: return "SIP_ENOTCONV";
+    case SIP_EDEVICE: return "SIP_EDEVICE";
+    case SIP_EBUSY: return "SIP_EBUSY";
+    case SIP_ECANCELLED: return "SIP_ECANCELLED";
+    }
+    return "SIP_UNKNOWN";
+}
+
+sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
+{
+    if (!p || !out) return set_error(SIP_EINVAL, "NULL argument");
+    if (p->ni < 1 || p->nj < 1 || p->nk < 1) return set_error(SIP_EINVAL, "dims must be >= 1");
+    if ((long long)p->ni * p->nj * p->nk > (1ll << 34)) return set_error(SIP_EINVAL, "block too large");
+    if (!(p->alpha >= 0.0 && p->alpha <= 1.0)) return set_error(SIP_EINVAL, "alpha must be in [0, 1]");
+    if (p->precision != SIP_FP64 && p->precision != SIP_MIXED) return set_error(SIP_EINVAL, "unknown precision");
+    for (int d = 0; d < 7; d++)
+        if (!p->a[d]) return set_error(SIP_EINVAL, "coefficient pointer %d is NULL", d);
+    hipStream_t s = (hipStream_t)stream;
+    sip_system_s *h = new sip_system_s();
+    h->g = make_geom(p->ni, p->nj, p->nk);
+    h->fp32 = p->precision == SIP_MIXED;
+    h->precision = p->precision;
+    h->alpha = p->alpha;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return set_error(SIP_EDEVICE, "no HIP device");
+    }
+    h->timeout_ticks = timeout_ticks_for(h->device, 2.0);
+    sip_status st = system_alloc(h, s);
+    if (st != SIP_OK) {
+        free_system(h);
+        return st;
+    }
+    auto bail = [&](sip_status e) {
+        hipStreamSynchronize(s);
+        free_system(h);
+        return e;
+    };
+    const Geom &g = h->g;
+    if (launch_to_sheared(g, 7, p->a, h->A, g.elems, 1, s) != hipSuccess)
+        return bail(set_error(SIP_EDEVICE, "reorder launch failed"));
+    if (launch_init_ctl(h->ctl, 1, 0, 0.0, 1, s) != hipSuccess) return bail(set_error(SIP_EDEVICE, "init failed"));
+    st = ensure_hist(h, 64, s);
+    if (st != SIP_OK) return bail(st);
+    Job &J = h->job;
+    J.g = g;
+    J.A = h->A;
+    J.b = h->bx;
+    J.x = h->bx + g.elems;
+    J.LU = h->LU;
+    J.y = h->y;
+    J.face = h->face;
+    J.part = h->part;
+    J.hist = h->hist;
+    J.ctl = h->ctl;
+    J.alpha = h->alpha;
+    J.fw = FACE_WORDS_SWEEP;
+    const std::vector<Geom> gs{g};
+    const std::vector<int2> of = topo_order(gs, false), ob = topo_order(gs, true);
+    if (hipMemcpyAsync(h->d_job, &J, sizeof(Job), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->order_f, of.data(), of.size() * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->order_b, ob.data(), ob.size() * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess)
+        return bail(set_error(SIP_EDEVICE, "upload failed"));
+    // the factorisation exchanges U triples (FACE_WORDS per step); the sweeps one value
+    h->job_factor = J;
+    h->job_factor.fw = FACE_WORDS;
+    J.fw = FACE_WORDS_SWEEP;
+    if (hipMemcpyAsync(h->d_job_factor, &h->job_factor, sizeof(Job), hipMemcpyHostToDevice, s) != hipSuccess)
+        return bail(set_error(SIP_EDEVICE, "upload failed"));
+    LaunchArgs fa = fwd_args(h);
+    fa.jobs = h->d_job_factor;
+    if (launch_factor(fa, h->fp32, s) != hipSuccess) return bail(set_error(SIP_EDEVICE, "factor launch failed"));
+    if (hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return bail(set_error(SIP_EDEVICE, "factorisation failed: %s", hipGetErrorString(hipGetLastError())));
+    if (h->h_ctl->stop != RUN) return bail(stop_status(h->h_ctl->stop));
+    *out = h;
+    return SIP_OK;
+}
+
+sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter, double *rel_res_hist, void *stream)
+{
+    if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
+    if (n_iter < 0) return set_error(SIP_EINVAL, "n_iter must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    TRY(ensure_hist(h, n_iter + 1, s));
+    const Geom &g = h->g;
+    const double *src[2] = {b, x};
+    HIPTRY(launch_to_sheared(g, 2, src, h->bx, g.elems, 0, s));
+    HIPTRY(launch_init_ctl(h->ctl, 1, (uint32_t)n_iter, 0.0, 0, s));
+    int left = n_iter;
+    while (left >= CHUNK) {
+        TRY(launch_chunk(h, s));
+        left -= CHUNK;
+    }
+    TRY(launch_iterations(h, left, s));
+    HIPTRY(launch_forward(fwd_args(h), h->fp32, s));   // residual of the final iterate
+    HIPTRY(launch_from_sheared_f64(g, h->bx + g.elems, x, h->ctl, s));
+    if (!rel_res_hist) return SIP_OK;
+    HIPTRY(hipMemcpyAsync(h->h_hist, h->hist, (size_t)(n_iter + 1) * 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    std::memcpy(rel_res_hist, h->h_hist, (size_t)(n_iter + 1) * 8);
+    const uint32_t stop = h->h_ctl->stop;
+    if (stop == ZERO_RHS) {
+        for (int q = 0; q <= n_iter; q++) rel_res_hist[q] = 0.0;
+        return SIP_OK;
+    }
+    if (stop == MAXITER || stop == RUN) return SIP_OK;
+    return stop_status(stop);
+}
+
+sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int32_t max_iter, sip_info *info,
+                     void *stream)
+{
+    if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
+    if (!(rtol > 0.0) || max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    TRY(ensure_hist(h, max_iter + 1, s));
+    const Geom &g = h->g;
+    const double *src[2] = {b, x};
+    HIPTRY(launch_to_sheared(g, 2, src, h->bx, g.elems, 0, s));
+    HIPTRY(launch_init_ctl(h->ctl, 1, (uint32_t)max_iter, rtol, 0, s));
+    hipEvent_t ev[2];
+    HIPTRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    HIPTRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    long long fwd_launched = 0;
+    sip_status st = SIP_OK;
+    for (int c = 0;; c++) {
+        st = launch_chunk(h, s);
+        if (st != SIP_OK) break;
+        fwd_launched += CHUNK;
+        if (hipMemcpyAsync(&h->h_ctl[c & 1], h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipEventRecord(ev[c & 1], s) != hipSuccess) {
+            st = set_error(SIP_EDEVICE, "status copy failed");
+            break;
+        }
+        if (fwd_launched > max_iter) break;
+        if (c > 0) {
+            if (hipEventSynchronize(ev[(c - 1) & 1]) != hipSuccess) {
+                st = set_error(SIP_EDEVICE, "event wait failed");
+                break;
+            }
+            if (h->h_ctl[(c - 1) & 1].stop != RUN) break;
+        }
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (st != SIP_OK) {
+        hipStreamSynchronize(s);
+        return st;
+    }
+    HIPTRY(launch_from_sheared_f64(g, h->bx + g.elems, x, h->ctl, s));
+    HIPTRY(hipMemcpyAsync(&h->h_ctl[2], h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    const Ctl &c = h->h_ctl[2];
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) {
+        info->iters = (int32_t)c.iter;
+        info->rel_res = c.rho;
+        info->seconds = secs;
+    }
+    if (c.stop == RUN) return set_error(SIP_EDEVICE, "solve ended without a stop decision");
+    return stop_status(c.stop);
+}
+
+sip_status sip_export_factors(sip_system h, double *const out[7], void *stream)
+{
+    if (!h || !out) return set_error(SIP_EINVAL, "NULL argument");
+    for (int d = 0; d < 7; d++)
+        if (!out[d]) return set_error(SIP_EINVAL, "output pointer %d is NULL", d);
+    HIPTRY(launch_export_factors(h->g, h->LU, h->fp32, out, (hipStream_t)stream));
+    return SIP_OK;
+}
+
+sip_status sip_system_info(sip_system h, int32_t dims[3], int32_t *precision, size_t *device_bytes)
+{
+    if (!h) return set_error(SIP_EINVAL, "NULL handle");
+    if (dims) {
+        dims[0] = h->g.ni;
+        dims[1] = h->g.nj;
+        dims[2] = h->g.nk;
+    }
+    if (precision) *precision = h->precision;
+    if (device_bytes) *device_bytes = h->bytes;
+    return SIP_OK;
+}
+
+sip_status sip_system_destroy(sip_system h)
+{
+    if (!h) return set_error(SIP_EINVAL, "NULL handle");
+    free_system(h);
+    return SIP_OK;
+}
+
+}  // extern "C"

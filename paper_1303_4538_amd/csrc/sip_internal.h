@@ -1,0 +1,105 @@
+// Internal declarations shared by the gfx950 kernels and the host runtime.
+//
+// Data layout ("tile-sheared hyperplane order").  A block of ni x nj x nk
+// cells is cut into tile columns of TI x TJ cells in (i, j) that run through
+// all of k.  Inside a tile, cell (i', j', k) belongs to the local hyperplane
+// s = i' + j' + k and is stored at
+//     tile * tile_elems + (s + 1) * TT + j' * TI + i'          (TT = TI * TJ)
+// so the TI*TJ cells that one wavefront step touches are contiguous.  Planes
+// -1 and steps (= nk + TI + TJ - 2) are zero margins; slots whose k falls
+// outside [0, nk) or whose (i, j) falls outside the block are zero padding.
+// Any order that visits W, S and B before P computes the same SIP values as
+// the lexicographic one, and the local hyperplane order does.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace sipk {
+
+constexpr int TI = 8;          // tile extent in i (lanes)
+constexpr int TJ = 8;          // tile extent in j
+constexpr int TT = TI * TJ;    // one wave: lane = j' * TI + i'
+
+enum Stop : uint32_t {
+    RUN = 0,
+    CONVERGED = 1,
+    MAXITER = 2,
+    ZERO_RHS = 3,
+    BREAKDOWN = 4,
+    TIMEOUT = 5,
+};
+
+struct Geom {
+    int ni, nj, nk;
+    int nti, ntj, ntiles;
+    int steps;                 // nk + TI + TJ - 2 local hyperplanes per tile
+    int planes;                // steps + 2 (with the two margins)
+    long long tile_elems;      // planes * TT
+    long long elems;           // ntiles * tile_elems
+};
+
+// Per-system control block in device memory.  Written by the last
+// workgroup of each sweep ("finaliser") and read by the next launch.
+struct Ctl {
+    uint32_t done;             // workgroups of this job finished in the current launch
+    uint32_t epoch;            // sequence tag of the current sweep (face words)
+    uint32_t iter;             // iteration index n of the next forward sweep
+    uint32_t max_iter;
+    uint32_t stop;             // Stop
+    uint32_t err;              // sticky: 1 device wait timed out, 2 breakdown
+    uint32_t pad0, pad1;
+    double rtol;               // <= 0: never converge (fixed iteration count)
+    double bnorm2;             // sum of b^2
+    double rho;                // relative residual of the last forward sweep
+};
+
+// One block of a batched launch (a single solve is a batch of one).
+struct Job {
+    Geom g;
+    const double *A;           // 7 * elems FP64 coefficients P,W,E,S,N,B,T (sheared)
+    const double *b;           // elems FP64
+    double *x;                 // elems FP64
+    void *LU;                  // 7 * elems factors Lb,Lw,Ls,1/Lp,Un,Ue,Ut (FP64 or FP32)
+    void *y;                   // elems forward-sweep result (FP64 or FP32)
+    uint64_t *face;            // ntiles * steps * FACE_WORDS tagged face words
+    double *part;              // 2 * ntiles per-tile partial sums
+    double *hist;              // max_iter + 1 relative residuals
+    Ctl *ctl;
+    double alpha;
+    int fw;                    // face words per local step (FACE_WORDS_SWEEP or FACE_WORDS)
+};
+
+// Launch-wide ticket and completion counters (reset by the last workgroup).
+struct LaunchCtl {
+    uint32_t ticket;
+    uint32_t done;
+};
+
+struct LaunchArgs {
+    const Job *jobs;
+    const int2 *order;         // ticket -> (job, tile), topological per job
+    LaunchCtl *lc;
+    int total;                 // number of workgroups = sum of ntiles
+    uint64_t timeout_ticks;    // wall-clock ticks before a wait gives up
+};
+
+// Face words per local step of one tile: (TI + TJ) entries of 3 FP64 values,
+// 2 words each (the factorisation's U triples; sweeps use fewer).
+constexpr int FACE_WORDS = (TI + TJ) * 6;
+// The sweeps exchange one value per face entry: at most 2 words (FP64).
+constexpr int FACE_WORDS_SWEEP = (TI + TJ) * 2;
+
+Geom make_geom(int ni, int nj, int nk);
+
+// Kernel launchers (sip_kernels.hip).  All are asynchronous on `s`.
+hipError_t launch_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int reset_epoch, hipStream_t s);
+hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, double *dst,
+                             long long dst_stride, int mask_couplings, hipStream_t s);
+hipError_t launch_from_sheared_f64(const Geom &g, const double *src, double *dst, const Ctl *zero_if_zero_rhs,
+                                   hipStream_t s);
+hipError_t launch_export_factors(const Geom &g, const void *LU, int fp32, double *const *dst, hipStream_t s);
+hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s);
+hipError_t launch_forward(const LaunchArgs &a, int fp32, hipStream_t s);
+hipError_t launch_backward(const LaunchArgs &a, int fp32, hipStream_t s);
+
+}  // namespace sipk

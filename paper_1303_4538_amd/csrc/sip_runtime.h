@@ -1,0 +1,48 @@
+// Host-side runtime structures of the SIP library.
+#pragma once
+#include "../../include/sip.h"
+#include "sip_internal.h"
+
+#include <string>
+#include <vector>
+
+namespace sipk {
+
+constexpr int CHUNK = 8;   // iterations per graph-captured launch chunk
+
+extern thread_local std::string g_last_error;
+sip_status set_error(sip_status st, const char *fmt, ...);
+uint64_t timeout_ticks_for(int device, double seconds);
+std::vector<int2> topo_order(const std::vector<Geom> &gs, bool backward);
+size_t system_bytes(const Geom &g, int fp32);
+
+}  // namespace sipk
+
+struct sip_system_s {
+    sipk::Geom g{};
+    int fp32 = 0;
+    int precision = 0;
+    double alpha = 0.0;
+    int device = 0;
+    uint64_t timeout_ticks = 0;
+    size_t bytes = 0;
+    double *A = nullptr;            // 7 * elems
+    void *LU = nullptr;             // 7 * elems of FP64 or FP32
+    double *bx = nullptr;           // b then x, elems each
+    void *y = nullptr;
+    uint64_t *face = nullptr;
+    double *part = nullptr;
+    sipk::Ctl *ctl = nullptr;
+    double *hist = nullptr;
+    int hist_cap = 0;
+    sipk::Job job{};                // sweeps
+    sipk::Job job_factor{};         // factorisation (wider face words)
+    sipk::Job *d_job = nullptr;
+    sipk::Job *d_job_factor = nullptr;
+    int2 *order_f = nullptr, *order_b = nullptr;
+    sipk::LaunchCtl *lc = nullptr;
+    sipk::Ctl *h_ctl = nullptr;     // pinned, 4 slots
+    double *h_hist = nullptr;       // pinned
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t chunk_exec = nullptr;
+};
