@@ -109,6 +109,14 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
  * In the mixed precision the FP32 factors are widened.  Stream-ordered. */
 sip_status sip_export_factors(sip_system h, double *const out[7], void *stream);
 
+/* sip_profile_sweeps -- measurement hook: runs n_iter iterations like
+ * sip_iterate (x updated in place) with a HIP event recorded before and
+ * after every sweep launch on `stream`, synchronises, and writes the average
+ * device time in milliseconds of one forward sweep (ms[0]) and one backward
+ * sweep (ms[1]) to host memory.  n_iter >= 1.  Errors: SIP_EINVAL,
+ * SIP_EDEVICE. */
+sip_status sip_profile_sweeps(sip_system h, const double *b, double *x, int32_t n_iter, double ms[2], void *stream);
+
 /* sip_system_info -- dims, precision and device bytes held by a handle. */
 sip_status sip_system_info(sip_system h, int32_t dims[3], int32_t *precision, size_t *device_bytes);
 

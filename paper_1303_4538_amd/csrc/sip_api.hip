@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -175,8 +176,8 @@ static sip_status launch_iterations(sip_system_s *h, int n, hipStream_t s)
 {
     const LaunchArgs fa = fwd_args(h), ba = bwd_args(h);
     for (int q = 0; q < n; q++) {
-        HIPTRY(launch_forward(fa, h->fp32, s));
-        HIPTRY(launch_backward(ba, h->fp32, s));
+        HIPTRY(launch_forward(fa, h->fp32, h->plan, s));
+        HIPTRY(launch_backward(ba, h->fp32, h->plan, s));
     }
     return SIP_OK;
 }
@@ -255,6 +256,10 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     hipStream_t s = (hipStream_t)stream;
     sip_system_s *h = new sip_system_s();
     h->g = make_geom(p->ni, p->nj, p->nk);
+    if (h->g.elems >= (1ll << 29)) {   // kernels address every array with 32-bit byte offsets
+        delete h;
+        return set_error(SIP_EINVAL, "block too large: more than 2^29 cells in the sheared layout");
+    }
     h->fp32 = p->precision == SIP_MIXED;
     h->precision = p->precision;
     h->alpha = p->alpha;
@@ -263,6 +268,10 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
         return set_error(SIP_EDEVICE, "no HIP device");
     }
     h->timeout_ticks = timeout_ticks_for(h->device, 2.0);
+    if (const char *e = getenv("SIP_SWEEP_LOADERS")) {   // tuning override
+        const int nl = atoi(e);
+        if (nl == 2 || nl == 4 || nl == 6 || nl == 8) h->plan.loaders = nl;
+    }
     sip_status st = system_alloc(h, s);
     if (st != SIP_OK) {
         free_system(h);
@@ -331,7 +340,7 @@ sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
         left -= CHUNK;
     }
     TRY(launch_iterations(h, left, s));
-    HIPTRY(launch_forward(fwd_args(h), h->fp32, s));   // residual of the final iterate
+    HIPTRY(launch_forward(fwd_args(h), h->fp32, h->plan, s));   // residual of the final iterate
     HIPTRY(launch_from_sheared_f64(g, h->bx + g.elems, x, h->ctl, s));
     if (!rel_res_hist) return SIP_OK;
     HIPTRY(hipMemcpyAsync(h->h_hist, h->hist, (size_t)(n_iter + 1) * 8, hipMemcpyDeviceToHost, s));
@@ -408,6 +417,45 @@ sip_status sip_export_factors(sip_system h, double *const out[7], void *stream)
     for (int d = 0; d < 7; d++)
         if (!out[d]) return set_error(SIP_EINVAL, "output pointer %d is NULL", d);
     HIPTRY(launch_export_factors(h->g, h->LU, h->fp32, out, (hipStream_t)stream));
+    return SIP_OK;
+}
+
+sip_status sip_profile_sweeps(sip_system h, const double *b, double *x, int32_t n_iter, double ms[2], void *stream)
+{
+    if (!h || !b || !x || !ms) return set_error(SIP_EINVAL, "NULL argument");
+    if (n_iter < 1) return set_error(SIP_EINVAL, "n_iter must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    TRY(ensure_hist(h, n_iter + 1, s));
+    const Geom &g = h->g;
+    const double *src[2] = {b, x};
+    HIPTRY(launch_to_sheared(g, 2, src, h->bx, g.elems, 0, s));
+    HIPTRY(launch_init_ctl(h->ctl, 1, (uint32_t)n_iter, 0.0, 0, s));
+    std::vector<hipEvent_t> ev(2 * n_iter + 1);
+    for (auto &e : ev) HIPTRY(hipEventCreate(&e));
+    const LaunchArgs fa = fwd_args(h), ba = bwd_args(h);
+    sip_status st = SIP_OK;
+    if (hipEventRecord(ev[0], s) != hipSuccess) st = set_error(SIP_EDEVICE, "event record failed");
+    for (int q = 0; q < n_iter && st == SIP_OK; q++) {
+        if (launch_forward(fa, h->fp32, h->plan, s) != hipSuccess || hipEventRecord(ev[2 * q + 1], s) != hipSuccess ||
+            launch_backward(ba, h->fp32, h->plan, s) != hipSuccess || hipEventRecord(ev[2 * q + 2], s) != hipSuccess)
+            st = set_error(SIP_EDEVICE, "launch failed");
+    }
+    if (st == SIP_OK && launch_from_sheared_f64(g, h->bx + g.elems, x, h->ctl, s) != hipSuccess)
+        st = set_error(SIP_EDEVICE, "reorder failed");
+    if (st == SIP_OK && hipStreamSynchronize(s) != hipSuccess) st = set_error(SIP_EDEVICE, "synchronise failed");
+    double f = 0.0, bk = 0.0;
+    for (int q = 0; q < n_iter && st == SIP_OK; q++) {
+        float a = 0.f, c = 0.f;
+        if (hipEventElapsedTime(&a, ev[2 * q], ev[2 * q + 1]) != hipSuccess ||
+            hipEventElapsedTime(&c, ev[2 * q + 1], ev[2 * q + 2]) != hipSuccess)
+            st = set_error(SIP_EDEVICE, "event timing failed");
+        f += a;
+        bk += c;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (st != SIP_OK) return st;
+    ms[0] = f / n_iter;
+    ms[1] = bk / n_iter;
     return SIP_OK;
 }
 

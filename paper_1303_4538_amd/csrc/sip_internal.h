@@ -99,7 +99,11 @@ hipError_t launch_from_sheared_f64(const Geom &g, const double *src, double *dst
                                    hipStream_t s);
 hipError_t launch_export_factors(const Geom &g, const void *LU, int fp32, double *const *dst, hipStream_t s);
 hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s);
-hipError_t launch_forward(const LaunchArgs &a, int fp32, hipStream_t s);
-hipError_t launch_backward(const LaunchArgs &a, int fp32, hipStream_t s);
+// Launch shape of the sweeps: loader waves per tile (2, 4, 6 or 8).
+struct SweepPlan {
+    int loaders = 4;
+};
+hipError_t launch_forward(const LaunchArgs &a, int fp32, const SweepPlan &p, hipStream_t s);
+hipError_t launch_backward(const LaunchArgs &a, int fp32, const SweepPlan &p, hipStream_t s);
 
 }  // namespace sipk

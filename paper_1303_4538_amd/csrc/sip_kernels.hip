@@ -52,6 +52,17 @@ Geom make_geom(int ni, int nj, int nk)
 
 namespace {
 
+// Pointers read from a job descriptor are generic to the compiler, which then
+// emits flat loads; flat loads count against the LDS counter, so every LDS
+// wait (e.g. before a barrier) would also wait for all outstanding prefetches.
+// Qualifying them as global memory keeps HBM traffic on the vector counter only.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T *gp(T *p)
+{
+    return (GLOBAL T *)p;
+}
+
 constexpr int WAVE = 64;
 constexpr int BLOCK = 2 * WAVE;
 constexpr int LP = 4;   // loader register-pipeline depth (steps of look-ahead)
@@ -59,12 +70,12 @@ constexpr int PD = 2;   // face-word prefetch distance of the recurrence wave
 
 // ---------------------------------------------------------------- helpers
 
-__device__ __forceinline__ uint64_t ll_load(const uint64_t *p)
+__device__ __forceinline__ uint64_t ll_load(const GLOBAL uint64_t *p)
 {
-    return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(const_cast<GLOBAL uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void ll_store(uint64_t *p, uint32_t tag, uint32_t payload)
+__device__ __forceinline__ void ll_store(GLOBAL uint64_t *p, uint32_t tag, uint32_t payload)
 {
     __hip_atomic_store(p, ((uint64_t)tag << 32) | payload, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -109,13 +120,17 @@ struct Halo {
     uint64_t b[NWORDS];
 };
 
+// Every lane loads its words unconditionally: lanes that need no halo point
+// at a dummy word.  Keeping the poll loads free of control flow lets the
+// compiler count them exactly (s_waitcnt vmcnt(N)) instead of draining all
+// prefetched polls at every step.
 template <int NWORDS>
-__device__ __forceinline__ void halo_issue(Halo<NWORDS> &h, bool na, const uint64_t *pa, bool nb, const uint64_t *pb)
+__device__ __forceinline__ void halo_issue(Halo<NWORDS> &h, const GLOBAL uint64_t *pa, const GLOBAL uint64_t *pb)
 {
 #pragma unroll
     for (int w = 0; w < NWORDS; w++) {
-        h.a[w] = na ? ll_load(pa + w) : 0ull;
-        h.b[w] = nb ? ll_load(pb + w) : 0ull;
+        h.a[w] = ll_load(pa + w);
+        h.b[w] = ll_load(pb + w);
     }
 }
 
@@ -134,13 +149,13 @@ __device__ __forceinline__ bool halo_ok(const Halo<NWORDS> &h, bool na, bool nb,
 // Re-poll until every lane's needed words carry `tag`.  Returns false if the
 // wait timed out or another workgroup raised the error flag.
 template <int NWORDS>
-__device__ bool halo_wait(Halo<NWORDS> &h, bool na, const uint64_t *pa, bool nb, const uint64_t *pb, uint32_t tag,
-                          Ctl *ctl, uint64_t timeout)
+__device__ __forceinline__ bool halo_wait(Halo<NWORDS> &h, bool na, const GLOBAL uint64_t *pa, bool nb, const GLOBAL uint64_t *pb,
+                          uint32_t tag, GLOBAL Ctl *ctl, uint64_t timeout)
 {
     if (!__any(!halo_ok(h, na, nb, tag))) return true;
     const uint64_t t0 = wall_clock64();
     for (;;) {
-        halo_issue(h, na, pa, nb, pb);
+        halo_issue(h, pa, pb);
         if (!__any(!halo_ok(h, na, nb, tag))) return true;
         if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u) return false;
         if (wall_clock64() - t0 > timeout) {
@@ -234,10 +249,26 @@ __device__ __forceinline__ int padded_intervals(int steps)
     return (u + LP - 1) / LP * LP;
 }
 
-// ------------------------------------------------------ forward sweep
-// Residual r = b - A x (FP64, fused), forward substitution
-// y = (r - Lb y_B - Lw y_W - Ls y_S) / Lp in precision F, and the per-tile
-// partial sums of r^2 (and of b^2 at iteration 0).
+// ------------------------------------------------------ sweeps
+// Workgroup = one recurrence wave (wave 0) + NL loader waves.  Loader wave l
+// owns the steps f with f % NL == l: at its turn (interval f) it consumes the
+// loads it issued NL intervals earlier, stages the operands of step f in the
+// LDS ring, writes back the recurrence result of step f - 2, and issues the
+// loads of step f + NL.  Its own vector-memory wait at a turn therefore only
+// covers loads that had NL intervals to arrive.  Interval u: loaders fill step
+// u, the recurrence wave processes step u - 1, results of step u - 2 are
+// written back; one workgroup barrier ends every interval.
+
+__device__ __forceinline__ int sweep_intervals(int steps, int pd)
+{
+    // interval 0 (fill only) plus the recurrence steps 0..steps (step `steps`
+    // only lets the last write-back happen), padded to the poll unroll
+    return 1 + (steps + 1 + pd - 1) / pd * pd;
+}
+
+// Forward: residual r = b - A x (FP64, fused), forward substitution
+// y = (r - Lb y_B - Lw y_W - Ls y_S) / Lp in precision F, per-tile partial
+// sums of r^2 (and of b^2, used at iteration 0).
 
 template <typename F>
 struct FwdLoad {
@@ -247,47 +278,81 @@ struct FwdLoad {
     F l[4];        // Lb, Lw, Ls, 1/Lp
 };
 
-template <typename F>
-__device__ __forceinline__ void fwd_issue(FwdLoad<F> &c, const Job &J, const TileView &v, int f)
+// Load through a uniform base pointer and a 32-bit element index (the host
+// guarantees every array stays below 4 GiB), which maps onto the
+// saddr + voffset form of global_load.
+template <typename T>
+__device__ __forceinline__ T ldg(const GLOBAL T *base, uint32_t idx)
 {
-    const Geom &g = J.g;
-    const bool act = f < g.steps && v.active(f, g.nk);
-    const long long e = v.base + (long long)f * TT;
-    const F *LU = (const F *)J.LU;
-#pragma unroll
-    for (int d = 0; d < 7; d++) c.a[d] = act ? J.A[d * g.elems + e] : 0.0;
-    c.b = act ? J.b[e] : 0.0;
-#pragma unroll
-    for (int d = 0; d < 4; d++) c.l[d] = act ? LU[d * g.elems + e] : F(0);
-    const double *X = J.x;
-    const long long te = g.tile_elems;
-    c.x[0] = act ? X[e] : 0.0;
-    c.x[5] = act ? X[e - TT] : 0.0;
-    c.x[6] = act ? X[e + TT] : 0.0;
-    // W neighbour: same tile plane f-1, or the W tile's plane f+TI-1, column TI-1
-    long long ew = -1, ee = -1, es = -1, en = -1;
-    if (v.ip > 0) ew = e - TT - 1;
-    else if (v.ti > 0) ew = (long long)(v.t - 1) * te + TT + (long long)(f + TI - 1) * TT + v.jp * TI + (TI - 1);
-    if (v.ip < TI - 1) ee = e + TT + 1;
-    else if (v.ti < g.nti - 1) ee = (long long)(v.t + 1) * te + TT + (long long)(f - TI + 1) * TT + v.jp * TI;
-    if (v.jp > 0) es = e - TT - TI;
-    else if (v.tj > 0) es = (long long)(v.t - g.nti) * te + TT + (long long)(f + TJ - 1) * TT + (TJ - 1) * TI + v.ip;
-    if (v.jp < TJ - 1) en = e + TT + TI;
-    else if (v.tj < g.ntj - 1) en = (long long)(v.t + g.nti) * te + TT + (long long)(f - TJ + 1) * TT + v.ip;
-    c.x[1] = (act && ew >= 0) ? X[ew] : 0.0;
-    c.x[2] = (act && ee >= 0) ? X[ee] : 0.0;
-    c.x[3] = (act && es >= 0) ? X[es] : 0.0;
-    c.x[4] = (act && en >= 0) ? X[en] : 0.0;
+    return *(const GLOBAL T *)((const GLOBAL char *)base + (size_t)(idx * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void stg(GLOBAL T *base, uint32_t idx, T v)
+{
+    *(GLOBAL T *)((GLOBAL char *)base + (size_t)(idx * (uint32_t)sizeof(T))) = v;
 }
 
+// Uniform base pointers and per-lane index deltas of the forward loader.
 template <typename F>
-__global__ __launch_bounds__(BLOCK) void k_forward(LaunchArgs a)
+struct FwdSrc {
+    const GLOBAL double *A[7];
+    const GLOBAL double *b, *x;
+    const GLOBAL F *L[4];
+    uint32_t e0;          // sheared index of (plane 0, this lane)
+    int32_t hw, he, hs, hn;   // index deltas of the W/E/S/N neighbours (0 where none)
+};
+
+template <typename F>
+__device__ __forceinline__ FwdSrc<F> fwd_src(const Job &J, const TileView &v)
+{
+    const Geom &g = J.g;
+    FwdSrc<F> q;
+#pragma unroll
+    for (int d = 0; d < 7; d++) q.A[d] = gp(J.A) + d * g.elems;
+    q.b = gp(J.b);
+    q.x = gp((const double *)J.x);
+#pragma unroll
+    for (int d = 0; d < 4; d++) q.L[d] = gp((const F *)J.LU) + d * g.elems;
+    q.e0 = (uint32_t)v.base;
+    const int te = (int)g.tile_elems;
+    // in-tile neighbours sit on planes -/+1; across a tile edge they are the
+    // neighbour tile's edge column/row on that tile's own local plane
+    q.hw = v.ip > 0 ? -TT - 1 : (v.ti > 0 ? -te + (TI - 1) * TT + (TI - 1) : 0);
+    q.he = v.ip < TI - 1 ? TT + 1 : (v.ti < g.nti - 1 ? te - (TI - 1) * TT - (TI - 1) : 0);
+    q.hs = v.jp > 0 ? -TT - TI : (v.tj > 0 ? -g.nti * te + (TJ - 1) * TT + (TJ - 1) * TI : 0);
+    q.hn = v.jp < TJ - 1 ? TT + TI : (v.tj < g.ntj - 1 ? g.nti * te - (TJ - 1) * TT - (TJ - 1) * TI : 0);
+    return q;
+}
+
+// Branch-free: inactive lanes read their own zero-padded slot (every index
+// stays inside the tile's planes -1..steps for f in [0, steps)).
+template <typename F>
+__device__ __forceinline__ void fwd_issue(FwdLoad<F> &c, const FwdSrc<F> &q, const TileView &v, int f, int nk)
+{
+    const bool act = v.active(f, nk);
+    const uint32_t e = q.e0 + (uint32_t)f * TT;
+#pragma unroll
+    for (int d = 0; d < 7; d++) c.a[d] = ldg(q.A[d], e);
+    c.b = ldg(q.b, e);
+#pragma unroll
+    for (int d = 0; d < 4; d++) c.l[d] = ldg(q.L[d], e);
+    c.x[0] = ldg(q.x, e);
+    c.x[5] = ldg(q.x, e - TT);
+    c.x[6] = ldg(q.x, e + TT);
+    c.x[1] = ldg(q.x, e + (act ? q.hw : 0));
+    c.x[2] = ldg(q.x, e + (act ? q.he : 0));
+    c.x[3] = ldg(q.x, e + (act ? q.hs : 0));
+    c.x[4] = ldg(q.x, e + (act ? q.hn : 0));
+}
+
+template <typename F, int NL, int PD>
+__global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
 {
     constexpr int NV = NW<F>::n;
-    __shared__ F ring[2][5][TT];     // r, Lb, Lw, Ls, 1/Lp for two steps
+    __shared__ F ring[2][5][TT];     // r, Lb, Lw, Ls, 1/Lp of two steps
     __shared__ F ybuf[2][TT];
     __shared__ int s_buf[4];
-    __shared__ double s_red[2];
+    __shared__ double s_part[NL][2];
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -303,113 +368,114 @@ __global__ __launch_bounds__(BLOCK) void k_forward(LaunchArgs a)
     const uint32_t iter = J.ctl->iter;
     const Geom g = J.g;
     const TileView v = make_view(g, as.tile, lane);
-    const int U = padded_intervals(g.steps);
+    const int U = sweep_intervals(g.steps, PD);
     const int FW = J.fw;
     const long long fstride = (long long)g.steps * FW;
-    uint64_t *face_t = J.face + (long long)v.t * fstride;
+    GLOBAL uint64_t *face_t = gp(J.face) + (long long)v.t * fstride;
+    GLOBAL Ctl *ctl = gp(J.ctl);
 
     ybuf[0][lane] = F(0);
     ybuf[1][lane] = F(0);
-    double rr = 0.0, bb = 0.0;
     __syncthreads();
 
     if (wave == 0) {
         // ---------------- recurrence wave
-        const uint64_t *faceW = v.ti > 0 ? J.face + (long long)(v.t - 1) * fstride : nullptr;
-        const uint64_t *faceS = v.tj > 0 ? J.face + (long long)(v.t - g.nti) * fstride : nullptr;
+        const GLOBAL uint64_t *faceW = v.ti > 0 ? gp(J.face) + (long long)(v.t - 1) * fstride : face_t;
+        const GLOBAL uint64_t *faceS = v.tj > 0 ? gp(J.face) + (long long)(v.t - g.nti) * fstride : face_t;
         Halo<NV> pv[PD];
         bool needW[PD], needS[PD];
-        const uint64_t *pW[PD], *pS[PD];
+        const GLOBAL uint64_t *pW[PD], *pS[PD];
         auto plan = [&](int q, int s2) {
-            const bool act = s2 < g.steps && v.active(s2, g.nk);
+            const bool act = v.active(s2, g.nk);
             needW[q] = act && v.ip == 0 && v.ti > 0;
             needS[q] = act && v.jp == 0 && v.tj > 0;
-            pW[q] = needW[q] ? faceW + (long long)(s2 + TI - 1) * FW + v.jp * NV : nullptr;
-            pS[q] = needS[q] ? faceS + (long long)(s2 + TJ - 1) * FW + (TJ + v.ip) * NV : nullptr;
-            halo_issue(pv[q], needW[q], pW[q], needS[q], pS[q]);
+            pW[q] = needW[q] ? faceW + (long long)(s2 + TI - 1) * FW + v.jp * NV : face_t;
+            pS[q] = needS[q] ? faceS + (long long)(s2 + TJ - 1) * FW + (TJ + v.ip) * NV : face_t;
+            halo_issue(pv[q], pW[q], pS[q]);
         };
 #pragma unroll
         for (int q = 0; q < PD; q++) plan(q, q);
         F yB = F(0);
         bool aborted = false;
-        for (int u0 = 0; u0 < U; u0 += LP) {
+        wg_barrier();   // interval 0: the loaders stage step 0
+        for (int s0 = 0; s0 + 1 < U; s0 += PD) {
 #pragma unroll
-            for (int w = 0; w < LP; w++) {
-                const int u = u0 + w;
-                const int s = u - 1;
-                const int q = ((w - 1) % PD + PD) % PD;   // == s mod PD (u0 is a multiple of LP, PD | LP)
-                if (s >= 0 && s < g.steps && !aborted) {
-                    const int slot = s & 1;
-                    const F r = ring[slot][0][lane];
-                    const F lb = ring[slot][1][lane];
-                    const F lw = ring[slot][2][lane];
-                    const F ls = ring[slot][3][lane];
-                    const F ilp = ring[slot][4][lane];
-                    if (!halo_wait(pv[q], needW[q], pW[q], needS[q], pS[q], tag, J.ctl, a.timeout_ticks)) {
-                        aborted = true;
-                    }
-                    F hw, hs;
-                    from_words(pv[q].a, hw);
-                    from_words(pv[q].b, hs);
-                    const int pr = (s - 1) & 1;
-                    const F yW = v.ip > 0 ? ybuf[pr][lane - (v.ip > 0 ? 1 : 0)] : hw;
-                    const F yS = v.jp > 0 ? ybuf[pr][lane - (v.jp > 0 ? TI : 0)] : hs;
-                    const bool act = v.active(s, g.nk);
-                    F t = r - lb * yB;
-                    t = t - lw * yW;
-                    t = t - ls * yS;
-                    const F y = act ? t * ilp : F(0);
-                    yB = y;
-                    ybuf[s & 1][lane] = y;
-                    plan(q, s + PD);
-                }
-                if (w == LP - 1 && aborted) s_buf[3] = 1;   // read by both waves after this barrier
+            for (int q = 0; q < PD; q++) {
+                const int s = s0 + q;
+                const int slot = s & 1;
+                const F r = ring[slot][0][lane];
+                const F lb = ring[slot][1][lane];
+                const F lw = ring[slot][2][lane];
+                const F ls = ring[slot][3][lane];
+                const F ilp = ring[slot][4][lane];
+                if (!aborted && !halo_wait(pv[q], needW[q], pW[q], needS[q], pS[q], tag, ctl, a.timeout_ticks))
+                    aborted = true;
+                F hw, hs;
+                from_words(pv[q].a, hw);
+                from_words(pv[q].b, hs);
+                const int pr = (s - 1) & 1;
+                const F yW = v.ip > 0 ? ybuf[pr][lane - (v.ip > 0 ? 1 : 0)] : (needW[q] ? hw : F(0));
+                const F yS = v.jp > 0 ? ybuf[pr][lane - (v.jp > 0 ? TI : 0)] : (needS[q] ? hs : F(0));
+                const bool act = v.active(s, g.nk);
+                F t = r - lb * yB;
+                t = t - lw * yW;
+                t = t - ls * yS;
+                const F y = act ? t * ilp : F(0);
+                yB = y;
+                ybuf[s & 1][lane] = y;
+                plan(q, s + PD);
+                if (q == PD - 1 && aborted) s_buf[3] = 1;   // read by every wave after this barrier
                 wg_barrier();
             }
             if (s_buf[3]) break;
         }
     } else {
-        // ---------------- loader wave
-        FwdLoad<F> pipe[LP];
+        // ---------------- loader waves
+        const int lw = wave - 1;
+        const FwdSrc<F> src = fwd_src<F>(J, v);
+        FwdLoad<F> c;
+        if (lw < g.steps) fwd_issue(c, src, v, lw, g.nk);
+        GLOBAL F *yout = gp((F *)J.y);
+        double rr = 0.0, bb = 0.0;
+        auto turn = [&](int u) {
+            const int f = u;
+            if (f < g.steps) {
+                const double ax = c.a[0] * c.x[0] + c.a[1] * c.x[1] + c.a[2] * c.x[2] + c.a[3] * c.x[3] +
+                                  c.a[4] * c.x[4] + c.a[5] * c.x[5] + c.a[6] * c.x[6];
+                const double r = c.b - ax;
+                rr += r * r;
+                bb += c.b * c.b;
+                const int slot = f & 1;
+                ring[slot][0][lane] = (F)r;
+                ring[slot][1][lane] = c.l[0];
+                ring[slot][2][lane] = c.l[1];
+                ring[slot][3][lane] = c.l[2];
+                ring[slot][4][lane] = c.l[3];
+            }
+            const int p = u - 2;
+            if (p >= 0 && p < g.steps) {
+                const F y = ybuf[p & 1][lane];
+                stg(yout, src.e0 + (uint32_t)p * TT, y);   // inactive lanes rewrite their zero padding
+                uint32_t wd[NV];
+                to_words(y, wd);
+                if (v.ip == TI - 1) {
 #pragma unroll
-        for (int q = 0; q < LP; q++) fwd_issue(pipe[q], J, v, q);
-        F *yout = (F *)J.y;
-        for (int u0 = 0; u0 < U; u0 += LP) {
-#pragma unroll
-            for (int w = 0; w < LP; w++) {
-                const int u = u0 + w;
-                const int p = u - 2;
-                if (p >= 0 && p < g.steps) {
-                    const F y = ybuf[p & 1][lane];
-                    if (v.active(p, g.nk)) yout[v.base + (long long)p * TT] = y;
-                    uint32_t wd[NV];
-                    to_words(y, wd);
-                    if (v.ip == TI - 1) {
-#pragma unroll
-                        for (int q = 0; q < NV; q++) ll_store(face_t + (long long)p * FW + v.jp * NV + q, tag, wd[q]);
-                    }
-                    if (v.jp == TJ - 1) {
-#pragma unroll
-                        for (int q = 0; q < NV; q++)
-                            ll_store(face_t + (long long)p * FW + (TJ + v.ip) * NV + q, tag, wd[q]);
-                    }
+                    for (int q = 0; q < NV; q++) ll_store(face_t + (long long)p * FW + v.jp * NV + q, tag, wd[q]);
                 }
-                const int f = u;
-                if (f < g.steps) {
-                    FwdLoad<F> &c = pipe[w];
-                    const double ax = c.a[0] * c.x[0] + c.a[1] * c.x[1] + c.a[2] * c.x[2] + c.a[3] * c.x[3] +
-                                      c.a[4] * c.x[4] + c.a[5] * c.x[5] + c.a[6] * c.x[6];
-                    const double r = c.b - ax;
-                    rr += r * r;
-                    bb += c.b * c.b;
-                    const int slot = f & 1;
-                    ring[slot][0][lane] = (F)r;
-                    ring[slot][1][lane] = c.l[0];
-                    ring[slot][2][lane] = c.l[1];
-                    ring[slot][3][lane] = c.l[2];
-                    ring[slot][4][lane] = c.l[3];
-                    fwd_issue(c, J, v, f + LP);
+                if (v.jp == TJ - 1) {
+#pragma unroll
+                    for (int q = 0; q < NV; q++)
+                        ll_store(face_t + (long long)p * FW + (TJ + v.ip) * NV + q, tag, wd[q]);
                 }
+            }
+            if (u + NL < g.steps) fwd_issue(c, src, v, u + NL, g.nk);
+        };
+        if (lw == 0) turn(0);
+        wg_barrier();
+        for (int s0 = 0; s0 + 1 < U; s0 += PD) {
+            for (int q = 0; q < PD; q++) {
+                const int u = s0 + q + 1;
+                if (u % NL == lw) turn(u);
                 wg_barrier();
             }
             if (s_buf[3]) break;
@@ -417,9 +483,19 @@ __global__ __launch_bounds__(BLOCK) void k_forward(LaunchArgs a)
         rr = wave_sum(rr);
         bb = wave_sum(bb);
         if (lane == 0) {
-            J.part[2 * v.t] = rr;
-            J.part[2 * v.t + 1] = bb;
+            s_part[lw][0] = rr;
+            s_part[lw][1] = bb;
         }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sr = 0.0, sb = 0.0;
+        for (int l = 0; l < NL; l++) {
+            sr += s_part[l][0];
+            sb += s_part[l][1];
+        }
+        gp(J.part)[2 * v.t] = sr;
+        gp(J.part)[2 * v.t + 1] = sb;
     }
 
     if (job_last(J, s_buf) && wave == 0) {
@@ -457,9 +533,8 @@ __global__ __launch_bounds__(BLOCK) void k_forward(LaunchArgs a)
     launch_done(a);
 }
 
-// ------------------------------------------------------ backward sweep
-// d = y - Un d_N - Ue d_E - Ut d_T in reverse local-hyperplane order, then
-// x += d in FP64.
+// Backward: d = y - Un d_N - Ue d_E - Ut d_T in reverse local-hyperplane
+// order (step s visits plane steps - 1 - s), then x += d in FP64.
 
 template <typename F>
 struct BwdLoad {
@@ -468,22 +543,25 @@ struct BwdLoad {
 };
 
 template <typename F>
-__device__ __forceinline__ void bwd_issue(BwdLoad<F> &c, const Job &J, const TileView &v, int q)
-{
-    const Geom &g = J.g;
-    const int s = g.steps - 1 - q;
-    const bool act = q < g.steps && v.active(s, g.nk);
-    const long long e = v.base + (long long)s * TT;
-    const F *LU = (const F *)J.LU;
-    const F *Y = (const F *)J.y;
-    c.y = act ? Y[e] : F(0);
-#pragma unroll
-    for (int d = 0; d < 3; d++) c.u[d] = act ? LU[(4 + d) * g.elems + e] : F(0);
-    c.x = act ? J.x[e] : 0.0;
-}
+struct BwdSrc {
+    const GLOBAL F *y;
+    const GLOBAL F *U[3];
+    GLOBAL double *x;
+    uint32_t e0;
+};
 
 template <typename F>
-__global__ __launch_bounds__(BLOCK) void k_backward(LaunchArgs a)
+__device__ __forceinline__ void bwd_issue(BwdLoad<F> &c, const BwdSrc<F> &q, int steps, int step)
+{
+    const uint32_t e = q.e0 + (uint32_t)(steps - 1 - step) * TT;
+    c.y = ldg(q.y, e);
+#pragma unroll
+    for (int d = 0; d < 3; d++) c.u[d] = ldg(q.U[d], e);
+    c.x = ldg((const GLOBAL double *)q.x, e);
+}
+
+template <typename F, int NL, int PD>
+__global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
 {
     constexpr int NV = NW<F>::n;
     __shared__ F ring[2][4][TT];     // y, Un, Ue, Ut
@@ -504,105 +582,111 @@ __global__ __launch_bounds__(BLOCK) void k_backward(LaunchArgs a)
     const uint32_t tag = J.ctl->epoch;
     const Geom g = J.g;
     const TileView v = make_view(g, as.tile, lane);
-    const int U = padded_intervals(g.steps);
+    const int U = sweep_intervals(g.steps, PD);
     const int FW = J.fw;
     const long long fstride = (long long)g.steps * FW;
-    uint64_t *face_t = J.face + (long long)v.t * fstride;
+    GLOBAL uint64_t *face_t = gp(J.face) + (long long)v.t * fstride;
+    GLOBAL Ctl *ctl = gp(J.ctl);
 
     dbuf[0][lane] = F(0);
     dbuf[1][lane] = F(0);
     __syncthreads();
 
     if (wave == 0) {
-        const uint64_t *faceE = v.ti < g.nti - 1 ? J.face + (long long)(v.t + 1) * fstride : nullptr;
-        const uint64_t *faceN = v.tj < g.ntj - 1 ? J.face + (long long)(v.t + g.nti) * fstride : nullptr;
+        const GLOBAL uint64_t *faceE = v.ti < g.nti - 1 ? gp(J.face) + (long long)(v.t + 1) * fstride : face_t;
+        const GLOBAL uint64_t *faceN = v.tj < g.ntj - 1 ? gp(J.face) + (long long)(v.t + g.nti) * fstride : face_t;
         Halo<NV> pv[PD];
         bool needE[PD], needN[PD];
-        const uint64_t *pE[PD], *pN[PD];
-        auto plan = [&](int q, int s2) {   // s2: backward step index
+        const GLOBAL uint64_t *pE[PD], *pN[PD];
+        auto plan = [&](int q, int s2) {   // s2: backward step
             const bool act = s2 < g.steps && v.active(g.steps - 1 - s2, g.nk);
             needE[q] = act && v.ip == TI - 1 && v.ti < g.nti - 1;
             needN[q] = act && v.jp == TJ - 1 && v.tj < g.ntj - 1;
-            pE[q] = needE[q] ? faceE + (long long)(s2 + TI - 1) * FW + v.jp * NV : nullptr;
-            pN[q] = needN[q] ? faceN + (long long)(s2 + TJ - 1) * FW + (TJ + v.ip) * NV : nullptr;
-            halo_issue(pv[q], needE[q], pE[q], needN[q], pN[q]);
+            pE[q] = needE[q] ? faceE + (long long)(s2 + TI - 1) * FW + v.jp * NV : face_t;
+            pN[q] = needN[q] ? faceN + (long long)(s2 + TJ - 1) * FW + (TJ + v.ip) * NV : face_t;
+            halo_issue(pv[q], pE[q], pN[q]);
         };
 #pragma unroll
         for (int q = 0; q < PD; q++) plan(q, q);
         F dT = F(0);
         bool aborted = false;
-        for (int u0 = 0; u0 < U; u0 += LP) {
+        wg_barrier();
+        for (int s0 = 0; s0 + 1 < U; s0 += PD) {
 #pragma unroll
-            for (int w = 0; w < LP; w++) {
-                const int u = u0 + w;
-                const int s = u - 1;   // backward step
-                const int q = ((w - 1) % PD + PD) % PD;
-                if (s >= 0 && s < g.steps && !aborted) {
-                    const int slot = s & 1;
-                    const F yv = ring[slot][0][lane];
-                    const F un = ring[slot][1][lane];
-                    const F ue = ring[slot][2][lane];
-                    const F ut = ring[slot][3][lane];
-                    if (!halo_wait(pv[q], needE[q], pE[q], needN[q], pN[q], tag, J.ctl, a.timeout_ticks)) {
-                        aborted = true;
-                    }
-                    F he, hn;
-                    from_words(pv[q].a, he);
-                    from_words(pv[q].b, hn);
-                    const int pr = (s - 1) & 1;
-                    const F dE = v.ip < TI - 1 ? dbuf[pr][lane + (v.ip < TI - 1 ? 1 : 0)] : he;
-                    const F dN = v.jp < TJ - 1 ? dbuf[pr][lane + (v.jp < TJ - 1 ? TI : 0)] : hn;
-                    const bool act = v.active(g.steps - 1 - s, g.nk);
-                    F t = yv - un * dN;
-                    t = t - ue * dE;
-                    t = t - ut * dT;
-                    const F d = act ? t : F(0);
-                    dT = d;
-                    dbuf[s & 1][lane] = d;
-                    plan(q, s + PD);
-                }
-                if (w == LP - 1 && aborted) s_buf[3] = 1;   // read by both waves after this barrier
+            for (int q = 0; q < PD; q++) {
+                const int s = s0 + q;
+                const int slot = s & 1;
+                const F yv = ring[slot][0][lane];
+                const F un = ring[slot][1][lane];
+                const F ue = ring[slot][2][lane];
+                const F ut = ring[slot][3][lane];
+                if (!aborted && !halo_wait(pv[q], needE[q], pE[q], needN[q], pN[q], tag, ctl, a.timeout_ticks))
+                    aborted = true;
+                F he, hn;
+                from_words(pv[q].a, he);
+                from_words(pv[q].b, hn);
+                const int pr = (s - 1) & 1;
+                const F dE = v.ip < TI - 1 ? dbuf[pr][lane + (v.ip < TI - 1 ? 1 : 0)] : (needE[q] ? he : F(0));
+                const F dN = v.jp < TJ - 1 ? dbuf[pr][lane + (v.jp < TJ - 1 ? TI : 0)] : (needN[q] ? hn : F(0));
+                const bool act = s < g.steps && v.active(g.steps - 1 - s, g.nk);
+                F t = yv - un * dN;
+                t = t - ue * dE;
+                t = t - ut * dT;
+                const F d = act ? t : F(0);
+                dT = d;
+                dbuf[s & 1][lane] = d;
+                plan(q, s + PD);
+                if (q == PD - 1 && aborted) s_buf[3] = 1;
                 wg_barrier();
             }
             if (s_buf[3]) break;
         }
     } else {
-        BwdLoad<F> pipe[LP];
+        const int lw = wave - 1;
+        BwdSrc<F> src;
+        src.y = gp((const F *)J.y);
 #pragma unroll
-        for (int q = 0; q < LP; q++) bwd_issue(pipe[q], J, v, q);
-        for (int u0 = 0; u0 < U; u0 += LP) {
+        for (int d = 0; d < 3; d++) src.U[d] = gp((const F *)J.LU) + (4 + d) * g.elems;
+        src.x = gp(J.x);
+        src.e0 = (uint32_t)v.base;
+        BwdLoad<F> c;
+        if (lw < g.steps) bwd_issue(c, src, g.steps, lw);
+        auto turn = [&](int u) {
+            const int f = u;
+            if (f < g.steps) {
+                const int slot = f & 1;
+                ring[slot][0][lane] = c.y;
+                ring[slot][1][lane] = c.u[0];
+                ring[slot][2][lane] = c.u[1];
+                ring[slot][3][lane] = c.u[2];
+                xring[f & 3][lane] = c.x;
+            }
+            const int p = u - 2;
+            if (p >= 0 && p < g.steps) {
+                const int sp = g.steps - 1 - p;
+                const F d = dbuf[p & 1][lane];
+                const double xv = xring[p & 3][lane];
+                stg(src.x, src.e0 + (uint32_t)sp * TT, xv + (double)d);   // padding: 0 + 0
+                uint32_t wd[NV];
+                to_words(d, wd);
+                if (v.ip == 0) {
 #pragma unroll
-            for (int w = 0; w < LP; w++) {
-                const int u = u0 + w;
-                const int p = u - 2;
-                if (p >= 0 && p < g.steps) {
-                    const int sp = g.steps - 1 - p;
-                    const F d = dbuf[p & 1][lane];
-                    const double xv = xring[p & 3][lane];
-                    if (v.active(sp, g.nk)) J.x[v.base + (long long)sp * TT] = xv + (double)d;
-                    uint32_t wd[NV];
-                    to_words(d, wd);
-                    if (v.ip == 0) {
-#pragma unroll
-                        for (int q = 0; q < NV; q++) ll_store(face_t + (long long)p * FW + v.jp * NV + q, tag, wd[q]);
-                    }
-                    if (v.jp == 0) {
-#pragma unroll
-                        for (int q = 0; q < NV; q++)
-                            ll_store(face_t + (long long)p * FW + (TJ + v.ip) * NV + q, tag, wd[q]);
-                    }
+                    for (int q = 0; q < NV; q++) ll_store(face_t + (long long)p * FW + v.jp * NV + q, tag, wd[q]);
                 }
-                const int f = u;
-                if (f < g.steps) {
-                    BwdLoad<F> &c = pipe[w];
-                    const int slot = f & 1;
-                    ring[slot][0][lane] = c.y;
-                    ring[slot][1][lane] = c.u[0];
-                    ring[slot][2][lane] = c.u[1];
-                    ring[slot][3][lane] = c.u[2];
-                    xring[f & 3][lane] = c.x;
-                    bwd_issue(c, J, v, f + LP);
+                if (v.jp == 0) {
+#pragma unroll
+                    for (int q = 0; q < NV; q++)
+                        ll_store(face_t + (long long)p * FW + (TJ + v.ip) * NV + q, tag, wd[q]);
                 }
+            }
+            if (u + NL < g.steps) bwd_issue(c, src, g.steps, u + NL);
+        };
+        if (lw == 0) turn(0);
+        wg_barrier();
+        for (int s0 = 0; s0 + 1 < U; s0 += PD) {
+            for (int q = 0; q < PD; q++) {
+                const int u = s0 + q + 1;
+                if (u % NL == lw) turn(u);
                 wg_barrier();
             }
             if (s_buf[3]) break;
@@ -655,7 +739,8 @@ __global__ __launch_bounds__(BLOCK) void k_factor(LaunchArgs a)
     const int U = padded_intervals(g.steps);
     const int FW = J.fw;
     const long long fstride = (long long)g.steps * FW;
-    uint64_t *face_t = J.face + (long long)v.t * fstride;
+    GLOBAL uint64_t *face_t = gp(J.face) + (long long)v.t * fstride;
+    GLOBAL Ctl *ctl = gp(J.ctl);
 
 #pragma unroll
     for (int d = 0; d < 3; d++) {
@@ -665,8 +750,8 @@ __global__ __launch_bounds__(BLOCK) void k_factor(LaunchArgs a)
     __syncthreads();
 
     if (wave == 0) {
-        const uint64_t *faceW = v.ti > 0 ? J.face + (long long)(v.t - 1) * fstride : nullptr;
-        const uint64_t *faceS = v.tj > 0 ? J.face + (long long)(v.t - g.nti) * fstride : nullptr;
+        const GLOBAL uint64_t *faceW = v.ti > 0 ? gp(J.face) + (long long)(v.t - 1) * fstride : face_t;
+        const GLOBAL uint64_t *faceS = v.tj > 0 ? gp(J.face) + (long long)(v.t - g.nti) * fstride : face_t;
         double unB = 0.0, ueB = 0.0, utB = 0.0;
         bool aborted = false, broke = false;
         for (int u0 = 0; u0 < U; u0 += LP) {
@@ -678,11 +763,11 @@ __global__ __launch_bounds__(BLOCK) void k_factor(LaunchArgs a)
                     const bool act = v.active(s, g.nk);
                     const bool nW = act && v.ip == 0 && v.ti > 0;
                     const bool nS = act && v.jp == 0 && v.tj > 0;
-                    const uint64_t *pW = nW ? faceW + (long long)(s + TI - 1) * FW + v.jp * NV : nullptr;
-                    const uint64_t *pS = nS ? faceS + (long long)(s + TJ - 1) * FW + (TJ + v.ip) * NV : nullptr;
+                    const GLOBAL uint64_t *pW = nW ? faceW + (long long)(s + TI - 1) * FW + v.jp * NV : face_t;
+                    const GLOBAL uint64_t *pS = nS ? faceS + (long long)(s + TJ - 1) * FW + (TJ + v.ip) * NV : face_t;
                     Halo<NV> h;
-                    halo_issue(h, nW, pW, nS, pS);
-                    if (!halo_wait(h, nW, pW, nS, pS, tag, J.ctl, a.timeout_ticks)) {
+                    halo_issue(h, pW, pS);
+                    if (!halo_wait(h, nW, pW, nS, pS, tag, ctl, a.timeout_ticks)) {
                         aborted = true;
                     }
                     double hw[3], hs[3];
@@ -690,6 +775,8 @@ __global__ __launch_bounds__(BLOCK) void k_factor(LaunchArgs a)
                     for (int d = 0; d < 3; d++) {
                         from_words(&h.a[2 * d], hw[d]);
                         from_words(&h.b[2 * d], hs[d]);
+                        if (!nW) hw[d] = 0.0;
+                        if (!nS) hs[d] = 0.0;
                     }
                     const int pr = (s - 1) & 1;
                     const int lw_ = lane - (v.ip > 0 ? 1 : 0);
@@ -739,18 +826,18 @@ __global__ __launch_bounds__(BLOCK) void k_factor(LaunchArgs a)
             if (s_buf[3]) break;
         }
         if (__any(broke) && lane == 0)
-            __hip_atomic_fetch_or(&J.ctl->err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_or(&ctl->err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
         double pipe[LP][7];
         auto issue = [&](double *c, int f) {
             const bool act = f < g.steps && v.active(f, g.nk);
             const long long e = v.base + (long long)f * TT;
 #pragma unroll
-            for (int d = 0; d < 7; d++) c[d] = act ? J.A[d * g.elems + e] : 0.0;
+            for (int d = 0; d < 7; d++) c[d] = act ? gp(J.A)[d * g.elems + e] : 0.0;
         };
 #pragma unroll
         for (int q = 0; q < LP; q++) issue(pipe[q], q);
-        F *LU = (F *)J.LU;
+        GLOBAL F *LU = gp((F *)J.LU);
         for (int u0 = 0; u0 < U; u0 += LP) {
 #pragma unroll
             for (int w = 0; w < LP; w++) {
@@ -950,22 +1037,43 @@ hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const LaunchArgs &a, int fp32, hipStream_t s)
+template <int NL, int PD>
+static hipError_t launch_sweep_nl(const LaunchArgs &a, int fp32, int backward, hipStream_t s)
 {
-    if (fp32)
-        hipLaunchKernelGGL(k_forward<float>, dim3(a.total), dim3(BLOCK), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_forward<double>, dim3(a.total), dim3(BLOCK), 0, s, a);
+    const dim3 block(WAVE * (1 + NL));
+    if (backward) {
+        if (fp32)
+            hipLaunchKernelGGL((k_backward<float, NL, PD>), dim3(a.total), block, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_backward<double, NL, PD>), dim3(a.total), block, 0, s, a);
+    } else {
+        if (fp32)
+            hipLaunchKernelGGL((k_forward<float, NL, PD>), dim3(a.total), block, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_forward<double, NL, PD>), dim3(a.total), block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const LaunchArgs &a, int fp32, hipStream_t s)
+static hipError_t launch_sweep(const LaunchArgs &a, int fp32, int backward, const SweepPlan &p, hipStream_t s)
 {
-    if (fp32)
-        hipLaunchKernelGGL(k_backward<float>, dim3(a.total), dim3(BLOCK), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_backward<double>, dim3(a.total), dim3(BLOCK), 0, s, a);
-    return hipGetLastError();
+    switch (p.loaders) {
+    case 2: return launch_sweep_nl<2, 4>(a, fp32, backward, s);
+    case 4: return launch_sweep_nl<4, 4>(a, fp32, backward, s);
+    case 6: return launch_sweep_nl<6, 4>(a, fp32, backward, s);
+    case 8: return launch_sweep_nl<8, 4>(a, fp32, backward, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_forward(const LaunchArgs &a, int fp32, const SweepPlan &p, hipStream_t s)
+{
+    return launch_sweep(a, fp32, 0, p, s);
+}
+
+hipError_t launch_backward(const LaunchArgs &a, int fp32, const SweepPlan &p, hipStream_t s)
+{
+    return launch_sweep(a, fp32, 1, p, s);
 }
 
 }  // namespace sipk

@@ -45,4 +45,5 @@ struct sip_system_s {
     double *h_hist = nullptr;       // pinned
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t chunk_exec = nullptr;
+    sipk::SweepPlan plan{};
 };

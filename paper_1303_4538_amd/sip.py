@@ -25,7 +25,7 @@ SIP_FP64, SIP_MIXED = 0, 1
 PRECISIONS = {"fp64": SIP_FP64, "mixed": SIP_MIXED, SIP_FP64: SIP_FP64, SIP_MIXED: SIP_MIXED}
 
 # every symbol include/sip.h declares
-EXPORTS = ("sip_factor", "sip_iterate", "sip_solve", "sip_export_factors", "sip_system_info",
+EXPORTS = ("sip_factor", "sip_iterate", "sip_solve", "sip_export_factors", "sip_profile_sweeps", "sip_system_info",
            "sip_system_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
            "sip_server_release", "sip_server_stats", "sip_server_destroy", "sip_status_str",
            "sip_last_error", "sip_abi_version")
@@ -78,6 +78,7 @@ def lib():
     L.sip_iterate.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
     L.sip_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(Info), vp]
     L.sip_export_factors.argtypes = [vp, ctypes.POINTER(vp), vp]
+    L.sip_profile_sweeps.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
     L.sip_system_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]
     L.sip_system_destroy.argtypes = [vp]
     L.sip_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
@@ -86,7 +87,7 @@ def lib():
     L.sip_server_release.argtypes = [vp, ctypes.c_uint64]
     L.sip_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
     L.sip_server_destroy.argtypes = [vp]
-    for f in ("sip_factor", "sip_iterate", "sip_solve", "sip_export_factors", "sip_system_info",
+    for f in ("sip_factor", "sip_iterate", "sip_solve", "sip_export_factors", "sip_profile_sweeps", "sip_system_info",
               "sip_system_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
               "sip_server_release", "sip_server_stats", "sip_server_destroy"):
         getattr(L, f).restype = ctypes.c_int32
@@ -199,6 +200,15 @@ def sip_export_factors(system, stream=None):
     ptrs = (ctypes.c_void_p * 7)(*[out[d].data_ptr() for d in range(7)])
     _check(lib().sip_export_factors(system._h, ptrs, _stream(stream)))
     return out
+
+
+def sip_profile_sweeps(system, b, x, n_iter, stream=None):
+    """Average device milliseconds of one forward and one backward sweep over
+    n_iter iterations (x updated in place).  Returns (fwd_ms, bwd_ms)."""
+    pb, px = _grid(b, system.shape, "b"), _grid(x, system.shape, "x")
+    ms = (ctypes.c_double * 2)()
+    _check(lib().sip_profile_sweeps(system._h, pb, px, int(n_iter), ms, _stream(stream)))
+    return ms[0], ms[1]
 
 
 # ----------------------------------------------------------------- server
