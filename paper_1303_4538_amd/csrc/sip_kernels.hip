@@ -517,11 +517,11 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
             } else if (nb2 == 0.0) {
                 st = ZERO_RHS;
                 c->rho = 0.0;
-                J.hist[iter] = 0.0;
+                if (J.hist) J.hist[iter] = 0.0;
             } else {
                 const double rho = sqrt(sr) / sqrt(nb2);
                 c->rho = rho;
-                J.hist[iter] = rho;
+                if (J.hist) J.hist[iter] = rho;
                 if (c->rtol > 0.0 && rho <= c->rtol) st = CONVERGED;
                 else if (iter >= c->max_iter) st = MAXITER;
             }

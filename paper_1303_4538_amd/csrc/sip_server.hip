@@ -1,10 +1,655 @@
-// placeholder, replaced by the server implementation
+// Batched and served SIP solves (sip_server_* / sip_batch_* in include/sip.h).
+//
+// The paper's redesigned solver owns its coefficients and reuses one
+// factorisation "for all iterations and time steps" (Sec. 4.1); a server
+// generalises that to many blocks and many right-hand sides on one GPU:
+//   - a request names a system by id; the first request of an id copies and
+//     factorises the coefficients, later requests reuse the resident factors;
+//   - admission is by an HBM budget (resident systems + per-request state);
+//     unreferenced systems are evicted least-recently-used when space is
+//     needed;
+//   - all admitted requests advance together: one epoch is `epoch_iters`
+//     iterations, each a batched forward launch and a batched backward launch
+//     whose workgroups take (request, tile) tickets from one merged order;
+//   - at every epoch boundary converged requests retire (x copied to the
+//     caller's array) and queued requests are admitted (continuous batching).
+// Every request's arithmetic depends only on its own data and tile order, so
+// a result is the same alone and in any mix.
+#include "sip_internal.h"
 #include "sip_runtime.h"
-extern "C" {
-sip_status sip_server_create(const sip_server_config *, sip_server *) { return sipk::set_error(SIP_EINVAL, "server not built"); }
-sip_status sip_batch_submit(sip_server, const sip_request *, uint64_t *) { return SIP_EINVAL; }
-sip_status sip_batch_poll(sip_server, uint64_t, int32_t, sip_result *) { return SIP_EINVAL; }
-sip_status sip_server_release(sip_server, uint64_t) { return SIP_EINVAL; }
-sip_status sip_server_stats(sip_server, uint64_t *) { return SIP_EINVAL; }
-sip_status sip_server_destroy(sip_server) { return SIP_EINVAL; }
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+using namespace sipk;
+
+namespace {
+
+constexpr int MAX_SLOTS = 4096;
+
+struct Resident {
+    uint64_t id = 0;
+    Geom g{};
+    int fp32 = 0;
+    double alpha = 0.92;
+    double *A = nullptr;
+    void *LU = nullptr;
+    size_t bytes = 0;
+    int refs = 0;
+    bool factored = false;
+    bool retain = false;
+    bool broken = false;
+    uint64_t last_use = 0;
+};
+
+struct Req {
+    uint64_t ticket = 0;
+    sip_request r{};
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int state = 0;   // 0 queued, 1 running, 2 done
+    sip_result res{};
+    // running state
+    Resident *sys = nullptr;
+    int slot = -1;
+    double *bx = nullptr;
+    void *y = nullptr;
+    uint64_t *face = nullptr;
+    double *part = nullptr;
+    double *hist = nullptr;
+    size_t bytes = 0;
+    bool fresh = true;       // b / x0 not staged yet
+    int factorised = 0;
+};
+
+size_t slot_bytes(const Geom &g, int fp32, int max_iter)
+{
+    const size_t E = (size_t)g.elems;
+    (void)max_iter;   // served requests keep no residual history
+    return E * (2 * 8 + (fp32 ? 4 : 8)) + (size_t)g.ntiles * g.steps * FACE_WORDS * 8 + (size_t)g.ntiles * 16;
 }
+
+size_t resident_bytes(const Geom &g, int fp32) { return (size_t)g.elems * (7 * 8 + 7 * (fp32 ? 4 : 8)); }
+
+}  // namespace
+
+struct sip_server_s {
+    sip_server_config cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t timeout_ticks = 0;
+    std::chrono::steady_clock::time_point t0;
+    std::thread thread;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool quit = false;
+    uint64_t next_ticket = 1;
+    std::deque<Req *> queue;
+    std::vector<Req *> running;
+    std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
+    std::unordered_map<uint64_t, std::unique_ptr<Resident>> systems;
+    size_t used = 0, peak = 0;
+    uint64_t clock = 0;
+    uint64_t stats[8] = {0};   // factorisations, evictions, epochs, resident, peak, completed, admitted, launches
+    // device-side scratch for launches
+    Ctl *ctl = nullptr;                      // MAX_SLOTS control blocks
+    Ctl *h_ctl = nullptr;                    // pinned mirror
+    std::vector<int> free_slots;
+    Job *d_jobs[2] = {nullptr, nullptr};     // per precision group
+    int2 *d_order[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int order_cap[2] = {0, 0};
+    int jobs_cap[2] = {0, 0};
+    LaunchCtl *lc = nullptr;
+    SweepPlan plan{};
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+    void loop();
+    bool admit_locked(std::vector<Req *> &admitted, std::vector<Resident *> &to_factor);
+    bool make_room_locked(size_t need);
+    void free_resident_locked(Resident *s);
+    void finish_locked(Req *q, sip_status st, int iters, double rho);
+    sip_status run_factor(const std::vector<Resident *> &sys, const std::vector<Req *> &owners);
+    sip_status run_epoch(std::vector<Req *> &act);
+    sip_status ensure_launch_buffers(int grp, int njobs, int ntiles);
+};
+
+namespace {
+
+sip_status dev_alloc(void **p, size_t n, hipStream_t s)
+{
+    hipError_t e = hipMallocAsync(p, n ? n : 1, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return set_error(SIP_ENOMEM, "device allocation of %zu bytes failed", n);
+    }
+    return SIP_OK;
+}
+
+void dev_free(void *p, hipStream_t s)
+{
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+}  // namespace
+
+void sip_server_s::free_resident_locked(Resident *s)
+{
+    dev_free(s->A, stream);
+    dev_free(s->LU, stream);
+    used -= s->bytes;
+    systems.erase(s->id);
+}
+
+bool sip_server_s::make_room_locked(size_t need)
+{
+    while (used + need > cfg.hbm_budget_bytes) {
+        Resident *victim = nullptr;
+        for (auto &kv : systems) {
+            Resident *s = kv.second.get();
+            if (s->refs == 0 && (!victim || s->last_use < victim->last_use)) victim = s;
+        }
+        if (!victim) return false;
+        free_resident_locked(victim);
+        stats[1]++;
+    }
+    return true;
+}
+
+bool sip_server_s::admit_locked(std::vector<Req *> &admitted, std::vector<Resident *> &to_factor)
+{
+    bool any = false;
+    for (auto it = queue.begin(); it != queue.end();) {
+        Req *q = *it;
+        if ((int)running.size() + (int)admitted.size() >= cfg.max_slots || free_slots.empty()) break;
+        const sip_problem &pb = q->r.problem;
+        Resident *s = nullptr;
+        auto f = systems.find(q->r.system_id);
+        if (f != systems.end()) s = f->second.get();
+        const Geom g = s ? s->g : make_geom(pb.ni, pb.nj, pb.nk);
+        const int fp32 = s ? s->fp32 : (pb.precision == SIP_MIXED);
+        const size_t need_slot = slot_bytes(g, fp32, q->r.max_iter);
+        const size_t need_sys = s ? 0 : resident_bytes(g, fp32);
+        if (s) s->refs++;   // pin while making room
+        const bool fits = make_room_locked(need_slot + need_sys);
+        if (s) s->refs--;
+        if (!fits) {
+            ++it;           // first fit: a smaller request behind may still fit
+            continue;
+        }
+        if (!s) {
+            bool ok = pb.ni == g.ni && pb.alpha >= 0.0 && pb.alpha <= 1.0;
+            for (int d = 0; d < 7; d++) ok = ok && pb.a[d] != nullptr;
+            if (!ok) {   // a request that must factorise needs its coefficients
+                finish_locked(q, SIP_EINVAL, 0, 0.0);
+                it = queue.erase(it);
+                continue;
+            }
+            auto rs = std::make_unique<Resident>();
+            rs->id = q->r.system_id;
+            rs->g = g;
+            rs->fp32 = fp32;
+            rs->alpha = pb.alpha;
+            rs->bytes = need_sys;
+            if (dev_alloc((void **)&rs->A, 7 * (size_t)g.elems * 8, stream) != SIP_OK ||
+                dev_alloc(&rs->LU, 7 * (size_t)g.elems * (fp32 ? 4 : 8), stream) != SIP_OK) {
+                dev_free(rs->A, stream);
+                dev_free(rs->LU, stream);
+                finish_locked(q, SIP_ENOMEM, 0, 0.0);
+                it = queue.erase(it);
+                continue;
+            }
+            used += need_sys;
+            s = rs.get();
+            systems[rs->id] = std::move(rs);
+            to_factor.push_back(s);
+            q->factorised = 1;
+        }
+        q->sys = s;
+        s->refs++;
+        s->retain = s->retain || q->r.retain;
+        s->last_use = ++clock;
+        q->bytes = need_slot;
+        const size_t E = (size_t)g.elems;
+        if (dev_alloc((void **)&q->bx, 2 * E * 8, stream) != SIP_OK ||
+            dev_alloc(&q->y, E * (fp32 ? 4 : 8), stream) != SIP_OK ||
+            dev_alloc((void **)&q->face, (size_t)g.ntiles * g.steps * FACE_WORDS * 8, stream) != SIP_OK ||
+            dev_alloc((void **)&q->part, (size_t)g.ntiles * 16, stream) != SIP_OK) {
+            dev_free(q->bx, stream);
+            dev_free(q->y, stream);
+            dev_free(q->face, stream);
+            dev_free(q->part, stream);
+            dev_free(q->hist, stream);
+            q->bx = nullptr;
+            q->y = nullptr;
+            q->face = nullptr;
+            q->part = nullptr;
+            q->hist = nullptr;
+            s->refs--;
+            finish_locked(q, SIP_ENOMEM, 0, 0.0);
+            it = queue.erase(it);
+            continue;
+        }
+        (void)hipMemsetAsync(q->face, 0, (size_t)g.ntiles * g.steps * FACE_WORDS * 8, stream);
+        used += need_slot;
+        peak = std::max(peak, used);
+        q->slot = free_slots.back();
+        free_slots.pop_back();
+        q->state = 1;
+        q->t_admit = now();
+        admitted.push_back(q);
+        stats[6]++;
+        it = queue.erase(it);
+        any = true;
+    }
+    return any;
+}
+
+void sip_server_s::finish_locked(Req *q, sip_status st, int iters, double rho)
+{
+    q->state = 2;
+    q->t_done = now();
+    q->res.status = st;
+    q->res.info.iters = iters;
+    q->res.info.rel_res = rho;
+    q->res.info.seconds = q->t_done - q->t_submit;
+    q->res.t_submit = q->t_submit;
+    q->res.t_admit = q->t_admit;
+    q->res.t_done = q->t_done;
+    q->res.factorised = q->factorised;
+    dev_free(q->bx, stream);
+    dev_free(q->y, stream);
+    dev_free(q->face, stream);
+    dev_free(q->part, stream);
+    dev_free(q->hist, stream);
+    q->bx = nullptr;
+    q->y = nullptr;
+    q->face = nullptr;
+    q->part = nullptr;
+    q->hist = nullptr;
+    if (q->slot >= 0) {
+        free_slots.push_back(q->slot);
+        q->slot = -1;
+        used -= q->bytes;
+    }
+    if (q->sys) {
+        Resident *s = q->sys;
+        q->sys = nullptr;
+        s->refs--;
+        s->last_use = ++clock;
+        if (s->refs == 0 && (!s->retain || s->broken)) free_resident_locked(s);
+    }
+    stats[5]++;
+    cv_done.notify_all();
+}
+
+sip_status sip_server_s::ensure_launch_buffers(int grp, int njobs, int ntiles)
+{
+    if (njobs > jobs_cap[grp]) {
+        dev_free(d_jobs[grp], stream);
+        const int cap = std::max(njobs, 64);
+        if (dev_alloc((void **)&d_jobs[grp], (size_t)cap * sizeof(Job), stream) != SIP_OK) return SIP_ENOMEM;
+        jobs_cap[grp] = cap;
+    }
+    if (ntiles > order_cap[grp]) {
+        dev_free(d_order[grp][0], stream);
+        dev_free(d_order[grp][1], stream);
+        const int cap = std::max(ntiles, 4096);
+        if (dev_alloc((void **)&d_order[grp][0], (size_t)cap * sizeof(int2), stream) != SIP_OK ||
+            dev_alloc((void **)&d_order[grp][1], (size_t)cap * sizeof(int2), stream) != SIP_OK)
+            return SIP_ENOMEM;
+        order_cap[grp] = cap;
+    }
+    return SIP_OK;
+}
+
+static Job job_of(const Resident *s, const Req *q, Ctl *ctl, int fw)
+{
+    Job J{};
+    J.g = s->g;
+    J.A = s->A;
+    J.LU = s->LU;
+    J.b = q->bx;
+    J.x = q->bx + s->g.elems;
+    J.y = q->y;
+    J.face = q->face;
+    J.part = q->part;
+    J.hist = q->hist;
+    J.ctl = ctl + q->slot;
+    J.alpha = s->alpha;
+    J.fw = fw;
+    return J;
+}
+
+// Factorise newly resident systems, all of them in one batched launch per
+// precision; each uses the face words of the request that brought it in.
+sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const std::vector<Req *> &owners)
+{
+    for (int grp = 0; grp < 2; grp++) {
+        std::vector<Job> jobs;
+        std::vector<Geom> gs;
+        for (size_t k = 0; k < sys.size(); k++) {
+            if (sys[k]->fp32 != grp) continue;
+            const sip_problem &pb = owners[k]->r.problem;
+            if (launch_to_sheared(sys[k]->g, 7, pb.a, sys[k]->A, sys[k]->g.elems, 1, stream) != hipSuccess)
+                return set_error(SIP_EDEVICE, "reorder failed");
+            // tags stay monotonic per slot (never reset): face words of the
+            // factorisation can never be mistaken for a later sweep's
+            if (launch_init_ctl(ctl + owners[k]->slot, 1, 0, 0.0, 0, stream) != hipSuccess)
+                return set_error(SIP_EDEVICE, "init failed");
+            jobs.push_back(job_of(sys[k], owners[k], ctl, FACE_WORDS));
+            gs.push_back(sys[k]->g);
+        }
+        if (jobs.empty()) continue;
+        const std::vector<int2> of = topo_order(gs, false);
+        if (ensure_launch_buffers(grp, (int)jobs.size(), (int)of.size()) != SIP_OK) return SIP_ENOMEM;
+        if (hipMemcpyAsync(d_jobs[grp], jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice, stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(d_order[grp][0], of.data(), of.size() * sizeof(int2), hipMemcpyHostToDevice, stream) !=
+                hipSuccess)
+            return set_error(SIP_EDEVICE, "upload failed");
+        const LaunchArgs la{d_jobs[grp], d_order[grp][0], lc, (int)of.size(), timeout_ticks};
+        if (launch_factor(la, grp, stream) != hipSuccess) return set_error(SIP_EDEVICE, "factor launch failed");
+        // the host copies of jobs/orders must live until the copies ran
+        if (hipStreamSynchronize(stream) != hipSuccess) return set_error(SIP_EDEVICE, "factorisation failed");
+        stats[7]++;
+    }
+    stats[0] += sys.size();
+    return SIP_OK;
+}
+
+// One epoch: epoch_iters (forward, backward) pairs over every running request.
+sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
+{
+    std::vector<Job> jobs[2];
+    std::vector<Geom> gs[2];
+    for (Req *q : act) {
+        const int grp = q->sys->fp32;
+        jobs[grp].push_back(job_of(q->sys, q, ctl, FACE_WORDS_SWEEP));
+        gs[grp].push_back(q->sys->g);
+    }
+    std::vector<int2> of[2], ob[2];
+    LaunchArgs fa[2], ba[2];
+    for (int grp = 0; grp < 2; grp++) {
+        if (jobs[grp].empty()) continue;
+        of[grp] = topo_order(gs[grp], false);
+        ob[grp] = topo_order(gs[grp], true);
+        if (ensure_launch_buffers(grp, (int)jobs[grp].size(), (int)of[grp].size()) != SIP_OK) return SIP_ENOMEM;
+        if (hipMemcpyAsync(d_jobs[grp], jobs[grp].data(), jobs[grp].size() * sizeof(Job), hipMemcpyHostToDevice,
+                           stream) != hipSuccess ||
+            hipMemcpyAsync(d_order[grp][0], of[grp].data(), of[grp].size() * sizeof(int2), hipMemcpyHostToDevice,
+                           stream) != hipSuccess ||
+            hipMemcpyAsync(d_order[grp][1], ob[grp].data(), ob[grp].size() * sizeof(int2), hipMemcpyHostToDevice,
+                           stream) != hipSuccess)
+            return set_error(SIP_EDEVICE, "upload failed");
+        fa[grp] = LaunchArgs{d_jobs[grp], d_order[grp][0], lc, (int)of[grp].size(), timeout_ticks};
+        ba[grp] = LaunchArgs{d_jobs[grp], d_order[grp][1], lc, (int)ob[grp].size(), timeout_ticks};
+    }
+    for (int it = 0; it < cfg.epoch_iters; it++) {
+        for (int grp = 0; grp < 2; grp++) {
+            if (jobs[grp].empty()) continue;
+            if (launch_forward(fa[grp], grp, plan, stream) != hipSuccess ||
+                launch_backward(ba[grp], grp, plan, stream) != hipSuccess)
+                return set_error(SIP_EDEVICE, "sweep launch failed");
+            stats[7] += 2;
+        }
+    }
+    if (hipMemcpyAsync(h_ctl, ctl, sizeof(Ctl) * MAX_SLOTS, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return set_error(SIP_EDEVICE, "epoch failed: %s", hipGetErrorString(hipGetLastError()));
+    stats[2]++;
+    return SIP_OK;
+}
+
+void sip_server_s::loop()
+{
+    (void)hipSetDevice(device);
+    for (;;) {
+        std::vector<Req *> admitted;
+        std::vector<Resident *> to_factor;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] { return quit || !queue.empty() || !running.empty(); });
+            if (quit) break;
+            admit_locked(admitted, to_factor);
+        }
+        // factorise new systems (owners = the admitted request that brought each in)
+        if (!to_factor.empty()) {
+            std::vector<Req *> owners;
+            for (Resident *s : to_factor)
+                for (Req *q : admitted)
+                    if (q->sys == s) {
+                        owners.push_back(q);
+                        break;
+                    }
+            const sip_status st = run_factor(to_factor, owners);
+            (void)hipMemcpyAsync(h_ctl, ctl, sizeof(Ctl) * MAX_SLOTS, hipMemcpyDeviceToHost, stream);
+            (void)hipStreamSynchronize(stream);
+            std::lock_guard<std::mutex> lk(mu);
+            for (size_t k = 0; k < to_factor.size(); k++) {
+                const uint32_t stop = st == SIP_OK ? h_ctl[owners[k]->slot].stop : TIMEOUT;
+                if (stop == RUN) {
+                    to_factor[k]->factored = true;
+                } else {
+                    to_factor[k]->broken = true;
+                }
+            }
+        }
+        // stage b and x0 of newly admitted requests; fail those whose system broke down
+        std::vector<Req *> ready;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (Req *q : admitted) {
+                if (q->sys->broken) {
+                    finish_locked(q, SIP_EBREAKDOWN, 0, 0.0);
+                    continue;
+                }
+                ready.push_back(q);
+            }
+        }
+        for (Req *q : ready) {
+            const Geom &g = q->sys->g;
+            const double *src[2] = {q->r.b, q->r.x0 ? q->r.x0 : nullptr};
+            if (q->r.x0) {
+                (void)launch_to_sheared(g, 2, src, q->bx, g.elems, 0, stream);
+            } else {
+                (void)launch_to_sheared(g, 1, src, q->bx, g.elems, 0, stream);
+                (void)hipMemsetAsync(q->bx + g.elems, 0, (size_t)g.elems * 8, stream);
+            }
+            (void)launch_init_ctl(ctl + q->slot, 1, (uint32_t)q->r.max_iter, q->r.rtol, 0, stream);
+        }
+        std::vector<Req *> act;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (Req *q : ready) running.push_back(q);
+            act = running;
+        }
+        if (act.empty()) continue;
+        const sip_status st = run_epoch(act);
+        // retire finished requests: copy x out, then report them done
+        std::vector<Req *> fin;
+        for (Req *q : act) {
+            const Ctl &c = h_ctl[q->slot];
+            if (st != SIP_OK || c.stop != RUN) {
+                if (st == SIP_OK)
+                    (void)launch_from_sheared_f64(q->sys->g, q->bx + q->sys->g.elems, q->r.x, ctl + q->slot, stream);
+                fin.push_back(q);
+            }
+        }
+        if (!fin.empty()) (void)hipStreamSynchronize(stream);
+        std::lock_guard<std::mutex> lk(mu);
+        for (Req *q : fin) {
+            const Ctl &c = h_ctl[q->slot];
+            sip_status rs = SIP_OK;
+            if (st != SIP_OK) rs = st;
+            else if (c.stop == MAXITER) rs = SIP_ENOTCONV;
+            else if (c.stop == BREAKDOWN) rs = SIP_EBREAKDOWN;
+            else if (c.stop == TIMEOUT) rs = SIP_EDEVICE;
+            finish_locked(q, rs, (int)c.iter, c.rho);
+            running.erase(std::find(running.begin(), running.end(), q));
+        }
+    }
+    // cancel everything still queued or running
+    std::lock_guard<std::mutex> lk(mu);
+    for (Req *q : queue) finish_locked(q, SIP_ECANCELLED, 0, 0.0);
+    queue.clear();
+    for (Req *q : running) finish_locked(q, SIP_ECANCELLED, 0, 0.0);
+    running.clear();
+}
+
+extern "C" {
+
+sip_status sip_server_create(const sip_server_config *c, sip_server *out)
+{
+    if (!c || !out) return set_error(SIP_EINVAL, "NULL argument");
+    if (c->max_slots < 1 || c->max_slots > MAX_SLOTS || c->epoch_iters < 1 || c->max_queue < 1)
+        return set_error(SIP_EINVAL, "bad server configuration");
+    auto *s = new sip_server_s();
+    s->cfg = *c;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return set_error(SIP_EDEVICE, "no HIP device");
+    }
+    if (s->cfg.hbm_budget_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)8 << 30;
+        s->cfg.hbm_budget_bytes = fr / 4 * 3;
+    }
+    if (const char *e = getenv("SIP_SWEEP_LOADERS")) {
+        const int nl = atoi(e);
+        if (nl == 2 || nl == 4 || nl == 6 || nl == 8) s->plan.loaders = nl;
+    }
+    s->timeout_ticks = timeout_ticks_for(s->device, 2.0);
+    s->t0 = std::chrono::steady_clock::now();
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc((void **)&s->ctl, sizeof(Ctl) * MAX_SLOTS) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_ctl, sizeof(Ctl) * MAX_SLOTS, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&s->lc, sizeof(LaunchCtl)) != hipSuccess ||
+        hipMemset(s->ctl, 0, sizeof(Ctl) * MAX_SLOTS) != hipSuccess || hipMemset(s->lc, 0, sizeof(LaunchCtl)) != hipSuccess ||
+        launch_init_ctl(s->ctl, MAX_SLOTS, 0, 0.0, 1, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        return set_error(SIP_ENOMEM, "server buffers");
+    }
+    for (int k = MAX_SLOTS - 1; k >= 0; k--) s->free_slots.push_back(k);
+    s->thread = std::thread([s] { s->loop(); });
+    *out = s;
+    return SIP_OK;
+}
+
+sip_status sip_batch_submit(sip_server s, const sip_request *r, uint64_t *ticket)
+{
+    if (!s || !r || !ticket) return set_error(SIP_EINVAL, "NULL argument");
+    if (!r->b || !r->x) return set_error(SIP_EINVAL, "b and x are required");
+    if (!(r->rtol > 0.0) || r->max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
+    const sip_problem &p = r->problem;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto f = s->systems.find(r->system_id);
+    const bool resident = f != s->systems.end();
+    bool queued_same = false;
+    for (Req *q : s->queue) queued_same = queued_same || q->r.system_id == r->system_id;
+    if (!resident && !queued_same) {
+        if (p.ni < 1 || p.nj < 1 || p.nk < 1) return set_error(SIP_EINVAL, "dims must be >= 1");
+        if (!(p.alpha >= 0.0 && p.alpha <= 1.0)) return set_error(SIP_EINVAL, "alpha must be in [0, 1]");
+        if (p.precision != SIP_FP64 && p.precision != SIP_MIXED) return set_error(SIP_EINVAL, "unknown precision");
+        for (int d = 0; d < 7; d++)
+            if (!p.a[d]) return set_error(SIP_EINVAL, "coefficient pointer %d is NULL", d);
+    }
+    const Geom g = resident ? f->second->g : make_geom(p.ni, p.nj, p.nk);
+    if (g.elems >= (1ll << 29)) return set_error(SIP_EINVAL, "block too large");
+    if (resident && (p.ni != g.ni || p.nj != g.nj || p.nk != g.nk))
+        return set_error(SIP_EINVAL, "dims differ from the resident system");
+    const int fp32 = resident ? f->second->fp32 : p.precision == SIP_MIXED;
+    const size_t need = slot_bytes(g, fp32, r->max_iter) + (resident ? 0 : resident_bytes(g, fp32));
+    if (need > s->cfg.hbm_budget_bytes) return set_error(SIP_ENOMEM, "request needs %zu bytes, budget %zu", need, s->cfg.hbm_budget_bytes);
+    if ((int)s->queue.size() >= s->cfg.max_queue) return set_error(SIP_EBUSY, "queue full");
+    auto q = std::make_unique<Req>();
+    q->ticket = s->next_ticket++;
+    q->r = *r;
+    q->t_submit = s->now();
+    *ticket = q->ticket;
+    s->queue.push_back(q.get());
+    s->reqs[q->ticket] = std::move(q);
+    s->cv_work.notify_one();
+    return SIP_OK;
+}
+
+sip_status sip_batch_poll(sip_server s, uint64_t ticket, int32_t wait_ms, sip_result *out)
+{
+    if (!s || !out) return set_error(SIP_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return set_error(SIP_EINVAL, "unknown ticket");
+    Req *q = it->second.get();
+    auto done = [&] { return q->state == 2; };
+    if (!done()) {
+        if (wait_ms < 0) s->cv_done.wait(lk, done);
+        else if (wait_ms > 0) s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), done);
+    }
+    if (!done()) return SIP_PENDING;
+    *out = q->res;
+    s->reqs.erase(it);
+    return SIP_OK;
+}
+
+sip_status sip_server_release(sip_server s, uint64_t system_id)
+{
+    if (!s) return set_error(SIP_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto f = s->systems.find(system_id);
+    if (f == s->systems.end()) return SIP_OK;
+    f->second->retain = false;
+    if (f->second->refs == 0) s->free_resident_locked(f->second.get());
+    return SIP_OK;
+}
+
+sip_status sip_server_stats(sip_server s, uint64_t out[8])
+{
+    if (!s || !out) return set_error(SIP_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stats[3] = s->used;
+    s->stats[4] = s->peak;
+    std::memcpy(out, s->stats, sizeof s->stats);
+    return SIP_OK;
+}
+
+sip_status sip_server_destroy(sip_server s)
+{
+    if (!s) return set_error(SIP_EINVAL, "NULL argument");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->quit = true;
+    }
+    s->cv_work.notify_all();
+    if (s->thread.joinable()) s->thread.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        std::vector<Resident *> all;
+        for (auto &kv : s->systems) all.push_back(kv.second.get());
+        for (Resident *r : all) s->free_resident_locked(r);
+    }
+    for (int grp = 0; grp < 2; grp++) {
+        dev_free(s->d_jobs[grp], s->stream);
+        dev_free(s->d_order[grp][0], s->stream);
+        dev_free(s->d_order[grp][1], s->stream);
+    }
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipFree(s->ctl);
+    (void)hipFree(s->lc);
+    (void)hipHostFree(s->h_ctl);
+    (void)hipStreamDestroy(s->stream);
+    delete s;
+    return SIP_OK;
+}
+
+}  // extern "C"
