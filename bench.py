@@ -41,7 +41,155 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--profile-iters", type=int, default=40)
     ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "large", "serving"],
+                    help="single: 256^3 block (default); batched: 64 uneven blocks through the solve "
+                         "server; large: 512x512x256 stretched Poisson; serving: Poisson-arrival "
+                         "request stream (8 right-hand sides per system)")
+    ap.add_argument("--serve-systems", type=int, default=40, help="systems in the serving stream (8 rhs each)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="server HBM budget")
+    ap.add_argument("--prof", action="store_true",
+                    help="short run for rocprofv3: factor + a few sweeps of the default workload and "
+                         "a 512 MiB device copy used to calibrate the HBM byte counters")
     return ap.parse_args()
+
+
+def prof_run(args):
+    """Minimal GPU work for counter collection (one process, no CPU oracle)."""
+    import torch
+
+    from paper_1303_4538_amd import problems, sip
+
+    sip.lib()
+    c = problems.config2(args.n)
+    A = torch.from_numpy(c["A"]).cuda()
+    b = torch.from_numpy(c["b"]).cuda()
+    src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")       # 512 MiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)                                                         # calibration copy
+    torch.cuda.synchronize()
+    S = sip.sip_factor(A, c["alpha"], "mixed")
+    x = torch.zeros_like(b)
+    fwd_ms, bwd_ms = sip.sip_profile_sweeps(S, b, x, 5)
+    S.close()
+    torch.cuda.synchronize()
+    print(f"prof: forward {fwd_ms:.4f} ms, backward {bwd_ms:.4f} ms per sweep", flush=True)
+
+
+def batched_run(args):
+    """64 independent blocks (dims uniform 32..160 per axis, half Poisson, half
+    convection-diffusion) submitted at once to the solve server, mixed
+    precision to 1e-8; value = total cell-iterations / wall time."""
+    import torch
+
+    from paper_1303_4538_amd import problems, sip
+
+    sip.lib()
+    meta = problems.config3_meta()
+    blocks = []
+    for dims, kind, ss in meta:
+        A, b = problems.make_block(dims, kind, ss)
+        blocks.append((dims, torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda()))
+    torch.cuda.synchronize()
+
+    def step(tag):
+        srv = sip.Server(max_slots=256, epoch_iters=8)
+        xs = [torch.zeros_like(b) for _, _, b in blocks]
+        t0 = time.perf_counter()
+        tickets = [srv.submit(tag * 1000 + q, A, b, xs[q], precision="mixed", rtol=RTOL, max_iter=200000)
+                   for q, (_, A, b) in enumerate(blocks)]
+        res = [srv.poll(t) for t in tickets]
+        t1 = time.perf_counter()
+        st = srv.stats()
+        srv.close()
+        ci = sum(dims[0] * dims[1] * dims[2] * r["iters"] for (dims, _, _), r in zip(blocks, res))
+        return t1 - t0, ci, res, st
+
+    for w in range(args.warmup):
+        step(w + 1)
+    tot_t, tot_ci, last = 0.0, 0, None
+    for k in range(args.steps):
+        dt, ci, res, st = step(100 + k)
+        tot_t += dt
+        tot_ci += ci
+        last = (res, st)
+    res, st = last
+    cells = sum(d[0] * d[1] * d[2] for d, _, _ in blocks)
+    value = tot_ci / tot_t
+    line = {
+        "metric": "cell-iterations/s (batched mixed SIP to 1e-8 rel. residual)",
+        "value": value, "unit": "cell-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": tot_t / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "64 blocks, dims uniform 32..160 per axis, half Poisson / half upwind "
+                               "convection-diffusion, one solve server, factor + mixed solve to 1e-8",
+                   "cells": cells, "max_iters": max(r["iters"] for r in res),
+                   "all_ok": all(r["status"] == 0 for r in res), "epochs": st["epochs"],
+                   "launches": st["launches"],
+                   "hbm_gbps_algorithmic": value * (FWD_BYTES["mixed"] + BWD_BYTES["mixed"]) / 1e9},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def serving_run(args):
+    """Poisson-arrival stream of solves against one continuous-batching server:
+    each system (lognormal dims 24..192 per axis, half Poisson / half
+    convection-diffusion) receives 8 right-hand sides; requests are shuffled
+    and submitted at their arrival times; factors stay resident across a
+    system's requests.  Reports latency percentiles beside throughput."""
+    import numpy as np
+    import torch
+
+    from paper_1303_4538_amd import problems, sip
+
+    sip.lib()
+    systems, reqs = problems.serving_stream(n_systems=args.serve_systems, rhs_per_system=8,
+                                            rate_hz=args.serve_rate)
+    As = []
+    for dims, kind, ss in systems:
+        As.append(torch.from_numpy(problems.system_coefficients(dims, kind, ss)).cuda())
+    bs = [torch.from_numpy(problems.request_rhs(systems[s][0], rs)).cuda() for _, s, _, rs in reqs]
+    xs = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    srv = sip.Server(hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_slots=512, epoch_iters=8)
+    t0 = time.perf_counter()
+    tickets = []
+    for q, (ta, s, m, _) in enumerate(reqs):
+        wait = t0 + ta - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(srv.submit(s, As[s], bs[q], xs[q], precision="mixed", rtol=RTOL, max_iter=200000,
+                                  retain=True))
+    res = [srv.poll(t) for t in tickets]
+    t1 = time.perf_counter()
+    st = srv.stats()
+    srv.close()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    run = np.array([r["t_done"] - r["t_admit"] for r in res])
+    cells = np.array([np.prod(systems[s][0]) for _, s, _, _ in reqs])
+    iters = np.array([r["iters"] for r in res])
+    ci = float((cells * iters).sum())
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    line = {
+        "metric": "served solves: cell-iterations/s and latency (mixed SIP to 1e-8)",
+        "value": ci / span, "unit": "cell-iterations/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": (t1 - t0) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} requests ({args.serve_systems} systems x 8 rhs), Poisson arrivals "
+                               f"{args.serve_rate:g}/s, lognormal dims 24..192, half Poisson / half CD, "
+                               f"HBM budget {args.serve_budget_gb:g} GB",
+                   "solves_per_s": len(res) / span,
+                   "offered_per_s": args.serve_rate,
+                   "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+                   "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
+                   "run_p50_ms": float(np.percentile(run, 50) * 1e3),
+                   "run_p99_ms": float(np.percentile(run, 99) * 1e3),
+                   "all_ok": all(r["status"] == 0 for r in res),
+                   "factorisations": st["factorisations"], "evictions": st["evictions"],
+                   "epochs": st["epochs"], "peak_bytes": st["peak_bytes"],
+                   "mean_cells": float(cells.mean()), "mean_iters": float(iters.mean())},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -50,6 +198,15 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is "
               "described in DESIGN.md, not implemented)", file=sys.stderr)
         sys.exit(2)
+    if args.prof:
+        prof_run(args)
+        return
+    if args.workload == "batched":
+        batched_run(args)
+        return
+    if args.workload == "serving":
+        serving_run(args)
+        return
     import numpy as np
     import torch
 
@@ -58,8 +215,14 @@ def main():
     sip.lib()                       # raises if the HIP library is not built
     dev = torch.device("cuda:0")
     n = args.n
-    cells = n ** 3
-    c = problems.config2(n)
+    if args.workload == "large":
+        c = problems.config4()
+        cells = 512 * 512 * 256
+        label = "512x512x256 stretched-grid Poisson (z ratio 1.05)"
+    else:
+        c = problems.config2(n)
+        cells = n ** 3
+        label = f"{n}^3 upwind convection-diffusion (D=1, max|F|=2)"
     A = torch.from_numpy(c["A"]).to(dev)
     b = torch.from_numpy(c["b"]).to(dev)
     torch.cuda.synchronize()
@@ -118,7 +281,7 @@ def main():
         t5 = time.perf_counter()
         cpu = {"value": cells * args.cpu_iters / (t5 - t4), "unit": "cell-iterations/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"{n}^3 convection-diffusion block, first {args.cpu_iters} mixed-form SIP iterations "
+               "sample": f"{label}, first {args.cpu_iters} mixed-form SIP iterations "
                          f"(FP64 residual, FP32 sweeps), single-threaded C oracle, factorisation untimed"}
 
     mean_it = sum(iters) / len(iters)
@@ -136,8 +299,7 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{n}^3 upwind convection-diffusion (D=1, max|F|=2), alpha 0.92, factor + mixed "
-                        f"solve to {RTOL:g}",
+            "workload": f"{label}, alpha 0.92, factor + mixed solve to {RTOL:g}",
             "cells": cells,
             "iterations": mean_it,
             "final_rel_res": max(rr for _, rr in results),
