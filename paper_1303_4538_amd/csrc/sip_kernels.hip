@@ -274,7 +274,9 @@ template <typename F>
 struct FwdLoad {
     double a[7];
     double b;
-    double x[7];   // P, W, E, S, N, B, T
+    double xt;     // x on plane f + 1 (this lane's T neighbour), staged into the LDS plane ring
+    double hx;     // x across the W or E tile edge (edge lanes only)
+    double hy;     // x across the S or N tile edge (edge lanes only)
     F l[4];        // Lb, Lw, Ls, 1/Lp
 };
 
@@ -299,7 +301,7 @@ struct FwdSrc {
     const GLOBAL double *b, *x;
     const GLOBAL F *L[4];
     uint32_t e0;          // sheared index of (plane 0, this lane)
-    int32_t hw, he, hs, hn;   // index deltas of the W/E/S/N neighbours (0 where none)
+    int32_t hx, hy;       // index deltas of the x halo this lane reads across a tile edge (0: none)
 };
 
 template <typename F>
@@ -315,12 +317,15 @@ __device__ __forceinline__ FwdSrc<F> fwd_src(const Job &J, const TileView &v)
     for (int d = 0; d < 4; d++) q.L[d] = gp((const F *)J.LU) + d * g.elems;
     q.e0 = (uint32_t)v.base;
     const int te = (int)g.tile_elems;
-    // in-tile neighbours sit on planes -/+1; across a tile edge they are the
-    // neighbour tile's edge column/row on that tile's own local plane
-    q.hw = v.ip > 0 ? -TT - 1 : (v.ti > 0 ? -te + (TI - 1) * TT + (TI - 1) : 0);
-    q.he = v.ip < TI - 1 ? TT + 1 : (v.ti < g.nti - 1 ? te - (TI - 1) * TT - (TI - 1) : 0);
-    q.hs = v.jp > 0 ? -TT - TI : (v.tj > 0 ? -g.nti * te + (TJ - 1) * TT + (TJ - 1) * TI : 0);
-    q.hn = v.jp < TJ - 1 ? TT + TI : (v.tj < g.ntj - 1 ? g.nti * te - (TJ - 1) * TT - (TJ - 1) * TI : 0);
+    // Across a tile edge the neighbour is the neighbour tile's edge column/row
+    // on that tile's own local plane: W at plane f+TI-1, E at f-TI+1, S at
+    // f+TJ-1, N at f-TJ+1.  A lane sits on at most one of the W/E edges and
+    // one of the S/N edges, so two loads cover every halo; in-tile
+    // neighbours come from the LDS plane ring.
+    q.hx = (v.ip == 0 && v.ti > 0) ? -te + (TI - 1) * TT + (TI - 1)
+         : (v.ip == TI - 1 && v.ti < g.nti - 1) ? te - (TI - 1) * TT - (TI - 1) : 0;
+    q.hy = (v.jp == 0 && v.tj > 0) ? -g.nti * te + (TJ - 1) * TT + (TJ - 1) * TI
+         : (v.jp == TJ - 1 && v.tj < g.ntj - 1) ? g.nti * te - (TJ - 1) * TT - (TJ - 1) * TI : 0;
     return q;
 }
 
@@ -336,13 +341,9 @@ __device__ __forceinline__ void fwd_issue(FwdLoad<F> &c, const FwdSrc<F> &q, con
     c.b = ldg(q.b, e);
 #pragma unroll
     for (int d = 0; d < 4; d++) c.l[d] = ldg(q.L[d], e);
-    c.x[0] = ldg(q.x, e);
-    c.x[5] = ldg(q.x, e - TT);
-    c.x[6] = ldg(q.x, e + TT);
-    c.x[1] = ldg(q.x, e + (act ? q.hw : 0));
-    c.x[2] = ldg(q.x, e + (act ? q.he : 0));
-    c.x[3] = ldg(q.x, e + (act ? q.hs : 0));
-    c.x[4] = ldg(q.x, e + (act ? q.hn : 0));
+    c.xt = ldg(q.x, e + TT);
+    c.hx = ldg(q.x, e + (act ? q.hx : 0));
+    c.hy = ldg(q.x, e + (act ? q.hy : 0));
 }
 
 template <typename F, int NL, int PD>
@@ -351,6 +352,7 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
     constexpr int NV = NW<F>::n;
     __shared__ F ring[2][5][TT];     // r, Lb, Lw, Ls, 1/Lp of two steps
     __shared__ F ybuf[2][TT];
+    __shared__ double xring[4][TT];  // x on planes f-1, f, f+1 (slot = plane & 3)
     __shared__ int s_buf[4];
     __shared__ double s_part[NL][2];
 
@@ -434,14 +436,26 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
         const int lw = wave - 1;
         const FwdSrc<F> src = fwd_src<F>(J, v);
         FwdLoad<F> c;
+        if (lw == 0) {   // planes -1 (zero margin) and 0 of the x ring
+            xring[3][lane] = 0.0;
+            xring[0][lane] = ldg(src.x, src.e0);
+        }
         if (lw < g.steps) fwd_issue(c, src, v, lw, g.nk);
         GLOBAL F *yout = gp((F *)J.y);
         double rr = 0.0, bb = 0.0;
         auto turn = [&](int u) {
             const int f = u;
             if (f < g.steps) {
-                const double ax = c.a[0] * c.x[0] + c.a[1] * c.x[1] + c.a[2] * c.x[2] + c.a[3] * c.x[3] +
-                                  c.a[4] * c.x[4] + c.a[5] * c.x[5] + c.a[6] * c.x[6];
+                // planes f-1 and f were staged by the two previous turns
+                xring[(f + 1) & 3][lane] = c.xt;
+                const double xP = xring[f & 3][lane];
+                const double xB = xring[(f - 1) & 3][lane];
+                const double xW = v.ip > 0 ? xring[(f - 1) & 3][lane - (v.ip > 0 ? 1 : 0)] : c.hx;
+                const double xE = v.ip < TI - 1 ? xring[(f + 1) & 3][lane + (v.ip < TI - 1 ? 1 : 0)] : c.hx;
+                const double xS = v.jp > 0 ? xring[(f - 1) & 3][lane - (v.jp > 0 ? TI : 0)] : c.hy;
+                const double xN = v.jp < TJ - 1 ? xring[(f + 1) & 3][lane + (v.jp < TJ - 1 ? TI : 0)] : c.hy;
+                const double ax = c.a[0] * xP + c.a[1] * xW + c.a[2] * xE + c.a[3] * xS + c.a[4] * xN +
+                                  c.a[5] * xB + c.a[6] * c.xt;
                 const double r = c.b - ax;
                 rr += r * r;
                 bb += c.b * c.b;
