@@ -105,6 +105,11 @@ __device__ __forceinline__ void from_words(const uint64_t *w, double &v)
     v = __longlong_as_double((long long)(((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0]));
 }
 
+// Materialises a value in every lane: keeps the compiler from sinking an LDS
+// read into a divergent branch (exec-masked branches cost more than the read).
+__device__ __forceinline__ void keep(float &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void keep(double &x) { asm volatile("" : "+v"(x)); }
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     // fixed butterfly order: the result does not depend on timing
@@ -382,17 +387,23 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
 
     if (wave == 0) {
         // ---------------- recurrence wave
-        const GLOBAL uint64_t *faceW = v.ti > 0 ? gp(J.face) + (long long)(v.t - 1) * fstride : face_t;
-        const GLOBAL uint64_t *faceS = v.tj > 0 ? gp(J.face) + (long long)(v.t - g.nti) * fstride : face_t;
+        // Poll addresses are word indices from one uniform base, chosen with
+        // selects: lanes without a halo read their own tile's first word.
+        // Everything in the step stays free of divergent branches.
+        const GLOBAL uint64_t *fbase = gp(J.face);
+        const uint32_t own = (uint32_t)v.t * (uint32_t)fstride;
+        const uint32_t baseW = (uint32_t)(v.t - 1) * (uint32_t)fstride + (uint32_t)((TI - 1) * FW + v.jp * NV);
+        const uint32_t baseS = (uint32_t)(v.t - g.nti) * (uint32_t)fstride + (uint32_t)((TJ - 1) * FW + (TJ + v.ip) * NV);
+        const bool edgeW = v.ip == 0 && v.ti > 0, edgeS = v.jp == 0 && v.tj > 0;
         Halo<NV> pv[PD];
         bool needW[PD], needS[PD];
         const GLOBAL uint64_t *pW[PD], *pS[PD];
         auto plan = [&](int q, int s2) {
             const bool act = v.active(s2, g.nk);
-            needW[q] = act && v.ip == 0 && v.ti > 0;
-            needS[q] = act && v.jp == 0 && v.tj > 0;
-            pW[q] = needW[q] ? faceW + (long long)(s2 + TI - 1) * FW + v.jp * NV : face_t;
-            pS[q] = needS[q] ? faceS + (long long)(s2 + TJ - 1) * FW + (TJ + v.ip) * NV : face_t;
+            needW[q] = act && edgeW;
+            needS[q] = act && edgeS;
+            pW[q] = fbase + (needW[q] ? baseW + (uint32_t)s2 * FW : own);
+            pS[q] = fbase + (needS[q] ? baseS + (uint32_t)s2 * FW : own);
             halo_issue(pv[q], pW[q], pS[q]);
         };
 #pragma unroll
@@ -416,8 +427,12 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
                 from_words(pv[q].a, hw);
                 from_words(pv[q].b, hs);
                 const int pr = (s - 1) & 1;
-                const F yW = v.ip > 0 ? ybuf[pr][lane - (v.ip > 0 ? 1 : 0)] : (needW[q] ? hw : F(0));
-                const F yS = v.jp > 0 ? ybuf[pr][lane - (v.jp > 0 ? TI : 0)] : (needS[q] ? hs : F(0));
+                F nW = ybuf[pr][lane - (v.ip > 0 ? 1 : 0)];
+                F nS = ybuf[pr][lane - (v.jp > 0 ? TI : 0)];
+                keep(nW);
+                keep(nS);
+                const F yW = v.ip > 0 ? nW : (needW[q] ? hw : F(0));
+                const F yS = v.jp > 0 ? nS : (needS[q] ? hs : F(0));
                 const bool act = v.active(s, g.nk);
                 F t = r - lb * yB;
                 t = t - lw * yW;
@@ -607,17 +622,20 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
     __syncthreads();
 
     if (wave == 0) {
-        const GLOBAL uint64_t *faceE = v.ti < g.nti - 1 ? gp(J.face) + (long long)(v.t + 1) * fstride : face_t;
-        const GLOBAL uint64_t *faceN = v.tj < g.ntj - 1 ? gp(J.face) + (long long)(v.t + g.nti) * fstride : face_t;
+        const GLOBAL uint64_t *fbase = gp(J.face);
+        const uint32_t own = (uint32_t)v.t * (uint32_t)fstride;
+        const uint32_t baseE = (uint32_t)(v.t + 1) * (uint32_t)fstride + (uint32_t)((TI - 1) * FW + v.jp * NV);
+        const uint32_t baseN = (uint32_t)(v.t + g.nti) * (uint32_t)fstride + (uint32_t)((TJ - 1) * FW + (TJ + v.ip) * NV);
+        const bool edgeE = v.ip == TI - 1 && v.ti < g.nti - 1, edgeN = v.jp == TJ - 1 && v.tj < g.ntj - 1;
         Halo<NV> pv[PD];
         bool needE[PD], needN[PD];
         const GLOBAL uint64_t *pE[PD], *pN[PD];
         auto plan = [&](int q, int s2) {   // s2: backward step
             const bool act = s2 < g.steps && v.active(g.steps - 1 - s2, g.nk);
-            needE[q] = act && v.ip == TI - 1 && v.ti < g.nti - 1;
-            needN[q] = act && v.jp == TJ - 1 && v.tj < g.ntj - 1;
-            pE[q] = needE[q] ? faceE + (long long)(s2 + TI - 1) * FW + v.jp * NV : face_t;
-            pN[q] = needN[q] ? faceN + (long long)(s2 + TJ - 1) * FW + (TJ + v.ip) * NV : face_t;
+            needE[q] = act && edgeE;
+            needN[q] = act && edgeN;
+            pE[q] = fbase + (needE[q] ? baseE + (uint32_t)s2 * FW : own);
+            pN[q] = fbase + (needN[q] ? baseN + (uint32_t)s2 * FW : own);
             halo_issue(pv[q], pE[q], pN[q]);
         };
 #pragma unroll
@@ -640,8 +658,12 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
                 from_words(pv[q].a, he);
                 from_words(pv[q].b, hn);
                 const int pr = (s - 1) & 1;
-                const F dE = v.ip < TI - 1 ? dbuf[pr][lane + (v.ip < TI - 1 ? 1 : 0)] : (needE[q] ? he : F(0));
-                const F dN = v.jp < TJ - 1 ? dbuf[pr][lane + (v.jp < TJ - 1 ? TI : 0)] : (needN[q] ? hn : F(0));
+                F nE = dbuf[pr][lane + (v.ip < TI - 1 ? 1 : 0)];
+                F nN = dbuf[pr][lane + (v.jp < TJ - 1 ? TI : 0)];
+                keep(nE);
+                keep(nN);
+                const F dE = v.ip < TI - 1 ? nE : (needE[q] ? he : F(0));
+                const F dN = v.jp < TJ - 1 ? nN : (needN[q] ? hn : F(0));
                 const bool act = s < g.steps && v.active(g.steps - 1 - s, g.nk);
                 F t = yv - un * dN;
                 t = t - ue * dE;
