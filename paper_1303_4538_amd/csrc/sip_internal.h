@@ -88,6 +88,11 @@ struct LaunchArgs {
 constexpr int FACE_WORDS = (TI + TJ) * 6;
 // The sweeps exchange one value per face entry: at most 2 words (FP64).
 constexpr int FACE_WORDS_SWEEP = (TI + TJ) * 2;
+// Behind the sweeps' ntiles * steps * FACE_WORDS_SWEEP words (inside the
+// buffer sized for the factorisation) each tile owns SINK_WORDS words that
+// absorb the face-record stores of steps past its last one.
+constexpr int SINK_WORDS = 32;
+static_assert(SINK_WORDS <= FACE_WORDS - FACE_WORDS_SWEEP, "sink lines must fit behind the sweep face words");
 
 Geom make_geom(int ni, int nj, int nk);
 

@@ -63,6 +63,21 @@ __device__ __forceinline__ GLOBAL T *gp(T *p)
     return (GLOBAL T *)p;
 }
 
+// The job descriptors do not change while a kernel runs.  Reading them
+// through the constant address space with a uniform index gives scalar loads,
+// so the descriptor's pointers and sizes live in scalar registers; a plain
+// load (the kernel has already written memory through its ticket counter)
+// would put every uniform pointer in vector registers.
+#define CONSTANT __attribute__((address_space(4)))
+__device__ __forceinline__ Job load_job(const LaunchArgs &a, int job)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const CONSTANT Job *)a.jobs)[job];
+#else
+    return a.jobs[job];   // host pass of a device function: never executed
+#endif
+}
+
 constexpr int WAVE = 64;
 constexpr int BLOCK = 2 * WAVE;
 constexpr int LP = 4;   // loader register-pipeline depth (steps of look-ahead)
@@ -258,16 +273,59 @@ __device__ __forceinline__ int padded_intervals(int steps)
 // Workgroup = one recurrence wave (wave 0) + NL loader waves.  Loader wave l
 // owns the steps f with f % NL == l: at its turn (interval f) it consumes the
 // loads it issued NL intervals earlier, stages the operands of step f in the
-// LDS ring, writes back the recurrence result of step f - 2, and issues the
-// loads of step f + NL.  Its own vector-memory wait at a turn therefore only
-// covers loads that had NL intervals to arrive.  Interval u: loaders fill step
-// u, the recurrence wave processes step u - 1, results of step u - 2 are
-// written back; one workgroup barrier ends every interval.
+// LDS ring and issues the loads of step f + NL.  Its own vector-memory wait at
+// a turn therefore only covers loads that had NL intervals to arrive.
+// Interval u: loaders fill step u, the recurrence wave processes step u - 1
+// and publishes its face words (and, forward, y) at once, so the neighbour
+// tiles see them without waiting for a loader turn; one workgroup barrier
+// ends every interval.  Backward, the owning loader applies x += d of step
+// u - 2.
+
+// Face records.  At every step a tile publishes the 16 face entries its
+// downstream neighbours read (entry e < TJ: row e of the column facing the i
+// neighbour; entry TJ + c: column c of the row facing the j neighbour), NV
+// words each.  The recurrence wave writes the whole record with one store in
+// which every lane writes a word (the 64 lanes cover the 16 NV words 64 / (16
+// NV) times over, with identical data), taking the value from the LDS copy
+// of the step it has just written.  With no store behind a branch the
+// compiler's vector-memory counts stay exact, and the wait for a prefetched
+// poll never waits for a later store.  Steps past the last one write the
+// tile's sink words.
+struct Post {
+    uint32_t rec;    // word index of this lane's word in the tile's record at step 0
+    uint32_t sink;   // word index of this lane's word in the tile's sink
+    int src;         // lane whose value this lane's word carries
+    int half;        // which 32-bit half of that value (FP64)
+};
+
+template <int NV>
+__device__ __forceinline__ Post make_post(const Geom &g, const TileView &v, long long fstride, int lane, int col_i, int row_j)
+{
+    Post p;
+    const int word = lane & (16 * NV - 1);
+    const int e = word / NV;
+    p.half = word % NV;
+    p.src = e < TJ ? e * TI + col_i : row_j * TI + (e - TJ);
+    p.rec = (uint32_t)v.t * (uint32_t)fstride + (uint32_t)word;
+    p.sink = (uint32_t)g.ntiles * (uint32_t)fstride + (uint32_t)v.t * SINK_WORDS + (uint32_t)word;
+    return p;
+}
+
+template <int NV, typename F>
+__device__ __forceinline__ void post_record(GLOBAL uint64_t *fbase, const Post &p, int s, int steps, int fw, uint32_t tag, F val)
+{
+    uint32_t wd[NV];
+    to_words(val, wd);
+    uint32_t w = wd[0];
+#pragma unroll
+    for (int q = 1; q < NV; q++) w = p.half == q ? wd[q] : w;
+    ll_store(fbase + (s < steps ? p.rec + (uint32_t)s * (uint32_t)fw : p.sink), tag, w);
+}
 
 __device__ __forceinline__ int sweep_intervals(int steps, int pd)
 {
     // interval 0 (fill only) plus the recurrence steps 0..steps (step `steps`
-    // only lets the last write-back happen), padded to the poll unroll
+    // only lets the last backward x update happen), padded to the poll unroll
     return 1 + (steps + 1 + pd - 1) / pd * pd;
 }
 
@@ -365,7 +423,7 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     if (threadIdx.x == 0) s_buf[3] = 0;
     const Assign as = take_ticket(a, s_buf);
-    const Job J = a.jobs[as.job];
+    const Job J = load_job(a, as.job);
     const uint32_t stop = J.ctl->stop;
     if (stop != RUN) {
         launch_done(a);
@@ -378,7 +436,6 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
     const int U = sweep_intervals(g.steps, PD);
     const int FW = J.fw;
     const long long fstride = (long long)g.steps * FW;
-    GLOBAL uint64_t *face_t = gp(J.face) + (long long)v.t * fstride;
     GLOBAL Ctl *ctl = gp(J.ctl);
 
     ybuf[0][lane] = F(0);
@@ -390,11 +447,14 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
         // Poll addresses are word indices from one uniform base, chosen with
         // selects: lanes without a halo read their own tile's first word.
         // Everything in the step stays free of divergent branches.
-        const GLOBAL uint64_t *fbase = gp(J.face);
+        GLOBAL uint64_t *fbase = gp(J.face);
         const uint32_t own = (uint32_t)v.t * (uint32_t)fstride;
         const uint32_t baseW = (uint32_t)(v.t - 1) * (uint32_t)fstride + (uint32_t)((TI - 1) * FW + v.jp * NV);
         const uint32_t baseS = (uint32_t)(v.t - g.nti) * (uint32_t)fstride + (uint32_t)((TJ - 1) * FW + (TJ + v.ip) * NV);
         const bool edgeW = v.ip == 0 && v.ti > 0, edgeS = v.jp == 0 && v.tj > 0;
+        GLOBAL F *yout = gp((F *)J.y);
+        const uint32_t e0 = (uint32_t)v.base;
+        const Post post = make_post<NV>(g, v, fstride, lane, TI - 1, TJ - 1);   // E column, N row
         Halo<NV> pv[PD];
         bool needW[PD], needS[PD];
         const GLOBAL uint64_t *pW[PD], *pS[PD];
@@ -406,8 +466,15 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
             pS[q] = fbase + (needS[q] ? baseS + (uint32_t)s2 * FW : own);
             halo_issue(pv[q], pW[q], pS[q]);
         };
+        // The prologue repeats a step's store pattern (zero margin, sink) ahead
+        // of each poll, so the loop is entered with the same counts as it
+        // loops back with.
 #pragma unroll
-        for (int q = 0; q < PD; q++) plan(q, q);
+        for (int q = 0; q < PD; q++) {
+            stg(yout, e0 + (uint32_t)g.steps * TT, F(0));
+            post_record<NV>(fbase, post, g.steps, g.steps, FW, tag, F(0));
+            plan(q, q);
+        }
         F yB = F(0);
         bool aborted = false;
         wg_barrier();   // interval 0: the loaders stage step 0
@@ -440,6 +507,10 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
                 const F y = act ? t * ilp : F(0);
                 yB = y;
                 ybuf[s & 1][lane] = y;
+                // publish at once (the neighbour tiles' next steps wait on
+                // these words); past the last step y lands in the zero margin
+                stg(yout, e0 + (uint32_t)min(s, g.steps) * TT, y);   // inactive lanes rewrite their zero padding
+                post_record<NV>(fbase, post, s, g.steps, FW, tag, ybuf[s & 1][post.src]);
                 plan(q, s + PD);
                 if (q == PD - 1 && aborted) s_buf[3] = 1;   // read by every wave after this barrier
                 wg_barrier();
@@ -456,7 +527,6 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
             xring[0][lane] = ldg(src.x, src.e0);
         }
         if (lw < g.steps) fwd_issue(c, src, v, lw, g.nk);
-        GLOBAL F *yout = gp((F *)J.y);
         double rr = 0.0, bb = 0.0;
         auto turn = [&](int u) {
             const int f = u;
@@ -480,22 +550,6 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
                 ring[slot][2][lane] = c.l[1];
                 ring[slot][3][lane] = c.l[2];
                 ring[slot][4][lane] = c.l[3];
-            }
-            const int p = u - 2;
-            if (p >= 0 && p < g.steps) {
-                const F y = ybuf[p & 1][lane];
-                stg(yout, src.e0 + (uint32_t)p * TT, y);   // inactive lanes rewrite their zero padding
-                uint32_t wd[NV];
-                to_words(y, wd);
-                if (v.ip == TI - 1) {
-#pragma unroll
-                    for (int q = 0; q < NV; q++) ll_store(face_t + (long long)p * FW + v.jp * NV + q, tag, wd[q]);
-                }
-                if (v.jp == TJ - 1) {
-#pragma unroll
-                    for (int q = 0; q < NV; q++)
-                        ll_store(face_t + (long long)p * FW + (TJ + v.ip) * NV + q, tag, wd[q]);
-                }
             }
             if (u + NL < g.steps) fwd_issue(c, src, v, u + NL, g.nk);
         };
@@ -602,7 +656,7 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     if (threadIdx.x == 0) s_buf[3] = 0;
     const Assign as = take_ticket(a, s_buf);
-    const Job J = a.jobs[as.job];
+    const Job J = load_job(a, as.job);
     const uint32_t stop = J.ctl->stop;
     if (stop != RUN) {
         launch_done(a);
@@ -614,7 +668,6 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
     const int U = sweep_intervals(g.steps, PD);
     const int FW = J.fw;
     const long long fstride = (long long)g.steps * FW;
-    GLOBAL uint64_t *face_t = gp(J.face) + (long long)v.t * fstride;
     GLOBAL Ctl *ctl = gp(J.ctl);
 
     dbuf[0][lane] = F(0);
@@ -622,11 +675,12 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
     __syncthreads();
 
     if (wave == 0) {
-        const GLOBAL uint64_t *fbase = gp(J.face);
+        GLOBAL uint64_t *fbase = gp(J.face);
         const uint32_t own = (uint32_t)v.t * (uint32_t)fstride;
         const uint32_t baseE = (uint32_t)(v.t + 1) * (uint32_t)fstride + (uint32_t)((TI - 1) * FW + v.jp * NV);
         const uint32_t baseN = (uint32_t)(v.t + g.nti) * (uint32_t)fstride + (uint32_t)((TJ - 1) * FW + (TJ + v.ip) * NV);
         const bool edgeE = v.ip == TI - 1 && v.ti < g.nti - 1, edgeN = v.jp == TJ - 1 && v.tj < g.ntj - 1;
+        const Post post = make_post<NV>(g, v, fstride, lane, 0, 0);   // W column, S row
         Halo<NV> pv[PD];
         bool needE[PD], needN[PD];
         const GLOBAL uint64_t *pE[PD], *pN[PD];
@@ -639,7 +693,10 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
             halo_issue(pv[q], pE[q], pN[q]);
         };
 #pragma unroll
-        for (int q = 0; q < PD; q++) plan(q, q);
+        for (int q = 0; q < PD; q++) {   // same store pattern as a step (sink only)
+            post_record<NV>(fbase, post, g.steps, g.steps, FW, tag, F(0));
+            plan(q, q);
+        }
         F dT = F(0);
         bool aborted = false;
         wg_barrier();
@@ -671,6 +728,7 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
                 const F d = act ? t : F(0);
                 dT = d;
                 dbuf[s & 1][lane] = d;
+                post_record<NV>(fbase, post, s, g.steps, FW, tag, dbuf[s & 1][post.src]);
                 plan(q, s + PD);
                 if (q == PD - 1 && aborted) s_buf[3] = 1;
                 wg_barrier();
@@ -697,25 +755,16 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
                 ring[slot][3][lane] = c.u[2];
                 xring[f & 3][lane] = c.x;
             }
+            // Issue the next loads before the x store: a load of x behind a
+            // store to x would wait for the store to complete.
+            if (u + NL < g.steps) bwd_issue(c, src, g.steps, u + NL);
             const int p = u - 2;
             if (p >= 0 && p < g.steps) {
                 const int sp = g.steps - 1 - p;
                 const F d = dbuf[p & 1][lane];
                 const double xv = xring[p & 3][lane];
                 stg(src.x, src.e0 + (uint32_t)sp * TT, xv + (double)d);   // padding: 0 + 0
-                uint32_t wd[NV];
-                to_words(d, wd);
-                if (v.ip == 0) {
-#pragma unroll
-                    for (int q = 0; q < NV; q++) ll_store(face_t + (long long)p * FW + v.jp * NV + q, tag, wd[q]);
-                }
-                if (v.jp == 0) {
-#pragma unroll
-                    for (int q = 0; q < NV; q++)
-                        ll_store(face_t + (long long)p * FW + (TJ + v.ip) * NV + q, tag, wd[q]);
-                }
             }
-            if (u + NL < g.steps) bwd_issue(c, src, g.steps, u + NL);
         };
         if (lw == 0) turn(0);
         wg_barrier();
@@ -762,7 +811,7 @@ __global__ __launch_bounds__(BLOCK) void k_factor(LaunchArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     if (threadIdx.x == 0) s_buf[3] = 0;
     const Assign as = take_ticket(a, s_buf);
-    const Job J = a.jobs[as.job];
+    const Job J = load_job(a, as.job);
     const uint32_t stop = J.ctl->stop;
     if (stop != RUN) {
         launch_done(a);
