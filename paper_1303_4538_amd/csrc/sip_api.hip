@@ -268,9 +268,9 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
         return set_error(SIP_EDEVICE, "no HIP device");
     }
     h->timeout_ticks = timeout_ticks_for(h->device, 2.0);
-    if (const char *e = getenv("SIP_SWEEP_LOADERS")) {   // tuning override
+    if (const char *e = getenv("SIP_SWEEP_PHASES")) {   // tuning override
         const int nl = atoi(e);
-        if (nl == 2 || nl == 4 || nl == 6 || nl == 8) h->plan.loaders = nl;
+        if (nl >= 1 && nl <= sipk::MAX_PHASES) h->plan.phases = nl;
     }
     sip_status st = system_alloc(h, s);
     if (st != SIP_OK) {

@@ -1,24 +1,36 @@
 // Internal declarations shared by the gfx950 kernels and the host runtime.
 //
-// Data layout ("tile-sheared hyperplane order").  A block of ni x nj x nk
-// cells is cut into tile columns of TI x TJ cells in (i, j) that run through
-// all of k.  Inside a tile, cell (i', j', k) belongs to the local hyperplane
-// s = i' + j' + k and is stored at
-//     tile * tile_elems + (s + 1) * TT + j' * TI + i'          (TT = TI * TJ)
-// so the TI*TJ cells that one wavefront step touches are contiguous.  Planes
-// -1 and steps (= nk + TI + TJ - 2) are zero margins; slots whose k falls
-// outside [0, nk) or whose (i, j) falls outside the block are zero padding.
-// Any order that visits W, S and B before P computes the same SIP values as
-// the lexicographic one, and the local hyperplane order does.
+// Data layout ("tile-sheared hyperplane order, 2 x 2 cells per lane").  A
+// block of ni x nj x nk cells is cut into tile columns of TI x TJ = 16 x 16
+// cells in (i, j) that run through all of k.  A tile is worked by one wave of
+// LI x LJ = 8 x 8 lanes; lane (i', j') owns the 2 x 2 cells (2 i' + a, 2 j' + b)
+// of the tile, "quadrant" q = 2 b + a.  Cell (i', j', q, k) belongs to the
+// local hyperplane (step) s = i' + j' + k and is stored at
+//     tile * tile_elems + (s + 1) * PLANE + q * TT + j' * LI + i'
+// (TT = 64 lanes, PLANE = 4 * TT), so the cells one step touches are 256
+// contiguous elements, 64 per quadrant.  Planes -1 and steps (= nk + LI + LJ
+// - 2) are zero margins; slots whose k falls outside [0, nk) or whose (i, j)
+// falls outside the block are zero padding.
+//
+// Why this order computes the SIP recurrences: cell (i, j, k) depends on its
+// W, S and B neighbours.  Inside a lane, quadrant (1, b) follows (0, b) and
+// (a, 1) follows (a, 0) in the same step; across lanes, the W neighbour of a
+// quadrant with a = 0 is lane i' - 1's quadrant (1, b) one step earlier, and
+// likewise in j; the B neighbour is the same slot one step earlier.  Any order
+// that visits W, S and B before P gives the values of the lexicographic one.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
 namespace sipk {
 
-constexpr int TI = 8;          // tile extent in i (lanes)
-constexpr int TJ = 8;          // tile extent in j
-constexpr int TT = TI * TJ;    // one wave: lane = j' * TI + i'
+constexpr int LI = 8;              // lanes of a tile in i
+constexpr int LJ = 8;              // lanes of a tile in j
+constexpr int TT = LI * LJ;        // one wave: lane = j' * LI + i'
+constexpr int NQ = 4;              // cells per lane (2 x 2), quadrant q = 2 b + a
+constexpr int TI = 2 * LI;         // tile extent in cells (i)
+constexpr int TJ = 2 * LJ;         // tile extent in cells (j)
+constexpr int PLANE = NQ * TT;     // elements per local step of a tile
 
 enum Stop : uint32_t {
     RUN = 0,
@@ -32,9 +44,9 @@ enum Stop : uint32_t {
 struct Geom {
     int ni, nj, nk;
     int nti, ntj, ntiles;
-    int steps;                 // nk + TI + TJ - 2 local hyperplanes per tile
+    int steps;                 // nk + LI + LJ - 2 local hyperplanes per tile
     int planes;                // steps + 2 (with the two margins)
-    long long tile_elems;      // planes * TT
+    long long tile_elems;      // planes * PLANE
     long long elems;           // ntiles * tile_elems
 };
 
@@ -83,15 +95,19 @@ struct LaunchArgs {
     uint64_t timeout_ticks;    // wall-clock ticks before a wait gives up
 };
 
-// Face words per local step of one tile: (TI + TJ) entries of 3 FP64 values,
-// 2 words each (the factorisation's U triples; sweeps use fewer).
-constexpr int FACE_WORDS = (TI + TJ) * 6;
-// The sweeps exchange one value per face entry: at most 2 words (FP64).
-constexpr int FACE_WORDS_SWEEP = (TI + TJ) * 2;
+// Face records.  At every local step a tile publishes the values its
+// downstream neighbours need: FACE_ENTRIES entries, entry e < TJ for cell row
+// j = e of the tile column facing the i neighbour, entry TJ + i for cell
+// column i of the tile row facing the j neighbour.
+constexpr int FACE_ENTRIES = TI + TJ;
+// Words per step: the factorisation sends U triples (3 FP64 values, 2 words
+// each); the sweeps one value (1 word FP32, 2 words FP64).
+constexpr int FACE_WORDS = FACE_ENTRIES * 6;
+constexpr int FACE_WORDS_SWEEP = FACE_ENTRIES * 2;
 // Behind the sweeps' ntiles * steps * FACE_WORDS_SWEEP words (inside the
 // buffer sized for the factorisation) each tile owns SINK_WORDS words that
 // absorb the face-record stores of steps past its last one.
-constexpr int SINK_WORDS = 32;
+constexpr int SINK_WORDS = FACE_WORDS_SWEEP;
 static_assert(SINK_WORDS <= FACE_WORDS - FACE_WORDS_SWEEP, "sink lines must fit behind the sweep face words");
 
 Geom make_geom(int ni, int nj, int nk);
@@ -104,9 +120,12 @@ hipError_t launch_from_sheared_f64(const Geom &g, const double *src, double *dst
                                    hipStream_t s);
 hipError_t launch_export_factors(const Geom &g, const void *LU, int fp32, double *const *dst, hipStream_t s);
 hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s);
-// Launch shape of the sweeps: loader waves per tile (2, 4, 6 or 8).
+// Launch shape of the sweeps: loader phases per tile (1 to 3).  Each phase
+// is NQ loader waves (one per quadrant); phases take turns step by step, so
+// a phase's loads have `phases` steps to arrive.
+constexpr int MAX_PHASES = 3;
 struct SweepPlan {
-    int loaders = 4;
+    int phases = 2;
 };
 hipError_t launch_forward(const LaunchArgs &a, int fp32, const SweepPlan &p, hipStream_t s);
 hipError_t launch_backward(const LaunchArgs &a, int fp32, const SweepPlan &p, hipStream_t s);

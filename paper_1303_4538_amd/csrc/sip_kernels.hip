@@ -2,22 +2,18 @@
 // residual + forward sweep, backward sweep + update.
 //
 // Every recurrence kernel is a pipeline over tile columns (see the layout in
-// sip_internal.h).  One workgroup = one tile = two waves:
-//   wave 0, "recurrence": walks the tile's local hyperplanes s = 0..steps-1;
-//     lane (i', j') handles cell (i', j', k = s - i' - j').  Its W/S (or E/N)
-//     neighbours inside the tile are the neighbouring lanes one step earlier
-//     (exchanged through LDS); across the tile edge the value comes from the
-//     neighbour tile's face words.  It touches global memory only to read
-//     those face words.
-//   wave 1, "loader": streams the coefficient / factor / vector planes from
-//     HBM a few steps ahead (register pipeline of depth LP), does all work
-//     that does not depend on the recurrence (the FP64 residual, the FP64
-//     update of x), stages operands in an LDS ring for wave 0 and writes wave
-//     0's results and face words back to HBM.
-// The two waves meet at one workgroup barrier per step; the barrier waits on
-// LDS traffic only, so the loader's loads stay in flight across it.
+// sip_internal.h).  One workgroup works one tile.  A "recurrence" wave walks
+// the tile's local hyperplanes s = 0..steps-1; lane (i', j') handles its four
+// cells (2 i' + a, 2 j' + b, k = s - i' - j') in dependency order.  Values of
+// the neighbouring lanes from the previous step come through LDS; across the
+// tile edge they come from the neighbour tile's face record in global memory.
+// In the sweeps, "loader" waves stream coefficient / factor / vector planes
+// from HBM a few steps ahead, do all work that does not depend on the
+// recurrence (the FP64 residual, the FP64 update of x) and stage operands in
+// an LDS ring.  Recurrence and loader waves meet at one workgroup barrier per
+// step; the barrier waits on LDS traffic only, so loads stay in flight.
 //
-// Face words: a value crossing a tile edge is written as 64-bit words
+// Face records: a value crossing a tile edge is written as 64-bit words
 // (sweep tag << 32 | 32 payload bits) with agent-scope relaxed atomic stores;
 // the consumer polls the words with agent-scope atomic loads until the tag
 // equals the current sweep's tag.  Each word is self-validating, so no fence
@@ -43,9 +39,9 @@ Geom make_geom(int ni, int nj, int nk)
     g.nti = (ni + TI - 1) / TI;
     g.ntj = (nj + TJ - 1) / TJ;
     g.ntiles = g.nti * g.ntj;
-    g.steps = nk + TI + TJ - 2;
+    g.steps = nk + LI + LJ - 2;
     g.planes = g.steps + 2;
-    g.tile_elems = (long long)g.planes * TT;
+    g.tile_elems = (long long)g.planes * PLANE;
     g.elems = (long long)g.ntiles * g.tile_elems;
     return g;
 }
@@ -79,9 +75,7 @@ __device__ __forceinline__ Job load_job(const LaunchArgs &a, int job)
 }
 
 constexpr int WAVE = 64;
-constexpr int BLOCK = 2 * WAVE;
-constexpr int LP = 4;   // loader register-pipeline depth (steps of look-ahead)
-constexpr int PD = 2;   // face-word prefetch distance of the recurrence wave
+constexpr int PD = 4;   // face-record prefetch distance of the recurrence wave (steps)
 
 // ---------------------------------------------------------------- helpers
 
@@ -169,8 +163,8 @@ __device__ __forceinline__ bool halo_ok(const Halo<NWORDS> &h, bool na, bool nb,
 // Re-poll until every lane's needed words carry `tag`.  Returns false if the
 // wait timed out or another workgroup raised the error flag.
 template <int NWORDS>
-__device__ __forceinline__ bool halo_wait(Halo<NWORDS> &h, bool na, const GLOBAL uint64_t *pa, bool nb, const GLOBAL uint64_t *pb,
-                          uint32_t tag, GLOBAL Ctl *ctl, uint64_t timeout)
+__device__ __forceinline__ bool halo_wait(Halo<NWORDS> &h, bool na, const GLOBAL uint64_t *pa, bool nb,
+                                          const GLOBAL uint64_t *pb, uint32_t tag, GLOBAL Ctl *ctl, uint64_t timeout)
 {
     if (!__any(!halo_ok(h, na, nb, tag))) return true;
     const uint64_t t0 = wall_clock64();
@@ -188,14 +182,11 @@ __device__ __forceinline__ bool halo_wait(Halo<NWORDS> &h, bool na, const GLOBAL
 
 // Per-lane view of the tile a workgroup owns.
 struct TileView {
-    int t, ti, tj, ip, jp, gi, gj;
-    bool in_ij;                 // (i, j) inside the block
-    long long base;             // sheared index of (plane 0, this lane) in this tile
-    __device__ bool active(int s, int nk) const
-    {
-        const int k = s - ip - jp;
-        return in_ij && (unsigned)k < (unsigned)nk;
-    }
+    int t, ti, tj, ip, jp;
+    uint32_t inq;               // bit q: quadrant q's cell lies inside the block in (i, j)
+    long long base;             // sheared index of (plane 0, quadrant 0, this lane)
+    __device__ bool kin(int s, int nk) const { return (unsigned)(s - ip - jp) < (unsigned)nk; }
+    __device__ bool active(int s, int nk, int q) const { return ((inq >> q) & 1u) && kin(s, nk); }
 };
 
 __device__ __forceinline__ TileView make_view(const Geom &g, int t, int lane)
@@ -204,17 +195,18 @@ __device__ __forceinline__ TileView make_view(const Geom &g, int t, int lane)
     v.t = t;
     v.ti = t % g.nti;
     v.tj = t / g.nti;
-    v.ip = lane % TI;
-    v.jp = lane / TI;
-    v.gi = v.ti * TI + v.ip;
-    v.gj = v.tj * TJ + v.jp;
-    v.in_ij = v.gi < g.ni && v.gj < g.nj;
-    v.base = (long long)t * g.tile_elems + TT + lane;
+    v.ip = lane % LI;
+    v.jp = lane / LI;
+    const int i0 = v.ti * TI + 2 * v.ip, j0 = v.tj * TJ + 2 * v.jp;
+    v.inq = 0u;
+#pragma unroll
+    for (int q = 0; q < NQ; q++)
+        if (i0 + (q & 1) < g.ni && j0 + (q >> 1) < g.nj) v.inq |= 1u << q;
+    v.base = (long long)t * g.tile_elems + PLANE + lane;
     return v;
 }
 
-// Workgroup prologue: take a ticket.  Returns the job index (or -1 if the
-// job is already stopped) and the tile in *tile.
+// Workgroup prologue: take a ticket.  Returns the job index and the tile.
 struct Assign {
     int job, tile;
 };
@@ -262,87 +254,6 @@ __device__ bool job_last(const Job &J, int *s_buf)
     return last;
 }
 
-__device__ __forceinline__ int padded_intervals(int steps)
-{
-    // intervals: fill f = u, recurrence s = u - 1, post p = u - 2
-    const int u = steps + 2;
-    return (u + LP - 1) / LP * LP;
-}
-
-// ------------------------------------------------------ sweeps
-// Workgroup = one recurrence wave (wave 0) + NL loader waves.  Loader wave l
-// owns the steps f with f % NL == l: at its turn (interval f) it consumes the
-// loads it issued NL intervals earlier, stages the operands of step f in the
-// LDS ring and issues the loads of step f + NL.  Its own vector-memory wait at
-// a turn therefore only covers loads that had NL intervals to arrive.
-// Interval u: loaders fill step u, the recurrence wave processes step u - 1
-// and publishes its face words (and, forward, y) at once, so the neighbour
-// tiles see them without waiting for a loader turn; one workgroup barrier
-// ends every interval.  Backward, the owning loader applies x += d of step
-// u - 2.
-
-// Face records.  At every step a tile publishes the 16 face entries its
-// downstream neighbours read (entry e < TJ: row e of the column facing the i
-// neighbour; entry TJ + c: column c of the row facing the j neighbour), NV
-// words each.  The recurrence wave writes the whole record with one store in
-// which every lane writes a word (the 64 lanes cover the 16 NV words 64 / (16
-// NV) times over, with identical data), taking the value from the LDS copy
-// of the step it has just written.  With no store behind a branch the
-// compiler's vector-memory counts stay exact, and the wait for a prefetched
-// poll never waits for a later store.  Steps past the last one write the
-// tile's sink words.
-struct Post {
-    uint32_t rec;    // word index of this lane's word in the tile's record at step 0
-    uint32_t sink;   // word index of this lane's word in the tile's sink
-    int src;         // lane whose value this lane's word carries
-    int half;        // which 32-bit half of that value (FP64)
-};
-
-template <int NV>
-__device__ __forceinline__ Post make_post(const Geom &g, const TileView &v, long long fstride, int lane, int col_i, int row_j)
-{
-    Post p;
-    const int word = lane & (16 * NV - 1);
-    const int e = word / NV;
-    p.half = word % NV;
-    p.src = e < TJ ? e * TI + col_i : row_j * TI + (e - TJ);
-    p.rec = (uint32_t)v.t * (uint32_t)fstride + (uint32_t)word;
-    p.sink = (uint32_t)g.ntiles * (uint32_t)fstride + (uint32_t)v.t * SINK_WORDS + (uint32_t)word;
-    return p;
-}
-
-template <int NV, typename F>
-__device__ __forceinline__ void post_record(GLOBAL uint64_t *fbase, const Post &p, int s, int steps, int fw, uint32_t tag, F val)
-{
-    uint32_t wd[NV];
-    to_words(val, wd);
-    uint32_t w = wd[0];
-#pragma unroll
-    for (int q = 1; q < NV; q++) w = p.half == q ? wd[q] : w;
-    ll_store(fbase + (s < steps ? p.rec + (uint32_t)s * (uint32_t)fw : p.sink), tag, w);
-}
-
-__device__ __forceinline__ int sweep_intervals(int steps, int pd)
-{
-    // interval 0 (fill only) plus the recurrence steps 0..steps (step `steps`
-    // only lets the last backward x update happen), padded to the poll unroll
-    return 1 + (steps + 1 + pd - 1) / pd * pd;
-}
-
-// Forward: residual r = b - A x (FP64, fused), forward substitution
-// y = (r - Lb y_B - Lw y_W - Ls y_S) / Lp in precision F, per-tile partial
-// sums of r^2 (and of b^2, used at iteration 0).
-
-template <typename F>
-struct FwdLoad {
-    double a[7];
-    double b;
-    double xt;     // x on plane f + 1 (this lane's T neighbour), staged into the LDS plane ring
-    double hx;     // x across the W or E tile edge (edge lanes only)
-    double hy;     // x across the S or N tile edge (edge lanes only)
-    F l[4];        // Lb, Lw, Ls, 1/Lp
-};
-
 // Load through a uniform base pointer and a 32-bit element index (the host
 // guarantees every array stays below 4 GiB), which maps onto the
 // saddr + voffset form of global_load.
@@ -357,65 +268,185 @@ __device__ __forceinline__ void stg(GLOBAL T *base, uint32_t idx, T v)
     *(GLOBAL T *)((GLOBAL char *)base + (size_t)(idx * (uint32_t)sizeof(T))) = v;
 }
 
-// Uniform base pointers and per-lane index deltas of the forward loader.
+// ------------------------------------------------------ face records
+// Entry e < TJ: cell row j = e of the tile column facing the i neighbour
+// (lane column ci, quadrant column ca); entry TJ + i: cell column i of the
+// tile row facing the j neighbour (lane row cj, quadrant row cb).  Downstream
+// in the forward direction the faces are the E column / N row (ci = LI - 1,
+// ca = 1, cj = LJ - 1, cb = 1), in the backward direction the W column / S row.
+__device__ __forceinline__ void entry_owner(int e, int ci, int ca, int cj, int cb, int &lane, int &q)
+{
+    if (e < TJ) {
+        lane = (e >> 1) * LI + ci;
+        q = (e & 1) * 2 + ca;
+    } else {
+        const int c = e - TJ;
+        lane = cj * LI + (c >> 1);
+        q = cb * 2 + (c & 1);
+    }
+}
+
+// The recurrence wave writes a step's whole record with one store in which
+// every lane writes a word (64 lanes cover the FACE_ENTRIES * NV words
+// 64 / (FACE_ENTRIES * NV) times over, with identical data), taking the value
+// from the LDS copy of the step it has just written.  With no store behind a
+// branch the compiler's vector-memory counts stay exact, and the wait for a
+// prefetched poll never waits for a later store.  Steps past the last one
+// write the tile's sink words.
+struct Post {
+    uint32_t rec;    // word index of this lane's word in the tile's record at step 0
+    uint32_t sink;   // word index of this lane's word in the tile's sink
+    int src, q;      // lane and quadrant whose value this lane's word carries
+    int half;        // which 32-bit half of that value (FP64)
+};
+
+template <int NV>
+__device__ __forceinline__ Post make_post(const Geom &g, const TileView &v, long long fstride, int lane, int ci, int ca,
+                                          int cj, int cb)
+{
+    static_assert(FACE_ENTRIES * NV <= WAVE, "one store per record");
+    Post p;
+    const int word = lane & (FACE_ENTRIES * NV - 1);
+    p.half = word % NV;
+    entry_owner(word / NV, ci, ca, cj, cb, p.src, p.q);
+    p.rec = (uint32_t)v.t * (uint32_t)fstride + (uint32_t)word;
+    p.sink = (uint32_t)g.ntiles * (uint32_t)fstride + (uint32_t)v.t * SINK_WORDS + (uint32_t)word;
+    return p;
+}
+
+template <int NV, typename F>
+__device__ __forceinline__ void post_record(GLOBAL uint64_t *fbase, const Post &p, int s, int steps, int fw, uint32_t tag,
+                                            F val)
+{
+    uint32_t wd[NV];
+    to_words(val, wd);
+    uint32_t w = wd[0];
+#pragma unroll
+    for (int q = 1; q < NV; q++) w = p.half == q ? wd[q] : w;
+    ll_store(fbase + (s < steps ? p.rec + (uint32_t)s * (uint32_t)fw : p.sink), tag, w);
+}
+
+// Poll plan of a recurrence wave.  A lane on the upstream i edge reads the
+// two entries of its cell rows (2 j', 2 j' + 1) from the i neighbour's record
+// LI - 1 steps ahead (the neighbour's edge lanes reach the same k that many
+// steps later); a lane on the j edge reads entries TJ + 2 i', TJ + 2 i' + 1
+// from the j neighbour.  NV words per entry.  Word indices come from one
+// uniform base with selects; lanes without a halo read their own tile's first
+// word.
+struct PollPlan {
+    uint32_t own, base_i, base_j;
+    bool edge_i, edge_j;
+};
+
+template <int NV>
+__device__ __forceinline__ PollPlan make_polls(const Geom &g, const TileView &v, long long fstride, int fw, bool backward)
+{
+    PollPlan p;
+    const int ti_up = backward ? v.t + 1 : v.t - 1;
+    const int tj_up = backward ? v.t + g.nti : v.t - g.nti;
+    p.own = (uint32_t)v.t * (uint32_t)fstride;
+    p.edge_i = backward ? (v.ip == LI - 1 && v.ti < g.nti - 1) : (v.ip == 0 && v.ti > 0);
+    p.edge_j = backward ? (v.jp == LJ - 1 && v.tj < g.ntj - 1) : (v.jp == 0 && v.tj > 0);
+    p.base_i = (uint32_t)(p.edge_i ? ti_up : v.t) * (uint32_t)fstride + (uint32_t)((LI - 1) * fw + 2 * v.jp * NV);
+    p.base_j = (uint32_t)(p.edge_j ? tj_up : v.t) * (uint32_t)fstride + (uint32_t)((LJ - 1) * fw + (TJ + 2 * v.ip) * NV);
+    return p;
+}
+
+// ------------------------------------------------------ sweeps
+// Workgroup = one recurrence wave (wave 0) + NL = NQ * NP loader waves.
+// Loader wave l works quadrant q = l % NQ of the steps f with f % NP = l / NQ:
+// at its turn (interval f) it consumes the loads it issued NP intervals
+// earlier, stages the operands of step f in the LDS ring and issues the loads
+// of step f + NP.  Its own vector-memory wait at a turn therefore only covers
+// loads that had NP intervals to arrive.  Interval u: loaders fill step u,
+// the recurrence wave processes step u - 1 and publishes its face record at
+// once; one workgroup barrier ends every interval.  Results of step u - 2
+// (forward y, backward x += d) are written back by step u's loaders.
+
+__device__ __forceinline__ int sweep_intervals(int steps, int pd)
+{
+    // interval 0 (fill only) plus the recurrence steps 0..steps (step `steps`
+    // only lets the last write-back happen), padded to the poll unroll
+    return 1 + (steps + 1 + pd - 1) / pd * pd;
+}
+
+// Forward: residual r = b - A x (FP64, fused), forward substitution
+// y = (r - Lb y_B - Lw y_W - Ls y_S) / Lp in precision F, per-tile partial
+// sums of r^2 (and of b^2, used at iteration 0).
+
+template <typename F>
+struct FwdLoad {
+    double a[7];
+    double b;
+    double x2;     // x on plane f + 2, staged into the LDS plane ring for the next steps
+    double hx;     // x across the W or E tile edge (edge slots only)
+    double hy;     // x across the S or N tile edge (edge slots only)
+    F l[4];        // Lb, Lw, Ls, 1/Lp
+};
+
+// Uniform base pointers and per-lane index deltas of a forward loader.
 template <typename F>
 struct FwdSrc {
     const GLOBAL double *A[7];
     const GLOBAL double *b, *x;
     const GLOBAL F *L[4];
-    uint32_t e0;          // sheared index of (plane 0, this lane)
-    int32_t hx, hy;       // index deltas of the x halo this lane reads across a tile edge (0: none)
+    uint32_t e0;          // sheared index of (plane 0, this quadrant, this lane)
+    int32_t hx, hy;       // index deltas of the x halo this slot reads across a tile edge (0: none)
 };
 
 template <typename F>
-__device__ __forceinline__ FwdSrc<F> fwd_src(const Job &J, const TileView &v)
+__device__ __forceinline__ FwdSrc<F> fwd_src(const Job &J, const TileView &v, int q)
 {
     const Geom &g = J.g;
-    FwdSrc<F> q;
+    FwdSrc<F> s;
 #pragma unroll
-    for (int d = 0; d < 7; d++) q.A[d] = gp(J.A) + d * g.elems;
-    q.b = gp(J.b);
-    q.x = gp((const double *)J.x);
+    for (int d = 0; d < 7; d++) s.A[d] = gp(J.A) + d * g.elems;
+    s.b = gp(J.b);
+    s.x = gp((const double *)J.x);
 #pragma unroll
-    for (int d = 0; d < 4; d++) q.L[d] = gp((const F *)J.LU) + d * g.elems;
-    q.e0 = (uint32_t)v.base;
+    for (int d = 0; d < 4; d++) s.L[d] = gp((const F *)J.LU) + d * g.elems;
+    s.e0 = (uint32_t)v.base + (uint32_t)(q * TT);
     const int te = (int)g.tile_elems;
-    // Across a tile edge the neighbour is the neighbour tile's edge column/row
-    // on that tile's own local plane: W at plane f+TI-1, E at f-TI+1, S at
-    // f+TJ-1, N at f-TJ+1.  A lane sits on at most one of the W/E edges and
-    // one of the S/N edges, so two loads cover every halo; in-tile
-    // neighbours come from the LDS plane ring.
-    q.hx = (v.ip == 0 && v.ti > 0) ? -te + (TI - 1) * TT + (TI - 1)
-         : (v.ip == TI - 1 && v.ti < g.nti - 1) ? te - (TI - 1) * TT - (TI - 1) : 0;
-    q.hy = (v.jp == 0 && v.tj > 0) ? -g.nti * te + (TJ - 1) * TT + (TJ - 1) * TI
-         : (v.jp == TJ - 1 && v.tj < g.ntj - 1) ? g.nti * te - (TJ - 1) * TT - (TJ - 1) * TI : 0;
-    return q;
+    const int a = q & 1, b = q >> 1;
+    const int dqi = ((q ^ 1) - q) * TT, dqj = ((q ^ 2) - q) * TT;
+    // Across a tile edge the neighbour cell sits on the neighbour tile's own
+    // local plane: W at f + LI - 1, E at f - LI + 1, S at f + LJ - 1, N at
+    // f - LJ + 1, in the other quadrant column (row).  A slot lies on at most
+    // one of the W/E edges and one of the S/N edges; in-tile neighbours come
+    // from the LDS plane ring.
+    s.hx = (a == 0) ? ((v.ip == 0 && v.ti > 0) ? -te + (LI - 1) * PLANE + dqi + (LI - 1) : 0)
+                    : ((v.ip == LI - 1 && v.ti < g.nti - 1) ? te - (LI - 1) * PLANE + dqi - (LI - 1) : 0);
+    s.hy = (b == 0) ? ((v.jp == 0 && v.tj > 0) ? -g.nti * te + (LJ - 1) * PLANE + dqj + (LJ - 1) * LI : 0)
+                    : ((v.jp == LJ - 1 && v.tj < g.ntj - 1) ? g.nti * te - (LJ - 1) * PLANE + dqj - (LJ - 1) * LI : 0);
+    return s;
 }
 
-// Branch-free: inactive lanes read their own zero-padded slot (every index
+// Branch-free: inactive slots read their own zero-padded slot (every index
 // stays inside the tile's planes -1..steps for f in [0, steps)).
 template <typename F>
-__device__ __forceinline__ void fwd_issue(FwdLoad<F> &c, const FwdSrc<F> &q, const TileView &v, int f, int nk)
+__device__ __forceinline__ void fwd_issue(FwdLoad<F> &c, const FwdSrc<F> &s, const TileView &v, int q, int f, int steps,
+                                          int nk)
 {
-    const bool act = v.active(f, nk);
-    const uint32_t e = q.e0 + (uint32_t)f * TT;
+    const bool act = v.active(f, nk, q);
+    const uint32_t e = s.e0 + (uint32_t)f * PLANE;
 #pragma unroll
-    for (int d = 0; d < 7; d++) c.a[d] = ldg(q.A[d], e);
-    c.b = ldg(q.b, e);
+    for (int d = 0; d < 7; d++) c.a[d] = ldg(s.A[d], e);
+    c.b = ldg(s.b, e);
 #pragma unroll
-    for (int d = 0; d < 4; d++) c.l[d] = ldg(q.L[d], e);
-    c.xt = ldg(q.x, e + TT);
-    c.hx = ldg(q.x, e + (act ? q.hx : 0));
-    c.hy = ldg(q.x, e + (act ? q.hy : 0));
+    for (int d = 0; d < 4; d++) c.l[d] = ldg(s.L[d], e);
+    c.x2 = ldg(s.x, s.e0 + (uint32_t)min(f + 2, steps) * PLANE);   // plane `steps` is the zero margin
+    c.hx = ldg(s.x, e + (act ? s.hx : 0));
+    c.hy = ldg(s.x, e + (act ? s.hy : 0));
 }
 
-template <typename F, int NL, int PD>
-__global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
+template <typename F, int NP>
+__global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
 {
     constexpr int NV = NW<F>::n;
-    __shared__ F ring[2][5][TT];     // r, Lb, Lw, Ls, 1/Lp of two steps
-    __shared__ F ybuf[2][TT];
-    __shared__ double xring[4][TT];  // x on planes f-1, f, f+1 (slot = plane & 3)
+    constexpr int NL = NQ * NP;
+    __shared__ F ring[2][5][NQ][TT];        // r, Lb, Lw, Ls, 1/Lp of two steps
+    __shared__ F ybuf[2][NQ][TT];
+    __shared__ double xring[4][NQ][TT];     // x on planes f-1..f+2 (slot = plane & 3)
     __shared__ int s_buf[4];
     __shared__ double s_part[NL][2];
 
@@ -438,79 +469,111 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
     const long long fstride = (long long)g.steps * FW;
     GLOBAL Ctl *ctl = gp(J.ctl);
 
-    ybuf[0][lane] = F(0);
-    ybuf[1][lane] = F(0);
-    __syncthreads();
+    for (int x = threadIdx.x; x < 2 * NQ * TT; x += blockDim.x) (&ybuf[0][0][0])[x] = F(0);
+    if (wave >= 1 && wave <= NQ) {   // phase-0 loaders: planes -1 (zero margin), 0 and 1 of the x ring
+        const int q = wave - 1;
+        const uint32_t e0 = (uint32_t)v.base + (uint32_t)(q * TT);
+        const GLOBAL double *xg = gp((const double *)J.x);
+        xring[3][q][lane] = 0.0;
+        xring[0][q][lane] = ldg(xg, e0);
+        xring[1][q][lane] = ldg(xg, e0 + (uint32_t)min(1, g.steps) * PLANE);
+    }
+    __syncthreads();   // the x ring prologue is read across quadrants by the first turn
 
     if (wave == 0) {
         // ---------------- recurrence wave
-        // Poll addresses are word indices from one uniform base, chosen with
-        // selects: lanes without a halo read their own tile's first word.
-        // Everything in the step stays free of divergent branches.
         GLOBAL uint64_t *fbase = gp(J.face);
-        const uint32_t own = (uint32_t)v.t * (uint32_t)fstride;
-        const uint32_t baseW = (uint32_t)(v.t - 1) * (uint32_t)fstride + (uint32_t)((TI - 1) * FW + v.jp * NV);
-        const uint32_t baseS = (uint32_t)(v.t - g.nti) * (uint32_t)fstride + (uint32_t)((TJ - 1) * FW + (TJ + v.ip) * NV);
-        const bool edgeW = v.ip == 0 && v.ti > 0, edgeS = v.jp == 0 && v.tj > 0;
-        GLOBAL F *yout = gp((F *)J.y);
-        const uint32_t e0 = (uint32_t)v.base;
-        const Post post = make_post<NV>(g, v, fstride, lane, TI - 1, TJ - 1);   // E column, N row
-        Halo<NV> pv[PD];
+        const PollPlan pp = make_polls<NV>(g, v, fstride, FW, false);
+        const Post post = make_post<NV>(g, v, fstride, lane, LI - 1, 1, LJ - 1, 1);   // E column, N row
+        Halo<2 * NV> pv[PD];
         bool needW[PD], needS[PD];
-        const GLOBAL uint64_t *pW[PD], *pS[PD];
+        uint32_t oW[PD], oS[PD];
         auto plan = [&](int q, int s2) {
-            const bool act = v.active(s2, g.nk);
-            needW[q] = act && edgeW;
-            needS[q] = act && edgeS;
-            pW[q] = fbase + (needW[q] ? baseW + (uint32_t)s2 * FW : own);
-            pS[q] = fbase + (needS[q] ? baseS + (uint32_t)s2 * FW : own);
-            halo_issue(pv[q], pW[q], pS[q]);
+            const bool act = v.inq != 0u && v.kin(s2, g.nk);
+            needW[q] = act && pp.edge_i;
+            needS[q] = act && pp.edge_j;
+            oW[q] = needW[q] ? pp.base_i + (uint32_t)s2 * FW : pp.own;
+            oS[q] = needS[q] ? pp.base_j + (uint32_t)s2 * FW : pp.own;
+            halo_issue(pv[q], fbase + oW[q], fbase + oS[q]);
         };
-        // The prologue repeats a step's store pattern (zero margin, sink) ahead
-        // of each poll, so the loop is entered with the same counts as it
-        // loops back with.
+        // The prologue repeats a step's store pattern (the sink) ahead of each
+        // poll, so the loop is entered with the same counts as it loops back with.
 #pragma unroll
         for (int q = 0; q < PD; q++) {
-            stg(yout, e0 + (uint32_t)g.steps * TT, F(0));
             post_record<NV>(fbase, post, g.steps, g.steps, FW, tag, F(0));
             plan(q, q);
         }
-        F yB = F(0);
+        F yB[NQ] = {F(0), F(0), F(0), F(0)};
         bool aborted = false;
+        const int dW = v.ip > 0 ? 1 : 0, dS = v.jp > 0 ? LI : 0;
         wg_barrier();   // interval 0: the loaders stage step 0
         for (int s0 = 0; s0 + 1 < U; s0 += PD) {
 #pragma unroll
             for (int q = 0; q < PD; q++) {
                 const int s = s0 + q;
                 const int slot = s & 1;
-                const F r = ring[slot][0][lane];
-                const F lb = ring[slot][1][lane];
-                const F lw = ring[slot][2][lane];
-                const F ls = ring[slot][3][lane];
-                const F ilp = ring[slot][4][lane];
-                if (!aborted && !halo_wait(pv[q], needW[q], pW[q], needS[q], pS[q], tag, ctl, a.timeout_ticks))
+                F r[NQ], lb[NQ], lw[NQ], ls[NQ], il[NQ];
+#pragma unroll
+                for (int c = 0; c < NQ; c++) {
+                    r[c] = ring[slot][0][c][lane];
+                    lb[c] = ring[slot][1][c][lane];
+                    lw[c] = ring[slot][2][c][lane];
+                    ls[c] = ring[slot][3][c][lane];
+                    il[c] = ring[slot][4][c][lane];
+                }
+                if (!aborted && !halo_wait(pv[q], needW[q], fbase + oW[q], needS[q], fbase + oS[q], tag, ctl,
+                                           a.timeout_ticks))
                     aborted = true;
-                F hw, hs;
-                from_words(pv[q].a, hw);
-                from_words(pv[q].b, hs);
+                F hw0, hw1, hs0, hs1;
+                from_words(&pv[q].a[0], hw0);
+                from_words(&pv[q].a[NV], hw1);
+                from_words(&pv[q].b[0], hs0);
+                from_words(&pv[q].b[NV], hs1);
                 const int pr = (s - 1) & 1;
-                F nW = ybuf[pr][lane - (v.ip > 0 ? 1 : 0)];
-                F nS = ybuf[pr][lane - (v.jp > 0 ? TI : 0)];
-                keep(nW);
-                keep(nS);
-                const F yW = v.ip > 0 ? nW : (needW[q] ? hw : F(0));
-                const F yS = v.jp > 0 ? nS : (needS[q] ? hs : F(0));
-                const bool act = v.active(s, g.nk);
-                F t = r - lb * yB;
-                t = t - lw * yW;
-                t = t - ls * yS;
-                const F y = act ? t * ilp : F(0);
-                yB = y;
-                ybuf[s & 1][lane] = y;
-                // publish at once (the neighbour tiles' next steps wait on
-                // these words); past the last step y lands in the zero margin
-                stg(yout, e0 + (uint32_t)min(s, g.steps) * TT, y);   // inactive lanes rewrite their zero padding
-                post_record<NV>(fbase, post, s, g.steps, FW, tag, ybuf[s & 1][post.src]);
+                F nW1 = ybuf[pr][1][lane - dW], nW3 = ybuf[pr][3][lane - dW];
+                F nS2 = ybuf[pr][2][lane - dS], nS3 = ybuf[pr][3][lane - dS];
+                keep(nW1);
+                keep(nW3);
+                keep(nS2);
+                keep(nS3);
+                const F zero = F(0);
+                const F W0 = dW ? nW1 : (needW[q] ? hw0 : zero);   // W of quadrant (0,0)
+                const F W2 = dW ? nW3 : (needW[q] ? hw1 : zero);   // W of quadrant (0,1)
+                const F S0 = dS ? nS2 : (needS[q] ? hs0 : zero);   // S of quadrant (0,0)
+                const F S1 = dS ? nS3 : (needS[q] ? hs1 : zero);   // S of quadrant (1,0)
+                const bool kin = v.kin(s, g.nk);
+                F y[NQ];
+                {
+                    F t = r[0] - lb[0] * yB[0];
+                    t = t - lw[0] * W0;
+                    t = t - ls[0] * S0;
+                    y[0] = (kin && (v.inq & 1u)) ? t * il[0] : zero;
+                }
+                {
+                    F t = r[1] - lb[1] * yB[1];
+                    t = t - lw[1] * y[0];
+                    t = t - ls[1] * S1;
+                    y[1] = (kin && (v.inq & 2u)) ? t * il[1] : zero;
+                }
+                {
+                    F t = r[2] - lb[2] * yB[2];
+                    t = t - lw[2] * W2;
+                    t = t - ls[2] * y[0];
+                    y[2] = (kin && (v.inq & 4u)) ? t * il[2] : zero;
+                }
+                {
+                    F t = r[3] - lb[3] * yB[3];
+                    t = t - lw[3] * y[2];
+                    t = t - ls[3] * y[1];
+                    y[3] = (kin && (v.inq & 8u)) ? t * il[3] : zero;
+                }
+#pragma unroll
+                for (int c = 0; c < NQ; c++) {
+                    yB[c] = y[c];
+                    ybuf[s & 1][c][lane] = y[c];
+                }
+                // publish at once: the neighbour tiles' next steps wait on this record
+                post_record<NV>(fbase, post, s, g.steps, FW, tag, ybuf[s & 1][post.q][post.src]);
                 plan(q, s + PD);
                 if (q == PD - 1 && aborted) s_buf[3] = 1;   // read by every wave after this barrier
                 wg_barrier();
@@ -520,45 +583,55 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
     } else {
         // ---------------- loader waves
         const int lw = wave - 1;
-        const FwdSrc<F> src = fwd_src<F>(J, v);
+        const int q = lw % NQ, ph = lw / NQ;
+        const int qa = q & 1, qb = q >> 1;
+        const FwdSrc<F> src = fwd_src<F>(J, v, q);
         FwdLoad<F> c;
-        if (lw == 0) {   // planes -1 (zero margin) and 0 of the x ring
-            xring[3][lane] = 0.0;
-            xring[0][lane] = ldg(src.x, src.e0);
-        }
-        if (lw < g.steps) fwd_issue(c, src, v, lw, g.nk);
+        if (ph < g.steps) fwd_issue(c, src, v, q, ph, g.steps, g.nk);
+        GLOBAL F *yout = gp((F *)J.y);
         double rr = 0.0, bb = 0.0;
+        // In-ring neighbours: the other quadrant column (row) of the same
+        // lane on the same plane, or of the neighbouring lane one plane down
+        // (W, S) / up (E, N).
+        const int dW = qa ? 0 : (v.ip > 0 ? 1 : 0), dE = qa ? (v.ip < LI - 1 ? 1 : 0) : 0;
+        const int dS = qb ? 0 : (v.jp > 0 ? LI : 0), dN = qb ? (v.jp < LJ - 1 ? LI : 0) : 0;
+        const bool inW = qa || v.ip > 0, inE = !qa || v.ip < LI - 1;
+        const bool inS = qb || v.jp > 0, inN = !qb || v.jp < LJ - 1;
         auto turn = [&](int u) {
             const int f = u;
             if (f < g.steps) {
-                // planes f-1 and f were staged by the two previous turns
-                xring[(f + 1) & 3][lane] = c.xt;
-                const double xP = xring[f & 3][lane];
-                const double xB = xring[(f - 1) & 3][lane];
-                const double xW = v.ip > 0 ? xring[(f - 1) & 3][lane - (v.ip > 0 ? 1 : 0)] : c.hx;
-                const double xE = v.ip < TI - 1 ? xring[(f + 1) & 3][lane + (v.ip < TI - 1 ? 1 : 0)] : c.hx;
-                const double xS = v.jp > 0 ? xring[(f - 1) & 3][lane - (v.jp > 0 ? TI : 0)] : c.hy;
-                const double xN = v.jp < TJ - 1 ? xring[(f + 1) & 3][lane + (v.jp < TJ - 1 ? TI : 0)] : c.hy;
+                // planes f-1..f+1 were staged by earlier turns
+                xring[(f + 2) & 3][q][lane] = c.x2;
+                const double xP = xring[f & 3][q][lane];
+                const double xB = xring[(f - 1) & 3][q][lane];
+                const double xT = xring[(f + 1) & 3][q][lane];
+                const double xW = inW ? xring[(f - 1 + qa) & 3][q ^ 1][lane - dW] : c.hx;
+                const double xE = inE ? xring[(f + qa) & 3][q ^ 1][lane + dE] : c.hx;
+                const double xS = inS ? xring[(f - 1 + qb) & 3][q ^ 2][lane - dS] : c.hy;
+                const double xN = inN ? xring[(f + qb) & 3][q ^ 2][lane + dN] : c.hy;
                 const double ax = c.a[0] * xP + c.a[1] * xW + c.a[2] * xE + c.a[3] * xS + c.a[4] * xN +
-                                  c.a[5] * xB + c.a[6] * c.xt;
+                                  c.a[5] * xB + c.a[6] * xT;
                 const double r = c.b - ax;
                 rr += r * r;
                 bb += c.b * c.b;
                 const int slot = f & 1;
-                ring[slot][0][lane] = (F)r;
-                ring[slot][1][lane] = c.l[0];
-                ring[slot][2][lane] = c.l[1];
-                ring[slot][3][lane] = c.l[2];
-                ring[slot][4][lane] = c.l[3];
+                ring[slot][0][q][lane] = (F)r;
+                ring[slot][1][q][lane] = c.l[0];
+                ring[slot][2][q][lane] = c.l[1];
+                ring[slot][3][q][lane] = c.l[2];
+                ring[slot][4][q][lane] = c.l[3];
             }
-            if (u + NL < g.steps) fwd_issue(c, src, v, u + NL, g.nk);
+            if (u + NP < g.steps) fwd_issue(c, src, v, q, u + NP, g.steps, g.nk);
+            const int p = u - 2;
+            if (p >= 0 && p < g.steps)   // inactive slots rewrite their zero padding
+                stg(yout, src.e0 + (uint32_t)p * PLANE, ybuf[p & 1][q][lane]);
         };
-        if (lw == 0) turn(0);
+        if (ph == 0) turn(0);
         wg_barrier();
         for (int s0 = 0; s0 + 1 < U; s0 += PD) {
-            for (int q = 0; q < PD; q++) {
-                const int u = s0 + q + 1;
-                if (u % NL == lw) turn(u);
+            for (int k = 0; k < PD; k++) {
+                const int u = s0 + k + 1;
+                if (u % NP == ph) turn(u);
                 wg_barrier();
             }
             if (s_buf[3]) break;
@@ -590,34 +663,35 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_forward(LaunchArgs a)
         sr = wave_sum(sr);
         sb = wave_sum(sb);
         if (lane == 0) {
-            Ctl *c = J.ctl;
-            if (iter == 0) c->bnorm2 = sb;
-            const double nb2 = iter == 0 ? sb : c->bnorm2;
+            Ctl *cc = J.ctl;
+            if (iter == 0) cc->bnorm2 = sb;
+            const double nb2 = iter == 0 ? sb : cc->bnorm2;
             uint32_t st = RUN;
-            const uint32_t err = c->err;
+            const uint32_t err = cc->err;
             if (err) {
                 st = (err & 2u) ? BREAKDOWN : TIMEOUT;
             } else if (nb2 == 0.0) {
                 st = ZERO_RHS;
-                c->rho = 0.0;
+                cc->rho = 0.0;
                 if (J.hist) J.hist[iter] = 0.0;
             } else {
                 const double rho = sqrt(sr) / sqrt(nb2);
-                c->rho = rho;
+                cc->rho = rho;
                 if (J.hist) J.hist[iter] = rho;
-                if (c->rtol > 0.0 && rho <= c->rtol) st = CONVERGED;
-                else if (iter >= c->max_iter) st = MAXITER;
+                if (cc->rtol > 0.0 && rho <= cc->rtol) st = CONVERGED;
+                else if (iter >= cc->max_iter) st = MAXITER;
             }
-            c->stop = st;
-            c->epoch = tag + 1u;
-            c->done = 0u;
+            cc->stop = st;
+            cc->epoch = tag + 1u;
+            cc->done = 0u;
         }
     }
     launch_done(a);
 }
 
 // Backward: d = y - Un d_N - Ue d_E - Ut d_T in reverse local-hyperplane
-// order (step s visits plane steps - 1 - s), then x += d in FP64.
+// order (step s visits plane steps - 1 - s; inside a lane quadrant (1,1)
+// first, (0,0) last), then x += d in FP64.
 
 template <typename F>
 struct BwdLoad {
@@ -634,22 +708,22 @@ struct BwdSrc {
 };
 
 template <typename F>
-__device__ __forceinline__ void bwd_issue(BwdLoad<F> &c, const BwdSrc<F> &q, int steps, int step)
+__device__ __forceinline__ void bwd_issue(BwdLoad<F> &c, const BwdSrc<F> &s, int steps, int step)
 {
-    const uint32_t e = q.e0 + (uint32_t)(steps - 1 - step) * TT;
-    c.y = ldg(q.y, e);
+    const uint32_t e = s.e0 + (uint32_t)(steps - 1 - step) * PLANE;
+    c.y = ldg(s.y, e);
 #pragma unroll
-    for (int d = 0; d < 3; d++) c.u[d] = ldg(q.U[d], e);
-    c.x = ldg((const GLOBAL double *)q.x, e);
+    for (int d = 0; d < 3; d++) c.u[d] = ldg(s.U[d], e);
+    c.x = ldg((const GLOBAL double *)s.x, e);
 }
 
-template <typename F, int NL, int PD>
-__global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
+template <typename F, int NP>
+__global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
 {
     constexpr int NV = NW<F>::n;
-    __shared__ F ring[2][4][TT];     // y, Un, Ue, Ut
-    __shared__ double xring[4][TT];
-    __shared__ F dbuf[2][TT];
+    __shared__ F ring[2][4][NQ][TT];     // y, Un, Ue, Ut
+    __shared__ double xring[4][NQ][TT];
+    __shared__ F dbuf[2][NQ][TT];
     __shared__ int s_buf[4];
 
     const int lane = threadIdx.x & (WAVE - 1);
@@ -670,65 +744,98 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
     const long long fstride = (long long)g.steps * FW;
     GLOBAL Ctl *ctl = gp(J.ctl);
 
-    dbuf[0][lane] = F(0);
-    dbuf[1][lane] = F(0);
+    for (int x = threadIdx.x; x < 2 * NQ * TT; x += blockDim.x) (&dbuf[0][0][0])[x] = F(0);
     __syncthreads();
 
     if (wave == 0) {
         GLOBAL uint64_t *fbase = gp(J.face);
-        const uint32_t own = (uint32_t)v.t * (uint32_t)fstride;
-        const uint32_t baseE = (uint32_t)(v.t + 1) * (uint32_t)fstride + (uint32_t)((TI - 1) * FW + v.jp * NV);
-        const uint32_t baseN = (uint32_t)(v.t + g.nti) * (uint32_t)fstride + (uint32_t)((TJ - 1) * FW + (TJ + v.ip) * NV);
-        const bool edgeE = v.ip == TI - 1 && v.ti < g.nti - 1, edgeN = v.jp == TJ - 1 && v.tj < g.ntj - 1;
-        const Post post = make_post<NV>(g, v, fstride, lane, 0, 0);   // W column, S row
-        Halo<NV> pv[PD];
+        const PollPlan pp = make_polls<NV>(g, v, fstride, FW, true);
+        const Post post = make_post<NV>(g, v, fstride, lane, 0, 0, 0, 0);   // W column, S row
+        Halo<2 * NV> pv[PD];
         bool needE[PD], needN[PD];
-        const GLOBAL uint64_t *pE[PD], *pN[PD];
+        uint32_t oE[PD], oN[PD];
         auto plan = [&](int q, int s2) {   // s2: backward step
-            const bool act = s2 < g.steps && v.active(g.steps - 1 - s2, g.nk);
-            needE[q] = act && edgeE;
-            needN[q] = act && edgeN;
-            pE[q] = fbase + (needE[q] ? baseE + (uint32_t)s2 * FW : own);
-            pN[q] = fbase + (needN[q] ? baseN + (uint32_t)s2 * FW : own);
-            halo_issue(pv[q], pE[q], pN[q]);
+            const bool act = s2 < g.steps && v.inq != 0u && v.kin(g.steps - 1 - s2, g.nk);
+            needE[q] = act && pp.edge_i;
+            needN[q] = act && pp.edge_j;
+            oE[q] = needE[q] ? pp.base_i + (uint32_t)s2 * FW : pp.own;
+            oN[q] = needN[q] ? pp.base_j + (uint32_t)s2 * FW : pp.own;
+            halo_issue(pv[q], fbase + oE[q], fbase + oN[q]);
         };
 #pragma unroll
         for (int q = 0; q < PD; q++) {   // same store pattern as a step (sink only)
             post_record<NV>(fbase, post, g.steps, g.steps, FW, tag, F(0));
             plan(q, q);
         }
-        F dT = F(0);
+        F dT[NQ] = {F(0), F(0), F(0), F(0)};
         bool aborted = false;
+        const int dE = v.ip < LI - 1 ? 1 : 0, dN = v.jp < LJ - 1 ? LI : 0;
         wg_barrier();
         for (int s0 = 0; s0 + 1 < U; s0 += PD) {
 #pragma unroll
             for (int q = 0; q < PD; q++) {
                 const int s = s0 + q;
                 const int slot = s & 1;
-                const F yv = ring[slot][0][lane];
-                const F un = ring[slot][1][lane];
-                const F ue = ring[slot][2][lane];
-                const F ut = ring[slot][3][lane];
-                if (!aborted && !halo_wait(pv[q], needE[q], pE[q], needN[q], pN[q], tag, ctl, a.timeout_ticks))
+                F yv[NQ], un[NQ], ue[NQ], ut[NQ];
+#pragma unroll
+                for (int c = 0; c < NQ; c++) {
+                    yv[c] = ring[slot][0][c][lane];
+                    un[c] = ring[slot][1][c][lane];
+                    ue[c] = ring[slot][2][c][lane];
+                    ut[c] = ring[slot][3][c][lane];
+                }
+                if (!aborted && !halo_wait(pv[q], needE[q], fbase + oE[q], needN[q], fbase + oN[q], tag, ctl,
+                                           a.timeout_ticks))
                     aborted = true;
-                F he, hn;
-                from_words(pv[q].a, he);
-                from_words(pv[q].b, hn);
+                F he0, he1, hn0, hn1;
+                from_words(&pv[q].a[0], he0);
+                from_words(&pv[q].a[NV], he1);
+                from_words(&pv[q].b[0], hn0);
+                from_words(&pv[q].b[NV], hn1);
                 const int pr = (s - 1) & 1;
-                F nE = dbuf[pr][lane + (v.ip < TI - 1 ? 1 : 0)];
-                F nN = dbuf[pr][lane + (v.jp < TJ - 1 ? TI : 0)];
-                keep(nE);
-                keep(nN);
-                const F dE = v.ip < TI - 1 ? nE : (needE[q] ? he : F(0));
-                const F dN = v.jp < TJ - 1 ? nN : (needN[q] ? hn : F(0));
-                const bool act = s < g.steps && v.active(g.steps - 1 - s, g.nk);
-                F t = yv - un * dN;
-                t = t - ue * dE;
-                t = t - ut * dT;
-                const F d = act ? t : F(0);
-                dT = d;
-                dbuf[s & 1][lane] = d;
-                post_record<NV>(fbase, post, s, g.steps, FW, tag, dbuf[s & 1][post.src]);
+                F nE0 = dbuf[pr][0][lane + dE], nE2 = dbuf[pr][2][lane + dE];
+                F nN0 = dbuf[pr][0][lane + dN], nN1 = dbuf[pr][1][lane + dN];
+                keep(nE0);
+                keep(nE2);
+                keep(nN0);
+                keep(nN1);
+                const F zero = F(0);
+                const F E1 = dE ? nE0 : (needE[q] ? he0 : zero);   // E of quadrant (1,0)
+                const F E3 = dE ? nE2 : (needE[q] ? he1 : zero);   // E of quadrant (1,1)
+                const F N2 = dN ? nN0 : (needN[q] ? hn0 : zero);   // N of quadrant (0,1)
+                const F N3 = dN ? nN1 : (needN[q] ? hn1 : zero);   // N of quadrant (1,1)
+                const bool kin = s < g.steps && v.kin(g.steps - 1 - s, g.nk);
+                F d[NQ];
+                {
+                    F t = yv[3] - un[3] * N3;
+                    t = t - ue[3] * E3;
+                    t = t - ut[3] * dT[3];
+                    d[3] = (kin && (v.inq & 8u)) ? t : zero;
+                }
+                {
+                    F t = yv[2] - un[2] * N2;
+                    t = t - ue[2] * d[3];
+                    t = t - ut[2] * dT[2];
+                    d[2] = (kin && (v.inq & 4u)) ? t : zero;
+                }
+                {
+                    F t = yv[1] - un[1] * d[3];
+                    t = t - ue[1] * E1;
+                    t = t - ut[1] * dT[1];
+                    d[1] = (kin && (v.inq & 2u)) ? t : zero;
+                }
+                {
+                    F t = yv[0] - un[0] * d[2];
+                    t = t - ue[0] * d[1];
+                    t = t - ut[0] * dT[0];
+                    d[0] = (kin && (v.inq & 1u)) ? t : zero;
+                }
+#pragma unroll
+                for (int c = 0; c < NQ; c++) {
+                    dT[c] = d[c];
+                    dbuf[s & 1][c][lane] = d[c];
+                }
+                post_record<NV>(fbase, post, s, g.steps, FW, tag, dbuf[s & 1][post.q][post.src]);
                 plan(q, s + PD);
                 if (q == PD - 1 && aborted) s_buf[3] = 1;
                 wg_barrier();
@@ -737,41 +844,42 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
         }
     } else {
         const int lw = wave - 1;
+        const int q = lw % NQ, ph = lw / NQ;
         BwdSrc<F> src;
         src.y = gp((const F *)J.y);
 #pragma unroll
         for (int d = 0; d < 3; d++) src.U[d] = gp((const F *)J.LU) + (4 + d) * g.elems;
         src.x = gp(J.x);
-        src.e0 = (uint32_t)v.base;
+        src.e0 = (uint32_t)v.base + (uint32_t)(q * TT);
         BwdLoad<F> c;
-        if (lw < g.steps) bwd_issue(c, src, g.steps, lw);
+        if (ph < g.steps) bwd_issue(c, src, g.steps, ph);
         auto turn = [&](int u) {
             const int f = u;
             if (f < g.steps) {
                 const int slot = f & 1;
-                ring[slot][0][lane] = c.y;
-                ring[slot][1][lane] = c.u[0];
-                ring[slot][2][lane] = c.u[1];
-                ring[slot][3][lane] = c.u[2];
-                xring[f & 3][lane] = c.x;
+                ring[slot][0][q][lane] = c.y;
+                ring[slot][1][q][lane] = c.u[0];
+                ring[slot][2][q][lane] = c.u[1];
+                ring[slot][3][q][lane] = c.u[2];
+                xring[f & 3][q][lane] = c.x;
             }
             // Issue the next loads before the x store: a load of x behind a
             // store to x would wait for the store to complete.
-            if (u + NL < g.steps) bwd_issue(c, src, g.steps, u + NL);
+            if (u + NP < g.steps) bwd_issue(c, src, g.steps, u + NP);
             const int p = u - 2;
             if (p >= 0 && p < g.steps) {
                 const int sp = g.steps - 1 - p;
-                const F d = dbuf[p & 1][lane];
-                const double xv = xring[p & 3][lane];
-                stg(src.x, src.e0 + (uint32_t)sp * TT, xv + (double)d);   // padding: 0 + 0
+                const F dv = dbuf[p & 1][q][lane];
+                const double xv = xring[p & 3][q][lane];
+                stg(src.x, src.e0 + (uint32_t)sp * PLANE, xv + (double)dv);   // padding: 0 + 0
             }
         };
-        if (lw == 0) turn(0);
+        if (ph == 0) turn(0);
         wg_barrier();
         for (int s0 = 0; s0 + 1 < U; s0 += PD) {
-            for (int q = 0; q < PD; q++) {
-                const int u = s0 + q + 1;
-                if (u % NL == lw) turn(u);
+            for (int k = 0; k < PD; k++) {
+                const int u = s0 + k + 1;
+                if (u % NP == ph) turn(u);
                 wg_barrier();
             }
             if (s_buf[3]) break;
@@ -779,11 +887,11 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
     }
 
     if (job_last(J, s_buf) && wave == 0 && lane == 0) {
-        Ctl *c = J.ctl;
-        if (c->err) c->stop = (c->err & 2u) ? BREAKDOWN : TIMEOUT;
-        c->iter = c->iter + 1u;
-        c->epoch = tag + 1u;
-        c->done = 0u;
+        Ctl *cc = J.ctl;
+        if (cc->err) cc->stop = (cc->err & 2u) ? BREAKDOWN : TIMEOUT;
+        cc->iter = cc->iter + 1u;
+        cc->epoch = tag + 1u;
+        cc->done = 0u;
     }
     launch_done(a);
 }
@@ -797,19 +905,51 @@ __global__ __launch_bounds__(WAVE *(1 + NL)) void k_backward(LaunchArgs a)
 //   Lp = A_P + P1 + P2 + P3 - Lb Ut_B - Lw Ue_W - Ls Un_S,
 //   Un = (A_N - P1) / Lp, Ue = (A_E - P2) / Lp, Ut = (A_T - P3) / Lp.
 // Computed in FP64; stored as F (the mixed form rounds the FP64 factors).
+// It runs once per system, so one wave per tile does everything: it loads
+// the coefficients one step ahead, polls the neighbour records, computes the
+// four cells of each lane in dependency order and writes the factors.
+
+struct U3 {
+    double n, e, t;
+};
+
+struct Fac {
+    double lb, lw, ls, ilp;
+    U3 u;
+};
+
+__device__ __forceinline__ Fac stone(const double *A, const U3 &B, const U3 &W, const U3 &S, double alpha, bool act,
+                                     bool &broke)
+{
+    Fac f{0.0, 0.0, 0.0, 0.0, {0.0, 0.0, 0.0}};
+    if (act) {
+        const double denB = 1.0 + alpha * (B.n + B.e);
+        const double denW = 1.0 + alpha * (W.n + W.t);
+        const double denS = 1.0 + alpha * (S.e + S.t);
+        f.lb = A[5] / denB;
+        f.lw = A[1] / denW;
+        f.ls = A[3] / denS;
+        const double p1 = alpha * (f.lb * B.n + f.lw * W.n);
+        const double p2 = alpha * (f.ls * S.e + f.lb * B.e);
+        const double p3 = alpha * (f.ls * S.t + f.lw * W.t);
+        const double lp = A[0] + p1 + p2 + p3 - f.lb * B.t - f.lw * W.e - f.ls * S.n;
+        if (denB == 0.0 || denW == 0.0 || denS == 0.0 || lp == 0.0 || !isfinite(lp)) broke = true;
+        f.ilp = 1.0 / lp;
+        f.u.n = (A[4] - p1) / lp;
+        f.u.e = (A[2] - p2) / lp;
+        f.u.t = (A[6] - p3) / lp;
+    }
+    return f;
+}
 
 template <typename F>
-__global__ __launch_bounds__(BLOCK) void k_factor(LaunchArgs a)
+__global__ __launch_bounds__(WAVE) void k_factor(LaunchArgs a)
 {
     constexpr int NV = 6;   // 3 FP64 values per face entry
-    __shared__ double ring[2][7][TT];
-    __shared__ double ubuf[2][3][TT];
-    __shared__ double obuf[2][4][TT];
+    __shared__ double ubuf[2][3][NQ][TT];
     __shared__ int s_buf[4];
 
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    if (threadIdx.x == 0) s_buf[3] = 0;
+    const int lane = threadIdx.x;
     const Assign as = take_ticket(a, s_buf);
     const Job J = load_job(a, as.job);
     const uint32_t stop = J.ctl->stop;
@@ -821,153 +961,116 @@ __global__ __launch_bounds__(BLOCK) void k_factor(LaunchArgs a)
     const Geom g = J.g;
     const double alpha = J.alpha;
     const TileView v = make_view(g, as.tile, lane);
-    const int U = padded_intervals(g.steps);
     const int FW = J.fw;
     const long long fstride = (long long)g.steps * FW;
-    GLOBAL uint64_t *face_t = gp(J.face) + (long long)v.t * fstride;
     GLOBAL Ctl *ctl = gp(J.ctl);
+    GLOBAL uint64_t *fbase = gp(J.face);
+    const PollPlan pp = make_polls<NV>(g, v, fstride, FW, false);
 
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        ubuf[0][d][lane] = 0.0;
-        ubuf[1][d][lane] = 0.0;
-    }
-    __syncthreads();
+    for (int x = lane; x < 2 * 3 * NQ * TT; x += WAVE) (&ubuf[0][0][0][0])[x] = 0.0;
 
-    if (wave == 0) {
-        const GLOBAL uint64_t *faceW = v.ti > 0 ? gp(J.face) + (long long)(v.t - 1) * fstride : face_t;
-        const GLOBAL uint64_t *faceS = v.tj > 0 ? gp(J.face) + (long long)(v.t - g.nti) * fstride : face_t;
-        double unB = 0.0, ueB = 0.0, utB = 0.0;
-        bool aborted = false, broke = false;
-        for (int u0 = 0; u0 < U; u0 += LP) {
+    // this lane's three record words: word w = lane + 64 m of entry w / 6
+    int rsrc[3], rq[3], rd[3], rh[3];
 #pragma unroll
-            for (int w = 0; w < LP; w++) {
-                const int u = u0 + w;
-                const int s = u - 1;
-                if (s >= 0 && s < g.steps && !aborted) {
-                    const bool act = v.active(s, g.nk);
-                    const bool nW = act && v.ip == 0 && v.ti > 0;
-                    const bool nS = act && v.jp == 0 && v.tj > 0;
-                    const GLOBAL uint64_t *pW = nW ? faceW + (long long)(s + TI - 1) * FW + v.jp * NV : face_t;
-                    const GLOBAL uint64_t *pS = nS ? faceS + (long long)(s + TJ - 1) * FW + (TJ + v.ip) * NV : face_t;
-                    Halo<NV> h;
-                    halo_issue(h, pW, pS);
-                    if (!halo_wait(h, nW, pW, nS, pS, tag, ctl, a.timeout_ticks)) {
-                        aborted = true;
-                    }
-                    double hw[3], hs[3];
-#pragma unroll
-                    for (int d = 0; d < 3; d++) {
-                        from_words(&h.a[2 * d], hw[d]);
-                        from_words(&h.b[2 * d], hs[d]);
-                        if (!nW) hw[d] = 0.0;
-                        if (!nS) hs[d] = 0.0;
-                    }
-                    const int pr = (s - 1) & 1;
-                    const int lw_ = lane - (v.ip > 0 ? 1 : 0);
-                    const int ls_ = lane - (v.jp > 0 ? TI : 0);
-                    const double unW = v.ip > 0 ? ubuf[pr][0][lw_] : hw[0];
-                    const double ueW = v.ip > 0 ? ubuf[pr][1][lw_] : hw[1];
-                    const double utW = v.ip > 0 ? ubuf[pr][2][lw_] : hw[2];
-                    const double unS = v.jp > 0 ? ubuf[pr][0][ls_] : hs[0];
-                    const double ueS = v.jp > 0 ? ubuf[pr][1][ls_] : hs[1];
-                    const double utS = v.jp > 0 ? ubuf[pr][2][ls_] : hs[2];
-                    const int slot = s & 1;
-                    const double aP = ring[slot][0][lane], aW = ring[slot][1][lane], aE = ring[slot][2][lane];
-                    const double aS = ring[slot][3][lane], aN = ring[slot][4][lane], aB = ring[slot][5][lane];
-                    const double aT = ring[slot][6][lane];
-                    double lb = 0, lw = 0, ls = 0, ilp = 0, un = 0, ue = 0, ut = 0;
-                    if (act) {
-                        const double denB = 1.0 + alpha * (unB + ueB);
-                        const double denW = 1.0 + alpha * (unW + utW);
-                        const double denS = 1.0 + alpha * (ueS + utS);
-                        lb = aB / denB;
-                        lw = aW / denW;
-                        ls = aS / denS;
-                        const double p1 = alpha * (lb * unB + lw * unW);
-                        const double p2 = alpha * (ls * ueS + lb * ueB);
-                        const double p3 = alpha * (ls * utS + lw * utW);
-                        const double lp = aP + p1 + p2 + p3 - lb * utB - lw * ueW - ls * unS;
-                        if (denB == 0.0 || denW == 0.0 || denS == 0.0 || lp == 0.0 || !isfinite(lp)) broke = true;
-                        ilp = 1.0 / lp;
-                        un = (aN - p1) / lp;
-                        ue = (aE - p2) / lp;
-                        ut = (aT - p3) / lp;
-                    }
-                    unB = un;
-                    ueB = ue;
-                    utB = ut;
-                    ubuf[s & 1][0][lane] = un;
-                    ubuf[s & 1][1][lane] = ue;
-                    ubuf[s & 1][2][lane] = ut;
-                    obuf[s & 1][0][lane] = lb;
-                    obuf[s & 1][1][lane] = lw;
-                    obuf[s & 1][2][lane] = ls;
-                    obuf[s & 1][3][lane] = ilp;
-                }
-                if (w == LP - 1 && aborted) s_buf[3] = 1;   // read by both waves after this barrier
-                wg_barrier();
-            }
-            if (s_buf[3]) break;
-        }
-        if (__any(broke) && lane == 0)
-            __hip_atomic_fetch_or(&ctl->err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        double pipe[LP][7];
-        auto issue = [&](double *c, int f) {
-            const bool act = f < g.steps && v.active(f, g.nk);
-            const long long e = v.base + (long long)f * TT;
-#pragma unroll
-            for (int d = 0; d < 7; d++) c[d] = act ? gp(J.A)[d * g.elems + e] : 0.0;
-        };
-#pragma unroll
-        for (int q = 0; q < LP; q++) issue(pipe[q], q);
-        GLOBAL F *LU = gp((F *)J.LU);
-        for (int u0 = 0; u0 < U; u0 += LP) {
-#pragma unroll
-            for (int w = 0; w < LP; w++) {
-                const int u = u0 + w;
-                const int p = u - 2;
-                if (p >= 0 && p < g.steps) {
-                    const long long e = v.base + (long long)p * TT;
-                    const int sl = p & 1;
-                    if (v.active(p, g.nk)) {
-#pragma unroll
-                        for (int d = 0; d < 4; d++) LU[d * g.elems + e] = (F)obuf[sl][d][lane];
-#pragma unroll
-                        for (int d = 0; d < 3; d++) LU[(4 + d) * g.elems + e] = (F)ubuf[sl][d][lane];
-                    }
-                    uint32_t wd[6];
-#pragma unroll
-                    for (int d = 0; d < 3; d++) to_words(ubuf[sl][d][lane], &wd[2 * d]);
-                    if (v.ip == TI - 1) {
-#pragma unroll
-                        for (int q = 0; q < 6; q++) ll_store(face_t + (long long)p * FW + v.jp * NV + q, tag, wd[q]);
-                    }
-                    if (v.jp == TJ - 1) {
-#pragma unroll
-                        for (int q = 0; q < 6; q++)
-                            ll_store(face_t + (long long)p * FW + (TJ + v.ip) * NV + q, tag, wd[q]);
-                    }
-                }
-                const int f = u;
-                if (f < g.steps) {
-                    const int slot = f & 1;
-#pragma unroll
-                    for (int d = 0; d < 7; d++) ring[slot][d][lane] = pipe[w][d];
-                    issue(pipe[w], f + LP);
-                }
-                wg_barrier();
-            }
-            if (s_buf[3]) break;
-        }
+    for (int m = 0; m < 3; m++) {
+        const int w = lane + WAVE * m;
+        entry_owner(w / NV, LI - 1, 1, LJ - 1, 1, rsrc[m], rq[m]);
+        rd[m] = (w % NV) / 2;
+        rh[m] = w & 1;
     }
 
-    if (job_last(J, s_buf) && wave == 0 && lane == 0) {
-        Ctl *c = J.ctl;
-        if (c->err) c->stop = (c->err & 2u) ? BREAKDOWN : TIMEOUT;
-        c->epoch = tag + 1u;
-        c->done = 0u;
+    const uint32_t base = (uint32_t)v.base;
+    const GLOBAL double *Ag[7];
+    GLOBAL F *LU[7];
+#pragma unroll
+    for (int d = 0; d < 7; d++) {
+        Ag[d] = gp(J.A) + d * g.elems;
+        LU[d] = gp((F *)J.LU) + d * g.elems;
+    }
+    auto load_step = [&](double (*A)[7], int s) {   // plane `steps` is the zero margin
+        const uint32_t e = base + (uint32_t)min(s, g.steps) * PLANE;
+#pragma unroll
+        for (int q = 0; q < NQ; q++)
+#pragma unroll
+            for (int d = 0; d < 7; d++) A[q][d] = ldg(Ag[d], e + (uint32_t)(q * TT));
+    };
+    double Ac[NQ][7], An[NQ][7];
+    load_step(Ac, 0);
+    U3 uB[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; q++) uB[q] = U3{0.0, 0.0, 0.0};
+    bool aborted = false, broke = false;
+    const int dW = v.ip > 0 ? 1 : 0, dS = v.jp > 0 ? LI : 0;
+    for (int s = 0; s < g.steps && !aborted; s++) {
+        load_step(An, s + 1);
+        const bool act = v.inq != 0u && v.kin(s, g.nk);
+        const bool nW = act && pp.edge_i, nS = act && pp.edge_j;
+        const GLOBAL uint64_t *pW = fbase + (nW ? pp.base_i + (uint32_t)s * FW : pp.own);
+        const GLOBAL uint64_t *pS = fbase + (nS ? pp.base_j + (uint32_t)s * FW : pp.own);
+        Halo<2 * NV> h;
+        halo_issue(h, pW, pS);
+        if (!halo_wait(h, nW, pW, nS, pS, tag, ctl, a.timeout_ticks)) aborted = true;
+        U3 hW0, hW1, hS0, hS1;
+        from_words(&h.a[0], hW0.n);
+        from_words(&h.a[2], hW0.e);
+        from_words(&h.a[4], hW0.t);
+        from_words(&h.a[6], hW1.n);
+        from_words(&h.a[8], hW1.e);
+        from_words(&h.a[10], hW1.t);
+        from_words(&h.b[0], hS0.n);
+        from_words(&h.b[2], hS0.e);
+        from_words(&h.b[4], hS0.t);
+        from_words(&h.b[6], hS1.n);
+        from_words(&h.b[8], hS1.e);
+        from_words(&h.b[10], hS1.t);
+        const U3 z{0.0, 0.0, 0.0};
+        const int pr = (s - 1) & 1;
+        auto nb = [&](int q, int l) { return U3{ubuf[pr][0][q][l], ubuf[pr][1][q][l], ubuf[pr][2][q][l]}; };
+        const U3 W0 = dW ? nb(1, lane - 1) : (nW ? hW0 : z);    // W of quadrant (0,0)
+        const U3 W2 = dW ? nb(3, lane - 1) : (nW ? hW1 : z);    // W of quadrant (0,1)
+        const U3 S0 = dS ? nb(2, lane - LI) : (nS ? hS0 : z);   // S of quadrant (0,0)
+        const U3 S1 = dS ? nb(3, lane - LI) : (nS ? hS1 : z);   // S of quadrant (1,0)
+        const bool kin = v.kin(s, g.nk);
+        Fac f[NQ];
+        f[0] = stone(Ac[0], uB[0], W0, S0, alpha, kin && (v.inq & 1u), broke);
+        f[1] = stone(Ac[1], uB[1], f[0].u, S1, alpha, kin && (v.inq & 2u), broke);
+        f[2] = stone(Ac[2], uB[2], W2, f[0].u, alpha, kin && (v.inq & 4u), broke);
+        f[3] = stone(Ac[3], uB[3], f[2].u, f[1].u, alpha, kin && (v.inq & 8u), broke);
+        const uint32_t e = base + (uint32_t)s * PLANE;
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            uB[q] = f[q].u;
+            ubuf[s & 1][0][q][lane] = f[q].u.n;
+            ubuf[s & 1][1][q][lane] = f[q].u.e;
+            ubuf[s & 1][2][q][lane] = f[q].u.t;
+            const uint32_t eq = e + (uint32_t)(q * TT);
+            stg(LU[0], eq, (F)f[q].lb);
+            stg(LU[1], eq, (F)f[q].lw);
+            stg(LU[2], eq, (F)f[q].ls);
+            stg(LU[3], eq, (F)f[q].ilp);
+            stg(LU[4], eq, (F)f[q].u.n);
+            stg(LU[5], eq, (F)f[q].u.e);
+            stg(LU[6], eq, (F)f[q].u.t);
+        }
+        const uint32_t rec = (uint32_t)v.t * (uint32_t)fstride + (uint32_t)s * FW;
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+            uint32_t wd[2];
+            to_words(ubuf[s & 1][rd[m]][rq[m]][rsrc[m]], wd);
+            ll_store(fbase + rec + (uint32_t)(lane + WAVE * m), tag, rh[m] ? wd[1] : wd[0]);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; q++)
+#pragma unroll
+            for (int d = 0; d < 7; d++) Ac[q][d] = An[q][d];
+    }
+    if (__any(broke) && lane == 0) __hip_atomic_fetch_or(&ctl->err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+    if (job_last(J, s_buf) && lane == 0) {
+        Ctl *cc = J.ctl;
+        if (cc->err) cc->stop = (cc->err & 2u) ? BREAKDOWN : TIMEOUT;
+        cc->epoch = tag + 1u;
+        cc->done = 0u;
     }
     launch_done(a);
 }
@@ -985,20 +1088,22 @@ __device__ __forceinline__ bool decode_sheared(const Geom &g, long long e, int &
 {
     const int t = (int)(e / g.tile_elems);
     const long long rem = e - (long long)t * g.tile_elems;
-    const int pl = (int)(rem / TT) - 1;
-    const int ln = (int)(rem % TT);
-    const int ip = ln % TI, jp = ln / TI;
-    i = (t % g.nti) * TI + ip;
-    j = (t / g.nti) * TJ + jp;
+    const int pl = (int)(rem / PLANE) - 1;
+    const int w = (int)(rem % PLANE);
+    const int q = w / TT, ln = w % TT;
+    const int ip = ln % LI, jp = ln / LI;
+    i = (t % g.nti) * TI + 2 * ip + (q & 1);
+    j = (t / g.nti) * TJ + 2 * jp + (q >> 1);
     k = pl - ip - jp;
     return pl >= 0 && pl < g.steps && i < g.ni && j < g.nj && k >= 0 && k < g.nk;
 }
 
 __device__ __forceinline__ long long sheared_index(const Geom &g, int i, int j, int k)
 {
-    const int ti = i / TI, tj = j / TJ, ip = i % TI, jp = j % TJ;
+    const int ti = i / TI, tj = j / TJ, ii = i % TI, jj = j % TJ;
+    const int ip = ii >> 1, jp = jj >> 1, q = (jj & 1) * 2 + (ii & 1);
     const int t = tj * g.nti + ti;
-    return (long long)t * g.tile_elems + (long long)(k + ip + jp + 1) * TT + jp * TI + ip;
+    return (long long)t * g.tile_elems + (long long)(k + ip + jp + 1) * PLANE + q * TT + jp * LI + ip;
 }
 
 __global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, double *dst, long long dst_stride, int mask)
@@ -1116,37 +1221,36 @@ hipError_t launch_export_factors(const Geom &g, const void *LU, int fp32, double
 hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s)
 {
     if (fp32)
-        hipLaunchKernelGGL(k_factor<float>, dim3(a.total), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_factor<float>, dim3(a.total), dim3(WAVE), 0, s, a);
     else
-        hipLaunchKernelGGL(k_factor<double>, dim3(a.total), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_factor<double>, dim3(a.total), dim3(WAVE), 0, s, a);
     return hipGetLastError();
 }
 
-template <int NL, int PD>
-static hipError_t launch_sweep_nl(const LaunchArgs &a, int fp32, int backward, hipStream_t s)
+template <int NP>
+static hipError_t launch_sweep_np(const LaunchArgs &a, int fp32, int backward, hipStream_t s)
 {
-    const dim3 block(WAVE * (1 + NL));
+    const dim3 block(WAVE * (1 + NQ * NP));
     if (backward) {
         if (fp32)
-            hipLaunchKernelGGL((k_backward<float, NL, PD>), dim3(a.total), block, 0, s, a);
+            hipLaunchKernelGGL((k_backward<float, NP>), dim3(a.total), block, 0, s, a);
         else
-            hipLaunchKernelGGL((k_backward<double, NL, PD>), dim3(a.total), block, 0, s, a);
+            hipLaunchKernelGGL((k_backward<double, NP>), dim3(a.total), block, 0, s, a);
     } else {
         if (fp32)
-            hipLaunchKernelGGL((k_forward<float, NL, PD>), dim3(a.total), block, 0, s, a);
+            hipLaunchKernelGGL((k_forward<float, NP>), dim3(a.total), block, 0, s, a);
         else
-            hipLaunchKernelGGL((k_forward<double, NL, PD>), dim3(a.total), block, 0, s, a);
+            hipLaunchKernelGGL((k_forward<double, NP>), dim3(a.total), block, 0, s, a);
     }
     return hipGetLastError();
 }
 
 static hipError_t launch_sweep(const LaunchArgs &a, int fp32, int backward, const SweepPlan &p, hipStream_t s)
 {
-    switch (p.loaders) {
-    case 2: return launch_sweep_nl<2, 4>(a, fp32, backward, s);
-    case 4: return launch_sweep_nl<4, 4>(a, fp32, backward, s);
-    case 6: return launch_sweep_nl<6, 4>(a, fp32, backward, s);
-    case 8: return launch_sweep_nl<8, 4>(a, fp32, backward, s);
+    switch (p.phases) {
+    case 1: return launch_sweep_np<1>(a, fp32, backward, s);
+    case 2: return launch_sweep_np<2>(a, fp32, backward, s);
+    case 3: return launch_sweep_np<3>(a, fp32, backward, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -524,9 +524,9 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)8 << 30;
         s->cfg.hbm_budget_bytes = fr / 4 * 3;
     }
-    if (const char *e = getenv("SIP_SWEEP_LOADERS")) {
+    if (const char *e = getenv("SIP_SWEEP_PHASES")) {
         const int nl = atoi(e);
-        if (nl == 2 || nl == 4 || nl == 6 || nl == 8) s->plan.loaders = nl;
+        if (nl >= 1 && nl <= sipk::MAX_PHASES) s->plan.phases = nl;
     }
     s->timeout_ticks = timeout_ticks_for(s->device, 2.0);
     s->t0 = std::chrono::steady_clock::now();

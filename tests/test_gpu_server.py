@@ -104,16 +104,19 @@ def test_resident_factors_reused(sip):
 
 def test_budget_forces_eviction_and_waiting(sip):
     data = [block(d, k, 200 + q) for q, (d, k) in enumerate(BLOCKS[:4])]
-    sizes = []
-    for A, _ in data:
-        nk, nj, ni = A.shape[1:]
-        sizes.append(ni * nj * nk)
-    # room for roughly one block at a time
-    budget = int(max(sizes) * 400)
-    srv = sip.Server(hbm_budget_bytes=budget, max_slots=16, epoch_iters=4)
     At = [dev(A) for A, _ in data]
     bt = [dev(b) for _, b in data]
     xt = [torch.zeros_like(b) for b in bt]
+    # the largest single-request footprint, measured by the server itself
+    probe = sip.Server(max_slots=16, epoch_iters=4)
+    for q in range(len(data)):
+        probe.poll(probe.submit(900 + q, At[q], bt[q], torch.zeros_like(bt[q]), retain=True))
+        probe.release(900 + q)
+    one = probe.stats()["peak_bytes"]
+    probe.close()
+    # room for roughly one block at a time
+    budget = int(one * 1.5)
+    srv = sip.Server(hbm_budget_bytes=budget, max_slots=16, epoch_iters=4)
     tickets = [srv.submit(100 + q, At[q], bt[q], xt[q], retain=True) for q in range(len(data))]
     res = [srv.poll(t) for t in tickets]
     st = srv.stats()
