@@ -75,7 +75,7 @@ __device__ __forceinline__ Job load_job(const LaunchArgs &a, int job)
 }
 
 constexpr int WAVE = 64;
-constexpr int PD = 4;   // face-record prefetch distance of the recurrence wave (steps)
+constexpr int PD = 2;   // face-record prefetch distance of the recurrence wave (steps)
 
 // ---------------------------------------------------------------- helpers
 
@@ -354,20 +354,22 @@ __device__ __forceinline__ PollPlan make_polls(const Geom &g, const TileView &v,
 
 // ------------------------------------------------------ sweeps
 // Workgroup = one recurrence wave (wave 0) + NL = NQ * NP loader waves.
-// Loader wave l works quadrant q = l % NQ of the steps f with f % NP = l / NQ:
-// at its turn (interval f) it consumes the loads it issued NP intervals
-// earlier, stages the operands of step f in the LDS ring and issues the loads
-// of step f + NP.  Its own vector-memory wait at a turn therefore only covers
-// loads that had NP intervals to arrive.  Interval u: loaders fill step u,
-// the recurrence wave processes step u - 1 and publishes its face record at
-// once; one workgroup barrier ends every interval.  Results of step u - 2
-// (forward y, backward x += d) are written back by step u's loaders.
+// Loader wave l works quadrant q = l % NQ of the steps f with f % NP = l / NQ.
+// Its turn for step f comes in interval f - 1: it consumes the loads it
+// issued NP turns earlier, stages the operands of step f in the LDS ring and
+// issues the loads of step f + NP, so its own vector-memory wait only covers
+// loads that had NP intervals to arrive.  In interval s + 1 the recurrence
+// wave processes step s with operands already in registers, publishes its
+// face record at once, and then reads the operands of step s + 1 (staged in
+// interval s) before the barrier, so no LDS round trip follows a barrier.
+// One workgroup barrier ends every interval.  Results of step f - 3 (forward
+// y, backward x += d) are written back by step f's loaders.
 
-__device__ __forceinline__ int sweep_intervals(int steps, int pd)
+__device__ __forceinline__ int sweep_steps(int steps, int pd)
 {
-    // interval 0 (fill only) plus the recurrence steps 0..steps (step `steps`
-    // only lets the last write-back happen), padded to the poll unroll
-    return 1 + (steps + 1 + pd - 1) / pd * pd;
+    // recurrence steps 0..steps (step `steps` only lets the last write-back
+    // happen), padded to the poll unroll
+    return (steps + 1 + pd - 1) / pd * pd;
 }
 
 // Forward: residual r = b - A x (FP64, fused), forward substitution
@@ -464,7 +466,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
     const uint32_t iter = J.ctl->iter;
     const Geom g = J.g;
     const TileView v = make_view(g, as.tile, lane);
-    const int U = sweep_intervals(g.steps, PD);
+    const int U = sweep_steps(g.steps, PD);
     const int FW = J.fw;
     const long long fstride = (long long)g.steps * FW;
     GLOBAL Ctl *ctl = gp(J.ctl);
@@ -506,21 +508,34 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
         F yB[NQ] = {F(0), F(0), F(0), F(0)};
         bool aborted = false;
         const int dW = v.ip > 0 ? 1 : 0, dS = v.jp > 0 ? LI : 0;
-        wg_barrier();   // interval 0: the loaders stage step 0
-        for (int s0 = 0; s0 + 1 < U; s0 += PD) {
+        F r[NQ], lb[NQ], lw[NQ], ls[NQ], il[NQ];
+        F nW1, nW3, nS2, nS3;
+        auto prefetch = [&](int s) {   // operands of step s: ring slot, in-tile neighbours of step s - 1
+            const int slot = s & 1, pr = (s - 1) & 1;
+#pragma unroll
+            for (int c = 0; c < NQ; c++) {
+                r[c] = ring[slot][0][c][lane];
+                lb[c] = ring[slot][1][c][lane];
+                lw[c] = ring[slot][2][c][lane];
+                ls[c] = ring[slot][3][c][lane];
+                il[c] = ring[slot][4][c][lane];
+            }
+            nW1 = ybuf[pr][1][lane - dW];
+            nW3 = ybuf[pr][3][lane - dW];
+            nS2 = ybuf[pr][2][lane - dS];
+            nS3 = ybuf[pr][3][lane - dS];
+            keep(nW1);
+            keep(nW3);
+            keep(nS2);
+            keep(nS3);
+        };
+        wg_barrier();   // interval -1: the loaders stage step 0
+        prefetch(0);
+        wg_barrier();   // interval 0: the loaders stage step 1
+        for (int s0 = 0; s0 < U; s0 += PD) {
 #pragma unroll
             for (int q = 0; q < PD; q++) {
                 const int s = s0 + q;
-                const int slot = s & 1;
-                F r[NQ], lb[NQ], lw[NQ], ls[NQ], il[NQ];
-#pragma unroll
-                for (int c = 0; c < NQ; c++) {
-                    r[c] = ring[slot][0][c][lane];
-                    lb[c] = ring[slot][1][c][lane];
-                    lw[c] = ring[slot][2][c][lane];
-                    ls[c] = ring[slot][3][c][lane];
-                    il[c] = ring[slot][4][c][lane];
-                }
                 if (!aborted && !halo_wait(pv[q], needW[q], fbase + oW[q], needS[q], fbase + oS[q], tag, ctl,
                                            a.timeout_ticks))
                     aborted = true;
@@ -529,13 +544,6 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                 from_words(&pv[q].a[NV], hw1);
                 from_words(&pv[q].b[0], hs0);
                 from_words(&pv[q].b[NV], hs1);
-                const int pr = (s - 1) & 1;
-                F nW1 = ybuf[pr][1][lane - dW], nW3 = ybuf[pr][3][lane - dW];
-                F nS2 = ybuf[pr][2][lane - dS], nS3 = ybuf[pr][3][lane - dS];
-                keep(nW1);
-                keep(nW3);
-                keep(nS2);
-                keep(nS3);
                 const F zero = F(0);
                 const F W0 = dW ? nW1 : (needW[q] ? hw0 : zero);   // W of quadrant (0,0)
                 const F W2 = dW ? nW3 : (needW[q] ? hw1 : zero);   // W of quadrant (0,1)
@@ -574,6 +582,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                 }
                 // publish at once: the neighbour tiles' next steps wait on this record
                 post_record<NV>(fbase, post, s, g.steps, FW, tag, ybuf[s & 1][post.q][post.src]);
+                prefetch(s + 1);
                 plan(q, s + PD);
                 if (q == PD - 1 && aborted) s_buf[3] = 1;   // read by every wave after this barrier
                 wg_barrier();
@@ -597,8 +606,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
         const int dS = qb ? 0 : (v.jp > 0 ? LI : 0), dN = qb ? (v.jp < LJ - 1 ? LI : 0) : 0;
         const bool inW = qa || v.ip > 0, inE = !qa || v.ip < LI - 1;
         const bool inS = qb || v.jp > 0, inN = !qb || v.jp < LJ - 1;
-        auto turn = [&](int u) {
-            const int f = u;
+        auto turn = [&](int f) {
             if (f < g.steps) {
                 // planes f-1..f+1 were staged by earlier turns
                 xring[(f + 2) & 3][q][lane] = c.x2;
@@ -621,17 +629,19 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                 ring[slot][3][q][lane] = c.l[2];
                 ring[slot][4][q][lane] = c.l[3];
             }
-            if (u + NP < g.steps) fwd_issue(c, src, v, q, u + NP, g.steps, g.nk);
-            const int p = u - 2;
+            if (f + NP < g.steps) fwd_issue(c, src, v, q, f + NP, g.steps, g.nk);
+            const int p = f - 3;
             if (p >= 0 && p < g.steps)   // inactive slots rewrite their zero padding
                 stg(yout, src.e0 + (uint32_t)p * PLANE, ybuf[p & 1][q][lane]);
         };
         if (ph == 0) turn(0);
-        wg_barrier();
-        for (int s0 = 0; s0 + 1 < U; s0 += PD) {
+        wg_barrier();   // interval -1
+        if (1 % NP == ph) turn(1);
+        wg_barrier();   // interval 0
+        for (int s0 = 0; s0 < U; s0 += PD) {
             for (int k = 0; k < PD; k++) {
-                const int u = s0 + k + 1;
-                if (u % NP == ph) turn(u);
+                const int f = s0 + k + 2;
+                if (f % NP == ph) turn(f);
                 wg_barrier();
             }
             if (s_buf[3]) break;
@@ -739,7 +749,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
     const uint32_t tag = J.ctl->epoch;
     const Geom g = J.g;
     const TileView v = make_view(g, as.tile, lane);
-    const int U = sweep_intervals(g.steps, PD);
+    const int U = sweep_steps(g.steps, PD);
     const int FW = J.fw;
     const long long fstride = (long long)g.steps * FW;
     GLOBAL Ctl *ctl = gp(J.ctl);
@@ -770,20 +780,33 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
         F dT[NQ] = {F(0), F(0), F(0), F(0)};
         bool aborted = false;
         const int dE = v.ip < LI - 1 ? 1 : 0, dN = v.jp < LJ - 1 ? LI : 0;
-        wg_barrier();
-        for (int s0 = 0; s0 + 1 < U; s0 += PD) {
+        F yv[NQ], un[NQ], ue[NQ], ut[NQ];
+        F nE0, nE2, nN0, nN1;
+        auto prefetch = [&](int s) {   // operands of step s: ring slot, in-tile neighbours of step s - 1
+            const int slot = s & 1, pr = (s - 1) & 1;
+#pragma unroll
+            for (int c = 0; c < NQ; c++) {
+                yv[c] = ring[slot][0][c][lane];
+                un[c] = ring[slot][1][c][lane];
+                ue[c] = ring[slot][2][c][lane];
+                ut[c] = ring[slot][3][c][lane];
+            }
+            nE0 = dbuf[pr][0][lane + dE];
+            nE2 = dbuf[pr][2][lane + dE];
+            nN0 = dbuf[pr][0][lane + dN];
+            nN1 = dbuf[pr][1][lane + dN];
+            keep(nE0);
+            keep(nE2);
+            keep(nN0);
+            keep(nN1);
+        };
+        wg_barrier();   // interval -1
+        prefetch(0);
+        wg_barrier();   // interval 0
+        for (int s0 = 0; s0 < U; s0 += PD) {
 #pragma unroll
             for (int q = 0; q < PD; q++) {
                 const int s = s0 + q;
-                const int slot = s & 1;
-                F yv[NQ], un[NQ], ue[NQ], ut[NQ];
-#pragma unroll
-                for (int c = 0; c < NQ; c++) {
-                    yv[c] = ring[slot][0][c][lane];
-                    un[c] = ring[slot][1][c][lane];
-                    ue[c] = ring[slot][2][c][lane];
-                    ut[c] = ring[slot][3][c][lane];
-                }
                 if (!aborted && !halo_wait(pv[q], needE[q], fbase + oE[q], needN[q], fbase + oN[q], tag, ctl,
                                            a.timeout_ticks))
                     aborted = true;
@@ -792,13 +815,6 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
                 from_words(&pv[q].a[NV], he1);
                 from_words(&pv[q].b[0], hn0);
                 from_words(&pv[q].b[NV], hn1);
-                const int pr = (s - 1) & 1;
-                F nE0 = dbuf[pr][0][lane + dE], nE2 = dbuf[pr][2][lane + dE];
-                F nN0 = dbuf[pr][0][lane + dN], nN1 = dbuf[pr][1][lane + dN];
-                keep(nE0);
-                keep(nE2);
-                keep(nN0);
-                keep(nN1);
                 const F zero = F(0);
                 const F E1 = dE ? nE0 : (needE[q] ? he0 : zero);   // E of quadrant (1,0)
                 const F E3 = dE ? nE2 : (needE[q] ? he1 : zero);   // E of quadrant (1,1)
@@ -836,6 +852,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
                     dbuf[s & 1][c][lane] = d[c];
                 }
                 post_record<NV>(fbase, post, s, g.steps, FW, tag, dbuf[s & 1][post.q][post.src]);
+                prefetch(s + 1);
                 plan(q, s + PD);
                 if (q == PD - 1 && aborted) s_buf[3] = 1;
                 wg_barrier();
@@ -853,8 +870,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
         src.e0 = (uint32_t)v.base + (uint32_t)(q * TT);
         BwdLoad<F> c;
         if (ph < g.steps) bwd_issue(c, src, g.steps, ph);
-        auto turn = [&](int u) {
-            const int f = u;
+        auto turn = [&](int f) {
             if (f < g.steps) {
                 const int slot = f & 1;
                 ring[slot][0][q][lane] = c.y;
@@ -865,8 +881,8 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
             }
             // Issue the next loads before the x store: a load of x behind a
             // store to x would wait for the store to complete.
-            if (u + NP < g.steps) bwd_issue(c, src, g.steps, u + NP);
-            const int p = u - 2;
+            if (f + NP < g.steps) bwd_issue(c, src, g.steps, f + NP);
+            const int p = f - 3;
             if (p >= 0 && p < g.steps) {
                 const int sp = g.steps - 1 - p;
                 const F dv = dbuf[p & 1][q][lane];
@@ -875,11 +891,13 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
             }
         };
         if (ph == 0) turn(0);
-        wg_barrier();
-        for (int s0 = 0; s0 + 1 < U; s0 += PD) {
+        wg_barrier();   // interval -1
+        if (1 % NP == ph) turn(1);
+        wg_barrier();   // interval 0
+        for (int s0 = 0; s0 < U; s0 += PD) {
             for (int k = 0; k < PD; k++) {
-                const int u = s0 + k + 1;
-                if (u % NP == ph) turn(u);
+                const int f = s0 + k + 2;
+                if (f % NP == ph) turn(f);
                 wg_barrier();
             }
             if (s_buf[3]) break;
