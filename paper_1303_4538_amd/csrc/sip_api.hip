@@ -256,9 +256,9 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     hipStream_t s = (hipStream_t)stream;
     sip_system_s *h = new sip_system_s();
     h->g = make_geom(p->ni, p->nj, p->nk);
-    if (h->g.elems >= (1ll << 29)) {   // kernels address every array with 32-bit byte offsets
+    if (h->g.elems >= MAX_ELEMS) {   // kernels address every array with 32-bit byte offsets
         delete h;
-        return set_error(SIP_EINVAL, "block too large: more than 2^29 cells in the sheared layout");
+        return set_error(SIP_EINVAL, "block too large: more than 2^28 cells in the sheared layout");
     }
     h->fp32 = p->precision == SIP_MIXED;
     h->precision = p->precision;

@@ -32,6 +32,29 @@ constexpr int TI = 2 * LI;         // tile extent in cells (i)
 constexpr int TJ = 2 * LJ;         // tile extent in cells (j)
 constexpr int PLANE = NQ * TT;     // elements per local step of a tile
 
+// Coefficient storage, 7 * elems doubles (pairs of 16 bytes, so the forward
+// sweep loads six coefficients with three 16-byte loads):
+//     (A_P, A_W) interleaved in [0, 2 elems), (A_E, A_S) in [2 elems, 4 elems),
+//     (A_N, A_B) in [4 elems, 6 elems), A_T in [6 elems, 7 elems).
+// Factor storage, 7 * elems of F: Lb, Lw, Ls, 1/Lp of a cell in 16-byte
+// groups (FP32: one group of four; FP64: (Lb, Lw) in [0, 2 elems) and
+// (Ls, 1/Lp) in [2 elems, 4 elems)), then Un, Ue, Ut as plain arrays.
+// Kernels address arrays with 32-bit byte offsets of 16-byte elements, so
+// elems stays below MAX_ELEMS.
+constexpr long long MAX_ELEMS = 1ll << 28;
+
+__host__ __device__ inline long long coef_index(int a, long long e, long long elems)
+{
+    return a < 6 ? (long long)(a >> 1) * 2 * elems + 2 * e + (a & 1) : 6 * elems + e;
+}
+
+template <typename F>
+__host__ __device__ inline long long factor_index(int d, long long e, long long elems)
+{
+    constexpr int W = 16 / (int)sizeof(F);   // factors per 16-byte group
+    return d < 4 ? (long long)(d / W) * W * elems + W * e + d % W : d * elems + e;
+}
+
 enum Stop : uint32_t {
     RUN = 0,
     CONVERGED = 1,
@@ -114,8 +137,9 @@ Geom make_geom(int ni, int nj, int nk);
 
 // Kernel launchers (sip_kernels.hip).  All are asynchronous on `s`.
 hipError_t launch_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int reset_epoch, hipStream_t s);
+// coefficients = 1: the 7 arrays are A (masked at the block boundary, stored interleaved).
 hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, double *dst,
-                             long long dst_stride, int mask_couplings, hipStream_t s);
+                             long long dst_stride, int coefficients, hipStream_t s);
 hipError_t launch_from_sheared_f64(const Geom &g, const double *src, double *dst, const Ctl *zero_if_zero_rhs,
                                    hipStream_t s);
 hipError_t launch_export_factors(const Geom &g, const void *LU, int fp32, double *const *dst, hipStream_t s);

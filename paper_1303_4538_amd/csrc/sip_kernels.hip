@@ -268,6 +268,21 @@ __device__ __forceinline__ void stg(GLOBAL T *base, uint32_t idx, T v)
     *(GLOBAL T *)((GLOBAL char *)base + (size_t)(idx * (uint32_t)sizeof(T))) = v;
 }
 
+// 16-byte groups of the coefficient and factor storage (sip_internal.h).
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+template <typename F> struct Grp;
+template <> struct Grp<float> {
+    typedef flt4 V;
+    static constexpr int W = 4, N = 1;   // factors per group, groups per cell
+};
+template <> struct Grp<double> {
+    typedef dbl2 V;
+    static constexpr int W = 2, N = 2;
+};
+__device__ __forceinline__ float lane_of(const flt4 &v, int k) { return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w; }
+__device__ __forceinline__ double lane_of(const dbl2 &v, int k) { return k == 0 ? v.x : v.y; }
+
 // ------------------------------------------------------ face records
 // Entry e < TJ: cell row j = e of the tile column facing the i neighbour
 // (lane column ci, quadrant column ca); entry TJ + i: cell column i of the
@@ -389,9 +404,9 @@ struct FwdLoad {
 // Uniform base pointers and per-lane index deltas of a forward loader.
 template <typename F>
 struct FwdSrc {
-    const GLOBAL double *A[7];
-    const GLOBAL double *b, *x;
-    const GLOBAL F *L[4];
+    const GLOBAL dbl2 *AP[3];   // (A_P, A_W), (A_E, A_S), (A_N, A_B)
+    const GLOBAL double *AT, *b, *x;
+    const GLOBAL typename Grp<F>::V *L[Grp<F>::N];   // Lb, Lw, Ls, 1/Lp
     uint32_t e0;          // sheared index of (plane 0, this quadrant, this lane)
     int32_t hx, hy;       // index deltas of the x halo this slot reads across a tile edge (0: none)
 };
@@ -402,11 +417,13 @@ __device__ __forceinline__ FwdSrc<F> fwd_src(const Job &J, const TileView &v, in
     const Geom &g = J.g;
     FwdSrc<F> s;
 #pragma unroll
-    for (int d = 0; d < 7; d++) s.A[d] = gp(J.A) + d * g.elems;
+    for (int p = 0; p < 3; p++) s.AP[p] = (const GLOBAL dbl2 *)(gp(J.A) + 2 * p * g.elems);
+    s.AT = gp(J.A) + 6 * g.elems;
     s.b = gp(J.b);
     s.x = gp((const double *)J.x);
 #pragma unroll
-    for (int d = 0; d < 4; d++) s.L[d] = gp((const F *)J.LU) + d * g.elems;
+    for (int k = 0; k < Grp<F>::N; k++)
+        s.L[k] = (const GLOBAL typename Grp<F>::V *)(gp((const F *)J.LU) + k * Grp<F>::W * g.elems);
     s.e0 = (uint32_t)v.base + (uint32_t)(q * TT);
     const int te = (int)g.tile_elems;
     const int a = q & 1, b = q >> 1;
@@ -432,10 +449,19 @@ __device__ __forceinline__ void fwd_issue(FwdLoad<F> &c, const FwdSrc<F> &s, con
     const bool act = v.active(f, nk, q);
     const uint32_t e = s.e0 + (uint32_t)f * PLANE;
 #pragma unroll
-    for (int d = 0; d < 7; d++) c.a[d] = ldg(s.A[d], e);
+    for (int p = 0; p < 3; p++) {
+        const dbl2 v2 = ldg(s.AP[p], e);
+        c.a[2 * p] = v2.x;
+        c.a[2 * p + 1] = v2.y;
+    }
+    c.a[6] = ldg(s.AT, e);
     c.b = ldg(s.b, e);
 #pragma unroll
-    for (int d = 0; d < 4; d++) c.l[d] = ldg(s.L[d], e);
+    for (int k = 0; k < Grp<F>::N; k++) {
+        const typename Grp<F>::V lv = ldg(s.L[k], e);
+#pragma unroll
+        for (int w = 0; w < Grp<F>::W; w++) c.l[k * Grp<F>::W + w] = lane_of(lv, w);
+    }
     c.x2 = ldg(s.x, s.e0 + (uint32_t)min(f + 2, steps) * PLANE);   // plane `steps` is the zero margin
     c.hx = ldg(s.x, e + (act ? s.hx : 0));
     c.hy = ldg(s.x, e + (act ? s.hy : 0));
@@ -998,19 +1024,30 @@ __global__ __launch_bounds__(WAVE) void k_factor(LaunchArgs a)
     }
 
     const uint32_t base = (uint32_t)v.base;
-    const GLOBAL double *Ag[7];
-    GLOBAL F *LU[7];
+    const GLOBAL dbl2 *AP[3];
 #pragma unroll
-    for (int d = 0; d < 7; d++) {
-        Ag[d] = gp(J.A) + d * g.elems;
-        LU[d] = gp((F *)J.LU) + d * g.elems;
-    }
+    for (int p = 0; p < 3; p++) AP[p] = (const GLOBAL dbl2 *)(gp(J.A) + 2 * p * g.elems);
+    const GLOBAL double *AT = gp(J.A) + 6 * g.elems;
+    typedef typename Grp<F>::V LV;
+    GLOBAL LV *LG[Grp<F>::N];
+#pragma unroll
+    for (int k = 0; k < Grp<F>::N; k++) LG[k] = (GLOBAL LV *)(gp((F *)J.LU) + k * Grp<F>::W * g.elems);
+    GLOBAL F *UG[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) UG[d] = gp((F *)J.LU) + (4 + d) * g.elems;
     auto load_step = [&](double (*A)[7], int s) {   // plane `steps` is the zero margin
         const uint32_t e = base + (uint32_t)min(s, g.steps) * PLANE;
 #pragma unroll
-        for (int q = 0; q < NQ; q++)
+        for (int q = 0; q < NQ; q++) {
+            const uint32_t eq = e + (uint32_t)(q * TT);
 #pragma unroll
-            for (int d = 0; d < 7; d++) A[q][d] = ldg(Ag[d], e + (uint32_t)(q * TT));
+            for (int p = 0; p < 3; p++) {
+                const dbl2 v2 = ldg(AP[p], eq);
+                A[q][2 * p] = v2.x;
+                A[q][2 * p + 1] = v2.y;
+            }
+            A[q][6] = ldg(AT, eq);
+        }
     };
     double Ac[NQ][7], An[NQ][7];
     load_step(Ac, 0);
@@ -1062,13 +1099,16 @@ __global__ __launch_bounds__(WAVE) void k_factor(LaunchArgs a)
             ubuf[s & 1][1][q][lane] = f[q].u.e;
             ubuf[s & 1][2][q][lane] = f[q].u.t;
             const uint32_t eq = e + (uint32_t)(q * TT);
-            stg(LU[0], eq, (F)f[q].lb);
-            stg(LU[1], eq, (F)f[q].lw);
-            stg(LU[2], eq, (F)f[q].ls);
-            stg(LU[3], eq, (F)f[q].ilp);
-            stg(LU[4], eq, (F)f[q].u.n);
-            stg(LU[5], eq, (F)f[q].u.e);
-            stg(LU[6], eq, (F)f[q].u.t);
+            const F lv[4] = {(F)f[q].lb, (F)f[q].lw, (F)f[q].ls, (F)f[q].ilp};
+            if constexpr (Grp<F>::N == 1) {
+                stg(LG[0], eq, flt4{lv[0], lv[1], lv[2], lv[3]});
+            } else {
+                stg(LG[0], eq, dbl2{lv[0], lv[1]});
+                stg(LG[Grp<F>::N - 1], eq, dbl2{lv[2], lv[3]});
+            }
+            stg(UG[0], eq, (F)f[q].u.n);
+            stg(UG[1], eq, (F)f[q].u.e);
+            stg(UG[2], eq, (F)f[q].u.t);
         }
         const uint32_t rec = (uint32_t)v.t * (uint32_t)fstride + (uint32_t)s * FW;
 #pragma unroll
@@ -1124,7 +1164,11 @@ __device__ __forceinline__ long long sheared_index(const Geom &g, int i, int j, 
     return (long long)t * g.tile_elems + (long long)(k + ip + jp + 1) * PLANE + q * TT + jp * LI + ip;
 }
 
-__global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, double *dst, long long dst_stride, int mask)
+// Copies narr natural-order arrays into the sheared layout, array a at
+// dst + a * dst_stride; with `coef` the 7 arrays are coefficients P..T: the
+// couplings pointing out of the block are zeroed and the arrays are stored
+// in the interleaved coefficient layout (sip_internal.h).
+__global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, double *dst, long long dst_stride, int coef)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.elems; e += stride) {
@@ -1133,13 +1177,13 @@ __global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, double *dst, long lo
         const long long n = ok ? ((long long)k * g.nj + j) * g.ni + i : 0;
         for (int a = 0; a < narr; a++) {
             double v = ok ? src.p[a][n] : 0.0;
-            if (mask && ok) {
+            if (coef && ok) {
                 // couplings that point out of the block are ignored
                 if ((a == 1 && i == 0) || (a == 2 && i == g.ni - 1) || (a == 3 && j == 0) ||
                     (a == 4 && j == g.nj - 1) || (a == 5 && k == 0) || (a == 6 && k == g.nk - 1))
                     v = 0.0;
             }
-            dst[a * dst_stride + e] = v;
+            dst[coef ? coef_index(a, e, dst_stride) : a * dst_stride + e] = v;
         }
     }
 }
@@ -1169,7 +1213,7 @@ __global__ void k_export_factors(Geom g, const F *LU, DstPtrs out)
         const long long e = sheared_index(g, i, j, k);
 #pragma unroll
         for (int d = 0; d < 7; d++) {
-            const double v = (double)LU[d * g.elems + e];
+            const double v = (double)LU[factor_index<F>(d, e, g.elems)];
             out.p[d][c] = (d == 3) ? 1.0 / v : v;
         }
     }
@@ -1208,12 +1252,12 @@ hipError_t launch_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int 
 }
 
 hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, double *dst, long long dst_stride,
-                             int mask_couplings, hipStream_t s)
+                             int coefficients, hipStream_t s)
 {
     SrcPtrs sp{};
     for (int a = 0; a < narr && a < 9; a++) sp.p[a] = src[a];
     hipLaunchKernelGGL(k_to_sheared, dim3(grid_for(g.elems)), dim3(256), 0, s, g, narr, sp, dst, dst_stride,
-                       mask_couplings);
+                       coefficients);
     return hipGetLastError();
 }
 

@@ -566,7 +566,7 @@ sip_status sip_batch_submit(sip_server s, const sip_request *r, uint64_t *ticket
             if (!p.a[d]) return set_error(SIP_EINVAL, "coefficient pointer %d is NULL", d);
     }
     const Geom g = resident ? f->second->g : make_geom(p.ni, p.nj, p.nk);
-    if (g.elems >= (1ll << 29)) return set_error(SIP_EINVAL, "block too large");
+    if (g.elems >= sipk::MAX_ELEMS) return set_error(SIP_EINVAL, "block too large");
     if (resident && (p.ni != g.ni || p.nj != g.nj || p.nk != g.nk))
         return set_error(SIP_EINVAL, "dims differ from the resident system");
     const int fp32 = resident ? f->second->fp32 : p.precision == SIP_MIXED;
