@@ -550,10 +550,6 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
             nW3 = ybuf[pr][3][lane - dW];
             nS2 = ybuf[pr][2][lane - dS];
             nS3 = ybuf[pr][3][lane - dS];
-            keep(nW1);
-            keep(nW3);
-            keep(nS2);
-            keep(nS3);
         };
         wg_barrier();   // interval -1: the loaders stage step 0
         prefetch(0);
@@ -570,6 +566,12 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                 from_words(&pv[q].a[NV], hw1);
                 from_words(&pv[q].b[0], hs0);
                 from_words(&pv[q].b[NV], hs1);
+                // pinned here, after the barrier that completed the reads: the
+                // selects below must not pull them into divergent branches
+                keep(nW1);
+                keep(nW3);
+                keep(nS2);
+                keep(nS3);
                 const F zero = F(0);
                 const F W0 = dW ? nW1 : (needW[q] ? hw0 : zero);   // W of quadrant (0,0)
                 const F W2 = dW ? nW3 : (needW[q] ? hw1 : zero);   // W of quadrant (0,1)
@@ -607,8 +609,9 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                     ybuf[s & 1][c][lane] = y[c];
                 }
                 // publish at once: the neighbour tiles' next steps wait on this record
-                post_record<NV>(fbase, post, s, g.steps, FW, tag, ybuf[s & 1][post.q][post.src]);
-                prefetch(s + 1);
+                const F rec = ybuf[s & 1][post.q][post.src];
+                prefetch(s + 1);   // issued before the record store waits for its value
+                post_record<NV>(fbase, post, s, g.steps, FW, tag, rec);
                 plan(q, s + PD);
                 if (q == PD - 1 && aborted) s_buf[3] = 1;   // read by every wave after this barrier
                 wg_barrier();
@@ -821,10 +824,6 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
             nE2 = dbuf[pr][2][lane + dE];
             nN0 = dbuf[pr][0][lane + dN];
             nN1 = dbuf[pr][1][lane + dN];
-            keep(nE0);
-            keep(nE2);
-            keep(nN0);
-            keep(nN1);
         };
         wg_barrier();   // interval -1
         prefetch(0);
@@ -841,6 +840,10 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
                 from_words(&pv[q].a[NV], he1);
                 from_words(&pv[q].b[0], hn0);
                 from_words(&pv[q].b[NV], hn1);
+                keep(nE0);   // after the barrier that completed the reads
+                keep(nE2);
+                keep(nN0);
+                keep(nN1);
                 const F zero = F(0);
                 const F E1 = dE ? nE0 : (needE[q] ? he0 : zero);   // E of quadrant (1,0)
                 const F E3 = dE ? nE2 : (needE[q] ? he1 : zero);   // E of quadrant (1,1)
@@ -877,8 +880,9 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
                     dT[c] = d[c];
                     dbuf[s & 1][c][lane] = d[c];
                 }
-                post_record<NV>(fbase, post, s, g.steps, FW, tag, dbuf[s & 1][post.q][post.src]);
-                prefetch(s + 1);
+                const F rec = dbuf[s & 1][post.q][post.src];
+                prefetch(s + 1);   // issued before the record store waits for its value
+                post_record<NV>(fbase, post, s, g.steps, FW, tag, rec);
                 plan(q, s + PD);
                 if (q == PD - 1 && aborted) s_buf[3] = 1;
                 wg_barrier();
