@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0
 # algorithmic HBM bytes per cell of one sweep launch (each array streamed once)
 FWD_BYTES = {"mixed": 56 + 8 + 8 + 16 + 4, "fp64": 56 + 8 + 8 + 32 + 8}    # A, b, x, L (Lb,Lw,Ls,1/Lp), y out
+A_SYM_SAVING = 56 - 32     # symmetric storage reads A_P, A_E, A_N, A_T only
 BWD_BYTES = {"mixed": 12 + 4 + 8 + 8, "fp64": 24 + 8 + 8 + 8}              # U, y, x in, x out
 RTOL = 1e-8
 # HBM bytes per launch of the sweep kernels on the 256^3 workload, from the
@@ -54,6 +55,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--profile-iters", type=int, default=40)
     ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--storage", default="full", choices=["full", "symmetric"],
+                    help="coefficient storage of the sweeps (symmetric: Poisson workloads only)")
     ap.add_argument("--workload", default="single", choices=["single", "batched", "large", "serving"],
                     help="single: 256^3 block (default); batched: 64 uneven blocks through the solve "
                          "server; large: 512x512x256 stretched Poisson; serving: Poisson-arrival "
@@ -241,7 +244,7 @@ def main():
     torch.cuda.synchronize()
 
     def step(precision):
-        S = sip.sip_factor(A, c["alpha"], precision)
+        S = sip.sip_factor(A, c["alpha"], precision, storage=args.storage)
         x = torch.zeros_like(b)
         st, it, rr, _ = sip.sip_solve(S, b, x, RTOL, 200000)
         S.close()
@@ -272,13 +275,15 @@ def main():
         extra["mixed_speedup_vs_fp64"] = (t3 - t2) / (elapsed / args.steps)
 
     # dominant kernel: the fused residual + forward sweep (events on the launch stream)
-    S = sip.sip_factor(A, c["alpha"], "mixed")
+    S = sip.sip_factor(A, c["alpha"], "mixed", storage=args.storage)
     x = torch.zeros_like(b)
     fwd_ms, bwd_ms = sip.sip_profile_sweeps(S, b, x, args.profile_iters)
     S.close()
-    achieved = FWD_BYTES["mixed"] * cells / (fwd_ms * 1e-3) / 1e9
+    fwd_bytes = FWD_BYTES["mixed"] - (A_SYM_SAVING if args.storage == "symmetric" else 0)
+    achieved = fwd_bytes * cells / (fwd_ms * 1e-3) / 1e9
     traffic = None
-    if args.n == MEASURED["n"] and kernels_sha256() == MEASURED["kernels_sha256"]:
+    if (args.workload == "single" and args.storage == "full" and args.n == MEASURED["n"]
+            and kernels_sha256() == MEASURED["kernels_sha256"]):
         traffic = round(MEASURED["fwd_bytes"] / (fwd_ms * 1e-3) / 1e9, 1)
     roofline = {"bound": "hbm", "kernel": "k_forward<float> (residual + forward sweep)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -315,11 +320,12 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{label}, alpha 0.92, factor + mixed solve to {RTOL:g}",
+            "workload": f"{label}, alpha 0.92, factor + mixed solve to {RTOL:g}"
+                        + (", symmetric coefficient storage" if args.storage == "symmetric" else ""),
             "cells": cells,
             "iterations": mean_it,
             "final_rel_res": max(rr for _, rr in results),
-            "hbm_gbps_algorithmic": value * (FWD_BYTES["mixed"] + BWD_BYTES["mixed"]) / 1e9,
+            "hbm_gbps_algorithmic": value * (fwd_bytes + BWD_BYTES["mixed"]) / 1e9,
             **extra,
         },
         "roofline": roofline,

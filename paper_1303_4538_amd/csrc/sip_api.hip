@@ -251,6 +251,8 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     if ((long long)p->ni * p->nj * p->nk > (1ll << 34)) return set_error(SIP_EINVAL, "block too large");
     if (!(p->alpha >= 0.0 && p->alpha <= 1.0)) return set_error(SIP_EINVAL, "alpha must be in [0, 1]");
     if (p->precision != SIP_FP64 && p->precision != SIP_MIXED) return set_error(SIP_EINVAL, "unknown precision");
+    if (p->storage != SIP_STORAGE_FULL && p->storage != SIP_STORAGE_SYMMETRIC)
+        return set_error(SIP_EINVAL, "unknown storage");
     for (int d = 0; d < 7; d++)
         if (!p->a[d]) return set_error(SIP_EINVAL, "coefficient pointer %d is NULL", d);
     hipStream_t s = (hipStream_t)stream;
@@ -283,6 +285,16 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
         return e;
     };
     const Geom &g = h->g;
+    h->sym = p->storage == SIP_STORAGE_SYMMETRIC;
+    if (h->sym) {   // the symmetric storage is only valid for a symmetric A
+        unsigned bad = 0;
+        if (hipMemsetAsync(h->part, 0, sizeof(unsigned), s) != hipSuccess ||
+            launch_check_symmetric(p->ni, p->nj, p->nk, p->a, (unsigned *)h->part, s) != hipSuccess ||
+            hipMemcpyAsync(&bad, h->part, sizeof(unsigned), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return bail(set_error(SIP_EDEVICE, "symmetry check failed"));
+        if (bad) return bail(set_error(SIP_EINVAL, "symmetric storage requested but %u couplings differ", bad));
+    }
     if (launch_to_sheared(g, 7, p->a, h->A, g.elems, 1, s) != hipSuccess)
         return bail(set_error(SIP_EDEVICE, "reorder launch failed"));
     if (launch_init_ctl(h->ctl, 1, 0, 0.0, 1, s) != hipSuccess) return bail(set_error(SIP_EDEVICE, "init failed"));
@@ -301,6 +313,7 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     J.ctl = h->ctl;
     J.alpha = h->alpha;
     J.fw = FACE_WORDS_SWEEP;
+    J.sym = h->sym;
     const std::vector<Geom> gs{g};
     const std::vector<int2> of = topo_order(gs, false), ob = topo_order(gs, true);
     if (hipMemcpyAsync(h->d_job, &J, sizeof(Job), hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -310,6 +323,7 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     // the factorisation exchanges U triples (FACE_WORDS per step); the sweeps one value
     h->job_factor = J;
     h->job_factor.fw = FACE_WORDS;
+    h->job_factor.sym = 0;   // the factorisation reads the full coefficients
     J.fw = FACE_WORDS_SWEEP;
     if (hipMemcpyAsync(h->d_job_factor, &h->job_factor, sizeof(Job), hipMemcpyHostToDevice, s) != hipSuccess)
         return bail(set_error(SIP_EDEVICE, "upload failed"));
@@ -320,6 +334,10 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
         hipStreamSynchronize(s) != hipSuccess)
         return bail(set_error(SIP_EDEVICE, "factorisation failed: %s", hipGetErrorString(hipGetLastError())));
     if (h->h_ctl->stop != RUN) return bail(stop_status(h->h_ctl->stop));
+    // the sweeps read the symmetric storage; it overwrites the full one, which
+    // only the factorisation needed
+    if (h->sym && (launch_to_sheared(g, 7, p->a, h->A, g.elems, 2, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess))
+        return bail(set_error(SIP_EDEVICE, "reorder launch failed"));
     *out = h;
     return SIP_OK;
 }

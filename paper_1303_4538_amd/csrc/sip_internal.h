@@ -42,6 +42,15 @@ constexpr int PLANE = NQ * TT;     // elements per local step of a tile
 // Kernels address arrays with 32-bit byte offsets of 16-byte elements, so
 // elems stays below MAX_ELEMS.
 constexpr long long MAX_ELEMS = 1ll << 28;
+// Symmetric coefficient storage (A_W(P) = A_E(W), A_S(P) = A_N(S),
+// A_B(P) = A_T(B)), 4 * elems doubles: A_P in [0, elems), (A_E, A_N)
+// interleaved in [elems, 3 elems), A_T in [3 elems, 4 elems).  The forward
+// sweep reads A_W, A_S, A_B from the neighbours' A_E, A_N, A_T.
+__host__ __device__ inline long long sym_index(int a, long long e, long long elems)
+{
+    // a in the full order P, W, E, S, N, B, T; only P, E, N, T are stored
+    return a == 0 ? e : a == 2 ? elems + 2 * e : a == 4 ? elems + 2 * e + 1 : 3 * elems + e;
+}
 
 __host__ __device__ inline long long coef_index(int a, long long e, long long elems)
 {
@@ -102,6 +111,7 @@ struct Job {
     Ctl *ctl;
     double alpha;
     int fw;                    // face words per local step (FACE_WORDS_SWEEP or FACE_WORDS)
+    int sym;                   // A in the symmetric storage (sweeps only; the factorisation reads the full one)
 };
 
 // Launch-wide ticket and completion counters (reset by the last workgroup).
@@ -137,9 +147,13 @@ Geom make_geom(int ni, int nj, int nk);
 
 // Kernel launchers (sip_kernels.hip).  All are asynchronous on `s`.
 hipError_t launch_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int reset_epoch, hipStream_t s);
-// coefficients = 1: the 7 arrays are A (masked at the block boundary, stored interleaved).
+// coefficients = 1: the 7 arrays are A (masked at the block boundary, stored
+// interleaved); 2: the same in the symmetric storage (P, E, N, T only).
 hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, double *dst,
                              long long dst_stride, int coefficients, hipStream_t s);
+// Counts the cells whose W, S or B coupling differs from the neighbour's E, N
+// or T one (bitwise) into *bad (device, zeroed by the caller).
+hipError_t launch_check_symmetric(int ni, int nj, int nk, const double *const *a, unsigned *bad, hipStream_t s);
 hipError_t launch_from_sheared_f64(const Geom &g, const double *src, double *dst, const Ctl *zero_if_zero_rhs,
                                    hipStream_t s);
 hipError_t launch_export_factors(const Geom &g, const void *LU, int fp32, double *const *dst, hipStream_t s);

@@ -391,6 +391,10 @@ __device__ __forceinline__ int sweep_steps(int steps, int pd)
 // y = (r - Lb y_B - Lw y_W - Ls y_S) / Lp in precision F, per-tile partial
 // sums of r^2 (and of b^2, used at iteration 0).
 
+// Full storage: a[] = A_P..A_T of plane f.  Symmetric storage: a[0] = A_P
+// of plane f, a[2], a[4], a[6] = A_E, A_N, A_T of plane f + 1 (staged into
+// the coefficient ring), a[1], a[3] = A_E of the W neighbour / A_N of the S
+// neighbour across a tile edge.
 template <typename F>
 struct FwdLoad {
     double a[7];
@@ -407,6 +411,7 @@ struct FwdSrc {
     const GLOBAL dbl2 *AP[3];   // (A_P, A_W), (A_E, A_S), (A_N, A_B)
     const GLOBAL double *AT, *b, *x;
     const GLOBAL typename Grp<F>::V *L[Grp<F>::N];   // Lb, Lw, Ls, 1/Lp
+    const GLOBAL double *SP, *ST, *SEN;                // symmetric storage: A_P, A_T, (A_E, A_N) pairs
     uint32_t e0;          // sheared index of (plane 0, this quadrant, this lane)
     int32_t hx, hy;       // index deltas of the x halo this slot reads across a tile edge (0: none)
 };
@@ -419,6 +424,9 @@ __device__ __forceinline__ FwdSrc<F> fwd_src(const Job &J, const TileView &v, in
 #pragma unroll
     for (int p = 0; p < 3; p++) s.AP[p] = (const GLOBAL dbl2 *)(gp(J.A) + 2 * p * g.elems);
     s.AT = gp(J.A) + 6 * g.elems;
+    s.SP = gp(J.A);
+    s.SEN = gp(J.A) + g.elems;
+    s.ST = gp(J.A) + 3 * g.elems;
     s.b = gp(J.b);
     s.x = gp((const double *)J.x);
 #pragma unroll
@@ -444,17 +452,30 @@ __device__ __forceinline__ FwdSrc<F> fwd_src(const Job &J, const TileView &v, in
 // stays inside the tile's planes -1..steps for f in [0, steps)).
 template <typename F>
 __device__ __forceinline__ void fwd_issue(FwdLoad<F> &c, const FwdSrc<F> &s, const TileView &v, int q, int f, int steps,
-                                          int nk)
+                                          int nk, bool sym)
 {
     const bool act = v.active(f, nk, q);
     const uint32_t e = s.e0 + (uint32_t)f * PLANE;
+    if (sym) {
+        const uint32_t e1 = s.e0 + (uint32_t)min(f + 1, steps) * PLANE;   // plane `steps` is the zero margin
+        c.a[0] = ldg(s.SP, e);
+        const dbl2 en = ldg((const GLOBAL dbl2 *)s.SEN, e1);
+        c.a[2] = en.x;
+        c.a[4] = en.y;
+        c.a[6] = ldg(s.ST, e1);
+        // W / S couplings across a tile edge: the neighbour cell's A_E / A_N
+        // (edge slots of quadrant column / row 0; the other lanes share one word)
+        c.a[1] = ldg(s.SEN, 2u * (e + (act && !(q & 1) ? s.hx : 0)));
+        c.a[3] = ldg(s.SEN, 2u * (e + (act && !(q & 2) ? s.hy : 0)) + 1u);
+    } else {
 #pragma unroll
-    for (int p = 0; p < 3; p++) {
-        const dbl2 v2 = ldg(s.AP[p], e);
-        c.a[2 * p] = v2.x;
-        c.a[2 * p + 1] = v2.y;
+        for (int p = 0; p < 3; p++) {
+            const dbl2 v2 = ldg(s.AP[p], e);
+            c.a[2 * p] = v2.x;
+            c.a[2 * p + 1] = v2.y;
+        }
+        c.a[6] = ldg(s.AT, e);
     }
-    c.a[6] = ldg(s.AT, e);
     c.b = ldg(s.b, e);
 #pragma unroll
     for (int k = 0; k < Grp<F>::N; k++) {
@@ -463,6 +484,10 @@ __device__ __forceinline__ void fwd_issue(FwdLoad<F> &c, const FwdSrc<F> &s, con
         for (int w = 0; w < Grp<F>::W; w++) c.l[k * Grp<F>::W + w] = lane_of(lv, w);
     }
     c.x2 = ldg(s.x, s.e0 + (uint32_t)min(f + 2, steps) * PLANE);   // plane `steps` is the zero margin
+    // x across a tile edge, loaded without control flow (a branch would cost
+    // the loader exact wait counts): the edge slots of a quadrant read the
+    // neighbour tile, the other lanes their own slot (unused, or zero padding
+    // for inactive slots, which keeps their residual zero)
     c.hx = ldg(s.x, e + (act ? s.hx : 0));
     c.hy = ldg(s.x, e + (act ? s.hy : 0));
 }
@@ -475,6 +500,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
     __shared__ F ring[2][5][NQ][TT];        // r, Lb, Lw, Ls, 1/Lp of two steps
     __shared__ F ybuf[2][NQ][TT];
     __shared__ double xring[4][NQ][TT];     // x on planes f-1..f+2 (slot = plane & 3)
+    __shared__ double cring[4][3][NQ][TT];  // symmetric storage: A_E, A_N, A_T on planes f-1..f+1
     __shared__ int s_buf[4];
     __shared__ double s_part[NL][2];
 
@@ -491,6 +517,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
     const uint32_t tag = J.ctl->epoch;
     const uint32_t iter = J.ctl->iter;
     const Geom g = J.g;
+    const bool sym = J.sym != 0;
     const TileView v = make_view(g, as.tile, lane);
     const int U = sweep_steps(g.steps, PD);
     const int FW = J.fw;
@@ -505,6 +532,14 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
         xring[3][q][lane] = 0.0;
         xring[0][q][lane] = ldg(xg, e0);
         xring[1][q][lane] = ldg(xg, e0 + (uint32_t)min(1, g.steps) * PLANE);
+        if (sym) {   // A_E, A_N, A_T of planes -1 (zero margin) and 0
+            const GLOBAL double *ag = gp(J.A);
+#pragma unroll
+            for (int d = 0; d < 3; d++) cring[3][d][q][lane] = 0.0;
+            cring[0][0][q][lane] = ldg(ag, (uint32_t)g.elems + 2u * e0);
+            cring[0][1][q][lane] = ldg(ag, (uint32_t)g.elems + 2u * e0 + 1u);
+            cring[0][2][q][lane] = ldg(ag, 3u * (uint32_t)g.elems + e0);
+        }
     }
     __syncthreads();   // the x ring prologue is read across quadrants by the first turn
 
@@ -625,7 +660,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
         const int qa = q & 1, qb = q >> 1;
         const FwdSrc<F> src = fwd_src<F>(J, v, q);
         FwdLoad<F> c;
-        if (ph < g.steps) fwd_issue(c, src, v, q, ph, g.steps, g.nk);
+        if (ph < g.steps) fwd_issue(c, src, v, q, ph, g.steps, g.nk, sym);
         GLOBAL F *yout = gp((F *)J.y);
         double rr = 0.0, bb = 0.0;
         // In-ring neighbours: the other quadrant column (row) of the same
@@ -635,6 +670,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
         const int dS = qb ? 0 : (v.jp > 0 ? LI : 0), dN = qb ? (v.jp < LJ - 1 ? LI : 0) : 0;
         const bool inW = qa || v.ip > 0, inE = !qa || v.ip < LI - 1;
         const bool inS = qb || v.jp > 0, inN = !qb || v.jp < LJ - 1;
+        const bool wall_w = !inW && v.ti == 0, wall_s = !inS && v.tj == 0;   // block boundary: no coupling
         auto turn = [&](int f) {
             if (f < g.steps) {
                 // planes f-1..f+1 were staged by earlier turns
@@ -646,8 +682,22 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                 const double xE = inE ? xring[(f + qa) & 3][q ^ 1][lane + dE] : c.hx;
                 const double xS = inS ? xring[(f - 1 + qb) & 3][q ^ 2][lane - dS] : c.hy;
                 const double xN = inN ? xring[(f + qb) & 3][q ^ 2][lane + dN] : c.hy;
-                const double ax = c.a[0] * xP + c.a[1] * xW + c.a[2] * xE + c.a[3] * xS + c.a[4] * xN +
-                                  c.a[5] * xB + c.a[6] * xT;
+                double aP = c.a[0], aW = c.a[1], aE = c.a[2], aS = c.a[3], aN = c.a[4], aB = c.a[5], aT = c.a[6];
+                if (sym) {
+                    // A_W = A_E of the W cell, A_S = A_N of the S cell, A_B = A_T of the B
+                    // cell, found where the x ring finds x_W, x_S, x_B; plane f + 1 is
+                    // staged for the next turns
+                    cring[(f + 1) & 3][0][q][lane] = c.a[2];
+                    cring[(f + 1) & 3][1][q][lane] = c.a[4];
+                    cring[(f + 1) & 3][2][q][lane] = c.a[6];
+                    aE = cring[f & 3][0][q][lane];
+                    aN = cring[f & 3][1][q][lane];
+                    aT = cring[f & 3][2][q][lane];
+                    aB = cring[(f - 1) & 3][2][q][lane];
+                    aW = inW ? cring[(f - 1 + qa) & 3][0][q ^ 1][lane - dW] : (wall_w ? 0.0 : c.a[1]);
+                    aS = inS ? cring[(f - 1 + qb) & 3][1][q ^ 2][lane - dS] : (wall_s ? 0.0 : c.a[3]);
+                }
+                const double ax = aP * xP + aW * xW + aE * xE + aS * xS + aN * xN + aB * xB + aT * xT;
                 const double r = c.b - ax;
                 rr += r * r;
                 bb += c.b * c.b;
@@ -658,7 +708,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                 ring[slot][3][q][lane] = c.l[2];
                 ring[slot][4][q][lane] = c.l[3];
             }
-            if (f + NP < g.steps) fwd_issue(c, src, v, q, f + NP, g.steps, g.nk);
+            if (f + NP < g.steps) fwd_issue(c, src, v, q, f + NP, g.steps, g.nk, sym);
             const int p = f - 3;
             if (p >= 0 && p < g.steps)   // inactive slots rewrite their zero padding
                 stg(yout, src.e0 + (uint32_t)p * PLANE, ybuf[p & 1][q][lane]);
@@ -1171,7 +1221,8 @@ __device__ __forceinline__ long long sheared_index(const Geom &g, int i, int j, 
 // Copies narr natural-order arrays into the sheared layout, array a at
 // dst + a * dst_stride; with `coef` the 7 arrays are coefficients P..T: the
 // couplings pointing out of the block are zeroed and the arrays are stored
-// in the interleaved coefficient layout (sip_internal.h).
+// in the interleaved coefficient layout (coef = 1) or the symmetric one
+// (coef = 2, P, E, N, T only; sip_internal.h).
 __global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, double *dst, long long dst_stride, int coef)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -1187,9 +1238,31 @@ __global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, double *dst, long lo
                     (a == 4 && j == g.nj - 1) || (a == 5 && k == 0) || (a == 6 && k == g.nk - 1))
                     v = 0.0;
             }
-            dst[coef ? coef_index(a, e, dst_stride) : a * dst_stride + e] = v;
+            if (coef == 2) {
+                if (a == 0 || a == 2 || a == 4 || a == 6) dst[sym_index(a, e, dst_stride)] = v;
+            } else {
+                dst[coef ? coef_index(a, e, dst_stride) : a * dst_stride + e] = v;
+            }
         }
     }
+}
+
+// A symmetric system has A_W(i,j,k) = A_E(i-1,j,k), A_S = A_N of (i,j-1,k) and
+// A_B = A_T of (i,j,k-1) for every interior coupling (bitwise).
+__global__ void k_check_symmetric(int ni, int nj, int nk, SrcPtrs a, unsigned *bad)
+{
+    const long long n = (long long)ni * nj * nk, plane = (long long)ni * nj;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    unsigned cnt = 0u;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += stride) {
+        const int i = (int)(c % ni);
+        const int j = (int)((c / ni) % nj);
+        const int k = (int)(c / plane);
+        if (i > 0 && !(a.p[1][c] == a.p[2][c - 1])) cnt++;
+        if (j > 0 && !(a.p[3][c] == a.p[4][c - ni])) cnt++;
+        if (k > 0 && !(a.p[5][c] == a.p[6][c - plane])) cnt++;
+    }
+    if (cnt) atomicAdd(bad, cnt);
 }
 
 __global__ void k_from_sheared(Geom g, const double *src, double *dst, const Ctl *ctl)
@@ -1262,6 +1335,14 @@ hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, 
     for (int a = 0; a < narr && a < 9; a++) sp.p[a] = src[a];
     hipLaunchKernelGGL(k_to_sheared, dim3(grid_for(g.elems)), dim3(256), 0, s, g, narr, sp, dst, dst_stride,
                        coefficients);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_symmetric(int ni, int nj, int nk, const double *const *a, unsigned *bad, hipStream_t s)
+{
+    SrcPtrs sp{};
+    for (int d = 0; d < 7; d++) sp.p[d] = a[d];
+    hipLaunchKernelGGL(k_check_symmetric, dim3(grid_for((long long)ni * nj * nk)), dim3(256), 0, s, ni, nj, nk, sp, bad);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ struct sip_system_s {
     sipk::Geom g{};
     int fp32 = 0;
     int precision = 0;
+    int sym = 0;                    // coefficients in the symmetric storage for the sweeps
     double alpha = 0.0;
     int device = 0;
     uint64_t timeout_ticks = 0;

@@ -49,6 +49,8 @@ struct Resident {
     bool factored = false;
     bool retain = false;
     bool broken = false;
+    int sym = 0;           // sweeps read the symmetric coefficient storage
+    bool asym = false;     // symmetric storage requested for a non-symmetric A
     uint64_t last_use = 0;
 };
 
@@ -109,6 +111,7 @@ struct sip_server_s {
     int order_cap[2] = {0, 0};
     int jobs_cap[2] = {0, 0};
     LaunchCtl *lc = nullptr;
+    unsigned *d_bad = nullptr, *h_bad = nullptr;   // symmetry check counter (device, pinned mirror)
     SweepPlan plan{};
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
@@ -199,6 +202,7 @@ bool sip_server_s::admit_locked(std::vector<Req *> &admitted, std::vector<Reside
             rs->g = g;
             rs->fp32 = fp32;
             rs->alpha = pb.alpha;
+            rs->sym = pb.storage == SIP_STORAGE_SYMMETRIC;
             rs->bytes = need_sys;
             if (dev_alloc((void **)&rs->A, 7 * (size_t)g.elems * 8, stream) != SIP_OK ||
                 dev_alloc(&rs->LU, 7 * (size_t)g.elems * (fp32 ? 4 : 8), stream) != SIP_OK) {
@@ -327,6 +331,7 @@ static Job job_of(const Resident *s, const Req *q, Ctl *ctl, int fw)
     J.ctl = ctl + q->slot;
     J.alpha = s->alpha;
     J.fw = fw;
+    J.sym = fw == FACE_WORDS ? 0 : s->sym;   // the factorisation reads the full coefficients
     return J;
 }
 
@@ -340,6 +345,17 @@ sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const st
         for (size_t k = 0; k < sys.size(); k++) {
             if (sys[k]->fp32 != grp) continue;
             const sip_problem &pb = owners[k]->r.problem;
+            if (sys[k]->sym) {   // the symmetric storage is only valid for a symmetric A
+                if (hipMemsetAsync(d_bad, 0, sizeof(unsigned), stream) != hipSuccess ||
+                    launch_check_symmetric(pb.ni, pb.nj, pb.nk, pb.a, d_bad, stream) != hipSuccess ||
+                    hipMemcpyAsync(h_bad, d_bad, sizeof(unsigned), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                    hipStreamSynchronize(stream) != hipSuccess)
+                    return set_error(SIP_EDEVICE, "symmetry check failed");
+                if (*h_bad) {
+                    sys[k]->asym = true;
+                    continue;
+                }
+            }
             if (launch_to_sheared(sys[k]->g, 7, pb.a, sys[k]->A, sys[k]->g.elems, 1, stream) != hipSuccess)
                 return set_error(SIP_EDEVICE, "reorder failed");
             // tags stay monotonic per slot (never reset): face words of the
@@ -359,6 +375,13 @@ sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const st
             return set_error(SIP_EDEVICE, "upload failed");
         const LaunchArgs la{d_jobs[grp], d_order[grp][0], lc, (int)of.size(), timeout_ticks};
         if (launch_factor(la, grp, stream) != hipSuccess) return set_error(SIP_EDEVICE, "factor launch failed");
+        // the sweeps of symmetric systems read the symmetric storage, which
+        // overwrites the full one once the factorisation is done
+        for (size_t k = 0; k < sys.size(); k++)
+            if (sys[k]->fp32 == grp && sys[k]->sym && !sys[k]->asym &&
+                launch_to_sheared(sys[k]->g, 7, owners[k]->r.problem.a, sys[k]->A, sys[k]->g.elems, 2, stream) !=
+                    hipSuccess)
+                return set_error(SIP_EDEVICE, "reorder failed");
         // the host copies of jobs/orders must live until the copies ran
         if (hipStreamSynchronize(stream) != hipSuccess) return set_error(SIP_EDEVICE, "factorisation failed");
         stats[7]++;
@@ -437,7 +460,7 @@ void sip_server_s::loop()
             std::lock_guard<std::mutex> lk(mu);
             for (size_t k = 0; k < to_factor.size(); k++) {
                 const uint32_t stop = st == SIP_OK ? h_ctl[owners[k]->slot].stop : TIMEOUT;
-                if (stop == RUN) {
+                if (stop == RUN && !to_factor[k]->asym) {
                     to_factor[k]->factored = true;
                 } else {
                     to_factor[k]->broken = true;
@@ -450,7 +473,7 @@ void sip_server_s::loop()
             std::lock_guard<std::mutex> lk(mu);
             for (Req *q : admitted) {
                 if (q->sys->broken) {
-                    finish_locked(q, SIP_EBREAKDOWN, 0, 0.0);
+                    finish_locked(q, q->sys->asym ? SIP_EINVAL : SIP_EBREAKDOWN, 0, 0.0);
                     continue;
                 }
                 ready.push_back(q);
@@ -534,6 +557,8 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
         hipMalloc((void **)&s->ctl, sizeof(Ctl) * MAX_SLOTS) != hipSuccess ||
         hipHostMalloc((void **)&s->h_ctl, sizeof(Ctl) * MAX_SLOTS, hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void **)&s->lc, sizeof(LaunchCtl)) != hipSuccess ||
+        hipMalloc((void **)&s->d_bad, sizeof(unsigned)) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_bad, sizeof(unsigned), hipHostMallocDefault) != hipSuccess ||
         hipMemset(s->ctl, 0, sizeof(Ctl) * MAX_SLOTS) != hipSuccess || hipMemset(s->lc, 0, sizeof(LaunchCtl)) != hipSuccess ||
         launch_init_ctl(s->ctl, MAX_SLOTS, 0, 0.0, 1, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess) {
@@ -562,6 +587,8 @@ sip_status sip_batch_submit(sip_server s, const sip_request *r, uint64_t *ticket
         if (p.ni < 1 || p.nj < 1 || p.nk < 1) return set_error(SIP_EINVAL, "dims must be >= 1");
         if (!(p.alpha >= 0.0 && p.alpha <= 1.0)) return set_error(SIP_EINVAL, "alpha must be in [0, 1]");
         if (p.precision != SIP_FP64 && p.precision != SIP_MIXED) return set_error(SIP_EINVAL, "unknown precision");
+        if (p.storage != SIP_STORAGE_FULL && p.storage != SIP_STORAGE_SYMMETRIC)
+            return set_error(SIP_EINVAL, "unknown storage");
         for (int d = 0; d < 7; d++)
             if (!p.a[d]) return set_error(SIP_EINVAL, "coefficient pointer %d is NULL", d);
     }
@@ -647,6 +674,8 @@ sip_status sip_server_destroy(sip_server s)
     (void)hipFree(s->ctl);
     (void)hipFree(s->lc);
     (void)hipHostFree(s->h_ctl);
+    (void)hipFree(s->d_bad);
+    (void)hipHostFree(s->h_bad);
     (void)hipStreamDestroy(s->stream);
     delete s;
     return SIP_OK;

@@ -39,7 +39,8 @@ class SipError(RuntimeError):
 
 class Problem(ctypes.Structure):
     _fields_ = [("ni", ctypes.c_int32), ("nj", ctypes.c_int32), ("nk", ctypes.c_int32),
-                ("a", ctypes.c_void_p * 7), ("alpha", ctypes.c_double), ("precision", ctypes.c_int32)]
+                ("a", ctypes.c_void_p * 7), ("alpha", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("storage", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -122,7 +123,10 @@ def _grid(t, shape, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_problem(A, alpha, precision):
+STORAGES = {"full": 0, "symmetric": 1}
+
+
+def make_problem(A, alpha, precision, storage="full"):
     if A.dim() != 4 or A.shape[0] != 7:
         raise ValueError("A must have shape (7, nk, nj, ni)")
     _grid(A, A.shape, "A")
@@ -133,6 +137,7 @@ def make_problem(A, alpha, precision):
         p.a[d] = A[d].data_ptr()
     p.alpha = float(alpha)
     p.precision = PRECISIONS[precision]
+    p.storage = STORAGES[storage]
     return p
 
 
@@ -167,9 +172,10 @@ class System:
             pass
 
 
-def sip_factor(A, alpha=0.92, precision="fp64", stream=None):
-    """Copy A (7, nk, nj, ni) into the library and factorise it (Stone)."""
-    p = make_problem(A, alpha, precision)
+def sip_factor(A, alpha=0.92, precision="fp64", stream=None, storage="full"):
+    """Copy A (7, nk, nj, ni) into the library and factorise it (Stone).
+    storage="symmetric" keeps only A_P, A_E, A_N, A_T for the sweeps."""
+    p = make_problem(A, alpha, precision, storage)
     h = ctypes.c_void_p()
     _check(lib().sip_factor(ctypes.byref(p), _stream(stream), ctypes.byref(h)))
     return System(h, (p.ni, p.nj, p.nk), PRECISIONS[precision])
@@ -224,12 +230,12 @@ class Server:
         self._keep = {}
 
     def submit(self, system_id, A, b, x, alpha=0.92, precision="mixed", rtol=1e-8, max_iter=100000,
-               x0=None, retain=False):
+               x0=None, retain=False, storage="full"):
         """Submit a solve; returns a ticket.  A may be None when the system is resident."""
         r = Request()
         r.system_id = int(system_id)
         if A is not None:
-            r.problem = make_problem(A, alpha, precision)
+            r.problem = make_problem(A, alpha, precision, storage)
         else:
             nk, nj, ni = b.shape
             r.problem.ni, r.problem.nj, r.problem.nk = ni, nj, nk
