@@ -50,6 +50,8 @@ def _load():
     lib.oracle_factor.restype = i
     lib.oracle_residual.argtypes = [i, i, i, _D, _D, _D, _D]
     lib.oracle_residual.restype = None
+    lib.oracle_residual_f32.argtypes = [i, i, i, _F, _F, _F, _F]
+    lib.oracle_residual_f32.restype = None
     lib.oracle_norm2.argtypes = [_D, ctypes.c_size_t]
     lib.oracle_norm2.restype = d
     lib.oracle_forward.argtypes = [i, i, i, _D, _D, _D]
@@ -101,6 +103,23 @@ def residual(A, b, x):
     return r
 
 
+def residual_f32(A, b, x):
+    """All-FP32 form: r = b - A x with FP32 inputs and FP32 arithmetic."""
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    ni, nj, nk = _dims(A)
+    r = np.empty_like(b)
+    _load().oracle_residual_f32(ni, nj, nk, _ptr(A, _F), _ptr(b, _F), _ptr(x, _F), _ptr(r, _F))
+    return r
+
+
+def _mode(mixed, fp32):
+    if mixed and fp32:
+        raise ValueError("choose one of mixed and fp32")
+    return 2 if fp32 else 1 if mixed else 0
+
+
 def norm2(v):
     v = _f64(v).ravel()
     return _load().oracle_norm2(_ptr(v), v.size)
@@ -140,21 +159,23 @@ def backward_f32(LU32, y32):
     return d
 
 
-def iterate(A, LU, b, x0, n_iter, mixed=False):
+def iterate(A, LU, b, x0, n_iter, mixed=False, fp32=False):
     """Run n_iter SIP updates from x0.  Returns (x, hist) with hist[n] = rho_n,
-    n = 0..n_iter (relative residual of the n-th iterate)."""
+    n = 0..n_iter (relative residual of the n-th iterate).  mixed: FP32 sweeps
+    with FP64 residual and update; fp32: everything in FP32 (x returned as
+    FP64)."""
     A, LU, b = _f64(A), _f64(LU), _f64(b)
     x = _f64(x0).copy()
     ni, nj, nk = _dims(A)
     hist = np.zeros(int(n_iter) + 1)
     rc = _load().oracle_iterate(ni, nj, nk, _ptr(A), _ptr(LU), _ptr(b), _ptr(x),
-                                int(n_iter), 1 if mixed else 0, _ptr(hist))
+                                int(n_iter), _mode(mixed, fp32), _ptr(hist))
     if rc < 0:
         raise MemoryError("oracle allocation failed")
     return x, hist
 
 
-def solve(A, LU, b, x0, rtol, max_iter, mixed=False):
+def solve(A, LU, b, x0, rtol, max_iter, mixed=False, fp32=False):
     """Iterate until rho_n <= rtol (or max_iter updates).
     Returns (x, iterations, rel_res, hist[0..iterations])."""
     A, LU, b = _f64(A), _f64(LU), _f64(b)
@@ -163,7 +184,7 @@ def solve(A, LU, b, x0, rtol, max_iter, mixed=False):
     hist = np.zeros(int(max_iter) + 1)
     rr = ctypes.c_double(0.0)
     it = _load().oracle_solve(ni, nj, nk, _ptr(A), _ptr(LU), _ptr(b), _ptr(x), float(rtol),
-                              int(max_iter), 1 if mixed else 0, _ptr(hist), ctypes.byref(rr))
+                              int(max_iter), _mode(mixed, fp32), _ptr(hist), ctypes.byref(rr))
     if it < 0:
         raise MemoryError("oracle allocation failed")
     return x, int(it), float(rr.value), hist[: it + 1]

@@ -50,6 +50,13 @@
  * Mixed form: factors computed in FP64 then rounded to FP32, r rounded to
  * FP32 before the forward sweep, both sweeps in FP32, d widened to FP64;
  * residual, norm and update stay FP64.
+ * All-FP32 form (the single-precision relaxation of Sec. 4.1: b and x are
+ * converted to single precision before the sweeps and only x is converted
+ * back afterwards): A, the factors (computed in FP64), b and x are rounded
+ * to FP32 on entry; residual, both sweeps and the update x += d run in FP32;
+ * x is widened to FP64 on exit.  rho_n is the norm of the FP32 residual over
+ * the norm of the FP32 b, each summed in FP64 (a reading: the paper does not
+ * say how the norm is summed).
  */
 #include <math.h>
 #include <stddef.h>
@@ -121,6 +128,34 @@ void oracle_residual(int ni, int nj, int nk, const double *A, const double *b, c
                 if (k < nk - 1) ax += A[AT * n + p] * x[IDX(i, j, k + 1)];
                 r[p] = b[p] - ax;
             }
+}
+
+/* All-FP32 form: r = b - A x with every product and sum in FP32, the terms
+ * added in the order P, W, E, S, N, B, T. */
+void oracle_residual_f32(int ni, int nj, int nk, const float *A, const float *b, const float *x, float *r)
+{
+    const size_t n = (size_t)ni * nj * nk;
+    for (int k = 0; k < nk; k++)
+        for (int j = 0; j < nj; j++)
+            for (int i = 0; i < ni; i++) {
+                const size_t p = IDX(i, j, k);
+                float ax = A[AP * n + p] * x[p];
+                if (i > 0) ax += A[AW * n + p] * x[IDX(i - 1, j, k)];
+                if (i < ni - 1) ax += A[AE * n + p] * x[IDX(i + 1, j, k)];
+                if (j > 0) ax += A[AS * n + p] * x[IDX(i, j - 1, k)];
+                if (j < nj - 1) ax += A[AN * n + p] * x[IDX(i, j + 1, k)];
+                if (k > 0) ax += A[AB * n + p] * x[IDX(i, j, k - 1)];
+                if (k < nk - 1) ax += A[AT * n + p] * x[IDX(i, j, k + 1)];
+                r[p] = b[p] - ax;
+            }
+}
+
+/* Euclidean norm of an FP32 vector, squares summed in FP64. */
+static double norm2_f32(const float *v, size_t n)
+{
+    double s = 0.0;
+    for (size_t p = 0; p < n; p++) s += (double)v[p] * (double)v[p];
+    return sqrt(s);
 }
 
 /* Euclidean norm, summed in lexicographic order. */
@@ -198,7 +233,52 @@ void oracle_backward_f32(int ni, int nj, int nk, const float *LU, const float *y
             }
 }
 
-/* Shared driver.  mode 0: FP64 sweeps; mode 1: mixed form.
+/* All-FP32 driver (mode 2 of the shared driver below). */
+static long oracle_run_f32(int ni, int nj, int nk, const double *A, const double *LU, const double *b,
+                           double *x, long n_iter, double rtol, double *hist, double *rel_res)
+{
+    const size_t n = (size_t)ni * nj * nk;
+    float *A32 = malloc(7 * n * sizeof(float)), *LU32 = malloc(7 * n * sizeof(float));
+    float *b32 = malloc(n * sizeof(float)), *x32 = malloc(n * sizeof(float));
+    float *r32 = malloc(n * sizeof(float)), *y32 = malloc(n * sizeof(float)), *d32 = malloc(n * sizeof(float));
+    long it = -1;
+    if (!A32 || !LU32 || !b32 || !x32 || !r32 || !y32 || !d32) goto out;
+    for (size_t q = 0; q < 7 * n; q++) {
+        A32[q] = (float)A[q];
+        LU32[q] = (float)LU[q];
+    }
+    for (size_t p = 0; p < n; p++) {
+        b32[p] = (float)b[p];
+        x32[p] = (float)x[p];
+    }
+    const double nb = norm2_f32(b32, n);
+    if (nb == 0.0) {
+        for (size_t p = 0; p < n; p++) x[p] = 0.0;
+        if (hist) for (long m = 0; m <= n_iter; m++) hist[m] = 0.0;
+        if (rel_res) *rel_res = 0.0;
+        it = 0;
+        goto out;
+    }
+    double rho = 0.0;
+    for (it = 0;; it++) {
+        oracle_residual_f32(ni, nj, nk, A32, b32, x32, r32);
+        rho = norm2_f32(r32, n) / nb;
+        if (hist) hist[it] = rho;
+        if (it >= n_iter) break;
+        if (rtol > 0.0 && rho <= rtol) break;
+        oracle_forward_f32(ni, nj, nk, LU32, r32, y32);
+        oracle_backward_f32(ni, nj, nk, LU32, y32, d32);
+        for (size_t p = 0; p < n; p++) x32[p] = x32[p] + d32[p];
+    }
+    for (size_t p = 0; p < n; p++) x[p] = (double)x32[p];
+    if (rel_res) *rel_res = rho;
+out:
+    free(A32); free(LU32); free(b32); free(x32); free(r32); free(y32); free(d32);
+    return it;
+}
+
+/* Shared driver.  mode 0: FP64 sweeps; mode 1: mixed form; mode 2: all-FP32
+ * form.
  * Stops after n_iter updates, or (rtol > 0) at the first n with
  * rho_n <= rtol, leaving x = x^n.  hist (nullable) receives rho_0..rho_n.
  * Returns the number of updates applied, or -1 on allocation failure.
@@ -206,6 +286,7 @@ void oracle_backward_f32(int ni, int nj, int nk, const float *LU, const float *y
 static long oracle_run(int ni, int nj, int nk, const double *A, const double *LU, const double *b,
                        double *x, long n_iter, double rtol, int mode, double *hist, double *rel_res)
 {
+    if (mode == 2) return oracle_run_f32(ni, nj, nk, A, LU, b, x, n_iter, rtol, hist, rel_res);
     const size_t n = (size_t)ni * nj * nk;
     const double nb = oracle_norm2(b, n);
     if (nb == 0.0) {
@@ -255,16 +336,17 @@ static long oracle_run(int ni, int nj, int nk, const double *A, const double *LU
     return it;
 }
 
-/* n_iter plain SIP iterations from x (in/out); hist has n_iter+1 entries. */
+/* n_iter plain SIP iterations from x (in/out); hist has n_iter+1 entries.
+ * mode: 0 FP64, 1 mixed form, 2 all-FP32 form. */
 long oracle_iterate(int ni, int nj, int nk, const double *A, const double *LU, const double *b,
-                    double *x, long n_iter, int mixed, double *hist)
+                    double *x, long n_iter, int mode, double *hist)
 {
-    return oracle_run(ni, nj, nk, A, LU, b, x, n_iter, 0.0, mixed ? 1 : 0, hist, NULL);
+    return oracle_run(ni, nj, nk, A, LU, b, x, n_iter, 0.0, mode, hist, NULL);
 }
 
 /* Iterate until rho_n <= rtol or max_iter updates; returns iterations. */
 long oracle_solve(int ni, int nj, int nk, const double *A, const double *LU, const double *b,
-                  double *x, double rtol, long max_iter, int mixed, double *hist, double *rel_res)
+                  double *x, double rtol, long max_iter, int mode, double *hist, double *rel_res)
 {
-    return oracle_run(ni, nj, nk, A, LU, b, x, max_iter, rtol, mixed ? 1 : 0, hist, rel_res);
+    return oracle_run(ni, nj, nk, A, LU, b, x, max_iter, rtol, mode, hist, rel_res);
 }

@@ -271,3 +271,93 @@ def test_config1_runs_and_converges(ora):
     assert hist[0] == pytest.approx(1.0)
     assert np.all(np.diff(hist) < 0)
     assert hist[-1] < 1e-9
+
+
+# ---------------------------------------------------------------- all-FP32 form
+# The paper's single-precision relaxation (Sec. 4.1): b, x and the
+# coefficients converted to FP32 before the sweeps, x converted back after.
+
+def test_fp32_residual_is_exact_on_small_integers(ora):
+    """With integer coefficients and values small enough that every product
+    and partial sum is an integer below 2^24, FP32 arithmetic is exact, so the
+    FP32 residual equals the FP64 one bitwise (stencil terms, signs, indices
+    and the dropped outward couplings all enter)."""
+    ni, nj, nk = 5, 4, 6
+    rng = np.random.default_rng(40)
+    A = rng.integers(-4, 5, (7, nk, nj, ni)).astype(np.float64)
+    x = rng.integers(-8, 9, (nk, nj, ni)).astype(np.float64)
+    b = rng.integers(-100, 101, (nk, nj, ni)).astype(np.float64)
+    r32 = ora.residual_f32(A, b, x)
+    assert r32.dtype == np.float32
+    r = b.ravel() - dense.dense_A(A) @ x.ravel()
+    assert np.array_equal(r32.ravel().astype(np.float64), r)
+
+
+def test_fp32_form_diagonal_system_is_exact(ora):
+    """A = diag(A_P) with powers of two: L U = A, one update gives x = b / A_P
+    exactly and rho_1 = 0."""
+    ni, nj, nk = 4, 3, 5
+    rng = np.random.default_rng(41)
+    A = np.zeros((7, nk, nj, ni))
+    A[0] = 2.0 ** rng.integers(-3, 4, (nk, nj, ni))
+    b = rng.integers(-50, 51, (nk, nj, ni)).astype(np.float64)
+    b[0, 0, 0] = 7.0
+    LU = ora.factor(A, 0.92)
+    x, hist = ora.iterate(A, LU, b, np.zeros_like(b), 1, fp32=True)
+    assert np.array_equal(x, b / A[0])
+    assert hist[0] == 1.0 and hist[1] == 0.0
+
+
+@pytest.mark.parametrize("kind", ["cd", "poisson", "stretched"])
+def test_fp32_form_tracks_dense_defect_correction(ora, kind):
+    """Eight FP32 updates stay within a few FP32 roundings of the exact
+    defect correction x_{n+1} = x_n + (L U)^-1 (b - A x_n), computed densely
+    in FP64 from the FP32-rounded A, factors and b (|dx| <= 2e-6 |x|, about
+    32 u32; rho within 1e-6)."""
+    ni, nj, nk = 6, 5, 7
+    rng = np.random.default_rng(42)
+    if kind == "cd":
+        A = problems.convection_diffusion(ni, nj, nk, rng)
+    elif kind == "poisson":
+        A = problems.poisson(ni, nj, nk)
+    else:
+        A = problems.stretched_poisson(ni, nj, nk)
+    b = rng.uniform(-1, 1, (nk, nj, ni))
+    LU = ora.factor(A, 0.92)
+    n = 8
+    x, hist = ora.iterate(A, LU, b, np.zeros_like(b), n, fp32=True)
+    A32 = A.astype(np.float32).astype(np.float64)
+    L, U = dense.dense_LU(LU.astype(np.float32).astype(np.float64))
+    Ad = dense.dense_A(A32)
+    b32 = b.astype(np.float32).astype(np.float64).ravel()
+    xr = np.zeros(b.size)
+    for m in range(n + 1):
+        r = b32 - Ad @ xr
+        assert abs(hist[m] - np.linalg.norm(r) / np.linalg.norm(b32)) <= 1e-6
+        if m < n:
+            xr = xr + np.linalg.solve(L @ U, r)
+    assert np.abs(x.ravel() - xr).max() <= 2e-6 * np.abs(xr).max()
+
+
+def test_fp32_form_stalls_at_single_precision(ora):
+    """The FP32 residual cannot fall far below the FP32 rounding of A x: the
+    all-FP32 form stalls between 1e-8 and 1e-5 where the FP64 form goes on to
+    1e-12; down to 1e-5 it needs the mixed form's iteration count (within 2)."""
+    ni, nj, nk = 16, 16, 16
+    A = problems.convection_diffusion(ni, nj, nk, np.random.default_rng(31))
+    b = np.random.default_rng(32).uniform(-1, 1, (nk, nj, ni))
+    LU = ora.factor(A, 0.92)
+    _, _, _, h32 = ora.solve(A, LU, b, np.zeros_like(b), 1e-12, 200, fp32=True)
+    _, it64, rr64, _ = ora.solve(A, LU, b, np.zeros_like(b), 1e-12, 200)
+    assert rr64 <= 1e-12 and it64 < 200
+    assert 1e-8 <= h32.min() <= 1e-5
+    _, itm, _, _ = ora.solve(A, LU, b, np.zeros_like(b), 1e-5, 200, mixed=True)
+    _, it3, rr3, _ = ora.solve(A, LU, b, np.zeros_like(b), 1e-5, 200, fp32=True)
+    assert rr3 <= 1e-5 and abs(it3 - itm) <= 2
+
+
+def test_fp32_form_zero_rhs(ora):
+    A = problems.poisson(4, 4, 4)
+    LU = ora.factor(A, 0.92)
+    x, it, rr, _ = ora.solve(A, LU, np.zeros((4, 4, 4)), np.ones((4, 4, 4)), 1e-5, 10, fp32=True)
+    assert it == 0 and rr == 0.0 and np.all(x == 0)
