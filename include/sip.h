@@ -45,8 +45,15 @@ typedef enum {
 
 typedef enum {
     SIP_FP64 = 0,           /* factors and sweeps in FP64                          */
-    SIP_MIXED = 1           /* factors and sweeps in FP32; residual, norm and the
+    SIP_MIXED = 1,          /* factors and sweeps in FP32; residual, norm and the
                                solution update in FP64 (defect correction)         */
+    SIP_FP32 = 2            /* the single-precision relaxation of Sec. 4.1: b and
+                               x converted to FP32 on entry and x back to FP64 on
+                               exit; coefficients, factors (computed in FP64),
+                               residual, sweeps and update all in FP32.  The
+                               residual stalls near 1e-7 relative; the norm is
+                               that of the FP32 residual, summed in FP64.  Not
+                               with SIP_STORAGE_SYMMETRIC.                        */
 } sip_precision;
 
 /* Storage of the coefficients during the sweeps (the paper's section 4.1,
@@ -77,7 +84,8 @@ typedef struct {
 
 typedef struct {
     int32_t iters;          /* updates applied                                     */
-    double rel_res;         /* ||b - A x||_2 / ||b||_2 of the returned x (FP64)    */
+    double rel_res;         /* ||b - A x||_2 / ||b||_2 of the returned x (FP64;
+                               SIP_FP32: the FP32 residual of the FP32 iterate)   */
     double seconds;         /* host wall time of the call                          */
 } sip_info;
 
@@ -97,7 +105,7 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out);
 /* sip_iterate -- apply exactly n_iter SIP updates to x (Sec. 4.1: the
  * original driver relaxes a fixed number of iterations):
  *   r = b - A x (FP64), forward sweep L y = r, backward sweep U d = y,
- *   x += d.
+ *   x += d (residual and update in FP32 with SIP_FP32).
  *   b        device, read only.
  *   x        device, read as the start vector and overwritten.
  *   n_iter   >= 0.
@@ -120,7 +128,8 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
 /* sip_export_factors -- write the factors in natural [nk][nj][ni] order as
  * FP64 into seven device arrays of ni*nj*nk doubles, in the order
  * Lb, Lw, Ls, Lp, Un, Ue, Ut (Lp is the pivot, U has a unit diagonal).
- * In the mixed precision the FP32 factors are widened.  Stream-ordered. */
+ * In the mixed and FP32 precisions the FP32 factors are widened.
+ * Stream-ordered. */
 sip_status sip_export_factors(sip_system h, double *const out[7], void *stream);
 
 /* sip_profile_sweeps -- measurement hook: runs n_iter iterations like

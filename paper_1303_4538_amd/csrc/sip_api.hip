@@ -1,8 +1,9 @@
 // Host runtime and C ABI of the SIP library (include/sip.h).
 //
 // A sip_system owns, in device memory and in the tile-sheared layout of
-// sip_internal.h: the coefficients (FP64), the factors (FP64 or FP32), b, x
-// (FP64), the forward-sweep result y, the tagged face words, per-tile
+// sip_internal.h: the coefficients (FP64; FP32 for the sweeps of the all-FP32
+// arithmetic), the factors (FP64 or FP32), b, x (FP64, or FP32 in the all-FP32
+// arithmetic), the forward-sweep result y, the tagged face words, per-tile
 // partial sums, the residual history and a control block.  A solve is a
 // stream-ordered sequence of launches: reorder b and x in, (forward sweep,
 // backward sweep) per iteration, reorder x out.  The stop test runs on the
@@ -163,6 +164,26 @@ sip_status ensure_hist(sip_system_s *h, int n, hipStream_t s)
     return SIP_OK;
 }
 
+// x in the library's layout: behind b, in the arithmetic's precision
+static void *x_of(const sip_system_s *h)
+{
+    return h->precision == ARITH_F32 ? (void *)((float *)h->bx + h->g.elems) : (void *)(h->bx + h->g.elems);
+}
+
+// Copies b and x into the library's layout (rounded to FP32 in the all-FP32
+// arithmetic, where the relaxation starts from single-precision copies).
+static hipError_t stage_in(const sip_system_s *h, const double *b, const double *x, hipStream_t s)
+{
+    const double *src[2] = {b, x};
+    return launch_to_sheared(h->g, 2, src, h->bx, h->g.elems, h->precision == ARITH_F32 ? SHEAR_F32 : SHEAR_F64, s);
+}
+
+// Natural-order FP64 x (widened from FP32 in the all-FP32 arithmetic).
+static hipError_t stage_out(const sip_system_s *h, double *x, hipStream_t s)
+{
+    return launch_from_sheared(h->g, x_of(h), h->precision == ARITH_F32, x, h->ctl, s);
+}
+
 LaunchArgs fwd_args(const sip_system_s *h)
 {
     return LaunchArgs{h->d_job, h->order_f, h->lc, h->g.ntiles, h->timeout_ticks};
@@ -176,8 +197,8 @@ static sip_status launch_iterations(sip_system_s *h, int n, hipStream_t s)
 {
     const LaunchArgs fa = fwd_args(h), ba = bwd_args(h);
     for (int q = 0; q < n; q++) {
-        HIPTRY(launch_forward(fa, h->fp32, h->plan, s));
-        HIPTRY(launch_backward(ba, h->fp32, h->plan, s));
+        HIPTRY(launch_forward(fa, h->precision, h->plan, s));
+        HIPTRY(launch_backward(ba, h->precision, h->plan, s));
     }
     return SIP_OK;
 }
@@ -250,9 +271,12 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     if (p->ni < 1 || p->nj < 1 || p->nk < 1) return set_error(SIP_EINVAL, "dims must be >= 1");
     if ((long long)p->ni * p->nj * p->nk > (1ll << 34)) return set_error(SIP_EINVAL, "block too large");
     if (!(p->alpha >= 0.0 && p->alpha <= 1.0)) return set_error(SIP_EINVAL, "alpha must be in [0, 1]");
-    if (p->precision != SIP_FP64 && p->precision != SIP_MIXED) return set_error(SIP_EINVAL, "unknown precision");
+    if (p->precision != SIP_FP64 && p->precision != SIP_MIXED && p->precision != SIP_FP32)
+        return set_error(SIP_EINVAL, "unknown precision");
     if (p->storage != SIP_STORAGE_FULL && p->storage != SIP_STORAGE_SYMMETRIC)
         return set_error(SIP_EINVAL, "unknown storage");
+    if (p->storage == SIP_STORAGE_SYMMETRIC && p->precision == SIP_FP32)
+        return set_error(SIP_EINVAL, "the symmetric storage is available with SIP_FP64 and SIP_MIXED only");
     for (int d = 0; d < 7; d++)
         if (!p->a[d]) return set_error(SIP_EINVAL, "coefficient pointer %d is NULL", d);
     hipStream_t s = (hipStream_t)stream;
@@ -262,7 +286,7 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
         delete h;
         return set_error(SIP_EINVAL, "block too large: more than 2^28 cells in the sheared layout");
     }
-    h->fp32 = p->precision == SIP_MIXED;
+    h->fp32 = p->precision != SIP_FP64;
     h->precision = p->precision;
     h->alpha = p->alpha;
     if (hipGetDevice(&h->device) != hipSuccess) {
@@ -295,7 +319,7 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
             return bail(set_error(SIP_EDEVICE, "symmetry check failed"));
         if (bad) return bail(set_error(SIP_EINVAL, "symmetric storage requested but %u couplings differ", bad));
     }
-    if (launch_to_sheared(g, 7, p->a, h->A, g.elems, 1, s) != hipSuccess)
+    if (launch_to_sheared(g, 7, p->a, h->A, g.elems, SHEAR_COEF, s) != hipSuccess)
         return bail(set_error(SIP_EDEVICE, "reorder launch failed"));
     if (launch_init_ctl(h->ctl, 1, 0, 0.0, 1, s) != hipSuccess) return bail(set_error(SIP_EDEVICE, "init failed"));
     st = ensure_hist(h, 64, s);
@@ -304,7 +328,7 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     J.g = g;
     J.A = h->A;
     J.b = h->bx;
-    J.x = h->bx + g.elems;
+    J.x = x_of(h);
     J.LU = h->LU;
     J.y = h->y;
     J.face = h->face;
@@ -334,9 +358,11 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
         hipStreamSynchronize(s) != hipSuccess)
         return bail(set_error(SIP_EDEVICE, "factorisation failed: %s", hipGetErrorString(hipGetLastError())));
     if (h->h_ctl->stop != RUN) return bail(stop_status(h->h_ctl->stop));
-    // the sweeps read the symmetric storage; it overwrites the full one, which
-    // only the factorisation needed
-    if (h->sym && (launch_to_sheared(g, 7, p->a, h->A, g.elems, 2, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess))
+    // the sweeps read the symmetric or the FP32 storage; it overwrites the full
+    // FP64 one, which only the factorisation needed
+    const int sweep_coef = h->sym ? SHEAR_SYM : h->precision == SIP_FP32 ? SHEAR_COEF32 : SHEAR_COEF;
+    if (sweep_coef != SHEAR_COEF && (launch_to_sheared(g, 7, p->a, h->A, g.elems, sweep_coef, s) != hipSuccess ||
+                                     hipStreamSynchronize(s) != hipSuccess))
         return bail(set_error(SIP_EDEVICE, "reorder launch failed"));
     *out = h;
     return SIP_OK;
@@ -348,9 +374,7 @@ sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
     if (n_iter < 0) return set_error(SIP_EINVAL, "n_iter must be >= 0");
     hipStream_t s = (hipStream_t)stream;
     TRY(ensure_hist(h, n_iter + 1, s));
-    const Geom &g = h->g;
-    const double *src[2] = {b, x};
-    HIPTRY(launch_to_sheared(g, 2, src, h->bx, g.elems, 0, s));
+    HIPTRY(stage_in(h, b, x, s));
     HIPTRY(launch_init_ctl(h->ctl, 1, (uint32_t)n_iter, 0.0, 0, s));
     int left = n_iter;
     while (left >= CHUNK) {
@@ -358,8 +382,8 @@ sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
         left -= CHUNK;
     }
     TRY(launch_iterations(h, left, s));
-    HIPTRY(launch_forward(fwd_args(h), h->fp32, h->plan, s));   // residual of the final iterate
-    HIPTRY(launch_from_sheared_f64(g, h->bx + g.elems, x, h->ctl, s));
+    HIPTRY(launch_forward(fwd_args(h), h->precision, h->plan, s));   // residual of the final iterate
+    HIPTRY(stage_out(h, x, s));
     if (!rel_res_hist) return SIP_OK;
     HIPTRY(hipMemcpyAsync(h->h_hist, h->hist, (size_t)(n_iter + 1) * 8, hipMemcpyDeviceToHost, s));
     HIPTRY(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -382,9 +406,7 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
     hipStream_t s = (hipStream_t)stream;
     const auto t0 = std::chrono::steady_clock::now();
     TRY(ensure_hist(h, max_iter + 1, s));
-    const Geom &g = h->g;
-    const double *src[2] = {b, x};
-    HIPTRY(launch_to_sheared(g, 2, src, h->bx, g.elems, 0, s));
+    HIPTRY(stage_in(h, b, x, s));
     HIPTRY(launch_init_ctl(h->ctl, 1, (uint32_t)max_iter, rtol, 0, s));
     hipEvent_t ev[2];
     HIPTRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
@@ -415,7 +437,7 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
         hipStreamSynchronize(s);
         return st;
     }
-    HIPTRY(launch_from_sheared_f64(g, h->bx + g.elems, x, h->ctl, s));
+    HIPTRY(stage_out(h, x, s));
     HIPTRY(hipMemcpyAsync(&h->h_ctl[2], h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
     const Ctl &c = h->h_ctl[2];
@@ -444,9 +466,7 @@ sip_status sip_profile_sweeps(sip_system h, const double *b, double *x, int32_t 
     if (n_iter < 1) return set_error(SIP_EINVAL, "n_iter must be >= 1");
     hipStream_t s = (hipStream_t)stream;
     TRY(ensure_hist(h, n_iter + 1, s));
-    const Geom &g = h->g;
-    const double *src[2] = {b, x};
-    HIPTRY(launch_to_sheared(g, 2, src, h->bx, g.elems, 0, s));
+    HIPTRY(stage_in(h, b, x, s));
     HIPTRY(launch_init_ctl(h->ctl, 1, (uint32_t)n_iter, 0.0, 0, s));
     std::vector<hipEvent_t> ev(2 * n_iter + 1);
     for (auto &e : ev) HIPTRY(hipEventCreate(&e));
@@ -454,11 +474,13 @@ sip_status sip_profile_sweeps(sip_system h, const double *b, double *x, int32_t 
     sip_status st = SIP_OK;
     if (hipEventRecord(ev[0], s) != hipSuccess) st = set_error(SIP_EDEVICE, "event record failed");
     for (int q = 0; q < n_iter && st == SIP_OK; q++) {
-        if (launch_forward(fa, h->fp32, h->plan, s) != hipSuccess || hipEventRecord(ev[2 * q + 1], s) != hipSuccess ||
-            launch_backward(ba, h->fp32, h->plan, s) != hipSuccess || hipEventRecord(ev[2 * q + 2], s) != hipSuccess)
+        if (launch_forward(fa, h->precision, h->plan, s) != hipSuccess ||
+            hipEventRecord(ev[2 * q + 1], s) != hipSuccess ||
+            launch_backward(ba, h->precision, h->plan, s) != hipSuccess ||
+            hipEventRecord(ev[2 * q + 2], s) != hipSuccess)
             st = set_error(SIP_EDEVICE, "launch failed");
     }
-    if (st == SIP_OK && launch_from_sheared_f64(g, h->bx + g.elems, x, h->ctl, s) != hipSuccess)
+    if (st == SIP_OK && stage_out(h, x, s) != hipSuccess)
         st = set_error(SIP_EDEVICE, "reorder failed");
     if (st == SIP_OK && hipStreamSynchronize(s) != hipSuccess) st = set_error(SIP_EDEVICE, "synchronise failed");
     double f = 0.0, bk = 0.0;

@@ -52,6 +52,15 @@ __host__ __device__ inline long long sym_index(int a, long long e, long long ele
     return a == 0 ? e : a == 2 ? elems + 2 * e : a == 4 ? elems + 2 * e + 1 : 3 * elems + e;
 }
 
+// FP32 coefficient storage of the all-FP32 arithmetic, 8 * elems floats in
+// two 16-byte groups per cell: (A_P, A_W, A_E, A_S) in [0, 4 elems) and
+// (A_N, A_B, A_T, 0) in [4 elems, 8 elems), so the forward sweep loads the
+// seven coefficients with two loads.
+__host__ __device__ inline long long coef32_index(int a, long long e, long long elems)
+{
+    return a < 4 ? 4 * e + a : 4 * elems + 4 * e + (a - 4);
+}
+
 __host__ __device__ inline long long coef_index(int a, long long e, long long elems)
 {
     return a < 6 ? (long long)(a >> 1) * 2 * elems + 2 * e + (a & 1) : 6 * elems + e;
@@ -63,6 +72,14 @@ __host__ __device__ inline long long factor_index(int d, long long e, long long 
     constexpr int W = 16 / (int)sizeof(F);   // factors per 16-byte group
     return d < 4 ? (long long)(d / W) * W * elems + W * e + d % W : d * elems + e;
 }
+
+// Arithmetic of the sweeps (the values of sip_precision):
+//   ARITH_F64    factors, sweeps, residual and update in FP64;
+//   ARITH_MIXED  FP32 factors and sweeps; residual, norm and update in FP64;
+//   ARITH_F32    FP32 coefficients, factors, b and x: the whole relaxation in
+//                FP32 (the factors are still computed in FP64 and rounded).
+enum Arith : int { ARITH_F64 = 0, ARITH_MIXED = 1, ARITH_F32 = 2 };
+constexpr int NARITH = 3;
 
 enum Stop : uint32_t {
     RUN = 0,
@@ -100,9 +117,9 @@ struct Ctl {
 // One block of a batched launch (a single solve is a batch of one).
 struct Job {
     Geom g;
-    const double *A;           // 7 * elems FP64 coefficients P,W,E,S,N,B,T (sheared)
-    const double *b;           // elems FP64
-    double *x;                 // elems FP64
+    const double *A;           // coefficients P,W,E,S,N,B,T (sheared; FP32 groups in ARITH_F32 sweeps)
+    const void *b;             // elems FP64 (FP32 in ARITH_F32)
+    void *x;                   // elems FP64 (FP32 in ARITH_F32)
     void *LU;                  // 7 * elems factors Lb,Lw,Ls,1/Lp,Un,Ue,Ut (FP64 or FP32)
     void *y;                   // elems forward-sweep result (FP64 or FP32)
     uint64_t *face;            // ntiles * steps * FACE_WORDS tagged face words
@@ -147,15 +164,19 @@ Geom make_geom(int ni, int nj, int nk);
 
 // Kernel launchers (sip_kernels.hip).  All are asynchronous on `s`.
 hipError_t launch_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int reset_epoch, hipStream_t s);
-// coefficients = 1: the 7 arrays are A (masked at the block boundary, stored
-// interleaved); 2: the same in the symmetric storage (P, E, N, T only).
-hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, double *dst,
-                             long long dst_stride, int coefficients, hipStream_t s);
+// Layouts written by launch_to_sheared: plain FP64 or FP32 arrays (array a
+// at dst + a * dst_stride elements), or the 7 coefficient arrays (masked at
+// the block boundary) in the interleaved FP64, symmetric FP64 or FP32 group
+// storage.
+enum Shear : int { SHEAR_F64 = 0, SHEAR_COEF = 1, SHEAR_SYM = 2, SHEAR_F32 = 3, SHEAR_COEF32 = 4 };
+hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, void *dst,
+                             long long dst_stride, int shear, hipStream_t s);
 // Counts the cells whose W, S or B coupling differs from the neighbour's E, N
 // or T one (bitwise) into *bad (device, zeroed by the caller).
 hipError_t launch_check_symmetric(int ni, int nj, int nk, const double *const *a, unsigned *bad, hipStream_t s);
-hipError_t launch_from_sheared_f64(const Geom &g, const double *src, double *dst, const Ctl *zero_if_zero_rhs,
-                                   hipStream_t s);
+// Natural-order FP64 copy of a sheared FP64 (src_f32 = 0) or FP32 array.
+hipError_t launch_from_sheared(const Geom &g, const void *src, int src_f32, double *dst, const Ctl *zero_if_zero_rhs,
+                               hipStream_t s);
 hipError_t launch_export_factors(const Geom &g, const void *LU, int fp32, double *const *dst, hipStream_t s);
 hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s);
 // Launch shape of the sweeps: loader phases per tile (1 to 3).  Each phase
@@ -165,7 +186,7 @@ constexpr int MAX_PHASES = 3;
 struct SweepPlan {
     int phases = 2;
 };
-hipError_t launch_forward(const LaunchArgs &a, int fp32, const SweepPlan &p, hipStream_t s);
-hipError_t launch_backward(const LaunchArgs &a, int fp32, const SweepPlan &p, hipStream_t s);
+hipError_t launch_forward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s);
+hipError_t launch_backward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s);
 
 }  // namespace sipk

@@ -9,8 +9,8 @@
 // tile edge they come from the neighbour tile's face record in global memory.
 // In the sweeps, "loader" waves stream coefficient / factor / vector planes
 // from HBM a few steps ahead, do all work that does not depend on the
-// recurrence (the FP64 residual, the FP64 update of x) and stage operands in
-// an LDS ring.  Recurrence and loader waves meet at one workgroup barrier per
+// recurrence (the residual, the update of x; FP64 except in the all-FP32
+// arithmetic) and stage operands in an LDS ring.  Recurrence and loader waves meet at one workgroup barrier per
 // step; the barrier waits on LDS traffic only, so loads stay in flight.
 //
 // Face records: a value crossing a tile edge is written as 64-bit words
@@ -27,6 +27,7 @@
 #include "sip_internal.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace sipk {
 
@@ -271,6 +272,7 @@ __device__ __forceinline__ void stg(GLOBAL T *base, uint32_t idx, T v)
 // 16-byte groups of the coefficient and factor storage (sip_internal.h).
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef float flt3 __attribute__((ext_vector_type(3)));   // 16-byte slot, 12 bytes loaded
 template <typename F> struct Grp;
 template <> struct Grp<float> {
     typedef flt4 V;
@@ -387,48 +389,54 @@ __device__ __forceinline__ int sweep_steps(int steps, int pd)
     return (steps + 1 + pd - 1) / pd * pd;
 }
 
-// Forward: residual r = b - A x (FP64, fused), forward substitution
+// Forward: residual r = b - A x (fused, in the precision R of b and x: FP64,
+// or FP32 in the all-FP32 arithmetic), forward substitution
 // y = (r - Lb y_B - Lw y_W - Ls y_S) / Lp in precision F, per-tile partial
-// sums of r^2 (and of b^2, used at iteration 0).
+// sums of r^2 (and of b^2, used at iteration 0), summed in FP64.
 
-// Full storage: a[] = A_P..A_T of plane f.  Symmetric storage: a[0] = A_P
-// of plane f, a[2], a[4], a[6] = A_E, A_N, A_T of plane f + 1 (staged into
-// the coefficient ring), a[1], a[3] = A_E of the W neighbour / A_N of the S
-// neighbour across a tile edge.
-template <typename F>
+// Full storage: a[] = A_P..A_T of plane f.  Symmetric storage (FP64 only):
+// a[0] = A_P of plane f, a[2], a[4], a[6] = A_E, A_N, A_T of plane f + 1
+// (staged into the coefficient ring), a[1], a[3] = A_E of the W neighbour /
+// A_N of the S neighbour across a tile edge.
+template <typename F, typename R>
 struct FwdLoad {
-    double a[7];
-    double b;
-    double x2;     // x on plane f + 2, staged into the LDS plane ring for the next steps
-    double hx;     // x across the W or E tile edge (edge slots only)
-    double hy;     // x across the S or N tile edge (edge slots only)
+    R a[7];
+    R b;
+    R x2;          // x on plane f + 2, staged into the LDS plane ring for the next steps
+    R hx;          // x across the W or E tile edge (edge slots only)
+    R hy;          // x across the S or N tile edge (edge slots only)
     F l[4];        // Lb, Lw, Ls, 1/Lp
 };
 
 // Uniform base pointers and per-lane index deltas of a forward loader.
-template <typename F>
+template <typename F, typename R>
 struct FwdSrc {
-    const GLOBAL dbl2 *AP[3];   // (A_P, A_W), (A_E, A_S), (A_N, A_B)
-    const GLOBAL double *AT, *b, *x;
+    const GLOBAL dbl2 *AP[3];   // FP64: (A_P, A_W), (A_E, A_S), (A_N, A_B)
+    const GLOBAL double *AT;
+    const GLOBAL flt4 *A4;      // FP32: (A_P, A_W, A_E, A_S)
+    const GLOBAL flt3 *A3;      // FP32: (A_N, A_B, A_T) of the (A_N, A_B, A_T, 0) group
+    const GLOBAL R *b, *x;
     const GLOBAL typename Grp<F>::V *L[Grp<F>::N];   // Lb, Lw, Ls, 1/Lp
     const GLOBAL double *SP, *ST, *SEN;                // symmetric storage: A_P, A_T, (A_E, A_N) pairs
     uint32_t e0;          // sheared index of (plane 0, this quadrant, this lane)
     int32_t hx, hy;       // index deltas of the x halo this slot reads across a tile edge (0: none)
 };
 
-template <typename F>
-__device__ __forceinline__ FwdSrc<F> fwd_src(const Job &J, const TileView &v, int q)
+template <typename F, typename R>
+__device__ __forceinline__ FwdSrc<F, R> fwd_src(const Job &J, const TileView &v, int q)
 {
     const Geom &g = J.g;
-    FwdSrc<F> s;
+    FwdSrc<F, R> s;
 #pragma unroll
     for (int p = 0; p < 3; p++) s.AP[p] = (const GLOBAL dbl2 *)(gp(J.A) + 2 * p * g.elems);
     s.AT = gp(J.A) + 6 * g.elems;
+    s.A4 = (const GLOBAL flt4 *)gp((const float *)J.A);
+    s.A3 = (const GLOBAL flt3 *)(gp((const float *)J.A) + 4 * g.elems);
     s.SP = gp(J.A);
     s.SEN = gp(J.A) + g.elems;
     s.ST = gp(J.A) + 3 * g.elems;
-    s.b = gp(J.b);
-    s.x = gp((const double *)J.x);
+    s.b = gp((const R *)J.b);
+    s.x = gp((const R *)J.x);
 #pragma unroll
     for (int k = 0; k < Grp<F>::N; k++)
         s.L[k] = (const GLOBAL typename Grp<F>::V *)(gp((const F *)J.LU) + k * Grp<F>::W * g.elems);
@@ -450,13 +458,26 @@ __device__ __forceinline__ FwdSrc<F> fwd_src(const Job &J, const TileView &v, in
 
 // Branch-free: inactive slots read their own zero-padded slot (every index
 // stays inside the tile's planes -1..steps for f in [0, steps)).
-template <typename F>
-__device__ __forceinline__ void fwd_issue(FwdLoad<F> &c, const FwdSrc<F> &s, const TileView &v, int q, int f, int steps,
-                                          int nk, bool sym)
+template <typename F, typename R>
+__device__ __forceinline__ void fwd_issue(FwdLoad<F, R> &c, const FwdSrc<F, R> &s, const TileView &v, int q, int f,
+                                          int steps, int nk, bool sym)
 {
     const bool act = v.active(f, nk, q);
     const uint32_t e = s.e0 + (uint32_t)f * PLANE;
-    if (sym) {
+    if constexpr (std::is_same<R, float>::value) {
+        // the pad of the second group is not loaded: a dead lane of a load in
+        // flight would be reused as soon as the load completes, which makes
+        // the compiler wait for every outstanding load
+        const flt4 c0 = ldg(s.A4, e);
+        const flt3 c1 = ldg(s.A3, e);
+        c.a[0] = c0.x;
+        c.a[1] = c0.y;
+        c.a[2] = c0.z;
+        c.a[3] = c0.w;
+        c.a[4] = c1.x;
+        c.a[5] = c1.y;
+        c.a[6] = c1.z;
+    } else if (sym) {
         const uint32_t e1 = s.e0 + (uint32_t)min(f + 1, steps) * PLANE;   // plane `steps` is the zero margin
         c.a[0] = ldg(s.SP, e);
         const dbl2 en = ldg((const GLOBAL dbl2 *)s.SEN, e1);
@@ -492,15 +513,16 @@ __device__ __forceinline__ void fwd_issue(FwdLoad<F> &c, const FwdSrc<F> &s, con
     c.hy = ldg(s.x, e + (act ? s.hy : 0));
 }
 
-template <typename F, int NP>
+template <typename F, typename R, int NP>
 __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
 {
     constexpr int NV = NW<F>::n;
     constexpr int NL = NQ * NP;
+    constexpr bool R64 = std::is_same<R, double>::value;   // the symmetric storage exists in FP64 only
     __shared__ F ring[2][5][NQ][TT];        // r, Lb, Lw, Ls, 1/Lp of two steps
     __shared__ F ybuf[2][NQ][TT];
-    __shared__ double xring[4][NQ][TT];     // x on planes f-1..f+2 (slot = plane & 3)
-    __shared__ double cring[4][3][NQ][TT];  // symmetric storage: A_E, A_N, A_T on planes f-1..f+1
+    __shared__ R xring[4][NQ][TT];          // x on planes f-1..f+2 (slot = plane & 3)
+    __shared__ double cring[R64 ? 4 : 1][3][NQ][TT];   // symmetric storage: A_E, A_N, A_T on planes f-1..f+1
     __shared__ int s_buf[4];
     __shared__ double s_part[NL][2];
 
@@ -517,7 +539,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
     const uint32_t tag = J.ctl->epoch;
     const uint32_t iter = J.ctl->iter;
     const Geom g = J.g;
-    const bool sym = J.sym != 0;
+    const bool sym = R64 && J.sym != 0;
     const TileView v = make_view(g, as.tile, lane);
     const int U = sweep_steps(g.steps, PD);
     const int FW = J.fw;
@@ -528,11 +550,11 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
     if (wave >= 1 && wave <= NQ) {   // phase-0 loaders: planes -1 (zero margin), 0 and 1 of the x ring
         const int q = wave - 1;
         const uint32_t e0 = (uint32_t)v.base + (uint32_t)(q * TT);
-        const GLOBAL double *xg = gp((const double *)J.x);
-        xring[3][q][lane] = 0.0;
+        const GLOBAL R *xg = gp((const R *)J.x);
+        xring[3][q][lane] = R(0);
         xring[0][q][lane] = ldg(xg, e0);
         xring[1][q][lane] = ldg(xg, e0 + (uint32_t)min(1, g.steps) * PLANE);
-        if (sym) {   // A_E, A_N, A_T of planes -1 (zero margin) and 0
+        if constexpr (R64) if (sym) {   // A_E, A_N, A_T of planes -1 (zero margin) and 0
             const GLOBAL double *ag = gp(J.A);
 #pragma unroll
             for (int d = 0; d < 3; d++) cring[3][d][q][lane] = 0.0;
@@ -658,8 +680,8 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
         const int lw = wave - 1;
         const int q = lw % NQ, ph = lw / NQ;
         const int qa = q & 1, qb = q >> 1;
-        const FwdSrc<F> src = fwd_src<F>(J, v, q);
-        FwdLoad<F> c;
+        const FwdSrc<F, R> src = fwd_src<F, R>(J, v, q);
+        FwdLoad<F, R> c;
         if (ph < g.steps) fwd_issue(c, src, v, q, ph, g.steps, g.nk, sym);
         GLOBAL F *yout = gp((F *)J.y);
         double rr = 0.0, bb = 0.0;
@@ -675,15 +697,15 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
             if (f < g.steps) {
                 // planes f-1..f+1 were staged by earlier turns
                 xring[(f + 2) & 3][q][lane] = c.x2;
-                const double xP = xring[f & 3][q][lane];
-                const double xB = xring[(f - 1) & 3][q][lane];
-                const double xT = xring[(f + 1) & 3][q][lane];
-                const double xW = inW ? xring[(f - 1 + qa) & 3][q ^ 1][lane - dW] : c.hx;
-                const double xE = inE ? xring[(f + qa) & 3][q ^ 1][lane + dE] : c.hx;
-                const double xS = inS ? xring[(f - 1 + qb) & 3][q ^ 2][lane - dS] : c.hy;
-                const double xN = inN ? xring[(f + qb) & 3][q ^ 2][lane + dN] : c.hy;
-                double aP = c.a[0], aW = c.a[1], aE = c.a[2], aS = c.a[3], aN = c.a[4], aB = c.a[5], aT = c.a[6];
-                if (sym) {
+                const R xP = xring[f & 3][q][lane];
+                const R xB = xring[(f - 1) & 3][q][lane];
+                const R xT = xring[(f + 1) & 3][q][lane];
+                const R xW = inW ? xring[(f - 1 + qa) & 3][q ^ 1][lane - dW] : c.hx;
+                const R xE = inE ? xring[(f + qa) & 3][q ^ 1][lane + dE] : c.hx;
+                const R xS = inS ? xring[(f - 1 + qb) & 3][q ^ 2][lane - dS] : c.hy;
+                const R xN = inN ? xring[(f + qb) & 3][q ^ 2][lane + dN] : c.hy;
+                R aP = c.a[0], aW = c.a[1], aE = c.a[2], aS = c.a[3], aN = c.a[4], aB = c.a[5], aT = c.a[6];
+                if constexpr (R64) if (sym) {
                     // A_W = A_E of the W cell, A_S = A_N of the S cell, A_B = A_T of the B
                     // cell, found where the x ring finds x_W, x_S, x_B; plane f + 1 is
                     // staged for the next turns
@@ -697,10 +719,10 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                     aW = inW ? cring[(f - 1 + qa) & 3][0][q ^ 1][lane - dW] : (wall_w ? 0.0 : c.a[1]);
                     aS = inS ? cring[(f - 1 + qb) & 3][1][q ^ 2][lane - dS] : (wall_s ? 0.0 : c.a[3]);
                 }
-                const double ax = aP * xP + aW * xW + aE * xE + aS * xS + aN * xN + aB * xB + aT * xT;
-                const double r = c.b - ax;
-                rr += r * r;
-                bb += c.b * c.b;
+                const R ax = aP * xP + aW * xW + aE * xE + aS * xS + aN * xN + aB * xB + aT * xT;
+                const R r = c.b - ax;
+                rr += (double)r * (double)r;
+                bb += (double)c.b * (double)c.b;
                 const int slot = f & 1;
                 ring[slot][0][q][lane] = (F)r;
                 ring[slot][1][q][lane] = c.l[0];
@@ -780,38 +802,38 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
 
 // Backward: d = y - Un d_N - Ue d_E - Ut d_T in reverse local-hyperplane
 // order (step s visits plane steps - 1 - s; inside a lane quadrant (1,1)
-// first, (0,0) last), then x += d in FP64.
+// first, (0,0) last), then x += d in the precision R of x.
 
-template <typename F>
+template <typename F, typename R>
 struct BwdLoad {
     F y, u[3];   // y, Un, Ue, Ut
-    double x;
+    R x;
 };
 
-template <typename F>
+template <typename F, typename R>
 struct BwdSrc {
     const GLOBAL F *y;
     const GLOBAL F *U[3];
-    GLOBAL double *x;
+    GLOBAL R *x;
     uint32_t e0;
 };
 
-template <typename F>
-__device__ __forceinline__ void bwd_issue(BwdLoad<F> &c, const BwdSrc<F> &s, int steps, int step)
+template <typename F, typename R>
+__device__ __forceinline__ void bwd_issue(BwdLoad<F, R> &c, const BwdSrc<F, R> &s, int steps, int step)
 {
     const uint32_t e = s.e0 + (uint32_t)(steps - 1 - step) * PLANE;
     c.y = ldg(s.y, e);
 #pragma unroll
     for (int d = 0; d < 3; d++) c.u[d] = ldg(s.U[d], e);
-    c.x = ldg((const GLOBAL double *)s.x, e);
+    c.x = ldg((const GLOBAL R *)s.x, e);
 }
 
-template <typename F, int NP>
+template <typename F, typename R, int NP>
 __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
 {
     constexpr int NV = NW<F>::n;
     __shared__ F ring[2][4][NQ][TT];     // y, Un, Ue, Ut
-    __shared__ double xring[4][NQ][TT];
+    __shared__ R xring[4][NQ][TT];
     __shared__ F dbuf[2][NQ][TT];
     __shared__ int s_buf[4];
 
@@ -942,13 +964,13 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
     } else {
         const int lw = wave - 1;
         const int q = lw % NQ, ph = lw / NQ;
-        BwdSrc<F> src;
+        BwdSrc<F, R> src;
         src.y = gp((const F *)J.y);
 #pragma unroll
         for (int d = 0; d < 3; d++) src.U[d] = gp((const F *)J.LU) + (4 + d) * g.elems;
-        src.x = gp(J.x);
+        src.x = gp((R *)J.x);
         src.e0 = (uint32_t)v.base + (uint32_t)(q * TT);
-        BwdLoad<F> c;
+        BwdLoad<F, R> c;
         if (ph < g.steps) bwd_issue(c, src, g.steps, ph);
         auto turn = [&](int f) {
             if (f < g.steps) {
@@ -966,8 +988,8 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
             if (p >= 0 && p < g.steps) {
                 const int sp = g.steps - 1 - p;
                 const F dv = dbuf[p & 1][q][lane];
-                const double xv = xring[p & 3][q][lane];
-                stg(src.x, src.e0 + (uint32_t)sp * PLANE, xv + (double)dv);   // padding: 0 + 0
+                const R xv = xring[p & 3][q][lane];
+                stg(src.x, src.e0 + (uint32_t)sp * PLANE, xv + (R)dv);   // padding: 0 + 0
             }
         };
         if (ph == 0) turn(0);
@@ -1218,13 +1240,15 @@ __device__ __forceinline__ long long sheared_index(const Geom &g, int i, int j, 
     return (long long)t * g.tile_elems + (long long)(k + ip + jp + 1) * PLANE + q * TT + jp * LI + ip;
 }
 
-// Copies narr natural-order arrays into the sheared layout, array a at
-// dst + a * dst_stride; with `coef` the 7 arrays are coefficients P..T: the
-// couplings pointing out of the block are zeroed and the arrays are stored
-// in the interleaved coefficient layout (coef = 1) or the symmetric one
-// (coef = 2, P, E, N, T only; sip_internal.h).
-__global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, double *dst, long long dst_stride, int coef)
+// Copies narr natural-order FP64 arrays into the sheared layout `shear`
+// (T = float for SHEAR_F32 and SHEAR_COEF32, rounding to nearest): plain
+// arrays at dst + a * dst_stride, or the 7 coefficient arrays P..T with the
+// couplings that point out of the block zeroed, in the interleaved, symmetric
+// (P, E, N, T only) or FP32 group storage (sip_internal.h).
+template <typename T>
+__global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, T *dst, long long dst_stride, int shear)
 {
+    const bool coef = shear == SHEAR_COEF || shear == SHEAR_SYM || shear == SHEAR_COEF32;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.elems; e += stride) {
         int i, j, k;
@@ -1238,10 +1262,13 @@ __global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, double *dst, long lo
                     (a == 4 && j == g.nj - 1) || (a == 5 && k == 0) || (a == 6 && k == g.nk - 1))
                     v = 0.0;
             }
-            if (coef == 2) {
-                if (a == 0 || a == 2 || a == 4 || a == 6) dst[sym_index(a, e, dst_stride)] = v;
+            if (shear == SHEAR_SYM) {
+                if (a == 0 || a == 2 || a == 4 || a == 6) dst[sym_index(a, e, dst_stride)] = (T)v;
+            } else if (shear == SHEAR_COEF32) {
+                dst[coef32_index(a, e, dst_stride)] = (T)v;
+                if (a == 6) dst[coef32_index(7, e, dst_stride)] = T(0);   // pad of the second group
             } else {
-                dst[coef ? coef_index(a, e, dst_stride) : a * dst_stride + e] = v;
+                dst[coef ? coef_index(a, e, dst_stride) : a * dst_stride + e] = (T)v;
             }
         }
     }
@@ -1265,7 +1292,8 @@ __global__ void k_check_symmetric(int ni, int nj, int nk, SrcPtrs a, unsigned *b
     if (cnt) atomicAdd(bad, cnt);
 }
 
-__global__ void k_from_sheared(Geom g, const double *src, double *dst, const Ctl *ctl)
+template <typename T>
+__global__ void k_from_sheared(Geom g, const T *src, double *dst, const Ctl *ctl)
 {
     const long long n = (long long)g.ni * g.nj * g.nk;
     const bool zero = ctl != nullptr && ctl->stop == ZERO_RHS;
@@ -1274,7 +1302,7 @@ __global__ void k_from_sheared(Geom g, const double *src, double *dst, const Ctl
         const int i = (int)(c % g.ni);
         const int j = (int)((c / g.ni) % g.nj);
         const int k = (int)(c / ((long long)g.ni * g.nj));
-        dst[c] = zero ? 0.0 : src[sheared_index(g, i, j, k)];
+        dst[c] = zero ? 0.0 : (double)src[sheared_index(g, i, j, k)];
     }
 }
 
@@ -1328,13 +1356,17 @@ hipError_t launch_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int 
     return hipGetLastError();
 }
 
-hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, double *dst, long long dst_stride,
-                             int coefficients, hipStream_t s)
+hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, void *dst, long long dst_stride,
+                             int shear, hipStream_t s)
 {
     SrcPtrs sp{};
     for (int a = 0; a < narr && a < 9; a++) sp.p[a] = src[a];
-    hipLaunchKernelGGL(k_to_sheared, dim3(grid_for(g.elems)), dim3(256), 0, s, g, narr, sp, dst, dst_stride,
-                       coefficients);
+    const dim3 grid(grid_for(g.elems));
+    if (shear == SHEAR_F32 || shear == SHEAR_COEF32)
+        hipLaunchKernelGGL(k_to_sheared<float>, grid, dim3(256), 0, s, g, narr, sp, (float *)dst, dst_stride, shear);
+    else
+        hipLaunchKernelGGL(k_to_sheared<double>, grid, dim3(256), 0, s, g, narr, sp, (double *)dst, dst_stride,
+                           shear);
     return hipGetLastError();
 }
 
@@ -1346,10 +1378,14 @@ hipError_t launch_check_symmetric(int ni, int nj, int nk, const double *const *a
     return hipGetLastError();
 }
 
-hipError_t launch_from_sheared_f64(const Geom &g, const double *src, double *dst, const Ctl *ctl, hipStream_t s)
+hipError_t launch_from_sheared(const Geom &g, const void *src, int src_f32, double *dst, const Ctl *ctl,
+                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_from_sheared, dim3(grid_for((long long)g.ni * g.nj * g.nk)), dim3(256), 0, s, g, src, dst,
-                       ctl);
+    const dim3 grid(grid_for((long long)g.ni * g.nj * g.nk));
+    if (src_f32)
+        hipLaunchKernelGGL(k_from_sheared<float>, grid, dim3(256), 0, s, g, (const float *)src, dst, ctl);
+    else
+        hipLaunchKernelGGL(k_from_sheared<double>, grid, dim3(256), 0, s, g, (const double *)src, dst, ctl);
     return hipGetLastError();
 }
 
@@ -1374,42 +1410,46 @@ hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int NP>
-static hipError_t launch_sweep_np(const LaunchArgs &a, int fp32, int backward, hipStream_t s)
+template <typename F, typename R, int NP>
+static hipError_t launch_sweep_t(const LaunchArgs &a, int backward, hipStream_t s)
 {
     const dim3 block(WAVE * (1 + NQ * NP));
-    if (backward) {
-        if (fp32)
-            hipLaunchKernelGGL((k_backward<float, NP>), dim3(a.total), block, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_backward<double, NP>), dim3(a.total), block, 0, s, a);
-    } else {
-        if (fp32)
-            hipLaunchKernelGGL((k_forward<float, NP>), dim3(a.total), block, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_forward<double, NP>), dim3(a.total), block, 0, s, a);
-    }
+    if (backward)
+        hipLaunchKernelGGL((k_backward<F, R, NP>), dim3(a.total), block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_forward<F, R, NP>), dim3(a.total), block, 0, s, a);
     return hipGetLastError();
 }
 
-static hipError_t launch_sweep(const LaunchArgs &a, int fp32, int backward, const SweepPlan &p, hipStream_t s)
+template <int NP>
+static hipError_t launch_sweep_np(const LaunchArgs &a, int arith, int backward, hipStream_t s)
 {
-    switch (p.phases) {
-    case 1: return launch_sweep_np<1>(a, fp32, backward, s);
-    case 2: return launch_sweep_np<2>(a, fp32, backward, s);
-    case 3: return launch_sweep_np<3>(a, fp32, backward, s);
+    switch (arith) {
+    case ARITH_F64: return launch_sweep_t<double, double, NP>(a, backward, s);
+    case ARITH_MIXED: return launch_sweep_t<float, double, NP>(a, backward, s);
+    case ARITH_F32: return launch_sweep_t<float, float, NP>(a, backward, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_forward(const LaunchArgs &a, int fp32, const SweepPlan &p, hipStream_t s)
+static hipError_t launch_sweep(const LaunchArgs &a, int arith, int backward, const SweepPlan &p, hipStream_t s)
 {
-    return launch_sweep(a, fp32, 0, p, s);
+    switch (p.phases) {
+    case 1: return launch_sweep_np<1>(a, arith, backward, s);
+    case 2: return launch_sweep_np<2>(a, arith, backward, s);
+    case 3: return launch_sweep_np<3>(a, arith, backward, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
-hipError_t launch_backward(const LaunchArgs &a, int fp32, const SweepPlan &p, hipStream_t s)
+hipError_t launch_forward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s)
 {
-    return launch_sweep(a, fp32, 1, p, s);
+    return launch_sweep(a, arith, 0, p, s);
+}
+
+hipError_t launch_backward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s)
+{
+    return launch_sweep(a, arith, 1, p, s);
 }
 
 }  // namespace sipk

@@ -20,8 +20,8 @@ size_t system_bytes(const Geom &g, int fp32);
 
 struct sip_system_s {
     sipk::Geom g{};
-    int fp32 = 0;
-    int precision = 0;
+    int fp32 = 0;                   // factors stored in FP32
+    int precision = 0;              // sip_precision = the sweeps' Arith
     int sym = 0;                    // coefficients in the symmetric storage for the sweeps
     double alpha = 0.0;
     int device = 0;
@@ -29,7 +29,7 @@ struct sip_system_s {
     size_t bytes = 0;
     double *A = nullptr;            // 7 * elems
     void *LU = nullptr;             // 7 * elems of FP64 or FP32
-    double *bx = nullptr;           // b then x, elems each
+    double *bx = nullptr;           // b then x, elems each (FP64, or FP32 in the all-FP32 arithmetic)
     void *y = nullptr;
     uint64_t *face = nullptr;
     double *part = nullptr;

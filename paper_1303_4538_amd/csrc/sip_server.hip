@@ -40,7 +40,8 @@ constexpr int MAX_SLOTS = 4096;
 struct Resident {
     uint64_t id = 0;
     Geom g{};
-    int fp32 = 0;
+    int fp32 = 0;          // factors stored in FP32
+    int arith = 0;         // sweep arithmetic (sip_precision)
     double alpha = 0.92;
     double *A = nullptr;
     void *LU = nullptr;
@@ -106,10 +107,10 @@ struct sip_server_s {
     Ctl *ctl = nullptr;                      // MAX_SLOTS control blocks
     Ctl *h_ctl = nullptr;                    // pinned mirror
     std::vector<int> free_slots;
-    Job *d_jobs[2] = {nullptr, nullptr};     // per precision group
-    int2 *d_order[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-    int order_cap[2] = {0, 0};
-    int jobs_cap[2] = {0, 0};
+    Job *d_jobs[NARITH] = {};                // per launch group (factor storage, or sweep arithmetic)
+    int2 *d_order[NARITH][2] = {};
+    int order_cap[NARITH] = {};
+    int jobs_cap[NARITH] = {};
     LaunchCtl *lc = nullptr;
     unsigned *d_bad = nullptr, *h_bad = nullptr;   // symmetry check counter (device, pinned mirror)
     SweepPlan plan{};
@@ -179,7 +180,8 @@ bool sip_server_s::admit_locked(std::vector<Req *> &admitted, std::vector<Reside
         auto f = systems.find(q->r.system_id);
         if (f != systems.end()) s = f->second.get();
         const Geom g = s ? s->g : make_geom(pb.ni, pb.nj, pb.nk);
-        const int fp32 = s ? s->fp32 : (pb.precision == SIP_MIXED);
+        const int arith = s ? s->arith : pb.precision;
+        const int fp32 = arith != SIP_FP64;
         const size_t need_slot = slot_bytes(g, fp32, q->r.max_iter);
         const size_t need_sys = s ? 0 : resident_bytes(g, fp32);
         if (s) s->refs++;   // pin while making room
@@ -201,6 +203,7 @@ bool sip_server_s::admit_locked(std::vector<Req *> &admitted, std::vector<Reside
             rs->id = q->r.system_id;
             rs->g = g;
             rs->fp32 = fp32;
+            rs->arith = arith;
             rs->alpha = pb.alpha;
             rs->sym = pb.storage == SIP_STORAGE_SYMMETRIC;
             rs->bytes = need_sys;
@@ -316,6 +319,12 @@ sip_status sip_server_s::ensure_launch_buffers(int grp, int njobs, int ntiles)
     return SIP_OK;
 }
 
+// x behind b in the request's buffer, in the precision of the sweeps
+static void *x_of(const Resident *s, const Req *q)
+{
+    return s->arith == ARITH_F32 ? (void *)((float *)q->bx + s->g.elems) : (void *)(q->bx + s->g.elems);
+}
+
 static Job job_of(const Resident *s, const Req *q, Ctl *ctl, int fw)
 {
     Job J{};
@@ -323,7 +332,7 @@ static Job job_of(const Resident *s, const Req *q, Ctl *ctl, int fw)
     J.A = s->A;
     J.LU = s->LU;
     J.b = q->bx;
-    J.x = q->bx + s->g.elems;
+    J.x = x_of(s, q);
     J.y = q->y;
     J.face = q->face;
     J.part = q->part;
@@ -356,7 +365,7 @@ sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const st
                     continue;
                 }
             }
-            if (launch_to_sheared(sys[k]->g, 7, pb.a, sys[k]->A, sys[k]->g.elems, 1, stream) != hipSuccess)
+            if (launch_to_sheared(sys[k]->g, 7, pb.a, sys[k]->A, sys[k]->g.elems, SHEAR_COEF, stream) != hipSuccess)
                 return set_error(SIP_EDEVICE, "reorder failed");
             // tags stay monotonic per slot (never reset): face words of the
             // factorisation can never be mistaken for a later sweep's
@@ -375,13 +384,17 @@ sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const st
             return set_error(SIP_EDEVICE, "upload failed");
         const LaunchArgs la{d_jobs[grp], d_order[grp][0], lc, (int)of.size(), timeout_ticks};
         if (launch_factor(la, grp, stream) != hipSuccess) return set_error(SIP_EDEVICE, "factor launch failed");
-        // the sweeps of symmetric systems read the symmetric storage, which
-        // overwrites the full one once the factorisation is done
-        for (size_t k = 0; k < sys.size(); k++)
-            if (sys[k]->fp32 == grp && sys[k]->sym && !sys[k]->asym &&
-                launch_to_sheared(sys[k]->g, 7, owners[k]->r.problem.a, sys[k]->A, sys[k]->g.elems, 2, stream) !=
+        // the sweeps of symmetric systems read the symmetric storage, those of
+        // the all-FP32 arithmetic FP32 coefficients; either overwrites the full
+        // FP64 storage once the factorisation is done
+        for (size_t k = 0; k < sys.size(); k++) {
+            if (sys[k]->fp32 != grp || sys[k]->asym) continue;
+            const int sc = sys[k]->sym ? SHEAR_SYM : sys[k]->arith == ARITH_F32 ? SHEAR_COEF32 : SHEAR_COEF;
+            if (sc != SHEAR_COEF &&
+                launch_to_sheared(sys[k]->g, 7, owners[k]->r.problem.a, sys[k]->A, sys[k]->g.elems, sc, stream) !=
                     hipSuccess)
                 return set_error(SIP_EDEVICE, "reorder failed");
+        }
         // the host copies of jobs/orders must live until the copies ran
         if (hipStreamSynchronize(stream) != hipSuccess) return set_error(SIP_EDEVICE, "factorisation failed");
         stats[7]++;
@@ -393,16 +406,16 @@ sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const st
 // One epoch: epoch_iters (forward, backward) pairs over every running request.
 sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
 {
-    std::vector<Job> jobs[2];
-    std::vector<Geom> gs[2];
+    std::vector<Job> jobs[NARITH];
+    std::vector<Geom> gs[NARITH];
     for (Req *q : act) {
-        const int grp = q->sys->fp32;
+        const int grp = q->sys->arith;
         jobs[grp].push_back(job_of(q->sys, q, ctl, FACE_WORDS_SWEEP));
         gs[grp].push_back(q->sys->g);
     }
-    std::vector<int2> of[2], ob[2];
-    LaunchArgs fa[2], ba[2];
-    for (int grp = 0; grp < 2; grp++) {
+    std::vector<int2> of[NARITH], ob[NARITH];
+    LaunchArgs fa[NARITH], ba[NARITH];
+    for (int grp = 0; grp < NARITH; grp++) {
         if (jobs[grp].empty()) continue;
         of[grp] = topo_order(gs[grp], false);
         ob[grp] = topo_order(gs[grp], true);
@@ -418,7 +431,7 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
         ba[grp] = LaunchArgs{d_jobs[grp], d_order[grp][1], lc, (int)ob[grp].size(), timeout_ticks};
     }
     for (int it = 0; it < cfg.epoch_iters; it++) {
-        for (int grp = 0; grp < 2; grp++) {
+        for (int grp = 0; grp < NARITH; grp++) {
             if (jobs[grp].empty()) continue;
             if (launch_forward(fa[grp], grp, plan, stream) != hipSuccess ||
                 launch_backward(ba[grp], grp, plan, stream) != hipSuccess)
@@ -482,11 +495,13 @@ void sip_server_s::loop()
         for (Req *q : ready) {
             const Geom &g = q->sys->g;
             const double *src[2] = {q->r.b, q->r.x0 ? q->r.x0 : nullptr};
+            const bool f32 = q->sys->arith == ARITH_F32;   // the relaxation starts from FP32 copies
+            const int sh = f32 ? SHEAR_F32 : SHEAR_F64;
             if (q->r.x0) {
-                (void)launch_to_sheared(g, 2, src, q->bx, g.elems, 0, stream);
+                (void)launch_to_sheared(g, 2, src, q->bx, g.elems, sh, stream);
             } else {
-                (void)launch_to_sheared(g, 1, src, q->bx, g.elems, 0, stream);
-                (void)hipMemsetAsync(q->bx + g.elems, 0, (size_t)g.elems * 8, stream);
+                (void)launch_to_sheared(g, 1, src, q->bx, g.elems, sh, stream);
+                (void)hipMemsetAsync(x_of(q->sys, q), 0, (size_t)g.elems * (f32 ? 4 : 8), stream);
             }
             (void)launch_init_ctl(ctl + q->slot, 1, (uint32_t)q->r.max_iter, q->r.rtol, 0, stream);
         }
@@ -504,7 +519,8 @@ void sip_server_s::loop()
             const Ctl &c = h_ctl[q->slot];
             if (st != SIP_OK || c.stop != RUN) {
                 if (st == SIP_OK)
-                    (void)launch_from_sheared_f64(q->sys->g, q->bx + q->sys->g.elems, q->r.x, ctl + q->slot, stream);
+                    (void)launch_from_sheared(q->sys->g, x_of(q->sys, q), q->sys->arith == ARITH_F32, q->r.x,
+                                              ctl + q->slot, stream);
                 fin.push_back(q);
             }
         }
@@ -586,9 +602,12 @@ sip_status sip_batch_submit(sip_server s, const sip_request *r, uint64_t *ticket
     if (!resident && !queued_same) {
         if (p.ni < 1 || p.nj < 1 || p.nk < 1) return set_error(SIP_EINVAL, "dims must be >= 1");
         if (!(p.alpha >= 0.0 && p.alpha <= 1.0)) return set_error(SIP_EINVAL, "alpha must be in [0, 1]");
-        if (p.precision != SIP_FP64 && p.precision != SIP_MIXED) return set_error(SIP_EINVAL, "unknown precision");
+        if (p.precision != SIP_FP64 && p.precision != SIP_MIXED && p.precision != SIP_FP32)
+            return set_error(SIP_EINVAL, "unknown precision");
         if (p.storage != SIP_STORAGE_FULL && p.storage != SIP_STORAGE_SYMMETRIC)
             return set_error(SIP_EINVAL, "unknown storage");
+        if (p.storage == SIP_STORAGE_SYMMETRIC && p.precision == SIP_FP32)
+            return set_error(SIP_EINVAL, "the symmetric storage is available with SIP_FP64 and SIP_MIXED only");
         for (int d = 0; d < 7; d++)
             if (!p.a[d]) return set_error(SIP_EINVAL, "coefficient pointer %d is NULL", d);
     }
@@ -596,7 +615,7 @@ sip_status sip_batch_submit(sip_server s, const sip_request *r, uint64_t *ticket
     if (g.elems >= sipk::MAX_ELEMS) return set_error(SIP_EINVAL, "block too large");
     if (resident && (p.ni != g.ni || p.nj != g.nj || p.nk != g.nk))
         return set_error(SIP_EINVAL, "dims differ from the resident system");
-    const int fp32 = resident ? f->second->fp32 : p.precision == SIP_MIXED;
+    const int fp32 = resident ? f->second->fp32 : p.precision != SIP_FP64;
     const size_t need = slot_bytes(g, fp32, r->max_iter) + (resident ? 0 : resident_bytes(g, fp32));
     if (need > s->cfg.hbm_budget_bytes) return set_error(SIP_ENOMEM, "request needs %zu bytes, budget %zu", need, s->cfg.hbm_budget_bytes);
     if ((int)s->queue.size() >= s->cfg.max_queue) return set_error(SIP_EBUSY, "queue full");
@@ -665,7 +684,7 @@ sip_status sip_server_destroy(sip_server s)
         for (auto &kv : s->systems) all.push_back(kv.second.get());
         for (Resident *r : all) s->free_resident_locked(r);
     }
-    for (int grp = 0; grp < 2; grp++) {
+    for (int grp = 0; grp < NARITH; grp++) {
         dev_free(s->d_jobs[grp], s->stream);
         dev_free(s->d_order[grp][0], s->stream);
         dev_free(s->d_order[grp][1], s->stream);

@@ -21,8 +21,9 @@ SIP_EINVAL, SIP_ENOMEM, SIP_EBREAKDOWN, SIP_ENOTCONV = -1, -2, -3, -4
 SIP_EDEVICE, SIP_EBUSY, SIP_ECANCELLED = -5, -6, -7
 STATUS_NAMES = {0: "SIP_OK", 1: "SIP_PENDING", -1: "SIP_EINVAL", -2: "SIP_ENOMEM", -3: "SIP_EBREAKDOWN",
                 -4: "SIP_ENOTCONV", -5: "SIP_EDEVICE", -6: "SIP_EBUSY", -7: "SIP_ECANCELLED"}
-SIP_FP64, SIP_MIXED = 0, 1
-PRECISIONS = {"fp64": SIP_FP64, "mixed": SIP_MIXED, SIP_FP64: SIP_FP64, SIP_MIXED: SIP_MIXED}
+SIP_FP64, SIP_MIXED, SIP_FP32 = 0, 1, 2
+PRECISIONS = {"fp64": SIP_FP64, "mixed": SIP_MIXED, "fp32": SIP_FP32,
+              SIP_FP64: SIP_FP64, SIP_MIXED: SIP_MIXED, SIP_FP32: SIP_FP32}
 
 # every symbol include/sip.h declares
 EXPORTS = ("sip_factor", "sip_iterate", "sip_solve", "sip_export_factors", "sip_profile_sweeps", "sip_system_info",
