@@ -125,6 +125,31 @@ sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
 sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int32_t max_iter,
                      sip_info *info, void *stream);
 
+/* sip_iterate_multi / sip_solve_multi -- nrhs right-hand sides of one
+ * factorised system.  The paper reuses one factorisation for all later
+ * solves (Sec. 4.1); here two right-hand sides also share one pass of the
+ * sweeps over the coefficients and factors, which halves that traffic per
+ * right-hand side.  Pairs (r, r + 1) are swept together with SIP_MIXED and
+ * SIP_FP32; an odd last one, and every one with SIP_FP64, goes through the
+ * one-right-hand-side path.
+ *   b[r], x[r]  device arrays as in sip_iterate / sip_solve (r < nrhs).
+ *   Every right-hand side gets exactly the iterates, residual history and
+ *   stop decision it would get alone (bitwise): in sip_solve_multi each one
+ *   stops at its own first n with rho_n <= rtol and keeps that x_n while its
+ *   partner goes on.
+ *   rel_res_hist  NULL, or HOST memory of nrhs * (n_iter + 1) doubles,
+ *           right-hand side r's history at r * (n_iter + 1).
+ *   info    NULL, or HOST memory of nrhs entries.
+ * sip_solve_multi, and sip_iterate_multi with a history, synchronise the
+ * stream.  Errors: SIP_EINVAL, SIP_ENOMEM (buffers for
+ * the pairs are allocated on first use and kept by the handle), SIP_ENOTCONV
+ * (sip_solve_multi: some right-hand side reached max_iter; the others are
+ * still solved), SIP_EDEVICE. */
+sip_status sip_iterate_multi(sip_system h, int32_t nrhs, const double *const *b, double *const *x, int32_t n_iter,
+                             double *rel_res_hist, void *stream);
+sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, double *const *x, double rtol,
+                           int32_t max_iter, sip_info *info, void *stream);
+
 /* sip_export_factors -- write the factors in natural [nk][nj][ni] order as
  * FP64 into seven device arrays of ni*nj*nk doubles, in the order
  * Lb, Lw, Ls, Lp, Un, Ue, Ut (Lp is the pivot, U has a unit diagonal).

@@ -85,9 +85,12 @@ static void free_system(sip_system_s *h)
     if (h->chunk_exec) hipGraphExecDestroy(h->chunk_exec);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     for (void *p : {(void *)h->A, h->LU, (void *)h->bx, h->y, (void *)h->face, (void *)h->part, (void *)h->ctl,
-                    (void *)h->hist, (void *)h->d_job, (void *)h->d_job_factor, (void *)h->order_f, (void *)h->order_b, (void *)h->lc})
+                    (void *)h->hist, (void *)h->d_job, (void *)h->d_job_factor, (void *)h->order_f, (void *)h->order_b,
+                    (void *)h->lc, (void *)h->mbx, h->my, (void *)h->mface, (void *)h->mpart, (void *)h->mctl,
+                    (void *)h->mhist, (void *)h->d_mjob})
         if (p) hipFree(p);
     if (h->h_ctl) hipHostFree(h->h_ctl);
+    if (h->h_mctl) hipHostFree(h->h_mctl);
     if (h->h_hist) hipHostFree(h->h_hist);
     delete h;
 }
@@ -237,6 +240,95 @@ static sip_status stop_status(uint32_t stop)
     default:
         return set_error(SIP_EDEVICE, "a device-side wait timed out");
     }
+}
+
+// ------------------------------------------------ two right-hand sides
+
+// Buffers of the two-right-hand-side sweeps, allocated on first use, and a
+// residual history of at least hist_n entries per right-hand side.
+static sip_status ensure_multi(sip_system_s *h, int hist_n, hipStream_t s)
+{
+    const Geom &g = h->g;
+    const size_t E = (size_t)g.elems;
+    bool upload = false;
+    if (!h->mbx) {
+        const size_t fbytes = (size_t)g.ntiles * g.steps * FACE_WORDS_SWEEP * 8 + (size_t)g.ntiles * SINK_WORDS * 8;
+        TRY(alloc_dev((void **)&h->mbx, 4 * E * 8, "b and x pairs"));
+        TRY(alloc_dev(&h->my, 2 * E * 4, "y pairs"));
+        TRY(alloc_dev((void **)&h->mface, fbytes, "face words"));
+        TRY(alloc_dev((void **)&h->mpart, (size_t)g.ntiles * 4 * 8, "partials"));
+        TRY(alloc_dev((void **)&h->mctl, 3 * sizeof(Ctl), "control"));
+        TRY(alloc_dev((void **)&h->d_mjob, sizeof(Job), "job"));
+        HIPTRY(hipHostMalloc((void **)&h->h_mctl, 9 * sizeof(Ctl), hipHostMallocDefault));
+        HIPTRY(hipMemsetAsync(h->my, 0, 2 * E * 4, s));
+        HIPTRY(hipMemsetAsync(h->mface, 0, fbytes, s));   // tags start at 1: no stale word matches
+        HIPTRY(launch_init_ctl(h->mctl, 3, 0, 0.0, 1, s));
+        h->bytes += 4 * E * 8 + 2 * E * 4 + fbytes + (size_t)g.ntiles * 32 + 3 * sizeof(Ctl);
+        upload = true;
+    }
+    if (hist_n > h->mhist_cap) {
+        HIPTRY(hipStreamSynchronize(s));
+        if (h->mhist) hipFree(h->mhist);
+        h->mhist = nullptr;
+        h->mhist_cap = 0;
+        const int cap = std::max(hist_n, 64);
+        TRY(alloc_dev((void **)&h->mhist, (size_t)2 * cap * 8, "history"));
+        h->mhist_cap = cap;
+        upload = true;
+    }
+    if (upload) {
+        Job &J = h->mjob;
+        J = h->job;
+        const bool f32 = h->precision == ARITH_F32;
+        J.b = h->mbx;
+        J.x = f32 ? (void *)((float *)h->mbx + 2 * E) : (void *)(h->mbx + 2 * E);
+        J.y = h->my;
+        J.face = h->mface;
+        J.part = h->mpart;
+        J.ctl = h->mctl;
+        J.hist = h->mhist;
+        J.hstride = h->mhist_cap;
+        J.m = 2;
+        J.fw = FACE_WORDS_SWEEP;
+        HIPTRY(hipMemcpyAsync(h->d_mjob, &J, sizeof(Job), hipMemcpyHostToDevice, s));
+        HIPTRY(hipStreamSynchronize(s));
+    }
+    return SIP_OK;
+}
+
+static LaunchArgs multi_args(const sip_system_s *h, bool backward)
+{
+    return LaunchArgs{h->d_mjob, backward ? h->order_b : h->order_f, h->lc, h->g.ntiles, h->timeout_ticks};
+}
+
+static sip_status multi_iterations(sip_system_s *h, int n, hipStream_t s)
+{
+    const LaunchArgs fa = multi_args(h, false), ba = multi_args(h, true);
+    for (int q = 0; q < n; q++) {
+        HIPTRY(launch_forward(fa, h->precision, h->plan, s, 2));
+        HIPTRY(launch_backward(ba, h->precision, h->plan, s, 2));
+    }
+    return SIP_OK;
+}
+
+static hipError_t multi_stage_in(const sip_system_s *h, const double *b0, const double *b1, const double *x0,
+                                 const double *x1, hipStream_t s)
+{
+    const Geom &g = h->g;
+    const bool f32 = h->precision == ARITH_F32;
+    const int sh = f32 ? SHEAR_PAIR_F32 : SHEAR_PAIR_F64;
+    const double *bs[2] = {b0, b1}, *xs[2] = {x0, x1};
+    hipError_t e = launch_to_sheared(g, 2, bs, h->mbx, g.elems, sh, s);
+    if (e != hipSuccess) return e;
+    return launch_to_sheared(g, 2, xs, h->mjob.x, g.elems, sh, s);
+}
+
+static hipError_t multi_stage_out(const sip_system_s *h, double *x0, double *x1, hipStream_t s)
+{
+    const bool f32 = h->precision == ARITH_F32;
+    hipError_t e = launch_from_sheared(h->g, h->mjob.x, f32, x0, h->mctl + 1, s, 2, 0);
+    if (e != hipSuccess) return e;
+    return launch_from_sheared(h->g, h->mjob.x, f32, x1, h->mctl + 2, s, 2, 1);
 }
 
 }  // namespace sipk
@@ -496,6 +588,120 @@ sip_status sip_profile_sweeps(sip_system h, const double *b, double *x, int32_t 
     if (st != SIP_OK) return st;
     ms[0] = f / n_iter;
     ms[1] = bk / n_iter;
+    return SIP_OK;
+}
+
+// Right-hand sides without a partner (FP64 factors, or the last of an odd
+// count) run through the one-right-hand-side path.
+static bool pairs_ok(const sip_system_s *h) { return h->precision == SIP_MIXED || h->precision == SIP_FP32; }
+
+sip_status sip_iterate_multi(sip_system h, int32_t nrhs, const double *const *b, double *const *x, int32_t n_iter,
+                             double *rel_res_hist, void *stream)
+{
+    if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
+    if (nrhs < 1 || n_iter < 0) return set_error(SIP_EINVAL, "need nrhs >= 1 and n_iter >= 0");
+    for (int r = 0; r < nrhs; r++)
+        if (!b[r] || !x[r]) return set_error(SIP_EINVAL, "right-hand side %d: NULL b or x", r);
+    hipStream_t s = (hipStream_t)stream;
+    const int npair = pairs_ok(h) ? nrhs / 2 : 0;
+    const size_t hn = (size_t)n_iter + 1;
+    if (npair > 0) TRY(ensure_multi(h, n_iter + 1, s));
+    for (int pr = 0; pr < npair; pr++) {
+        const int r0 = 2 * pr, r1 = r0 + 1;
+        HIPTRY(multi_stage_in(h, b[r0], b[r1], x[r0], x[r1], s));
+        HIPTRY(launch_init_ctl(h->mctl, 3, (uint32_t)n_iter, 0.0, 0, s));
+        TRY(multi_iterations(h, n_iter, s));
+        HIPTRY(launch_forward(multi_args(h, false), h->precision, h->plan, s, 2));   // residual of the final iterates
+        HIPTRY(multi_stage_out(h, x[r0], x[r1], s));
+        if (!rel_res_hist) continue;
+        std::vector<double> hb(2 * (size_t)h->mhist_cap);
+        HIPTRY(hipMemcpyAsync(hb.data(), h->mhist, hb.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPTRY(hipMemcpyAsync(h->h_mctl, h->mctl, 3 * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPTRY(hipStreamSynchronize(s));
+        for (int m = 0; m < 2; m++) {
+            double *dst = rel_res_hist + (size_t)(r0 + m) * hn;
+            std::memcpy(dst, hb.data() + (size_t)m * h->mhist_cap, hn * 8);
+            if (h->h_mctl[1 + m].stop == ZERO_RHS)
+                for (size_t q = 0; q < hn; q++) dst[q] = 0.0;
+        }
+        const uint32_t stop = h->h_mctl[0].stop;
+        if (stop == BREAKDOWN || stop == TIMEOUT) return stop_status(stop);
+    }
+    for (int r = 2 * npair; r < nrhs; r++)
+        TRY(sip_iterate(h, b[r], x[r], n_iter, rel_res_hist ? rel_res_hist + (size_t)r * hn : nullptr, stream));
+    return SIP_OK;
+}
+
+sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, double *const *x, double rtol,
+                           int32_t max_iter, sip_info *info, void *stream)
+{
+    if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
+    if (nrhs < 1) return set_error(SIP_EINVAL, "need nrhs >= 1");
+    if (!(rtol > 0.0) || max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
+    for (int r = 0; r < nrhs; r++)
+        if (!b[r] || !x[r]) return set_error(SIP_EINVAL, "right-hand side %d: NULL b or x", r);
+    hipStream_t s = (hipStream_t)stream;
+    const int npair = pairs_ok(h) ? nrhs / 2 : 0;
+    sip_status worst = SIP_OK;
+    // the finaliser records rho_n for n <= max_iter
+    if (npair > 0) TRY(ensure_multi(h, max_iter + 1, s));
+    for (int pr = 0; pr < npair; pr++) {
+        const auto t0 = std::chrono::steady_clock::now();
+        const int r0 = 2 * pr, r1 = r0 + 1;
+        HIPTRY(multi_stage_in(h, b[r0], b[r1], x[r0], x[r1], s));
+        HIPTRY(launch_init_ctl(h->mctl, 3, (uint32_t)max_iter, rtol, 0, s));
+        sip_status st = SIP_OK;
+        long long launched = 0;
+        hipEvent_t ev[2];
+        HIPTRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        HIPTRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        for (int c = 0;; c++) {
+            st = multi_iterations(h, CHUNK, s);
+            if (st != SIP_OK) break;
+            launched += CHUNK;
+            if (hipMemcpyAsync(&h->h_mctl[3 * (c & 1)], h->mctl, 3 * sizeof(Ctl), hipMemcpyDeviceToHost, s) !=
+                    hipSuccess ||
+                hipEventRecord(ev[c & 1], s) != hipSuccess) {
+                st = set_error(SIP_EDEVICE, "status copy failed");
+                break;
+            }
+            if (launched > max_iter) break;
+            if (c > 0) {
+                if (hipEventSynchronize(ev[(c - 1) & 1]) != hipSuccess) {
+                    st = set_error(SIP_EDEVICE, "event wait failed");
+                    break;
+                }
+                if (h->h_mctl[3 * ((c - 1) & 1)].stop != RUN) break;
+            }
+        }
+        hipEventDestroy(ev[0]);
+        hipEventDestroy(ev[1]);
+        if (st != SIP_OK) {
+            hipStreamSynchronize(s);
+            return st;
+        }
+        HIPTRY(multi_stage_out(h, x[r0], x[r1], s));
+        HIPTRY(hipMemcpyAsync(&h->h_mctl[6], h->mctl, 3 * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPTRY(hipStreamSynchronize(s));
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        const Ctl *c = &h->h_mctl[6];
+        if (c[0].stop == RUN) return set_error(SIP_EDEVICE, "solve ended without a stop decision");
+        if (c[0].stop == BREAKDOWN || c[0].stop == TIMEOUT) return stop_status(c[0].stop);
+        for (int m = 0; m < 2; m++) {
+            if (info) {
+                info[r0 + m].iters = (int32_t)c[1 + m].iter;
+                info[r0 + m].rel_res = c[1 + m].stop == ZERO_RHS ? 0.0 : c[1 + m].rho;
+                info[r0 + m].seconds = secs;
+            }
+            if (c[1 + m].stop == MAXITER) worst = SIP_ENOTCONV;
+        }
+    }
+    for (int r = 2 * npair; r < nrhs; r++) {
+        const sip_status st = sip_solve(h, b[r], x[r], rtol, max_iter, info ? info + r : nullptr, stream);
+        if (st == SIP_ENOTCONV) worst = SIP_ENOTCONV;
+        else if (st != SIP_OK) return st;
+    }
+    if (worst == SIP_ENOTCONV) return set_error(SIP_ENOTCONV, "a right-hand side reached max_iter");
     return SIP_OK;
 }
 

@@ -125,10 +125,12 @@ struct Job {
     uint64_t *face;            // ntiles * steps * FACE_WORDS tagged face words
     double *part;              // 2 * ntiles per-tile partial sums
     double *hist;              // max_iter + 1 relative residuals
-    Ctl *ctl;
+    Ctl *ctl;                  // m = 1: the control block; m > 1: ctl[0] the sweep's, ctl[1 + r] right-hand side r's
     double alpha;
     int fw;                    // face words per local step (FACE_WORDS_SWEEP or FACE_WORDS)
     int sym;                   // A in the symmetric storage (sweeps only; the factorisation reads the full one)
+    int m;                     // right-hand sides swept together (b, x, y hold m values per cell)
+    int hstride;               // m > 1: history of right-hand side r at hist + r * hstride
 };
 
 // Launch-wide ticket and completion counters (reset by the last workgroup).
@@ -168,15 +170,20 @@ hipError_t launch_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int 
 // at dst + a * dst_stride elements), or the 7 coefficient arrays (masked at
 // the block boundary) in the interleaved FP64, symmetric FP64 or FP32 group
 // storage.
-enum Shear : int { SHEAR_F64 = 0, SHEAR_COEF = 1, SHEAR_SYM = 2, SHEAR_F32 = 3, SHEAR_COEF32 = 4 };
+// SHEAR_PAIR_F64 / SHEAR_PAIR_F32 interleave two arrays per cell (dst[2 e + a],
+// narr = 2): the b or x pairs of a two-right-hand-side sweep.
+enum Shear : int {
+    SHEAR_F64 = 0, SHEAR_COEF = 1, SHEAR_SYM = 2, SHEAR_F32 = 3, SHEAR_COEF32 = 4, SHEAR_PAIR_F64 = 5, SHEAR_PAIR_F32 = 6
+};
 hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, void *dst,
                              long long dst_stride, int shear, hipStream_t s);
 // Counts the cells whose W, S or B coupling differs from the neighbour's E, N
 // or T one (bitwise) into *bad (device, zeroed by the caller).
 hipError_t launch_check_symmetric(int ni, int nj, int nk, const double *const *a, unsigned *bad, hipStream_t s);
-// Natural-order FP64 copy of a sheared FP64 (src_f32 = 0) or FP32 array.
+// Natural-order FP64 copy of a sheared FP64 (src_f32 = 0) or FP32 array;
+// with comp = 2, component `which` of a pair array.
 hipError_t launch_from_sheared(const Geom &g, const void *src, int src_f32, double *dst, const Ctl *zero_if_zero_rhs,
-                               hipStream_t s);
+                               hipStream_t s, int comp = 1, int which = 0);
 hipError_t launch_export_factors(const Geom &g, const void *LU, int fp32, double *const *dst, hipStream_t s);
 hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s);
 // Launch shape of the sweeps: loader phases per tile (1 to 3).  Each phase
@@ -186,7 +193,10 @@ constexpr int MAX_PHASES = 3;
 struct SweepPlan {
     int phases = 2;
 };
-hipError_t launch_forward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s);
-hipError_t launch_backward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s);
+// nrhs: right-hand sides per job (1, or 2 with FP32 factors: ARITH_MIXED,
+// ARITH_F32); every job of the launch must have Job::m == nrhs.
+constexpr int MAX_SWEEP_RHS = 2;
+hipError_t launch_forward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s, int nrhs = 1);
+hipError_t launch_backward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s, int nrhs = 1);
 
 }  // namespace sipk

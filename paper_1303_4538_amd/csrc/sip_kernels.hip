@@ -273,6 +273,46 @@ __device__ __forceinline__ void stg(GLOBAL T *base, uint32_t idx, T v)
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef float flt3 __attribute__((ext_vector_type(3)));   // 16-byte slot, 12 bytes loaded
+typedef float flt2 __attribute__((ext_vector_type(2)));
+
+// The values of M right-hand sides at one cell, stored together: T for
+// M = 1, a two-lane vector for M = 2 (b, x, y, d and the face records of the
+// right-hand sides of one multi-RHS sweep travel together).
+template <typename T, int M> struct PackOf;
+template <> struct PackOf<double, 1> { typedef double T; };
+template <> struct PackOf<float, 1> { typedef float T; };
+template <> struct PackOf<double, 2> { typedef dbl2 T; };
+template <> struct PackOf<float, 2> { typedef flt2 T; };
+template <typename T, int M> using Pk = typename PackOf<T, M>::T;
+__device__ __forceinline__ double el(double v, int) { return v; }
+__device__ __forceinline__ float el(float v, int) { return v; }
+__device__ __forceinline__ double el(const dbl2 &v, int m) { return m ? v.y : v.x; }
+__device__ __forceinline__ float el(const flt2 &v, int m) { return m ? v.y : v.x; }
+__device__ __forceinline__ void set_el(double &v, int, double x) { v = x; }
+__device__ __forceinline__ void set_el(float &v, int, float x) { v = x; }
+__device__ __forceinline__ void set_el(dbl2 &v, int m, double x)
+{
+    if (m) v.y = x;
+    else v.x = x;
+}
+__device__ __forceinline__ void set_el(flt2 &v, int m, float x)
+{
+    if (m) v.y = x;
+    else v.x = x;
+}
+// a pair of FP32 values travels in the face records as two words, like FP64
+template <> struct NW<flt2> { static constexpr int n = 2; };
+__device__ __forceinline__ void to_words(const flt2 &v, uint32_t *w)
+{
+    w[0] = __float_as_uint(v.x);
+    w[1] = __float_as_uint(v.y);
+}
+__device__ __forceinline__ void from_words(const uint64_t *w, flt2 &v)
+{
+    v.x = __uint_as_float((uint32_t)w[0]);
+    v.y = __uint_as_float((uint32_t)w[1]);
+}
+__device__ __forceinline__ void keep(flt2 &x) { asm volatile("" : "+v"(x)); }
 template <typename F> struct Grp;
 template <> struct Grp<float> {
     typedef flt4 V;
@@ -398,35 +438,35 @@ __device__ __forceinline__ int sweep_steps(int steps, int pd)
 // a[0] = A_P of plane f, a[2], a[4], a[6] = A_E, A_N, A_T of plane f + 1
 // (staged into the coefficient ring), a[1], a[3] = A_E of the W neighbour /
 // A_N of the S neighbour across a tile edge.
-template <typename F, typename R>
+template <typename F, typename R, int M>
 struct FwdLoad {
     R a[7];
-    R b;
-    R x2;          // x on plane f + 2, staged into the LDS plane ring for the next steps
-    R hx;          // x across the W or E tile edge (edge slots only)
-    R hy;          // x across the S or N tile edge (edge slots only)
+    Pk<R, M> b;
+    Pk<R, M> x2;   // x on plane f + 2, staged into the LDS plane ring for the next steps
+    Pk<R, M> hx;   // x across the W or E tile edge (edge slots only)
+    Pk<R, M> hy;   // x across the S or N tile edge (edge slots only)
     F l[4];        // Lb, Lw, Ls, 1/Lp
 };
 
 // Uniform base pointers and per-lane index deltas of a forward loader.
-template <typename F, typename R>
+template <typename F, typename R, int M>
 struct FwdSrc {
     const GLOBAL dbl2 *AP[3];   // FP64: (A_P, A_W), (A_E, A_S), (A_N, A_B)
     const GLOBAL double *AT;
     const GLOBAL flt4 *A4;      // FP32: (A_P, A_W, A_E, A_S)
     const GLOBAL flt3 *A3;      // FP32: (A_N, A_B, A_T) of the (A_N, A_B, A_T, 0) group
-    const GLOBAL R *b, *x;
+    const GLOBAL Pk<R, M> *b, *x;
     const GLOBAL typename Grp<F>::V *L[Grp<F>::N];   // Lb, Lw, Ls, 1/Lp
     const GLOBAL double *SP, *ST, *SEN;                // symmetric storage: A_P, A_T, (A_E, A_N) pairs
     uint32_t e0;          // sheared index of (plane 0, this quadrant, this lane)
     int32_t hx, hy;       // index deltas of the x halo this slot reads across a tile edge (0: none)
 };
 
-template <typename F, typename R>
-__device__ __forceinline__ FwdSrc<F, R> fwd_src(const Job &J, const TileView &v, int q)
+template <typename F, typename R, int M>
+__device__ __forceinline__ FwdSrc<F, R, M> fwd_src(const Job &J, const TileView &v, int q)
 {
     const Geom &g = J.g;
-    FwdSrc<F, R> s;
+    FwdSrc<F, R, M> s;
 #pragma unroll
     for (int p = 0; p < 3; p++) s.AP[p] = (const GLOBAL dbl2 *)(gp(J.A) + 2 * p * g.elems);
     s.AT = gp(J.A) + 6 * g.elems;
@@ -435,8 +475,8 @@ __device__ __forceinline__ FwdSrc<F, R> fwd_src(const Job &J, const TileView &v,
     s.SP = gp(J.A);
     s.SEN = gp(J.A) + g.elems;
     s.ST = gp(J.A) + 3 * g.elems;
-    s.b = gp((const R *)J.b);
-    s.x = gp((const R *)J.x);
+    s.b = gp((const Pk<R, M> *)J.b);
+    s.x = gp((const Pk<R, M> *)J.x);
 #pragma unroll
     for (int k = 0; k < Grp<F>::N; k++)
         s.L[k] = (const GLOBAL typename Grp<F>::V *)(gp((const F *)J.LU) + k * Grp<F>::W * g.elems);
@@ -458,9 +498,9 @@ __device__ __forceinline__ FwdSrc<F, R> fwd_src(const Job &J, const TileView &v,
 
 // Branch-free: inactive slots read their own zero-padded slot (every index
 // stays inside the tile's planes -1..steps for f in [0, steps)).
-template <typename F, typename R>
-__device__ __forceinline__ void fwd_issue(FwdLoad<F, R> &c, const FwdSrc<F, R> &s, const TileView &v, int q, int f,
-                                          int steps, int nk, bool sym)
+template <typename F, typename R, int M>
+__device__ __forceinline__ void fwd_issue(FwdLoad<F, R, M> &c, const FwdSrc<F, R, M> &s, const TileView &v, int q,
+                                          int f, int steps, int nk, bool sym)
 {
     const bool act = v.active(f, nk, q);
     const uint32_t e = s.e0 + (uint32_t)f * PLANE;
@@ -513,18 +553,59 @@ __device__ __forceinline__ void fwd_issue(FwdLoad<F, R> &c, const FwdSrc<F, R> &
     c.hy = ldg(s.x, e + (act ? s.hy : 0));
 }
 
-template <typename F, typename R, int NP>
+// Finaliser of a forward sweep with several right-hand sides: per
+// right-hand side r, Ctl ctl[1 + r] holds its own stop state, residual and
+// iteration count; ctl[0] keeps the launch sequence (epoch, iteration) and
+// stops once every right-hand side has stopped.  A right-hand side that has
+// stopped keeps its x (the backward sweep skips its update), so its result is
+// the iterate at which it stopped, as in a solve of its own.
+template <int M>
+__device__ void finalise_multi(const Job &J, const double *sr, const double *sb, uint32_t iter, uint32_t tag)
+{
+    Ctl *c0 = J.ctl;
+    const uint32_t err = c0->err;
+    bool running = false, capped = false;
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        Ctl *cr = J.ctl + 1 + m;
+        if (iter == 0) cr->bnorm2 = sb[m];
+        const double nb2 = iter == 0 ? sb[m] : cr->bnorm2;
+        double rho = 0.0;
+        if (nb2 != 0.0) rho = sqrt(sr[m]) / sqrt(nb2);
+        if (J.hist) J.hist[m * J.hstride + iter] = rho;
+        if (cr->stop != RUN) continue;
+        uint32_t st = RUN;
+        if (nb2 == 0.0) st = ZERO_RHS;
+        else if (c0->rtol > 0.0 && rho <= c0->rtol) st = CONVERGED;
+        else if (iter >= c0->max_iter) st = MAXITER;
+        cr->rho = rho;
+        cr->iter = iter;
+        cr->stop = st;
+        running = running || st == RUN;
+        capped = capped || st == MAXITER;
+    }
+    uint32_t st = running ? RUN : capped ? MAXITER : CONVERGED;
+    if (err) st = (err & 2u) ? BREAKDOWN : TIMEOUT;
+    c0->stop = st;
+    c0->epoch = tag + 1u;
+    c0->done = 0u;
+}
+
+template <typename F, typename R, int NP, int M>
 __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
 {
-    constexpr int NV = NW<F>::n;
+    static_assert(M == 1 || std::is_same<F, float>::value, "several right-hand sides need FP32 factors");
+    typedef Pk<F, M> FV;   // y of the M right-hand sides
+    typedef Pk<R, M> RV;   // b, x of the M right-hand sides
+    constexpr int NV = NW<FV>::n;
     constexpr int NL = NQ * NP;
     constexpr bool R64 = std::is_same<R, double>::value;   // the symmetric storage exists in FP64 only
-    __shared__ F ring[2][5][NQ][TT];        // r, Lb, Lw, Ls, 1/Lp of two steps
-    __shared__ F ybuf[2][NQ][TT];
-    __shared__ R xring[4][NQ][TT];          // x on planes f-1..f+2 (slot = plane & 3)
+    __shared__ F ring[2][4 + M][NQ][TT];    // r of each right-hand side, then Lb, Lw, Ls, 1/Lp; two steps
+    __shared__ FV ybuf[2][NQ][TT];
+    __shared__ RV xring[4][NQ][TT];         // x on planes f-1..f+2 (slot = plane & 3)
     __shared__ double cring[R64 ? 4 : 1][3][NQ][TT];   // symmetric storage: A_E, A_N, A_T on planes f-1..f+1
     __shared__ int s_buf[4];
-    __shared__ double s_part[NL][2];
+    __shared__ double s_part[NL][2 * M];
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -546,12 +627,12 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
     const long long fstride = (long long)g.steps * FW;
     GLOBAL Ctl *ctl = gp(J.ctl);
 
-    for (int x = threadIdx.x; x < 2 * NQ * TT; x += blockDim.x) (&ybuf[0][0][0])[x] = F(0);
+    for (int x = threadIdx.x; x < 2 * NQ * TT; x += blockDim.x) (&ybuf[0][0][0])[x] = FV(0);
     if (wave >= 1 && wave <= NQ) {   // phase-0 loaders: planes -1 (zero margin), 0 and 1 of the x ring
         const int q = wave - 1;
         const uint32_t e0 = (uint32_t)v.base + (uint32_t)(q * TT);
-        const GLOBAL R *xg = gp((const R *)J.x);
-        xring[3][q][lane] = R(0);
+        const GLOBAL RV *xg = gp((const RV *)J.x);
+        xring[3][q][lane] = RV(0);
         xring[0][q][lane] = ldg(xg, e0);
         xring[1][q][lane] = ldg(xg, e0 + (uint32_t)min(1, g.steps) * PLANE);
         if constexpr (R64) if (sym) {   // A_E, A_N, A_T of planes -1 (zero margin) and 0
@@ -585,23 +666,24 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
         // poll, so the loop is entered with the same counts as it loops back with.
 #pragma unroll
         for (int q = 0; q < PD; q++) {
-            post_record<NV>(fbase, post, g.steps, g.steps, FW, tag, F(0));
+            post_record<NV>(fbase, post, g.steps, g.steps, FW, tag, FV(0));
             plan(q, q);
         }
-        F yB[NQ] = {F(0), F(0), F(0), F(0)};
+        FV yB[NQ] = {FV(0), FV(0), FV(0), FV(0)};
         bool aborted = false;
         const int dW = v.ip > 0 ? 1 : 0, dS = v.jp > 0 ? LI : 0;
-        F r[NQ], lb[NQ], lw[NQ], ls[NQ], il[NQ];
-        F nW1, nW3, nS2, nS3;
+        F r[M][NQ], lb[NQ], lw[NQ], ls[NQ], il[NQ];
+        FV nW1, nW3, nS2, nS3;
         auto prefetch = [&](int s) {   // operands of step s: ring slot, in-tile neighbours of step s - 1
             const int slot = s & 1, pr = (s - 1) & 1;
 #pragma unroll
             for (int c = 0; c < NQ; c++) {
-                r[c] = ring[slot][0][c][lane];
-                lb[c] = ring[slot][1][c][lane];
-                lw[c] = ring[slot][2][c][lane];
-                ls[c] = ring[slot][3][c][lane];
-                il[c] = ring[slot][4][c][lane];
+#pragma unroll
+                for (int m = 0; m < M; m++) r[m][c] = ring[slot][m][c][lane];
+                lb[c] = ring[slot][M][c][lane];
+                lw[c] = ring[slot][M + 1][c][lane];
+                ls[c] = ring[slot][M + 2][c][lane];
+                il[c] = ring[slot][M + 3][c][lane];
             }
             nW1 = ybuf[pr][1][lane - dW];
             nW3 = ybuf[pr][3][lane - dW];
@@ -618,7 +700,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                 if (!aborted && !halo_wait(pv[q], needW[q], fbase + oW[q], needS[q], fbase + oS[q], tag, ctl,
                                            a.timeout_ticks))
                     aborted = true;
-                F hw0, hw1, hs0, hs1;
+                FV hw0, hw1, hs0, hs1;
                 from_words(&pv[q].a[0], hw0);
                 from_words(&pv[q].a[NV], hw1);
                 from_words(&pv[q].b[0], hs0);
@@ -629,36 +711,44 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                 keep(nW3);
                 keep(nS2);
                 keep(nS3);
-                const F zero = F(0);
-                const F W0 = dW ? nW1 : (needW[q] ? hw0 : zero);   // W of quadrant (0,0)
-                const F W2 = dW ? nW3 : (needW[q] ? hw1 : zero);   // W of quadrant (0,1)
-                const F S0 = dS ? nS2 : (needS[q] ? hs0 : zero);   // S of quadrant (0,0)
-                const F S1 = dS ? nS3 : (needS[q] ? hs1 : zero);   // S of quadrant (1,0)
+                const FV zero = FV(0);
+                const FV W0 = dW ? nW1 : (needW[q] ? hw0 : zero);   // W of quadrant (0,0)
+                const FV W2 = dW ? nW3 : (needW[q] ? hw1 : zero);   // W of quadrant (0,1)
+                const FV S0 = dS ? nS2 : (needS[q] ? hs0 : zero);   // S of quadrant (0,0)
+                const FV S1 = dS ? nS3 : (needS[q] ? hs1 : zero);   // S of quadrant (1,0)
                 const bool kin = v.kin(s, g.nk);
-                F y[NQ];
-                {
-                    F t = r[0] - lb[0] * yB[0];
-                    t = t - lw[0] * W0;
-                    t = t - ls[0] * S0;
-                    y[0] = (kin && (v.inq & 1u)) ? t * il[0] : zero;
-                }
-                {
-                    F t = r[1] - lb[1] * yB[1];
-                    t = t - lw[1] * y[0];
-                    t = t - ls[1] * S1;
-                    y[1] = (kin && (v.inq & 2u)) ? t * il[1] : zero;
-                }
-                {
-                    F t = r[2] - lb[2] * yB[2];
-                    t = t - lw[2] * W2;
-                    t = t - ls[2] * y[0];
-                    y[2] = (kin && (v.inq & 4u)) ? t * il[2] : zero;
-                }
-                {
-                    F t = r[3] - lb[3] * yB[3];
-                    t = t - lw[3] * y[2];
-                    t = t - ls[3] * y[1];
-                    y[3] = (kin && (v.inq & 8u)) ? t * il[3] : zero;
+                FV y[NQ];
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    F y0, y1, y2, y3;
+                    {
+                        F t = r[m][0] - lb[0] * el(yB[0], m);
+                        t = t - lw[0] * el(W0, m);
+                        t = t - ls[0] * el(S0, m);
+                        y0 = (kin && (v.inq & 1u)) ? t * il[0] : F(0);
+                    }
+                    {
+                        F t = r[m][1] - lb[1] * el(yB[1], m);
+                        t = t - lw[1] * y0;
+                        t = t - ls[1] * el(S1, m);
+                        y1 = (kin && (v.inq & 2u)) ? t * il[1] : F(0);
+                    }
+                    {
+                        F t = r[m][2] - lb[2] * el(yB[2], m);
+                        t = t - lw[2] * el(W2, m);
+                        t = t - ls[2] * y0;
+                        y2 = (kin && (v.inq & 4u)) ? t * il[2] : F(0);
+                    }
+                    {
+                        F t = r[m][3] - lb[3] * el(yB[3], m);
+                        t = t - lw[3] * y2;
+                        t = t - ls[3] * y1;
+                        y3 = (kin && (v.inq & 8u)) ? t * il[3] : F(0);
+                    }
+                    set_el(y[0], m, y0);
+                    set_el(y[1], m, y1);
+                    set_el(y[2], m, y2);
+                    set_el(y[3], m, y3);
                 }
 #pragma unroll
                 for (int c = 0; c < NQ; c++) {
@@ -666,7 +756,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                     ybuf[s & 1][c][lane] = y[c];
                 }
                 // publish at once: the neighbour tiles' next steps wait on this record
-                const F rec = ybuf[s & 1][post.q][post.src];
+                const FV rec = ybuf[s & 1][post.q][post.src];
                 prefetch(s + 1);   // issued before the record store waits for its value
                 post_record<NV>(fbase, post, s, g.steps, FW, tag, rec);
                 plan(q, s + PD);
@@ -680,11 +770,13 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
         const int lw = wave - 1;
         const int q = lw % NQ, ph = lw / NQ;
         const int qa = q & 1, qb = q >> 1;
-        const FwdSrc<F, R> src = fwd_src<F, R>(J, v, q);
-        FwdLoad<F, R> c;
+        const FwdSrc<F, R, M> src = fwd_src<F, R, M>(J, v, q);
+        FwdLoad<F, R, M> c;
         if (ph < g.steps) fwd_issue(c, src, v, q, ph, g.steps, g.nk, sym);
-        GLOBAL F *yout = gp((F *)J.y);
-        double rr = 0.0, bb = 0.0;
+        GLOBAL FV *yout = gp((FV *)J.y);
+        double rr[M], bb[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) rr[m] = bb[m] = 0.0;
         // In-ring neighbours: the other quadrant column (row) of the same
         // lane on the same plane, or of the neighbouring lane one plane down
         // (W, S) / up (E, N).
@@ -697,13 +789,13 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
             if (f < g.steps) {
                 // planes f-1..f+1 were staged by earlier turns
                 xring[(f + 2) & 3][q][lane] = c.x2;
-                const R xP = xring[f & 3][q][lane];
-                const R xB = xring[(f - 1) & 3][q][lane];
-                const R xT = xring[(f + 1) & 3][q][lane];
-                const R xW = inW ? xring[(f - 1 + qa) & 3][q ^ 1][lane - dW] : c.hx;
-                const R xE = inE ? xring[(f + qa) & 3][q ^ 1][lane + dE] : c.hx;
-                const R xS = inS ? xring[(f - 1 + qb) & 3][q ^ 2][lane - dS] : c.hy;
-                const R xN = inN ? xring[(f + qb) & 3][q ^ 2][lane + dN] : c.hy;
+                const RV xP = xring[f & 3][q][lane];
+                const RV xB = xring[(f - 1) & 3][q][lane];
+                const RV xT = xring[(f + 1) & 3][q][lane];
+                const RV xW = inW ? xring[(f - 1 + qa) & 3][q ^ 1][lane - dW] : c.hx;
+                const RV xE = inE ? xring[(f + qa) & 3][q ^ 1][lane + dE] : c.hx;
+                const RV xS = inS ? xring[(f - 1 + qb) & 3][q ^ 2][lane - dS] : c.hy;
+                const RV xN = inN ? xring[(f + qb) & 3][q ^ 2][lane + dN] : c.hy;
                 R aP = c.a[0], aW = c.a[1], aE = c.a[2], aS = c.a[3], aN = c.a[4], aB = c.a[5], aT = c.a[6];
                 if constexpr (R64) if (sym) {
                     // A_W = A_E of the W cell, A_S = A_N of the S cell, A_B = A_T of the B
@@ -719,16 +811,21 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                     aW = inW ? cring[(f - 1 + qa) & 3][0][q ^ 1][lane - dW] : (wall_w ? 0.0 : c.a[1]);
                     aS = inS ? cring[(f - 1 + qb) & 3][1][q ^ 2][lane - dS] : (wall_s ? 0.0 : c.a[3]);
                 }
-                const R ax = aP * xP + aW * xW + aE * xE + aS * xS + aN * xN + aB * xB + aT * xT;
-                const R r = c.b - ax;
-                rr += (double)r * (double)r;
-                bb += (double)c.b * (double)c.b;
                 const int slot = f & 1;
-                ring[slot][0][q][lane] = (F)r;
-                ring[slot][1][q][lane] = c.l[0];
-                ring[slot][2][q][lane] = c.l[1];
-                ring[slot][3][q][lane] = c.l[2];
-                ring[slot][4][q][lane] = c.l[3];
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    const R ax = aP * el(xP, m) + aW * el(xW, m) + aE * el(xE, m) + aS * el(xS, m) +
+                                 aN * el(xN, m) + aB * el(xB, m) + aT * el(xT, m);
+                    const R bm = el(c.b, m);
+                    const R r = bm - ax;
+                    rr[m] += (double)r * (double)r;
+                    bb[m] += (double)bm * (double)bm;
+                    ring[slot][m][q][lane] = (F)r;
+                }
+                ring[slot][M][q][lane] = c.l[0];
+                ring[slot][M + 1][q][lane] = c.l[1];
+                ring[slot][M + 2][q][lane] = c.l[2];
+                ring[slot][M + 3][q][lane] = c.l[3];
             }
             if (f + NP < g.steps) fwd_issue(c, src, v, q, f + NP, g.steps, g.nk, sym);
             const int p = f - 3;
@@ -747,54 +844,61 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
             }
             if (s_buf[3]) break;
         }
-        rr = wave_sum(rr);
-        bb = wave_sum(bb);
-        if (lane == 0) {
-            s_part[lw][0] = rr;
-            s_part[lw][1] = bb;
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            rr[m] = wave_sum(rr[m]);
+            bb[m] = wave_sum(bb[m]);
+            if (lane == 0) {
+                s_part[lw][2 * m] = rr[m];
+                s_part[lw][2 * m + 1] = bb[m];
+            }
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double sr = 0.0, sb = 0.0;
-        for (int l = 0; l < NL; l++) {
-            sr += s_part[l][0];
-            sb += s_part[l][1];
-        }
-        gp(J.part)[2 * v.t] = sr;
-        gp(J.part)[2 * v.t + 1] = sb;
+    if (threadIdx.x < 2 * M) {   // per-tile partials, one thread per sum, fixed order
+        double sum = 0.0;
+        for (int l = 0; l < NL; l++) sum += s_part[l][threadIdx.x];
+        gp(J.part)[2 * M * v.t + threadIdx.x] = sum;
     }
 
     if (job_last(J, s_buf) && wave == 0) {
-        double sr = 0.0, sb = 0.0;
-        for (int t = lane; t < g.ntiles; t += WAVE) {
-            sr += J.part[2 * t];
-            sb += J.part[2 * t + 1];
-        }
-        sr = wave_sum(sr);
-        sb = wave_sum(sb);
-        if (lane == 0) {
-            Ctl *cc = J.ctl;
-            if (iter == 0) cc->bnorm2 = sb;
-            const double nb2 = iter == 0 ? sb : cc->bnorm2;
-            uint32_t st = RUN;
-            const uint32_t err = cc->err;
-            if (err) {
-                st = (err & 2u) ? BREAKDOWN : TIMEOUT;
-            } else if (nb2 == 0.0) {
-                st = ZERO_RHS;
-                cc->rho = 0.0;
-                if (J.hist) J.hist[iter] = 0.0;
-            } else {
-                const double rho = sqrt(sr) / sqrt(nb2);
-                cc->rho = rho;
-                if (J.hist) J.hist[iter] = rho;
-                if (cc->rtol > 0.0 && rho <= cc->rtol) st = CONVERGED;
-                else if (iter >= cc->max_iter) st = MAXITER;
+        double sr[M], sb[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            double a0 = 0.0, a1 = 0.0;
+            for (int t = lane; t < g.ntiles; t += WAVE) {
+                a0 += J.part[2 * M * t + 2 * m];
+                a1 += J.part[2 * M * t + 2 * m + 1];
             }
-            cc->stop = st;
-            cc->epoch = tag + 1u;
-            cc->done = 0u;
+            sr[m] = wave_sum(a0);
+            sb[m] = wave_sum(a1);
+        }
+        if (lane == 0) {
+            if constexpr (M > 1) {
+                finalise_multi<M>(J, sr, sb, iter, tag);
+            } else {
+                Ctl *cc = J.ctl;
+                if (iter == 0) cc->bnorm2 = sb[0];
+                const double nb2 = iter == 0 ? sb[0] : cc->bnorm2;
+                uint32_t st = RUN;
+                const uint32_t err = cc->err;
+                if (err) {
+                    st = (err & 2u) ? BREAKDOWN : TIMEOUT;
+                } else if (nb2 == 0.0) {
+                    st = ZERO_RHS;
+                    cc->rho = 0.0;
+                    if (J.hist) J.hist[iter] = 0.0;
+                } else {
+                    const double rho = sqrt(sr[0]) / sqrt(nb2);
+                    cc->rho = rho;
+                    if (J.hist) J.hist[iter] = rho;
+                    if (cc->rtol > 0.0 && rho <= cc->rtol) st = CONVERGED;
+                    else if (iter >= cc->max_iter) st = MAXITER;
+                }
+                cc->stop = st;
+                cc->epoch = tag + 1u;
+                cc->done = 0u;
+            }
         }
     }
     launch_done(a);
@@ -804,37 +908,41 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
 // order (step s visits plane steps - 1 - s; inside a lane quadrant (1,1)
 // first, (0,0) last), then x += d in the precision R of x.
 
-template <typename F, typename R>
+template <typename F, typename R, int M>
 struct BwdLoad {
-    F y, u[3];   // y, Un, Ue, Ut
-    R x;
+    Pk<F, M> y;
+    F u[3];      // Un, Ue, Ut
+    Pk<R, M> x;
 };
 
-template <typename F, typename R>
+template <typename F, typename R, int M>
 struct BwdSrc {
-    const GLOBAL F *y;
+    const GLOBAL Pk<F, M> *y;
     const GLOBAL F *U[3];
-    GLOBAL R *x;
+    GLOBAL Pk<R, M> *x;
     uint32_t e0;
 };
 
-template <typename F, typename R>
-__device__ __forceinline__ void bwd_issue(BwdLoad<F, R> &c, const BwdSrc<F, R> &s, int steps, int step)
+template <typename F, typename R, int M>
+__device__ __forceinline__ void bwd_issue(BwdLoad<F, R, M> &c, const BwdSrc<F, R, M> &s, int steps, int step)
 {
     const uint32_t e = s.e0 + (uint32_t)(steps - 1 - step) * PLANE;
     c.y = ldg(s.y, e);
 #pragma unroll
     for (int d = 0; d < 3; d++) c.u[d] = ldg(s.U[d], e);
-    c.x = ldg((const GLOBAL R *)s.x, e);
+    c.x = ldg((const GLOBAL Pk<R, M> *)s.x, e);
 }
 
-template <typename F, typename R, int NP>
+template <typename F, typename R, int NP, int M>
 __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
 {
-    constexpr int NV = NW<F>::n;
-    __shared__ F ring[2][4][NQ][TT];     // y, Un, Ue, Ut
-    __shared__ R xring[4][NQ][TT];
-    __shared__ F dbuf[2][NQ][TT];
+    typedef Pk<F, M> FV;
+    typedef Pk<R, M> RV;
+    constexpr int NV = NW<FV>::n;
+    __shared__ FV yring[2][NQ][TT];
+    __shared__ F ring[2][3][NQ][TT];     // Un, Ue, Ut
+    __shared__ RV xring[4][NQ][TT];
+    __shared__ FV dbuf[2][NQ][TT];
     __shared__ int s_buf[4];
 
     const int lane = threadIdx.x & (WAVE - 1);
@@ -855,7 +963,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
     const long long fstride = (long long)g.steps * FW;
     GLOBAL Ctl *ctl = gp(J.ctl);
 
-    for (int x = threadIdx.x; x < 2 * NQ * TT; x += blockDim.x) (&dbuf[0][0][0])[x] = F(0);
+    for (int x = threadIdx.x; x < 2 * NQ * TT; x += blockDim.x) (&dbuf[0][0][0])[x] = FV(0);
     __syncthreads();
 
     if (wave == 0) {
@@ -875,22 +983,23 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
         };
 #pragma unroll
         for (int q = 0; q < PD; q++) {   // same store pattern as a step (sink only)
-            post_record<NV>(fbase, post, g.steps, g.steps, FW, tag, F(0));
+            post_record<NV>(fbase, post, g.steps, g.steps, FW, tag, FV(0));
             plan(q, q);
         }
-        F dT[NQ] = {F(0), F(0), F(0), F(0)};
+        FV dT[NQ] = {FV(0), FV(0), FV(0), FV(0)};
         bool aborted = false;
         const int dE = v.ip < LI - 1 ? 1 : 0, dN = v.jp < LJ - 1 ? LI : 0;
-        F yv[NQ], un[NQ], ue[NQ], ut[NQ];
-        F nE0, nE2, nN0, nN1;
+        FV yv[NQ];
+        F un[NQ], ue[NQ], ut[NQ];
+        FV nE0, nE2, nN0, nN1;
         auto prefetch = [&](int s) {   // operands of step s: ring slot, in-tile neighbours of step s - 1
             const int slot = s & 1, pr = (s - 1) & 1;
 #pragma unroll
             for (int c = 0; c < NQ; c++) {
-                yv[c] = ring[slot][0][c][lane];
-                un[c] = ring[slot][1][c][lane];
-                ue[c] = ring[slot][2][c][lane];
-                ut[c] = ring[slot][3][c][lane];
+                yv[c] = yring[slot][c][lane];
+                un[c] = ring[slot][0][c][lane];
+                ue[c] = ring[slot][1][c][lane];
+                ut[c] = ring[slot][2][c][lane];
             }
             nE0 = dbuf[pr][0][lane + dE];
             nE2 = dbuf[pr][2][lane + dE];
@@ -907,7 +1016,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
                 if (!aborted && !halo_wait(pv[q], needE[q], fbase + oE[q], needN[q], fbase + oN[q], tag, ctl,
                                            a.timeout_ticks))
                     aborted = true;
-                F he0, he1, hn0, hn1;
+                FV he0, he1, hn0, hn1;
                 from_words(&pv[q].a[0], he0);
                 from_words(&pv[q].a[NV], he1);
                 from_words(&pv[q].b[0], hn0);
@@ -916,43 +1025,51 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
                 keep(nE2);
                 keep(nN0);
                 keep(nN1);
-                const F zero = F(0);
-                const F E1 = dE ? nE0 : (needE[q] ? he0 : zero);   // E of quadrant (1,0)
-                const F E3 = dE ? nE2 : (needE[q] ? he1 : zero);   // E of quadrant (1,1)
-                const F N2 = dN ? nN0 : (needN[q] ? hn0 : zero);   // N of quadrant (0,1)
-                const F N3 = dN ? nN1 : (needN[q] ? hn1 : zero);   // N of quadrant (1,1)
+                const FV zero = FV(0);
+                const FV E1 = dE ? nE0 : (needE[q] ? he0 : zero);   // E of quadrant (1,0)
+                const FV E3 = dE ? nE2 : (needE[q] ? he1 : zero);   // E of quadrant (1,1)
+                const FV N2 = dN ? nN0 : (needN[q] ? hn0 : zero);   // N of quadrant (0,1)
+                const FV N3 = dN ? nN1 : (needN[q] ? hn1 : zero);   // N of quadrant (1,1)
                 const bool kin = s < g.steps && v.kin(g.steps - 1 - s, g.nk);
-                F d[NQ];
-                {
-                    F t = yv[3] - un[3] * N3;
-                    t = t - ue[3] * E3;
-                    t = t - ut[3] * dT[3];
-                    d[3] = (kin && (v.inq & 8u)) ? t : zero;
-                }
-                {
-                    F t = yv[2] - un[2] * N2;
-                    t = t - ue[2] * d[3];
-                    t = t - ut[2] * dT[2];
-                    d[2] = (kin && (v.inq & 4u)) ? t : zero;
-                }
-                {
-                    F t = yv[1] - un[1] * d[3];
-                    t = t - ue[1] * E1;
-                    t = t - ut[1] * dT[1];
-                    d[1] = (kin && (v.inq & 2u)) ? t : zero;
-                }
-                {
-                    F t = yv[0] - un[0] * d[2];
-                    t = t - ue[0] * d[1];
-                    t = t - ut[0] * dT[0];
-                    d[0] = (kin && (v.inq & 1u)) ? t : zero;
+                FV d[NQ];
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    F d0, d1, d2, d3;
+                    {
+                        F t = el(yv[3], m) - un[3] * el(N3, m);
+                        t = t - ue[3] * el(E3, m);
+                        t = t - ut[3] * el(dT[3], m);
+                        d3 = (kin && (v.inq & 8u)) ? t : F(0);
+                    }
+                    {
+                        F t = el(yv[2], m) - un[2] * el(N2, m);
+                        t = t - ue[2] * d3;
+                        t = t - ut[2] * el(dT[2], m);
+                        d2 = (kin && (v.inq & 4u)) ? t : F(0);
+                    }
+                    {
+                        F t = el(yv[1], m) - un[1] * d3;
+                        t = t - ue[1] * el(E1, m);
+                        t = t - ut[1] * el(dT[1], m);
+                        d1 = (kin && (v.inq & 2u)) ? t : F(0);
+                    }
+                    {
+                        F t = el(yv[0], m) - un[0] * d2;
+                        t = t - ue[0] * d1;
+                        t = t - ut[0] * el(dT[0], m);
+                        d0 = (kin && (v.inq & 1u)) ? t : F(0);
+                    }
+                    set_el(d[0], m, d0);
+                    set_el(d[1], m, d1);
+                    set_el(d[2], m, d2);
+                    set_el(d[3], m, d3);
                 }
 #pragma unroll
                 for (int c = 0; c < NQ; c++) {
                     dT[c] = d[c];
                     dbuf[s & 1][c][lane] = d[c];
                 }
-                const F rec = dbuf[s & 1][post.q][post.src];
+                const FV rec = dbuf[s & 1][post.q][post.src];
                 prefetch(s + 1);   // issued before the record store waits for its value
                 post_record<NV>(fbase, post, s, g.steps, FW, tag, rec);
                 plan(q, s + PD);
@@ -964,21 +1081,25 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
     } else {
         const int lw = wave - 1;
         const int q = lw % NQ, ph = lw / NQ;
-        BwdSrc<F, R> src;
-        src.y = gp((const F *)J.y);
+        BwdSrc<F, R, M> src;
+        src.y = gp((const FV *)J.y);
 #pragma unroll
         for (int d = 0; d < 3; d++) src.U[d] = gp((const F *)J.LU) + (4 + d) * g.elems;
-        src.x = gp((R *)J.x);
+        src.x = gp((RV *)J.x);
         src.e0 = (uint32_t)v.base + (uint32_t)(q * TT);
-        BwdLoad<F, R> c;
+        // several right-hand sides: one that has stopped keeps its x
+        bool frozen[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) frozen[m] = M > 1 && J.ctl[1 + m].stop != RUN;
+        BwdLoad<F, R, M> c;
         if (ph < g.steps) bwd_issue(c, src, g.steps, ph);
         auto turn = [&](int f) {
             if (f < g.steps) {
                 const int slot = f & 1;
-                ring[slot][0][q][lane] = c.y;
-                ring[slot][1][q][lane] = c.u[0];
-                ring[slot][2][q][lane] = c.u[1];
-                ring[slot][3][q][lane] = c.u[2];
+                yring[slot][q][lane] = c.y;
+                ring[slot][0][q][lane] = c.u[0];
+                ring[slot][1][q][lane] = c.u[1];
+                ring[slot][2][q][lane] = c.u[2];
                 xring[f & 3][q][lane] = c.x;
             }
             // Issue the next loads before the x store: a load of x behind a
@@ -987,9 +1108,12 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
             const int p = f - 3;
             if (p >= 0 && p < g.steps) {
                 const int sp = g.steps - 1 - p;
-                const F dv = dbuf[p & 1][q][lane];
-                const R xv = xring[p & 3][q][lane];
-                stg(src.x, src.e0 + (uint32_t)sp * PLANE, xv + (R)dv);   // padding: 0 + 0
+                const FV dv = dbuf[p & 1][q][lane];
+                RV xv = xring[p & 3][q][lane];
+#pragma unroll
+                for (int m = 0; m < M; m++)
+                    if (!frozen[m]) set_el(xv, m, el(xv, m) + (R)el(dv, m));   // padding: 0 + 0
+                stg(src.x, src.e0 + (uint32_t)sp * PLANE, xv);
             }
         };
         if (ph == 0) turn(0);
@@ -1262,7 +1386,9 @@ __global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, T *dst, long long ds
                     (a == 4 && j == g.nj - 1) || (a == 5 && k == 0) || (a == 6 && k == g.nk - 1))
                     v = 0.0;
             }
-            if (shear == SHEAR_SYM) {
+            if (shear == SHEAR_PAIR_F64 || shear == SHEAR_PAIR_F32) {
+                dst[2 * e + a] = (T)v;
+            } else if (shear == SHEAR_SYM) {
                 if (a == 0 || a == 2 || a == 4 || a == 6) dst[sym_index(a, e, dst_stride)] = (T)v;
             } else if (shear == SHEAR_COEF32) {
                 dst[coef32_index(a, e, dst_stride)] = (T)v;
@@ -1293,7 +1419,7 @@ __global__ void k_check_symmetric(int ni, int nj, int nk, SrcPtrs a, unsigned *b
 }
 
 template <typename T>
-__global__ void k_from_sheared(Geom g, const T *src, double *dst, const Ctl *ctl)
+__global__ void k_from_sheared(Geom g, const T *src, double *dst, const Ctl *ctl, int comp, int which)
 {
     const long long n = (long long)g.ni * g.nj * g.nk;
     const bool zero = ctl != nullptr && ctl->stop == ZERO_RHS;
@@ -1302,7 +1428,7 @@ __global__ void k_from_sheared(Geom g, const T *src, double *dst, const Ctl *ctl
         const int i = (int)(c % g.ni);
         const int j = (int)((c / g.ni) % g.nj);
         const int k = (int)(c / ((long long)g.ni * g.nj));
-        dst[c] = zero ? 0.0 : (double)src[sheared_index(g, i, j, k)];
+        dst[c] = zero ? 0.0 : (double)src[comp * sheared_index(g, i, j, k) + which];
     }
 }
 
@@ -1362,7 +1488,7 @@ hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, 
     SrcPtrs sp{};
     for (int a = 0; a < narr && a < 9; a++) sp.p[a] = src[a];
     const dim3 grid(grid_for(g.elems));
-    if (shear == SHEAR_F32 || shear == SHEAR_COEF32)
+    if (shear == SHEAR_F32 || shear == SHEAR_COEF32 || shear == SHEAR_PAIR_F32)
         hipLaunchKernelGGL(k_to_sheared<float>, grid, dim3(256), 0, s, g, narr, sp, (float *)dst, dst_stride, shear);
     else
         hipLaunchKernelGGL(k_to_sheared<double>, grid, dim3(256), 0, s, g, narr, sp, (double *)dst, dst_stride,
@@ -1379,13 +1505,14 @@ hipError_t launch_check_symmetric(int ni, int nj, int nk, const double *const *a
 }
 
 hipError_t launch_from_sheared(const Geom &g, const void *src, int src_f32, double *dst, const Ctl *ctl,
-                               hipStream_t s)
+                               hipStream_t s, int comp, int which)
 {
     const dim3 grid(grid_for((long long)g.ni * g.nj * g.nk));
     if (src_f32)
-        hipLaunchKernelGGL(k_from_sheared<float>, grid, dim3(256), 0, s, g, (const float *)src, dst, ctl);
+        hipLaunchKernelGGL(k_from_sheared<float>, grid, dim3(256), 0, s, g, (const float *)src, dst, ctl, comp, which);
     else
-        hipLaunchKernelGGL(k_from_sheared<double>, grid, dim3(256), 0, s, g, (const double *)src, dst, ctl);
+        hipLaunchKernelGGL(k_from_sheared<double>, grid, dim3(256), 0, s, g, (const double *)src, dst, ctl, comp,
+                           which);
     return hipGetLastError();
 }
 
@@ -1410,46 +1537,55 @@ hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename F, typename R, int NP>
+template <typename F, typename R, int NP, int M>
 static hipError_t launch_sweep_t(const LaunchArgs &a, int backward, hipStream_t s)
 {
     const dim3 block(WAVE * (1 + NQ * NP));
     if (backward)
-        hipLaunchKernelGGL((k_backward<F, R, NP>), dim3(a.total), block, 0, s, a);
+        hipLaunchKernelGGL((k_backward<F, R, NP, M>), dim3(a.total), block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_forward<F, R, NP>), dim3(a.total), block, 0, s, a);
+        hipLaunchKernelGGL((k_forward<F, R, NP, M>), dim3(a.total), block, 0, s, a);
     return hipGetLastError();
 }
 
 template <int NP>
-static hipError_t launch_sweep_np(const LaunchArgs &a, int arith, int backward, hipStream_t s)
+static hipError_t launch_sweep_np(const LaunchArgs &a, int arith, int nrhs, int backward, hipStream_t s)
 {
+    if (nrhs == 2) {   // FP32 factors only: a pair of FP32 values fills a face record entry
+        switch (arith) {
+        case ARITH_MIXED: return launch_sweep_t<float, double, NP, 2>(a, backward, s);
+        case ARITH_F32: return launch_sweep_t<float, float, NP, 2>(a, backward, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (nrhs != 1) return hipErrorInvalidValue;
     switch (arith) {
-    case ARITH_F64: return launch_sweep_t<double, double, NP>(a, backward, s);
-    case ARITH_MIXED: return launch_sweep_t<float, double, NP>(a, backward, s);
-    case ARITH_F32: return launch_sweep_t<float, float, NP>(a, backward, s);
+    case ARITH_F64: return launch_sweep_t<double, double, NP, 1>(a, backward, s);
+    case ARITH_MIXED: return launch_sweep_t<float, double, NP, 1>(a, backward, s);
+    case ARITH_F32: return launch_sweep_t<float, float, NP, 1>(a, backward, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-static hipError_t launch_sweep(const LaunchArgs &a, int arith, int backward, const SweepPlan &p, hipStream_t s)
+static hipError_t launch_sweep(const LaunchArgs &a, int arith, int nrhs, int backward, const SweepPlan &p,
+                               hipStream_t s)
 {
     switch (p.phases) {
-    case 1: return launch_sweep_np<1>(a, arith, backward, s);
-    case 2: return launch_sweep_np<2>(a, arith, backward, s);
-    case 3: return launch_sweep_np<3>(a, arith, backward, s);
+    case 1: return launch_sweep_np<1>(a, arith, nrhs, backward, s);
+    case 2: return launch_sweep_np<2>(a, arith, nrhs, backward, s);
+    case 3: return launch_sweep_np<3>(a, arith, nrhs, backward, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_forward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s)
+hipError_t launch_forward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s, int nrhs)
 {
-    return launch_sweep(a, arith, 0, p, s);
+    return launch_sweep(a, arith, nrhs, 0, p, s);
 }
 
-hipError_t launch_backward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s)
+hipError_t launch_backward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s, int nrhs)
 {
-    return launch_sweep(a, arith, 1, p, s);
+    return launch_sweep(a, arith, nrhs, 1, p, s);
 }
 
 }  // namespace sipk

@@ -44,6 +44,18 @@ struct sip_system_s {
     sipk::LaunchCtl *lc = nullptr;
     sipk::Ctl *h_ctl = nullptr;     // pinned, 4 slots
     double *h_hist = nullptr;       // pinned
+    // two right-hand sides swept together (allocated on first use): b pairs
+    // then x pairs, y pairs, own face words and control blocks
+    double *mbx = nullptr;
+    void *my = nullptr;
+    uint64_t *mface = nullptr;
+    double *mpart = nullptr;
+    sipk::Ctl *mctl = nullptr;      // 3: the sweep's, then one per right-hand side
+    double *mhist = nullptr;        // 2 * mhist_cap
+    int mhist_cap = 0;
+    sipk::Job mjob{};
+    sipk::Job *d_mjob = nullptr;
+    sipk::Ctl *h_mctl = nullptr;    // pinned, 3 slots of 3
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t chunk_exec = nullptr;
     sipk::SweepPlan plan{};

@@ -26,7 +26,8 @@ PRECISIONS = {"fp64": SIP_FP64, "mixed": SIP_MIXED, "fp32": SIP_FP32,
               SIP_FP64: SIP_FP64, SIP_MIXED: SIP_MIXED, SIP_FP32: SIP_FP32}
 
 # every symbol include/sip.h declares
-EXPORTS = ("sip_factor", "sip_iterate", "sip_solve", "sip_export_factors", "sip_profile_sweeps", "sip_system_info",
+EXPORTS = ("sip_factor", "sip_iterate", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
+           "sip_profile_sweeps", "sip_system_info",
            "sip_system_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
            "sip_server_release", "sip_server_stats", "sip_server_destroy", "sip_status_str",
            "sip_last_error", "sip_abi_version")
@@ -79,6 +80,8 @@ def lib():
     L.sip_factor.argtypes = [ctypes.POINTER(Problem), vp, ctypes.POINTER(vp)]
     L.sip_iterate.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
     L.sip_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(Info), vp]
+    L.sip_iterate_multi.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, ctypes.POINTER(dbl), vp]
+    L.sip_solve_multi.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, i32, ctypes.POINTER(Info), vp]
     L.sip_export_factors.argtypes = [vp, ctypes.POINTER(vp), vp]
     L.sip_profile_sweeps.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
     L.sip_system_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]
@@ -89,7 +92,8 @@ def lib():
     L.sip_server_release.argtypes = [vp, ctypes.c_uint64]
     L.sip_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
     L.sip_server_destroy.argtypes = [vp]
-    for f in ("sip_factor", "sip_iterate", "sip_solve", "sip_export_factors", "sip_profile_sweeps", "sip_system_info",
+    for f in ("sip_factor", "sip_iterate", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
+              "sip_profile_sweeps", "sip_system_info",
               "sip_system_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
               "sip_server_release", "sip_server_stats", "sip_server_destroy"):
         getattr(L, f).restype = ctypes.c_int32
@@ -198,6 +202,35 @@ def sip_solve(system, b, x, rtol=1e-8, max_iter=100000, stream=None, raise_on_no
     st = lib().sip_solve(system._h, pb, px, float(rtol), int(max_iter), ctypes.byref(info), _stream(stream))
     _check(st, (SIP_OK,) if raise_on_notconv else (SIP_OK, SIP_ENOTCONV))
     return st, info.iters, info.rel_res, info.seconds
+
+
+def _grids(ts, shape, name):
+    ptrs = [_grid(t, shape, f"{name}[{r}]").value for r, t in enumerate(ts)]
+    return (ctypes.c_void_p * len(ptrs))(*ptrs)
+
+
+def sip_iterate_multi(system, bs, xs, n_iter, history=True, stream=None):
+    """n_iter SIP updates of several right-hand sides (pairs share one pass of
+    the sweeps); xs updated in place.  Returns hist[r, n] (numpy) or None."""
+    if len(bs) != len(xs) or not bs:
+        raise ValueError("need as many x as b, at least one")
+    pb, px = _grids(bs, system.shape, "b"), _grids(xs, system.shape, "x")
+    hist = np.zeros((len(bs), int(n_iter) + 1)) if history else None
+    hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history else None
+    _check(lib().sip_iterate_multi(system._h, len(bs), pb, px, int(n_iter), hp, _stream(stream)))
+    return hist
+
+
+def sip_solve_multi(system, bs, xs, rtol=1e-8, max_iter=100000, stream=None, raise_on_notconv=True):
+    """Solve several right-hand sides (each stops at its own tolerance).
+    Returns (status, [(iters, rel_res, seconds) per right-hand side])."""
+    if len(bs) != len(xs) or not bs:
+        raise ValueError("need as many x as b, at least one")
+    pb, px = _grids(bs, system.shape, "b"), _grids(xs, system.shape, "x")
+    info = (Info * len(bs))()
+    st = lib().sip_solve_multi(system._h, len(bs), pb, px, float(rtol), int(max_iter), info, _stream(stream))
+    _check(st, (SIP_OK,) if raise_on_notconv else (SIP_OK, SIP_ENOTCONV))
+    return st, [(i.iters, i.rel_res, i.seconds) for i in info]
 
 
 def sip_export_factors(system, stream=None):
