@@ -32,6 +32,9 @@ A_SYM_SAVING = 56 - 32     # symmetric storage reads A_P, A_E, A_N, A_T only
 BWD_BYTES = {"mixed": 12 + 4 + 8 + 8, "fp64": 24 + 8 + 8 + 8,              # U, y, x in, x out
              "fp32": 12 + 4 + 4 + 4}
 FP32_RTOL = 1e-5           # the all-FP32 relaxation stalls near 1e-7
+# a pair of right-hand sides per sweep: A and the factors once, b, x, y per right-hand side
+PAIR_FWD_BYTES = 56 + 16 + 2 * (8 + 8 + 4)     # per cell, both right-hand sides
+PAIR_BWD_BYTES = 12 + 2 * (4 + 8 + 8)
 RTOL = 1e-8
 # HBM bytes per launch of the sweep kernels on the 256^3 workload, from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes summarised in
@@ -61,10 +64,11 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--storage", default="full", choices=["full", "symmetric"],
                     help="coefficient storage of the sweeps (symmetric: Poisson workloads only)")
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "large", "serving"],
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "large", "serving", "pair"],
                     help="single: 256^3 block (default); batched: 64 uneven blocks through the solve "
                          "server; large: 512x512x256 stretched Poisson; serving: Poisson-arrival "
-                         "request stream (8 right-hand sides per system)")
+                         "request stream (8 right-hand sides per system); pair: the 256^3 block with "
+                         "two right-hand sides swept together")
     ap.add_argument("--serve-systems", type=int, default=40, help="systems in the serving stream (8 rhs each)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="server HBM budget")
@@ -245,6 +249,72 @@ def fp32_comparison(sip, A, b, alpha, cells):
             "stall_rel_res": float(min(hist))}
 
 
+def pair_run(args):
+    """256^3 convection-diffusion, two right-hand sides (the default one and
+    a second seeded one) solved together by sip_solve_multi to 1e-8 (mixed);
+    value = right-hand-side cell-iterations / wall time, factorisation in the
+    step.  The line also gives the same two solved one after the other."""
+    import numpy as np
+    import torch
+
+    from paper_1303_4538_amd import problems, sip
+
+    sip.lib()
+    dev = torch.device("cuda:0")
+    n = args.n
+    c = problems.config2(n)
+    cells = n ** 3
+    b2 = problems.rhs_uniform(n, n, n, np.random.default_rng(np.random.SeedSequence(problems.MASTER_SEED).spawn(3)[2]))
+    A = torch.from_numpy(c["A"]).to(dev)
+    bs = [torch.from_numpy(c["b"]).to(dev), torch.from_numpy(b2).to(dev)]
+    torch.cuda.synchronize()
+
+    def step(together):
+        S = sip.sip_factor(A, c["alpha"], "mixed")
+        xs = [torch.zeros_like(b) for b in bs]
+        if together:
+            st, info = sip.sip_solve_multi(S, bs, xs, RTOL, 200000)
+            its = [i[0] for i in info]
+        else:
+            its = [sip.sip_solve(S, b, x, RTOL, 200000)[1] for b, x in zip(bs, xs)]
+        S.close()
+        return its
+
+    for _ in range(args.warmup):
+        step(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = [step(True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = cells * sum(sum(i) for i in its) / elapsed
+    t1 = time.perf_counter()
+    its1 = step(False)
+    torch.cuda.synchronize()
+    alone = cells * sum(its1) / (time.perf_counter() - t1)
+    S = sip.sip_factor(A, c["alpha"], "mixed")
+    fwd_ms, bwd_ms = sip.sip_profile_sweeps_multi(S, bs, [torch.zeros_like(b) for b in bs], args.profile_iters)
+    S.close()
+    achieved = PAIR_FWD_BYTES * cells / (fwd_ms * 1e-3) / 1e9
+    line = {
+        "metric": "right-hand-side cell-iterations/s (two mixed SIP solves swept together, to 1e-8)",
+        "value": value, "unit": "cell-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{n}^3 upwind convection-diffusion (D=1, max|F|=2), two right-hand sides, "
+                               f"alpha 0.92, factor + sip_solve_multi to {RTOL:g}",
+                   "cells": cells, "iterations": its[-1], "one_after_the_other_cell_iters_per_s": alone,
+                   "speedup_vs_one_after_the_other": value / alone},
+        "roofline": {"bound": "hbm", "kernel": "k_forward<float, double, 2, 2> (pair forward sweep)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+                     "bwd_gbps": round(PAIR_BWD_BYTES * cells / (bwd_ms * 1e-3) / 1e9, 1)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -259,6 +329,9 @@ def main():
         return
     if args.workload == "serving":
         serving_run(args)
+        return
+    if args.workload == "pair":
+        pair_run(args)
         return
     import numpy as np
     import torch

@@ -135,8 +135,9 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
  *   b[r], x[r]  device arrays as in sip_iterate / sip_solve (r < nrhs).
  *   Every right-hand side gets exactly the iterates, residual history and
  *   stop decision it would get alone (bitwise): in sip_solve_multi each one
- *   stops at its own first n with rho_n <= rtol and keeps that x_n while its
- *   partner goes on.
+ *   stops at its own first n with rho_n <= rtol and keeps that x_n; once one
+ *   of a pair has stopped, the other goes on through the one-right-hand-side
+ *   path from its current iterate.
  *   rel_res_hist  NULL, or HOST memory of nrhs * (n_iter + 1) doubles,
  *           right-hand side r's history at r * (n_iter + 1).
  *   info    NULL, or HOST memory of nrhs entries.
@@ -164,6 +165,14 @@ sip_status sip_export_factors(sip_system h, double *const out[7], void *stream);
  * sweep (ms[1]) to host memory.  n_iter >= 1.  Errors: SIP_EINVAL,
  * SIP_EDEVICE. */
 sip_status sip_profile_sweeps(sip_system h, const double *b, double *x, int32_t n_iter, double ms[2], void *stream);
+
+/* sip_profile_sweeps_multi -- sip_profile_sweeps for one pair of
+ * right-hand sides (b[0], b[1], x[0], x[1]) swept together: the average
+ * device time of one pair forward sweep (ms[0]) and one pair backward sweep
+ * (ms[1]).  SIP_MIXED and SIP_FP32 only.  Errors: SIP_EINVAL, SIP_ENOMEM,
+ * SIP_EDEVICE. */
+sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double *const *x, int32_t n_iter,
+                                    double ms[2], void *stream);
 
 /* sip_system_info -- dims, precision and device bytes held by a handle. */
 sip_status sip_system_info(sip_system h, int32_t dims[3], int32_t *precision, size_t *device_bytes);

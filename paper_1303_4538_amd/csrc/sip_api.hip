@@ -652,6 +652,7 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
         HIPTRY(launch_init_ctl(h->mctl, 3, (uint32_t)max_iter, rtol, 0, s));
         sip_status st = SIP_OK;
         long long launched = 0;
+        bool split = false;   // one right-hand side stopped: its partner goes on alone
         hipEvent_t ev[2];
         HIPTRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
         HIPTRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -671,7 +672,12 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
                     st = set_error(SIP_EDEVICE, "event wait failed");
                     break;
                 }
-                if (h->h_mctl[3 * ((c - 1) & 1)].stop != RUN) break;
+                const Ctl *hc = &h->h_mctl[3 * ((c - 1) & 1)];
+                if (hc[0].stop != RUN) break;
+                if (hc[1].stop != RUN || hc[2].stop != RUN) {
+                    split = true;
+                    break;
+                }
             }
         }
         hipEventDestroy(ev[0]);
@@ -685,15 +691,24 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
         HIPTRY(hipStreamSynchronize(s));
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         const Ctl *c = &h->h_mctl[6];
-        if (c[0].stop == RUN) return set_error(SIP_EDEVICE, "solve ended without a stop decision");
+        if (c[0].stop == RUN && !split) return set_error(SIP_EDEVICE, "solve ended without a stop decision");
         if (c[0].stop == BREAKDOWN || c[0].stop == TIMEOUT) return stop_status(c[0].stop);
         for (int m = 0; m < 2; m++) {
-            if (info) {
-                info[r0 + m].iters = (int32_t)c[1 + m].iter;
-                info[r0 + m].rel_res = c[1 + m].stop == ZERO_RHS ? 0.0 : c[1 + m].rho;
-                info[r0 + m].seconds = secs;
+            sip_info one{(int32_t)c[1 + m].iter, c[1 + m].stop == ZERO_RHS ? 0.0 : c[1 + m].rho, secs};
+            if (c[1 + m].stop == RUN) {
+                // The partner has stopped: this one continues from its iterate
+                // x_N through the one-right-hand-side sweeps, which compute the
+                // same iterates and residuals as the pair sweeps.
+                const int32_t done = (int32_t)c[0].iter;
+                sip_info more{};
+                const sip_status s1 = sip_solve(h, b[r0 + m], x[r0 + m], rtol, max_iter - done, &more, stream);
+                if (s1 != SIP_OK && s1 != SIP_ENOTCONV) return s1;
+                one = sip_info{done + more.iters, more.rel_res, secs + more.seconds};
+                if (s1 == SIP_ENOTCONV) worst = SIP_ENOTCONV;
+            } else if (c[1 + m].stop == MAXITER) {
+                worst = SIP_ENOTCONV;
             }
-            if (c[1 + m].stop == MAXITER) worst = SIP_ENOTCONV;
+            if (info) info[r0 + m] = one;
         }
     }
     for (int r = 2 * npair; r < nrhs; r++) {
@@ -702,6 +717,46 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
         else if (st != SIP_OK) return st;
     }
     if (worst == SIP_ENOTCONV) return set_error(SIP_ENOTCONV, "a right-hand side reached max_iter");
+    return SIP_OK;
+}
+
+sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double *const *x, int32_t n_iter,
+                                    double ms[2], void *stream)
+{
+    if (!h || !b || !x || !b[0] || !b[1] || !x[0] || !x[1] || !ms) return set_error(SIP_EINVAL, "NULL argument");
+    if (n_iter < 1) return set_error(SIP_EINVAL, "n_iter must be >= 1");
+    if (!pairs_ok(h)) return set_error(SIP_EINVAL, "pairs of right-hand sides need FP32 factors");
+    hipStream_t s = (hipStream_t)stream;
+    TRY(ensure_multi(h, n_iter + 1, s));
+    HIPTRY(multi_stage_in(h, b[0], b[1], x[0], x[1], s));
+    HIPTRY(launch_init_ctl(h->mctl, 3, (uint32_t)n_iter, 0.0, 0, s));
+    std::vector<hipEvent_t> ev(2 * n_iter + 1);
+    for (auto &e : ev) HIPTRY(hipEventCreate(&e));
+    const LaunchArgs fa = multi_args(h, false), ba = multi_args(h, true);
+    sip_status st = SIP_OK;
+    if (hipEventRecord(ev[0], s) != hipSuccess) st = set_error(SIP_EDEVICE, "event record failed");
+    for (int q = 0; q < n_iter && st == SIP_OK; q++) {
+        if (launch_forward(fa, h->precision, h->plan, s, 2) != hipSuccess ||
+            hipEventRecord(ev[2 * q + 1], s) != hipSuccess ||
+            launch_backward(ba, h->precision, h->plan, s, 2) != hipSuccess ||
+            hipEventRecord(ev[2 * q + 2], s) != hipSuccess)
+            st = set_error(SIP_EDEVICE, "launch failed");
+    }
+    if (st == SIP_OK && multi_stage_out(h, x[0], x[1], s) != hipSuccess) st = set_error(SIP_EDEVICE, "reorder failed");
+    if (st == SIP_OK && hipStreamSynchronize(s) != hipSuccess) st = set_error(SIP_EDEVICE, "synchronise failed");
+    double f = 0.0, bk = 0.0;
+    for (int q = 0; q < n_iter && st == SIP_OK; q++) {
+        float a = 0.f, c = 0.f;
+        if (hipEventElapsedTime(&a, ev[2 * q], ev[2 * q + 1]) != hipSuccess ||
+            hipEventElapsedTime(&c, ev[2 * q + 1], ev[2 * q + 2]) != hipSuccess)
+            st = set_error(SIP_EDEVICE, "event timing failed");
+        f += a;
+        bk += c;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (st != SIP_OK) return st;
+    ms[0] = f / n_iter;
+    ms[1] = bk / n_iter;
     return SIP_OK;
 }
 

@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": SIP_FP64, "mixed": SIP_MIXED, "fp32": SIP_FP32,
 
 # every symbol include/sip.h declares
 EXPORTS = ("sip_factor", "sip_iterate", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
-           "sip_profile_sweeps", "sip_system_info",
+           "sip_profile_sweeps", "sip_profile_sweeps_multi", "sip_system_info",
            "sip_system_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
            "sip_server_release", "sip_server_stats", "sip_server_destroy", "sip_status_str",
            "sip_last_error", "sip_abi_version")
@@ -84,6 +84,7 @@ def lib():
     L.sip_solve_multi.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, i32, ctypes.POINTER(Info), vp]
     L.sip_export_factors.argtypes = [vp, ctypes.POINTER(vp), vp]
     L.sip_profile_sweeps.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
+    L.sip_profile_sweeps_multi.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, ctypes.POINTER(dbl), vp]
     L.sip_system_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]
     L.sip_system_destroy.argtypes = [vp]
     L.sip_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
@@ -93,7 +94,7 @@ def lib():
     L.sip_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
     L.sip_server_destroy.argtypes = [vp]
     for f in ("sip_factor", "sip_iterate", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
-              "sip_profile_sweeps", "sip_system_info",
+              "sip_profile_sweeps", "sip_profile_sweeps_multi", "sip_system_info",
               "sip_system_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
               "sip_server_release", "sip_server_stats", "sip_server_destroy"):
         getattr(L, f).restype = ctypes.c_int32
@@ -248,6 +249,16 @@ def sip_profile_sweeps(system, b, x, n_iter, stream=None):
     pb, px = _grid(b, system.shape, "b"), _grid(x, system.shape, "x")
     ms = (ctypes.c_double * 2)()
     _check(lib().sip_profile_sweeps(system._h, pb, px, int(n_iter), ms, _stream(stream)))
+    return ms[0], ms[1]
+
+
+def sip_profile_sweeps_multi(system, bs, xs, n_iter, stream=None):
+    """sip_profile_sweeps for one pair of right-hand sides swept together."""
+    if len(bs) != 2 or len(xs) != 2:
+        raise ValueError("one pair of right-hand sides")
+    pb, px = _grids(bs, system.shape, "b"), _grids(xs, system.shape, "x")
+    ms = (ctypes.c_double * 2)()
+    _check(lib().sip_profile_sweeps_multi(system._h, pb, px, int(n_iter), ms, _stream(stream)))
     return ms[0], ms[1]
 
 

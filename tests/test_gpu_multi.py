@@ -190,3 +190,18 @@ def test_pair_after_single_solves_and_back(sip):
         sip.sip_solve(S, bs[0], x, 1e-8, 5000)
         assert torch.equal(x, ref[0])
     S.close()
+
+
+def test_profile_pair_matches_iterate(sip):
+    dims = (20, 18, 9)
+    rng = np.random.default_rng(13)
+    A = system("cd", dims, rng)
+    bs = [dev(rng.uniform(-1, 1, A.shape[1:])) for _ in range(2)]
+    S = sip.sip_factor(dev(A), 0.92, "mixed")
+    xs = [torch.zeros_like(b) for b in bs]
+    fwd, bwd = sip.sip_profile_sweeps_multi(S, bs, xs, 3)
+    ys = [torch.zeros_like(b) for b in bs]
+    sip.sip_iterate_multi(S, bs, ys, 3)
+    S.close()
+    assert fwd > 0 and bwd > 0
+    assert all(torch.equal(xs[r], ys[r]) for r in range(2))
