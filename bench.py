@@ -38,11 +38,11 @@ PAIR_BWD_BYTES = 12 + 2 * (4 + 8 + 8)
 RTOL = 1e-8
 # HBM bytes per launch of the sweep kernels on the 256^3 workload, from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes summarised in
-# profiles/sweeps_256cube_cd_mixed.md (calibrated against a plain copy), with
+# profiles/sweeps_256cube_cd.md (calibrated against a plain copy), with
 # the SHA-256 of the kernel source they were taken with.  Once the source
 # differs the counters no longer describe the kernel and traffic is null.
-MEASURED = {"kernels_sha256": "8fda63c324fb6e79edabcd5c7e71f77284ebe7802b05f16e15f7fdf3c1487a37",
-            "n": 256, "fwd_bytes": 1769528257, "bwd_bytes": 602272173}
+MEASURED = {"kernels_sha256": "49506b0b04a09e56bdca024318f22701d49ca70d458836eabaf312365fdc6337",
+            "n": 256, "fwd_bytes": 1770467498, "bwd_bytes": 602239215}
 
 
 def kernels_sha256():
@@ -73,8 +73,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="server HBM budget")
     ap.add_argument("--prof", action="store_true",
-                    help="short run for rocprofv3: factor + a few sweeps of the default workload and "
-                         "a 512 MiB device copy used to calibrate the HBM byte counters")
+                    help="short run for rocprofv3: factor + a few sweeps of the default workload (mixed, "
+                         "a pair of right-hand sides, all-FP32) and a 512 MiB device copy used to calibrate "
+                         "the HBM byte counters")
     return ap.parse_args()
 
 
@@ -95,9 +96,17 @@ def prof_run(args):
     S = sip.sip_factor(A, c["alpha"], "mixed")
     x = torch.zeros_like(b)
     fwd_ms, bwd_ms = sip.sip_profile_sweeps(S, b, x, 5)
+    print(f"prof: mixed forward {fwd_ms:.4f} ms, backward {bwd_ms:.4f} ms per sweep", flush=True)
+    # the same block with two right-hand sides swept together
+    bs = [b, torch.flip(b, dims=(0,)).contiguous()]
+    f2, b2 = sip.sip_profile_sweeps_multi(S, bs, [torch.zeros_like(b), torch.zeros_like(b)], 5)
+    print(f"prof: pair forward {f2:.4f} ms, backward {b2:.4f} ms per sweep", flush=True)
+    S.close()
+    S = sip.sip_factor(A, c["alpha"], "fp32")   # the all-FP32 relaxation
+    f3, b3 = sip.sip_profile_sweeps(S, b, torch.zeros_like(b), 5)
+    print(f"prof: fp32 forward {f3:.4f} ms, backward {b3:.4f} ms per sweep", flush=True)
     S.close()
     torch.cuda.synchronize()
-    print(f"prof: forward {fwd_ms:.4f} ms, backward {bwd_ms:.4f} ms per sweep", flush=True)
 
 
 def batched_run(args):
