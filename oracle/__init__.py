@@ -5,5 +5,5 @@ Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 """
 from .oracle import (  # noqa: F401
     build, factor, residual, residual_f32, forward, backward, forward_f32, backward_f32,
-    iterate, solve, norm2,
+    iterate, solve, norm2, blocks,
 )

@@ -66,6 +66,9 @@ def _load():
     lib.oracle_iterate.restype = l
     lib.oracle_solve.argtypes = [i, i, i, _D, _D, _D, _D, d, l, i, _D, _D]
     lib.oracle_solve.restype = l
+    _I = ctypes.POINTER(ctypes.c_int)
+    lib.oracle_blocks_run.argtypes = [i, i, i, _D, d, _D, _D, i, _I, i, _I, i, _I, l, d, i, _D, _D]
+    lib.oracle_blocks_run.restype = l
     _lib = lib
     return lib
 
@@ -185,6 +188,33 @@ def solve(A, LU, b, x0, rtol, max_iter, mixed=False, fp32=False):
     rr = ctypes.c_double(0.0)
     it = _load().oracle_solve(ni, nj, nk, _ptr(A), _ptr(LU), _ptr(b), _ptr(x), float(rtol),
                               int(max_iter), _mode(mixed, fp32), _ptr(hist), ctypes.byref(rr))
+    if it < 0:
+        raise MemoryError("oracle allocation failed")
+    return x, int(it), float(rr.value), hist[: it + 1]
+
+
+def blocks(A, alpha, b, x0, cuts, n_iter, rtol=0.0, mixed=False):
+    """Multi-block domain: the block cut planes ``cuts = (ci, cj, ck)`` (each
+    starting at 0 and ending at the extent) split the domain into blocks, each
+    factorised on its own and coupled through the residual of the whole
+    domain once per iteration.  Runs n_iter updates, or stops at the first
+    rho_n <= rtol (rtol > 0).  Returns (x, iterations, rel_res, hist)."""
+    A, b = _f64(A), _f64(b)
+    x = _f64(x0).copy()
+    ni, nj, nk = _dims(A)
+    cs = [np.ascontiguousarray(c, dtype=np.intc) for c in cuts]
+    for c, ext in zip(cs, (ni, nj, nk)):
+        if c[0] != 0 or c[-1] != ext or np.any(np.diff(c) < 1):
+            raise ValueError("cut planes must rise from 0 to the extent")
+    hist = np.zeros(int(n_iter) + 1)
+    rr = ctypes.c_double(0.0)
+    P = ctypes.POINTER(ctypes.c_int)
+    it = _load().oracle_blocks_run(ni, nj, nk, _ptr(A), float(alpha), _ptr(b), _ptr(x),
+                                   len(cs[0]) - 1, cs[0].ctypes.data_as(P), len(cs[1]) - 1, cs[1].ctypes.data_as(P),
+                                   len(cs[2]) - 1, cs[2].ctypes.data_as(P), int(n_iter), float(rtol),
+                                   1 if mixed else 0, _ptr(hist), ctypes.byref(rr))
+    if it == -2:
+        raise FloatingPointError("SIP factorisation breakdown in a block")
     if it < 0:
         raise MemoryError("oracle allocation failed")
     return x, int(it), float(rr.value), hist[: it + 1]

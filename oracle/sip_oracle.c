@@ -350,3 +350,100 @@ long oracle_solve(int ni, int nj, int nk, const double *A, const double *LU, con
 {
     return oracle_run(ni, nj, nk, A, LU, b, x, max_iter, rtol, mode, hist, rel_res);
 }
+
+/* ------------------------------------------------------------------------
+ * Multi-block domain (Sec. 4.2: each block runs its own SIP solver; blocks
+ * are coupled only through values at block boundaries exchanged once per
+ * iteration, every block receiving the values of the same previous iterate,
+ * as with the non-blocking exchange that completes all transfers before any
+ * received value is used).  The domain of ni x nj x nk cells is cut into
+ * nbi x nbj x nbk blocks at the planes ci[0..nbi] (ci[0] = 0, ci[nbi] = ni),
+ * cj, ck.  Each block is factorised on its own (couplings that leave the
+ * block are ignored by the factorisation); one iteration computes the
+ * residual of the whole domain with every coupling, r = b - A x (this is
+ * where neighbour values enter), and each block applies its own forward and
+ * backward substitution to its part of r.  mode 0: FP64; mode 1: mixed form
+ * (r rounded to FP32, FP32 factors and sweeps).  Returns the number of
+ * updates, -1 on allocation failure, -2 on a breakdown in some block.
+ * ---------------------------------------------------------------------- */
+long oracle_blocks_run(int ni, int nj, int nk, const double *A, double alpha, const double *b, double *x,
+                       int nbi, const int *ci, int nbj, const int *cj, int nbk, const int *ck, long n_iter,
+                       double rtol, int mode, double *hist, double *rel_res)
+{
+    const size_t n = (size_t)ni * nj * nk;
+    const int nblk = nbi * nbj * nbk;
+    double **LU = calloc((size_t)nblk, sizeof(double *));
+    float **LU32 = calloc((size_t)nblk, sizeof(float *));
+    double *r = malloc(n * sizeof(double)), *rb = malloc(n * sizeof(double)), *yb = malloc(n * sizeof(double));
+    double *db = malloc(n * sizeof(double)), *Ab = malloc(7 * n * sizeof(double));
+    float *r32 = malloc(n * sizeof(float)), *y32 = malloc(n * sizeof(float)), *d32 = malloc(n * sizeof(float));
+    long it = -1;
+    if (!LU || !LU32 || !r || !rb || !yb || !db || !Ab || !r32 || !y32 || !d32) goto out;
+    /* factorise every block on its own */
+    for (int q = 0; q < nblk; q++) {
+        const int bi = q % nbi, bj = (q / nbi) % nbj, bk = q / (nbi * nbj);
+        const int mi = ci[bi + 1] - ci[bi], mj = cj[bj + 1] - cj[bj], mk = ck[bk + 1] - ck[bk];
+        const size_t m = (size_t)mi * mj * mk;
+        for (int d = 0; d < 7; d++)
+            for (int k = 0; k < mk; k++)
+                for (int j = 0; j < mj; j++)
+                    for (int i = 0; i < mi; i++)
+                        Ab[d * m + ((size_t)k * mj + j) * mi + i] =
+                            A[d * n + IDX(ci[bi] + i, cj[bj] + j, ck[bk] + k)];
+        LU[q] = malloc(7 * m * sizeof(double));
+        if (!LU[q]) goto out;
+        if (oracle_factor(mi, mj, mk, Ab, alpha, LU[q]) != 0) {
+            it = -2;
+            goto out;
+        }
+        if (mode == 1) {
+            LU32[q] = malloc(7 * m * sizeof(float));
+            if (!LU32[q]) goto out;
+            for (size_t t = 0; t < 7 * m; t++) LU32[q][t] = (float)LU[q][t];
+        }
+    }
+    const double nb = oracle_norm2(b, n);
+    if (nb == 0.0) {
+        for (size_t p = 0; p < n; p++) x[p] = 0.0;
+        if (hist) for (long m = 0; m <= n_iter; m++) hist[m] = 0.0;
+        if (rel_res) *rel_res = 0.0;
+        it = 0;
+        goto out;
+    }
+    double rho = 0.0;
+    for (it = 0;; it++) {
+        oracle_residual(ni, nj, nk, A, b, x, r);   /* every coupling: neighbour values enter here */
+        rho = oracle_norm2(r, n) / nb;
+        if (hist) hist[it] = rho;
+        if (it >= n_iter) break;
+        if (rtol > 0.0 && rho <= rtol) break;
+        for (int q = 0; q < nblk; q++) {
+            const int bi = q % nbi, bj = (q / nbi) % nbj, bk = q / (nbi * nbj);
+            const int mi = ci[bi + 1] - ci[bi], mj = cj[bj + 1] - cj[bj], mk = ck[bk + 1] - ck[bk];
+            const size_t m = (size_t)mi * mj * mk;
+            for (int k = 0; k < mk; k++)
+                for (int j = 0; j < mj; j++)
+                    for (int i = 0; i < mi; i++)
+                        rb[((size_t)k * mj + j) * mi + i] = r[IDX(ci[bi] + i, cj[bj] + j, ck[bk] + k)];
+            if (mode == 0) {
+                oracle_forward(mi, mj, mk, LU[q], rb, yb);
+                oracle_backward(mi, mj, mk, LU[q], yb, db);
+            } else {
+                for (size_t t = 0; t < m; t++) r32[t] = (float)rb[t];
+                oracle_forward_f32(mi, mj, mk, LU32[q], r32, y32);
+                oracle_backward_f32(mi, mj, mk, LU32[q], y32, d32);
+                for (size_t t = 0; t < m; t++) db[t] = (double)d32[t];
+            }
+            for (int k = 0; k < mk; k++)
+                for (int j = 0; j < mj; j++)
+                    for (int i = 0; i < mi; i++)
+                        x[IDX(ci[bi] + i, cj[bj] + j, ck[bk] + k)] += db[((size_t)k * mj + j) * mi + i];
+        }
+    }
+    if (rel_res) *rel_res = rho;
+out:
+    if (LU) for (int q = 0; q < nblk; q++) free(LU[q]);
+    if (LU32) for (int q = 0; q < nblk; q++) free(LU32[q]);
+    free(LU); free(LU32); free(r); free(rb); free(yb); free(db); free(Ab); free(r32); free(y32); free(d32);
+    return it;
+}

@@ -361,3 +361,95 @@ def test_fp32_form_zero_rhs(ora):
     LU = ora.factor(A, 0.92)
     x, it, rr, _ = ora.solve(A, LU, np.zeros((4, 4, 4)), np.ones((4, 4, 4)), 1e-5, 10, fp32=True)
     assert it == 0 and rr == 0.0 and np.all(x == 0)
+
+
+# ---------------------------------------------------------------- multi-block domain
+# Blocks factorised on their own, coupled once per iteration through the
+# residual of the whole domain (values of the previous iterate).
+
+def _block_boxes(cuts):
+    ci, cj, ck = cuts
+    for bk in range(len(ck) - 1):
+        for bj in range(len(cj) - 1):
+            for bi in range(len(ci) - 1):
+                yield (slice(ck[bk], ck[bk + 1]), slice(cj[bj], cj[bj + 1]), slice(ci[bi], ci[bi + 1]))
+
+
+def test_blocks_one_block_is_single_block_sip(ora):
+    A = problems.convection_diffusion(7, 6, 5, np.random.default_rng(50))
+    b = np.random.default_rng(51).uniform(-1, 1, (5, 6, 7))
+    x0 = np.random.default_rng(52).uniform(-1, 1, b.shape)
+    xb, it, _, hb = ora.blocks(A, 0.92, b, x0, ([0, 7], [0, 6], [0, 5]), 6)
+    xs, hs = ora.iterate(A, ora.factor(A, 0.92), b, x0, 6)
+    assert it == 6 and np.array_equal(xb, xs) and np.array_equal(hb, hs)
+
+
+@pytest.mark.parametrize("cuts", [([0, 3, 6], [0, 5], [0, 2, 4]), ([0, 2, 4, 6], [0, 1, 5], [0, 4])])
+def test_blocks_are_dense_block_jacobi_with_sip_blocks(ora, cuts):
+    """x_{n+1} = x_n + M^-1 (b - A x_n) with M the block-diagonal matrix of the
+    blocks' own L U (each from a factorisation of the block alone), densely."""
+    ni, nj, nk = 6, 5, 4
+    A = problems.convection_diffusion(ni, nj, nk, np.random.default_rng(53))
+    b = np.random.default_rng(54).uniform(-1, 1, (nk, nj, ni))
+    n = 5
+    xb, _, _, hb = ora.blocks(A, 0.92, b, np.zeros_like(b), cuts, n)
+    gidx = np.arange(ni * nj * nk).reshape(nk, nj, ni)
+    M = np.zeros((b.size, b.size))
+    for box in _block_boxes(cuts):
+        L, U = dense.dense_LU(ora.factor(A[(slice(None),) + box], 0.92))
+        g = gidx[box].ravel()
+        M[np.ix_(g, g)] = L @ U
+    Ad = dense.dense_A(A)
+    xr = np.zeros(b.size)
+    for m in range(n + 1):
+        r = b.ravel() - Ad @ xr
+        assert abs(hb[m] - np.linalg.norm(r) / np.linalg.norm(b)) <= 1e-14
+        if m < n:
+            xr = xr + np.linalg.solve(M, r)
+    assert np.abs(xb.ravel() - xr).max() <= 1e-12 * np.abs(xr).max()
+
+
+def test_decoupled_blocks_iterate_on_their_own(ora):
+    """With no coupling across the cut planes each block runs its own SIP."""
+    ni, nj, nk = 8, 6, 5
+    cuts = ([0, 3, 8], [0, 6], [0, 2, 5])
+    A = problems.convection_diffusion(ni, nj, nk, np.random.default_rng(55))
+    for c in (3,):
+        A[2, :, :, c - 1] = 0.0     # E of the cells left of i = 3
+        A[1, :, :, c] = 0.0         # W of the cells right of it
+    A[6, 1, :, :] = 0.0             # T of k = 1
+    A[5, 2, :, :] = 0.0             # B of k = 2
+    b = np.random.default_rng(56).uniform(-1, 1, (nk, nj, ni))
+    xb, _, _, _ = ora.blocks(A, 0.92, b, np.zeros_like(b), cuts, 7)
+    for box in _block_boxes(cuts):
+        Ab = A[(slice(None),) + box]
+        xs, _ = ora.iterate(Ab, ora.factor(Ab, 0.92), b[box], np.zeros_like(b[box]), 7)
+        assert np.array_equal(xb[box], xs)
+
+
+def test_blocks_fixed_point_and_slower_coupling(ora):
+    """The coupled iteration converges to A^-1 b; cutting a block into more
+    blocks only slows it (block coupling through lagged values)."""
+    ni, nj, nk = 12, 10, 8
+    A = problems.convection_diffusion(ni, nj, nk, np.random.default_rng(57))
+    b = np.random.default_rng(58).uniform(-1, 1, (nk, nj, ni))
+    x, it, rr, _ = ora.blocks(A, 0.92, b, np.zeros_like(b), ([0, 6, 12], [0, 5, 10], [0, 4, 8]), 5000, 1e-13)
+    xd = np.linalg.solve(dense.dense_A(A), b.ravel())
+    assert rr <= 1e-13 and np.abs(x.ravel() - xd).max() <= 1e-11 * np.abs(xd).max()
+    its = []
+    for cuts in (([0, 12], [0, 10], [0, 8]), ([0, 6, 12], [0, 10], [0, 8]), ([0, 6, 12], [0, 5, 10], [0, 4, 8]),
+                 ([0, 3, 6, 9, 12], [0, 5, 10], [0, 4, 8])):
+        its.append(ora.blocks(A, 0.92, b, np.zeros_like(b), cuts, 5000, 1e-8)[1])
+    assert its == sorted(its) and its[-1] > its[0]
+
+
+def test_blocks_mixed_form_reaches_fp64_accuracy(ora):
+    ni, nj, nk = 16, 12, 10
+    A = problems.convection_diffusion(ni, nj, nk, np.random.default_rng(59))
+    b = np.random.default_rng(60).uniform(-1, 1, (nk, nj, ni))
+    cuts = ([0, 8, 16], [0, 6, 12], [0, 10])
+    x64, it64, _, _ = ora.blocks(A, 0.92, b, np.zeros_like(b), cuts, 5000, 1e-8)
+    x32, it32, rr32, _ = ora.blocks(A, 0.92, b, np.zeros_like(b), cuts, 5000, 1e-8, mixed=True)
+    assert rr32 <= 1e-8 and abs(it32 - it64) <= 2
+    r = b.ravel() - dense.dense_A(A) @ x32.ravel()
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-8
