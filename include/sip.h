@@ -151,6 +151,45 @@ sip_status sip_iterate_multi(sip_system h, int32_t nrhs, const double *const *b,
 sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, double *const *x, double rtol,
                            int32_t max_iter, sip_info *info, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Multi-block domain (Sec. 4.2: SIP runs per block; blocks are coupled only
+ * through values at block boundaries, exchanged once per iteration, and with
+ * the non-blocking exchange every block uses the values of the previous
+ * exchange).  A domain of ni x nj x nk cells is cut into nb[0] x nb[1] x nb[2]
+ * blocks at the planes cuts[d][0..nb[d]] (cuts[d][0] = 0, cuts[d][nb[d]] =
+ * the extent, rising).  Each block is factorised on its own (couplings that
+ * leave a block do not enter its factors); one iteration forms, for every
+ * block, b - (couplings into the other blocks) x of the previous iterate,
+ * runs the block's forward and backward sweeps on it (all blocks in one
+ * launch per sweep) and updates x; rho_n is the relative residual of the
+ * whole domain.  This is a different iteration from single-block SIP and
+ * needs more iterations, the more blocks the more.
+ * ------------------------------------------------------------------------ */
+typedef struct sip_blocks_s *sip_blocks;
+
+typedef struct {
+    sip_problem domain;         /* dims, coefficients (device, read during the call only),
+                                   alpha, precision (SIP_FP64 or SIP_MIXED), storage */
+    int32_t nb[3];              /* blocks along i, j, k (nb[0] * nb[1] * nb[2] <= 4096) */
+    const int32_t *cuts[3];     /* HOST arrays of nb[d] + 1 cut planes */
+} sip_block_problem;
+
+/* sip_blocks_factor -- copy and factorise every block.  Synchronises the
+ * stream.  Errors: SIP_EINVAL (dims, cuts, precision SIP_FP32), SIP_ENOMEM,
+ * SIP_EBREAKDOWN (in some block), SIP_EDEVICE. */
+sip_status sip_blocks_factor(const sip_block_problem *p, void *stream, sip_blocks *out);
+/* sip_blocks_iterate / sip_blocks_solve -- as sip_iterate / sip_solve for
+ * the whole domain: b and x are natural-order arrays of the domain (device);
+ * rel_res_hist (HOST, n_iter + 1 doubles) and info as there.  Both
+ * synchronise the stream. */
+sip_status sip_blocks_iterate(sip_blocks h, const double *b, double *x, int32_t n_iter, double *rel_res_hist,
+                              void *stream);
+sip_status sip_blocks_solve(sip_blocks h, const double *b, double *x, double rtol, int32_t max_iter, sip_info *info,
+                            void *stream);
+/* sip_blocks_info -- number of blocks and device bytes held. */
+sip_status sip_blocks_info(sip_blocks h, int32_t *nblocks, size_t *device_bytes);
+sip_status sip_blocks_destroy(sip_blocks h);
+
 /* sip_export_factors -- write the factors in natural [nk][nj][ni] order as
  * FP64 into seven device arrays of ni*nj*nk doubles, in the order
  * Lb, Lw, Ls, Lp, Un, Ue, Ut (Lp is the pivot, U has a unit diagonal).

@@ -99,6 +99,15 @@ struct Geom {
     long long elems;           // ntiles * tile_elems
 };
 
+// Sheared index of cell (i, j, k) (the layout at the top of this file).
+__host__ __device__ inline long long sheared_of(const Geom &g, int i, int j, int k)
+{
+    const int ti = i / TI, tj = j / TJ, ii = i % TI, jj = j % TJ;
+    const int ip = ii >> 1, jp = jj >> 1, q = (jj & 1) * 2 + (ii & 1);
+    const int t = tj * g.nti + ti;
+    return (long long)t * g.tile_elems + (long long)(k + ip + jp + 1) * PLANE + q * TT + jp * LI + ip;
+}
+
 // Per-system control block in device memory.  Written by the last
 // workgroup of each sweep ("finaliser") and read by the next launch.
 struct Ctl {
@@ -130,6 +139,8 @@ struct Job {
     int fw;                    // face words per local step (FACE_WORDS_SWEEP or FACE_WORDS)
     int sym;                   // A in the symmetric storage (sweeps only; the factorisation reads the full one)
     int m;                     // right-hand sides swept together (b, x, y hold m values per cell)
+    int coupled;               // block of a multi-block domain: the forward finaliser leaves the stop
+                               // decision to the domain's control kernel (rho <- sum r^2, bnorm2 <- sum b^2)
     int hstride;               // m > 1: history of right-hand side r at hist + r * hstride
 };
 
@@ -163,6 +174,40 @@ constexpr int SINK_WORDS = FACE_WORDS_SWEEP;
 static_assert(SINK_WORDS <= FACE_WORDS - FACE_WORDS_SWEEP, "sink lines must fit behind the sweep face words");
 
 Geom make_geom(int ni, int nj, int nk);
+
+// Multi-block domain: exchange tables.  For every cell of a block with a
+// coupling into another block, the effective right-hand side of the block's
+// sweeps is b - sum over those couplings of A_nb x_nb, with x_nb the
+// neighbour block's current iterate.
+struct XCell {
+    uint32_t block, e;         // destination block and its sheared index
+    uint32_t begin, end;       // its terms
+};
+struct XTerm {
+    uint32_t block, e;         // source block and sheared index of x_nb
+    double coef;               // A_nb of the destination cell
+};
+// Per-block pointers used by the domain kernels (device arrays of nblk).
+struct BlockPtrs {
+    const double *const *b;    // sheared b of each block
+    double *const *beff;       // effective right-hand side
+    const double *const *x;    // sheared x
+    Ctl *const *ctl;           // control blocks
+};
+// Copies a box of nc = bi x bj x bk cells between a natural-order domain array
+// (dims ni x nj x nk, box origin i0, j0, k0) and a contiguous natural-order
+// block array: to_block = 1 gathers into the block array, 0 scatters out.
+hipError_t launch_box_copy(const double *src, double *dst, int ni, int nj, int nk, int i0, int j0, int k0, int bi,
+                           int bj, int bk, int to_block, hipStream_t s);
+// Coefficients of the exchange terms: coef[t] = a[dir[t]][gidx[t]].
+hipError_t launch_gather_coef(XTerm *terms, long long nterms, const uint8_t *dir, const long long *gidx,
+                              const double *const *a, hipStream_t s);
+hipError_t launch_exchange(const XCell *cells, long long ncells, const XTerm *terms, BlockPtrs p, hipStream_t s);
+// domain->bnorm2 = sum of v^2 over n values (deterministic; part: 256 doubles).
+hipError_t launch_sumsq(const double *v, long long n, double *part, Ctl *domain, hipStream_t s);
+// Sums the blocks' partial norms (block order), records rho_n in hist and
+// decides the stop for the whole domain, copied into every block's control.
+hipError_t launch_blocks_control(BlockPtrs p, int nblk, Ctl *domain, double *hist, hipStream_t s);
 
 // Kernel launchers (sip_kernels.hip).  All are asynchronous on `s`.
 hipError_t launch_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int reset_epoch, hipStream_t s);

@@ -876,6 +876,12 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
         if (lane == 0) {
             if constexpr (M > 1) {
                 finalise_multi<M>(J, sr, sb, iter, tag);
+            } else if (J.coupled) {   // the domain's control kernel decides
+                Ctl *cc = J.ctl;
+                cc->rho = sr[0];
+                if (iter == 0) cc->bnorm2 = sb[0];
+                cc->epoch = tag + 1u;
+                cc->done = 0u;
             } else {
                 Ctl *cc = J.ctl;
                 if (iter == 0) cc->bnorm2 = sb[0];
@@ -1356,13 +1362,6 @@ __device__ __forceinline__ bool decode_sheared(const Geom &g, long long e, int &
     return pl >= 0 && pl < g.steps && i < g.ni && j < g.nj && k >= 0 && k < g.nk;
 }
 
-__device__ __forceinline__ long long sheared_index(const Geom &g, int i, int j, int k)
-{
-    const int ti = i / TI, tj = j / TJ, ii = i % TI, jj = j % TJ;
-    const int ip = ii >> 1, jp = jj >> 1, q = (jj & 1) * 2 + (ii & 1);
-    const int t = tj * g.nti + ti;
-    return (long long)t * g.tile_elems + (long long)(k + ip + jp + 1) * PLANE + q * TT + jp * LI + ip;
-}
 
 // Copies narr natural-order FP64 arrays into the sheared layout `shear`
 // (T = float for SHEAR_F32 and SHEAR_COEF32, rounding to nearest): plain
@@ -1428,7 +1427,7 @@ __global__ void k_from_sheared(Geom g, const T *src, double *dst, const Ctl *ctl
         const int i = (int)(c % g.ni);
         const int j = (int)((c / g.ni) % g.nj);
         const int k = (int)(c / ((long long)g.ni * g.nj));
-        dst[c] = zero ? 0.0 : (double)src[comp * sheared_index(g, i, j, k) + which];
+        dst[c] = zero ? 0.0 : (double)src[comp * sheared_of(g, i, j, k) + which];
     }
 }
 
@@ -1441,7 +1440,7 @@ __global__ void k_export_factors(Geom g, const F *LU, DstPtrs out)
         const int i = (int)(c % g.ni);
         const int j = (int)((c / g.ni) % g.nj);
         const int k = (int)(c / ((long long)g.ni * g.nj));
-        const long long e = sheared_index(g, i, j, k);
+        const long long e = sheared_of(g, i, j, k);
 #pragma unroll
         for (int d = 0; d < 7; d++) {
             const double v = (double)LU[factor_index<F>(d, e, g.elems)];
@@ -1466,6 +1465,99 @@ __global__ void k_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int 
     c.rho = 0.0;
 }
 
+// ------------------------------------------------------ multi-block domain
+
+__global__ void k_box_copy(const double *src, double *dst, int ni, int nj, int nk, int i0, int j0, int k0, int bi,
+                           int bj, int bk, int to_block)
+{
+    const long long nc = (long long)bi * bj * bk;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < nc; c += stride) {
+        const int i = (int)(c % bi);
+        const int j = (int)((c / bi) % bj);
+        const int k = (int)(c / ((long long)bi * bj));
+        const long long gidx = ((long long)(k + k0) * nj + (j + j0)) * ni + (i + i0);
+        if (to_block) dst[c] = src[gidx];
+        else dst[gidx] = src[c];
+    }
+}
+
+__global__ void k_gather_coef(XTerm *terms, long long nterms, const uint8_t *dir, const long long *gidx, SrcPtrs a)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nterms; t += stride)
+        terms[t].coef = a.p[dir[t]][gidx[t]];
+}
+
+// beff = b - sum of the couplings into other blocks times their x (every
+// block's x is the same iterate: the exchange runs between two sweeps).
+__global__ void k_exchange(const XCell *cells, long long ncells, const XTerm *terms, BlockPtrs p)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncells; c += stride) {
+        const XCell xc = cells[c];
+        double v = p.b[xc.block][xc.e];
+        for (uint32_t t = xc.begin; t < xc.end; t++) {
+            const XTerm xt = terms[t];
+            v -= xt.coef * p.x[xt.block][xt.e];
+        }
+        p.beff[xc.block][xc.e] = v;
+    }
+}
+
+// ||b||^2 of the domain's b (natural order): SUMSQ_BLOCKS fixed partials,
+// then one workgroup adds them in order (the result does not depend on timing).
+constexpr int SUMSQ_BLOCKS = 256;
+__global__ void k_sumsq(const double *v, long long n, double *part)
+{
+    __shared__ double s_w[4];
+    double a = 0.0;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x)
+        a += v[c] * v[c];
+    a = wave_sum(a);
+    if ((threadIdx.x & (WAVE - 1)) == 0) s_w[threadIdx.x / WAVE] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+}
+
+__global__ void k_sumsq_final(const double *part, Ctl *g)
+{
+    if (threadIdx.x != 0) return;
+    double a = 0.0;
+    for (int q = 0; q < SUMSQ_BLOCKS; q++) a += part[q];
+    g->bnorm2 = a;
+}
+
+// The blocks' forward finalisers left sum r^2 of their cells in ctl->rho.
+__global__ void k_blocks_control(BlockPtrs p, int nblk, Ctl *g, double *hist)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double sr = 0.0;
+    uint32_t err = 0u;
+    const uint32_t iter = p.ctl[0]->iter;
+    for (int q = 0; q < nblk; q++) {   // fixed block order: the norm does not depend on timing
+        sr += p.ctl[q]->rho;
+        err |= p.ctl[q]->err;
+    }
+    const double nb2 = g->bnorm2;   // of the domain's b (the blocks sweep on beff)
+    uint32_t st = RUN;
+    double rho = 0.0;
+    if (err) {
+        st = (err & 2u) ? BREAKDOWN : TIMEOUT;
+    } else if (nb2 == 0.0) {
+        st = ZERO_RHS;
+    } else {
+        rho = sqrt(sr) / sqrt(nb2);
+        if (g->rtol > 0.0 && rho <= g->rtol) st = CONVERGED;
+        else if (iter >= g->max_iter) st = MAXITER;
+    }
+    g->rho = rho;
+    g->iter = iter;
+    g->stop = st;
+    if (hist) hist[iter] = rho;
+    for (int q = 0; q < nblk; q++) p.ctl[q]->stop = st;
+}
+
 int grid_for(long long n)
 {
     long long b = (n + 255) / 256;
@@ -1475,6 +1567,44 @@ int grid_for(long long n)
 }
 
 }  // namespace
+
+hipError_t launch_box_copy(const double *src, double *dst, int ni, int nj, int nk, int i0, int j0, int k0, int bi,
+                           int bj, int bk, int to_block, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_box_copy, dim3(grid_for((long long)bi * bj * bk)), dim3(256), 0, s, src, dst, ni, nj, nk, i0,
+                       j0, k0, bi, bj, bk, to_block);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_coef(XTerm *terms, long long nterms, const uint8_t *dir, const long long *gidx,
+                              const double *const *a, hipStream_t s)
+{
+    if (nterms == 0) return hipSuccess;
+    SrcPtrs sp{};
+    for (int d = 0; d < 7; d++) sp.p[d] = a[d];
+    hipLaunchKernelGGL(k_gather_coef, dim3(grid_for(nterms)), dim3(256), 0, s, terms, nterms, dir, gidx, sp);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange(const XCell *cells, long long ncells, const XTerm *terms, BlockPtrs p, hipStream_t s)
+{
+    if (ncells == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_exchange, dim3(grid_for(ncells)), dim3(256), 0, s, cells, ncells, terms, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const double *v, long long n, double *part, Ctl *domain, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sumsq, dim3(SUMSQ_BLOCKS), dim3(256), 0, s, v, n, part);
+    hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(64), 0, s, part, domain);
+    return hipGetLastError();
+}
+
+hipError_t launch_blocks_control(BlockPtrs p, int nblk, Ctl *domain, double *hist, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_blocks_control, dim3(1), dim3(64), 0, s, p, nblk, domain, hist);
+    return hipGetLastError();
+}
 
 hipError_t launch_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int reset_epoch, hipStream_t s)
 {

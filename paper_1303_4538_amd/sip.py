@@ -28,7 +28,8 @@ PRECISIONS = {"fp64": SIP_FP64, "mixed": SIP_MIXED, "fp32": SIP_FP32,
 # every symbol include/sip.h declares
 EXPORTS = ("sip_factor", "sip_iterate", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
            "sip_profile_sweeps", "sip_profile_sweeps_multi", "sip_system_info",
-           "sip_system_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
+           "sip_system_destroy", "sip_blocks_factor", "sip_blocks_iterate", "sip_blocks_solve", "sip_blocks_info",
+           "sip_blocks_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
            "sip_server_release", "sip_server_stats", "sip_server_destroy", "sip_status_str",
            "sip_last_error", "sip_abi_version")
 
@@ -43,6 +44,10 @@ class Problem(ctypes.Structure):
     _fields_ = [("ni", ctypes.c_int32), ("nj", ctypes.c_int32), ("nk", ctypes.c_int32),
                 ("a", ctypes.c_void_p * 7), ("alpha", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("storage", ctypes.c_int32)]
+
+
+class BlockProblem(ctypes.Structure):
+    _fields_ = [("domain", Problem), ("nb", ctypes.c_int32 * 3), ("cuts", ctypes.POINTER(ctypes.c_int32) * 3)]
 
 
 class Info(ctypes.Structure):
@@ -83,6 +88,11 @@ def lib():
     L.sip_iterate_multi.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, ctypes.POINTER(dbl), vp]
     L.sip_solve_multi.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, i32, ctypes.POINTER(Info), vp]
     L.sip_export_factors.argtypes = [vp, ctypes.POINTER(vp), vp]
+    L.sip_blocks_factor.argtypes = [ctypes.POINTER(BlockProblem), vp, ctypes.POINTER(vp)]
+    L.sip_blocks_iterate.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
+    L.sip_blocks_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(Info), vp]
+    L.sip_blocks_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]
+    L.sip_blocks_destroy.argtypes = [vp]
     L.sip_profile_sweeps.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
     L.sip_profile_sweeps_multi.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, ctypes.POINTER(dbl), vp]
     L.sip_system_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]
@@ -95,7 +105,8 @@ def lib():
     L.sip_server_destroy.argtypes = [vp]
     for f in ("sip_factor", "sip_iterate", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
               "sip_profile_sweeps", "sip_profile_sweeps_multi", "sip_system_info",
-              "sip_system_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
+              "sip_system_destroy", "sip_blocks_factor", "sip_blocks_iterate", "sip_blocks_solve", "sip_blocks_info",
+              "sip_blocks_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
               "sip_server_release", "sip_server_stats", "sip_server_destroy"):
         getattr(L, f).restype = ctypes.c_int32
     L.sip_status_str.argtypes = [ctypes.c_int32]
@@ -260,6 +271,68 @@ def sip_profile_sweeps_multi(system, bs, xs, n_iter, stream=None):
     ms = (ctypes.c_double * 2)()
     _check(lib().sip_profile_sweeps_multi(system._h, pb, px, int(n_iter), ms, _stream(stream)))
     return ms[0], ms[1]
+
+
+# ----------------------------------------------------------------- multi-block domain
+
+class Blocks:
+    """A domain cut into blocks, each factorised alone and coupled through
+    boundary values once per iteration (sip_blocks_*)."""
+
+    def __init__(self, handle, dims, nblocks):
+        self._h = handle
+        self.ni, self.nj, self.nk = dims
+        self.nblocks = nblocks
+
+    @property
+    def shape(self):
+        return (self.nk, self.nj, self.ni)
+
+    def iterate(self, b, x, n_iter, history=True, stream=None):
+        pb, px = _grid(b, self.shape, "b"), _grid(x, self.shape, "x")
+        hist = np.zeros(int(n_iter) + 1) if history else None
+        hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history else None
+        _check(lib().sip_blocks_iterate(self._h, pb, px, int(n_iter), hp, _stream(stream)))
+        return hist
+
+    def solve(self, b, x, rtol=1e-8, max_iter=100000, stream=None, raise_on_notconv=True):
+        pb, px = _grid(b, self.shape, "b"), _grid(x, self.shape, "x")
+        info = Info()
+        st = lib().sip_blocks_solve(self._h, pb, px, float(rtol), int(max_iter), ctypes.byref(info), _stream(stream))
+        _check(st, (SIP_OK,) if raise_on_notconv else (SIP_OK, SIP_ENOTCONV))
+        return st, info.iters, info.rel_res, info.seconds
+
+    def info(self):
+        n = ctypes.c_int32()
+        nbytes = ctypes.c_size_t()
+        _check(lib().sip_blocks_info(self._h, ctypes.byref(n), ctypes.byref(nbytes)))
+        return dict(nblocks=n.value, device_bytes=nbytes.value)
+
+    def close(self):
+        if self._h:
+            lib().sip_blocks_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sip_blocks_factor(A, cuts, alpha=0.92, precision="mixed", stream=None, storage="full"):
+    """Cut the domain A (7, nk, nj, ni) at the planes cuts = (ci, cj, ck) (each
+    from 0 to the extent) and factorise every block."""
+    bp = BlockProblem()
+    bp.domain = make_problem(A, alpha, precision, storage)
+    arrs = [(ctypes.c_int32 * len(c))(*[int(v) for v in c]) for c in cuts]
+    for d in range(3):
+        bp.nb[d] = len(cuts[d]) - 1
+        bp.cuts[d] = ctypes.cast(arrs[d], ctypes.POINTER(ctypes.c_int32))
+    h = ctypes.c_void_p()
+    _check(lib().sip_blocks_factor(ctypes.byref(bp), _stream(stream), ctypes.byref(h)))
+    nblk = (len(cuts[0]) - 1) * (len(cuts[1]) - 1) * (len(cuts[2]) - 1)
+    return Blocks(h, (bp.domain.ni, bp.domain.nj, bp.domain.nk), nblk)
 
 
 # ----------------------------------------------------------------- server

@@ -53,3 +53,5 @@ def test_struct_layouts_match_header():
     # sip_problem: 3 int32, pad, 7 pointers, double, int32 (+pad)
     assert ctypes.sizeof(sip.Problem) == 4 * 3 + 4 + 8 * 7 + 8 + 8
     assert ctypes.sizeof(sip.Info) == 24
+    # sip_block_problem: sip_problem, 3 int32 (+pad), 3 pointers
+    assert ctypes.sizeof(sip.BlockProblem) == ctypes.sizeof(sip.Problem) + 12 + 4 + 24

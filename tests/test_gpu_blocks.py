@@ -1,0 +1,139 @@
+"""Multi-block domain on the GPU (sip_blocks_*): blocks factorised alone,
+coupled once per iteration through boundary values of the previous iterate
+(the paper's Sec. 4.2 exchange semantics).
+
+Bar (FP64): every iterate x_n within 1e-12 * max|x_n| of the multi-block
+oracle, rho_n within 1e-12; a solve stops within one iteration of the
+oracle's.  Mixed: final residual <= rtol re-checked by the oracle in FP64,
+iteration count within 2 of the mixed multi-block oracle.  One block gives
+bitwise the single-block solver's iterates.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1303_4538_amd import problems
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sip():
+    from paper_1303_4538_amd import sip as s
+    s.lib()
+    assert torch.cuda.is_available()
+    return s
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def make(kind, dims, seed):
+    ni, nj, nk = dims
+    rng = np.random.default_rng(seed)
+    if kind == "poisson":
+        A = problems.poisson(ni, nj, nk)
+    elif kind == "stretched":
+        A = problems.stretched_poisson(ni, nj, nk)
+    else:
+        A = problems.convection_diffusion(ni, nj, nk, rng)
+    return A, rng.uniform(-1, 1, (nk, nj, ni))
+
+
+# (dims, cuts): blocks that are not tile multiples, one-cell-thick blocks,
+# cuts along one, two and three axes, many blocks
+CASES = [
+    ((24, 20, 18), ([0, 12, 24], [0, 20], [0, 18])),
+    ((24, 20, 18), ([0, 12, 24], [0, 9, 20], [0, 7, 18])),
+    ((33, 17, 9), ([0, 1, 16, 33], [0, 17], [0, 4, 5, 9])),
+    ((40, 40, 12), ([0, 17, 40], [0, 16, 32, 40], [0, 12])),
+    ((16, 16, 30), ([0, 16], [0, 16], [0, 10, 20, 30])),
+    ((20, 18, 16), ([0, 5, 10, 15, 20], [0, 6, 12, 18], [0, 8, 16])),
+]
+
+
+@pytest.mark.parametrize("kind", ["cd", "stretched"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_blocks_iterates_match_oracle(sip, case, kind):
+    dims, cuts = CASES[case]
+    A, b = make(kind, dims, 70 + case)
+    x0 = np.random.default_rng(7).uniform(-0.5, 0.5, b.shape)
+    log(f"blocks {kind} {dims} {[len(c) - 1 for c in cuts]}")
+    B = sip.sip_blocks_factor(dev(A), cuts, 0.92, "fp64")
+    n = 6
+    xt = dev(x0)
+    hg = B.iterate(dev(b), xt, n)
+    B.close()
+    xo, _, _, ho = oracle.blocks(A, 0.92, b, x0, cuts, n)
+    assert np.abs(xt.cpu().numpy() - xo).max() <= 1e-12 * np.abs(xo).max()
+    assert np.abs(hg - ho).max() <= 1e-12
+
+
+def test_one_block_is_the_single_block_solver(sip):
+    A, b = make("cd", (21, 18, 13), 80)
+    cuts = ([0, 21], [0, 18], [0, 13])
+    for precision in ("fp64", "mixed"):
+        B = sip.sip_blocks_factor(dev(A), cuts, 0.92, precision)
+        xb = torch.zeros_like(dev(b))
+        hb = B.iterate(dev(b), xb, 7)
+        B.close()
+        S = sip.sip_factor(dev(A), 0.92, precision)
+        xs = torch.zeros_like(dev(b))
+        hs = sip.sip_iterate(S, dev(b), xs, 7)
+        S.close()
+        # same iterates; rho differs in the last bits (the domain sums ||b|| in
+        # its own reduction order)
+        assert torch.equal(xb, xs), precision
+        assert np.abs(hb - hs).max() <= 1e-14, precision
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_blocks_solve_matches_oracle(sip, precision):
+    dims, cuts = (40, 36, 30), ([0, 20, 40], [0, 18, 36], [0, 15, 30])
+    A, b = make("cd", dims, 81)
+    B = sip.sip_blocks_factor(dev(A), cuts, 0.92, precision)
+    xt = torch.zeros_like(dev(b))
+    st, it, rr, _ = B.solve(dev(b), xt, 1e-8, 5000)
+    B.close()
+    _, ito, _, _ = oracle.blocks(A, 0.92, b, np.zeros_like(b), cuts, 5000, 1e-8, mixed=(precision == "mixed"))
+    assert st == sip.SIP_OK and rr <= 1e-8
+    assert abs(it - ito) <= (1 if precision == "fp64" else 2)
+    r = oracle.norm2(oracle.residual(A, b, xt.cpu().numpy())) / oracle.norm2(b)
+    assert r <= 1e-8 * (1 + 1e-9)
+    # coupling through lagged boundary values costs iterations
+    S = sip.sip_factor(dev(A), 0.92, precision)
+    xs = torch.zeros_like(dev(b))
+    _, its, _, _ = sip.sip_solve(S, dev(b), xs, 1e-8, 5000)
+    S.close()
+    assert it > its
+
+
+def test_blocks_zero_rhs_and_not_converged(sip):
+    dims, cuts = (20, 16, 12), ([0, 10, 20], [0, 16], [0, 6, 12])
+    A, b = make("poisson", dims, 82)
+    B = sip.sip_blocks_factor(dev(A), cuts, 0.92, "mixed")
+    bz = torch.zeros((12, 16, 20), dtype=torch.float64, device="cuda")
+    xt = torch.ones_like(bz)
+    st, it, rr, _ = B.solve(bz, xt, 1e-8, 10)
+    assert st == sip.SIP_OK and it == 0 and rr == 0.0 and float(xt.abs().max()) == 0.0
+    xt = torch.zeros_like(bz)
+    st, it, rr, _ = B.solve(dev(b), xt, 1e-14, 5, raise_on_notconv=False)
+    B.close()
+    assert st == sip.SIP_ENOTCONV and it == 5
+
+
+def test_blocks_invalid_arguments(sip):
+    A, _ = make("poisson", (8, 8, 8), 83)
+    for cuts in (([0, 4], [0, 8], [0, 8]), ([0, 5, 5, 8], [0, 8], [0, 8]), ([1, 8], [0, 8], [0, 8])):
+        with pytest.raises(sip.SipError) as e:
+            sip.sip_blocks_factor(dev(A), cuts, 0.92, "mixed")
+        assert e.value.status == sip.SIP_EINVAL
+    with pytest.raises(sip.SipError) as e:
+        sip.sip_blocks_factor(dev(A), ([0, 8], [0, 8], [0, 8]), 0.92, "fp32")
+    assert e.value.status == sip.SIP_EINVAL
