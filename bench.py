@@ -462,7 +462,7 @@ def main():
     if (args.workload == "single" and args.storage == "full" and args.n == MEASURED["n"]
             and kernels_sha256() == MEASURED["kernels_sha256"]):
         traffic = round(MEASURED["fwd_bytes"] / (fwd_ms * 1e-3) / 1e9, 1)
-    roofline = {"bound": "hbm", "kernel": "k_forward<float, double, 2> (FP64 residual + FP32 forward sweep)",
+    roofline = {"bound": "hbm", "kernel": "k_forward<float, double, 2, 1> (FP64 residual + FP32 forward sweep)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
