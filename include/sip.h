@@ -213,6 +213,18 @@ sip_status sip_profile_sweeps(sip_system h, const double *b, double *x, int32_t 
 sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double *const *x, int32_t n_iter,
                                     double ms[2], void *stream);
 
+/* sip_tune -- autotuner of the sweep launch shape: times n_iter iterations
+ * from x = 0 with b (device, read only) for every loader-phase count the
+ * sweeps support (1 to 3; each phase is a group of loader waves that prefetch
+ * for alternate steps), keeps the fastest for this handle and records it for
+ * the block shape and precision, so that later sip_factor calls and solve
+ * servers in the process start with it.  Results are unchanged bitwise (the
+ * launch shape does not change the arithmetic).  *phases (nullable, host)
+ * receives the choice.  Synchronises the stream.  The environment variable
+ * SIP_SWEEP_PHASES (1..3), read by sip_factor, overrides tuned plans.
+ * Errors: SIP_EINVAL, SIP_EDEVICE. */
+sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phases, void *stream);
+
 /* sip_system_info -- dims, precision and device bytes held by a handle. */
 sip_status sip_system_info(sip_system h, int32_t dims[3], int32_t *precision, size_t *device_bytes);
 

@@ -19,7 +19,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 using namespace sipk;
@@ -185,6 +188,20 @@ static hipError_t stage_in(const sip_system_s *h, const double *b, const double 
 static hipError_t stage_out(const sip_system_s *h, double *x, hipStream_t s)
 {
     return launch_from_sheared(h->g, x_of(h), h->precision == ARITH_F32, x, h->ctl, s);
+}
+
+// Tuned sweep plans by block shape and arithmetic (filled by sip_tune,
+// consulted by sip_factor and the server).
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int, int>, SweepPlan> g_tuned;
+
+bool tuned_plan(const Geom &g, int arith, int sym, SweepPlan *out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto f = g_tuned.find(std::make_tuple(g.ni, g.nj, g.nk, arith, sym));
+    if (f == g_tuned.end()) return false;
+    *out = f->second;
+    return true;
 }
 
 LaunchArgs fwd_args(const sip_system_s *h)
@@ -389,6 +406,8 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     if (const char *e = getenv("SIP_SWEEP_PHASES")) {   // tuning override
         const int nl = atoi(e);
         if (nl >= 1 && nl <= sipk::MAX_PHASES) h->plan.phases = nl;
+    } else {
+        (void)tuned_plan(h->g, p->precision, p->storage == SIP_STORAGE_SYMMETRIC, &h->plan);
     }
     sip_status st = system_alloc(h, s);
     if (st != SIP_OK) {
@@ -757,6 +776,63 @@ sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double
     if (st != SIP_OK) return st;
     ms[0] = f / n_iter;
     ms[1] = bk / n_iter;
+    return SIP_OK;
+}
+
+sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phases, void *stream)
+{
+    if (!h || !b) return set_error(SIP_EINVAL, "NULL argument");
+    if (n_iter < 1) return set_error(SIP_EINVAL, "n_iter must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    TRY(ensure_hist(h, n_iter + 1, s));
+    const Geom &g = h->g;
+    const LaunchArgs fa = fwd_args(h), ba = bwd_args(h);
+    hipEvent_t e0, e1;
+    HIPTRY(hipEventCreate(&e0));
+    HIPTRY(hipEventCreate(&e1));
+    int best = h->plan.phases;
+    float best_ms = 0.f;
+    sip_status st = SIP_OK;
+    for (int np = 1; np <= MAX_PHASES && st == SIP_OK; np++) {
+        SweepPlan pl;
+        pl.phases = np;
+        // the same iterations from x = 0 for every candidate
+        const double *src[1] = {b};
+        if (launch_to_sheared(g, 1, src, h->bx, g.elems, h->precision == ARITH_F32 ? SHEAR_F32 : SHEAR_F64, s) !=
+                hipSuccess ||
+            hipMemsetAsync(x_of(h), 0, (size_t)g.elems * (h->precision == ARITH_F32 ? 4 : 8), s) != hipSuccess ||
+            launch_init_ctl(h->ctl, 1, (uint32_t)n_iter, 0.0, 0, s) != hipSuccess ||
+            hipEventRecord(e0, s) != hipSuccess) {
+            st = set_error(SIP_EDEVICE, "tuning launch failed");
+            break;
+        }
+        for (int q = 0; q < n_iter && st == SIP_OK; q++)
+            if (launch_forward(fa, h->precision, pl, s) != hipSuccess ||
+                launch_backward(ba, h->precision, pl, s) != hipSuccess)
+                st = set_error(SIP_EDEVICE, "tuning launch failed");
+        float ms = 0.f;
+        if (st == SIP_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = set_error(SIP_EDEVICE, "tuning timing failed");
+        if (st == SIP_OK && (np == 1 || ms < best_ms)) {
+            best = np;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SIP_OK) return st;
+    if (h->plan.phases != best && h->chunk_exec) {   // the captured chunk holds the old kernels
+        HIPTRY(hipStreamSynchronize(s));
+        hipGraphExecDestroy(h->chunk_exec);
+        h->chunk_exec = nullptr;
+    }
+    h->plan.phases = best;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[std::make_tuple(g.ni, g.nj, g.nk, h->precision, h->sym)] = h->plan;
+    }
+    if (phases) *phases = best;
     return SIP_OK;
 }
 

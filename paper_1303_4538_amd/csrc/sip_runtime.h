@@ -15,6 +15,8 @@ sip_status set_error(sip_status st, const char *fmt, ...);
 uint64_t timeout_ticks_for(int device, double seconds);
 std::vector<int2> topo_order(const std::vector<Geom> &gs, bool backward);
 size_t system_bytes(const Geom &g, int fp32);
+// The sweep plan sip_tune chose for this shape and arithmetic, if any.
+bool tuned_plan(const Geom &g, int arith, int sym, SweepPlan *out);
 
 }  // namespace sipk
 

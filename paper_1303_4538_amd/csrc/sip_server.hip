@@ -114,6 +114,7 @@ struct sip_server_s {
     LaunchCtl *lc = nullptr;
     unsigned *d_bad = nullptr, *h_bad = nullptr;   // symmetry check counter (device, pinned mirror)
     SweepPlan plan{};
+    bool plan_forced = false;   // SIP_SWEEP_PHASES set: no tuned plans
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
     void loop();
@@ -430,11 +431,21 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
         fa[grp] = LaunchArgs{d_jobs[grp], d_order[grp][0], lc, (int)of[grp].size(), timeout_ticks};
         ba[grp] = LaunchArgs{d_jobs[grp], d_order[grp][1], lc, (int)ob[grp].size(), timeout_ticks};
     }
+    // launch shape of each group: the tuned plan of its largest block (sip_tune)
+    SweepPlan gplan[NARITH];
+    for (int grp = 0; grp < NARITH; grp++) {
+        gplan[grp] = plan;
+        if (plan_forced || jobs[grp].empty()) continue;
+        const Job *big = &jobs[grp][0];
+        for (const Job &J : jobs[grp])
+            if (J.g.elems > big->g.elems) big = &J;
+        (void)tuned_plan(big->g, grp, big->sym, &gplan[grp]);
+    }
     for (int it = 0; it < cfg.epoch_iters; it++) {
         for (int grp = 0; grp < NARITH; grp++) {
             if (jobs[grp].empty()) continue;
-            if (launch_forward(fa[grp], grp, plan, stream) != hipSuccess ||
-                launch_backward(ba[grp], grp, plan, stream) != hipSuccess)
+            if (launch_forward(fa[grp], grp, gplan[grp], stream) != hipSuccess ||
+                launch_backward(ba[grp], grp, gplan[grp], stream) != hipSuccess)
                 return set_error(SIP_EDEVICE, "sweep launch failed");
             stats[7] += 2;
         }
@@ -565,7 +576,10 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
     }
     if (const char *e = getenv("SIP_SWEEP_PHASES")) {
         const int nl = atoi(e);
-        if (nl >= 1 && nl <= sipk::MAX_PHASES) s->plan.phases = nl;
+        if (nl >= 1 && nl <= sipk::MAX_PHASES) {
+            s->plan.phases = nl;
+            s->plan_forced = true;
+        }
     }
     s->timeout_ticks = timeout_ticks_for(s->device, 2.0);
     s->t0 = std::chrono::steady_clock::now();

@@ -226,3 +226,23 @@ def test_config2_full_size(sip):
     assert st == sip.SIP_OK and rr <= 1e-8
     r_cpu = oracle.norm2(oracle.residual(A, b, xt.cpu().numpy())) / oracle.norm2(b)
     assert r_cpu <= 1e-8 * (1 + 1e-9)
+
+
+def test_tune_keeps_results_and_records_the_plan(sip):
+    """The autotuner picks a launch shape; solves before and after it, and on
+    a new system of the same shape (which starts with the tuned plan), are
+    bitwise the same."""
+    A, b = make("cd", (40, 33, 21), 17)
+    S = sip.sip_factor(dev(A), 0.92, "mixed")
+    x1 = torch.zeros_like(dev(b))
+    _, it1, _, _ = sip.sip_solve(S, dev(b), x1, 1e-8, 5000)
+    ph = sip.sip_tune(S, dev(b), 3)
+    assert 1 <= ph <= 3
+    x2 = torch.zeros_like(dev(b))
+    _, it2, _, _ = sip.sip_solve(S, dev(b), x2, 1e-8, 5000)
+    S.close()
+    S = sip.sip_factor(dev(A), 0.92, "mixed")
+    x3 = torch.zeros_like(dev(b))
+    _, it3, _, _ = sip.sip_solve(S, dev(b), x3, 1e-8, 5000)
+    S.close()
+    assert it1 == it2 == it3 and torch.equal(x1, x2) and torch.equal(x1, x3)
