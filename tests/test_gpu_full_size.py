@@ -1,0 +1,137 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the
+benchmark times.
+
+* 512 x 512 x 256 stretched-grid Poisson (67 M cells): FP64 factors and the
+  first two iterates elementwise against the oracle (1e-13 / 1e-12), then
+  mixed iterates with the FP64 residual of the result re-checked by the
+  oracle on every cell.
+* 64 uneven blocks through one solve server (mixed to 1e-8): every block's
+  result equals its solo solve bitwise and its FP64 residual, re-checked by
+  the oracle, is <= 1e-8.
+* 256^3 with the all-FP32 relaxation, a pair of right-hand sides and the
+  domain cut into 2^3 blocks: first iterates against the oracle (all-FP32,
+  multi-block) or against the solo solves (pair, bitwise).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1303_4538_amd import problems
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sip():
+    from paper_1303_4538_amd import sip as s
+    s.lib()
+    assert torch.cuda.is_available()
+    return s
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def test_config4_large_block(sip):
+    c = problems.config4()
+    A, b = c["A"], c["b"]
+    log("512x512x256 stretched Poisson: factor fp64")
+    At, bt = dev(A), dev(b)
+    S = sip.sip_factor(At, c["alpha"], "fp64")
+    LU = oracle.factor(A, c["alpha"])
+    Lg = sip.sip_export_factors(S).cpu().numpy()
+    zero = LU == 0
+    rel = np.where(zero, np.abs(Lg), np.abs(Lg - LU) / np.maximum(np.abs(LU), 1e-300))
+    assert float(rel.max()) <= 1e-13
+    del Lg, rel, zero
+    log("  2 iterations fp64")
+    xt = torch.zeros_like(bt)
+    hg = sip.sip_iterate(S, bt, xt, 2)
+    S.close()
+    xo, ho = oracle.iterate(A, LU, b, np.zeros_like(b), 2)
+    assert np.abs(xt.cpu().numpy() - xo).max() <= 1e-12 * np.abs(xo).max()
+    assert np.abs(hg - ho).max() <= 1e-12
+    del xo
+    log("  40 mixed iterations, residual re-checked")
+    S = sip.sip_factor(At, c["alpha"], "mixed")
+    xt = torch.zeros_like(bt)
+    hg = sip.sip_iterate(S, bt, xt, 40)
+    S.close()
+    r = oracle.norm2(oracle.residual(A, b, xt.cpu().numpy())) / oracle.norm2(b)
+    assert abs(r - hg[-1]) <= 1e-12
+    assert hg[-1] < hg[0]
+
+
+def test_config3_batched_blocks(sip):
+    meta = problems.config3_meta()
+    blocks = []
+    for dims, kind, ss in meta:
+        A, b = problems.make_block(dims, kind, ss)
+        blocks.append((A, b, dev(A), dev(b)))
+    log(f"64 blocks, {sum(A.shape[1] * A.shape[2] * A.shape[3] for A, _, _, _ in blocks)} cells, one server")
+    srv = sip.Server(max_slots=256, epoch_iters=8)
+    xs = [torch.zeros_like(bt) for _, _, _, bt in blocks]
+    tickets = [srv.submit(q, At, bt, xs[q], precision="mixed", rtol=1e-8, max_iter=200000)
+               for q, (_, _, At, bt) in enumerate(blocks)]
+    res = [srv.poll(t) for t in tickets]
+    srv.close()
+    for q, (A, b, At, bt) in enumerate(blocks):
+        assert res[q]["status"] == sip.SIP_OK and res[q]["rel_res"] <= 1e-8
+        S = sip.sip_factor(At, 0.92, "mixed")
+        xa = torch.zeros_like(bt)
+        _, it, _, _ = sip.sip_solve(S, bt, xa, 1e-8, 200000)
+        S.close()
+        assert res[q]["iters"] == it and torch.equal(xs[q], xa), f"block {q}"
+        rc = oracle.norm2(oracle.residual(A, b, xs[q].cpu().numpy())) / oracle.norm2(b)
+        assert rc <= 1e-8 * (1 + 1e-9), f"block {q}"
+
+
+@pytest.fixture(scope="module")
+def cube():
+    return problems.config2()
+
+
+def test_config2_all_fp32(sip, cube):
+    A, b = cube["A"], cube["b"]
+    log("256^3 all-FP32: 2 iterations against the oracle")
+    S = sip.sip_factor(dev(A), cube["alpha"], "fp32")
+    xt = torch.zeros_like(dev(b))
+    hg = sip.sip_iterate(S, dev(b), xt, 2)
+    S.close()
+    xo, ho = oracle.iterate(A, oracle.factor(A, cube["alpha"]), b, np.zeros_like(b), 2, fp32=True)
+    assert np.abs(xt.cpu().numpy() - xo).max() <= 4e-6 * np.abs(xo).max()
+    assert np.abs(hg - ho).max() <= 2e-6
+
+
+def test_config2_pair(sip, cube):
+    A, b = cube["A"], cube["b"]
+    log("256^3 pair of right-hand sides: 3 iterations against the solo solves")
+    b2 = np.ascontiguousarray(b[::-1])
+    S = sip.sip_factor(dev(A), cube["alpha"], "mixed")
+    bs = [dev(b), dev(b2)]
+    xs = [torch.zeros_like(bs[0]), torch.zeros_like(bs[0])]
+    hp = sip.sip_iterate_multi(S, bs, xs, 3)
+    for r in range(2):
+        xa = torch.zeros_like(bs[0])
+        ha = sip.sip_iterate(S, bs[r], xa, 3)
+        assert torch.equal(xs[r], xa) and np.array_equal(hp[r], ha)
+    S.close()
+
+
+def test_config2_blocks(sip, cube):
+    A, b = cube["A"], cube["b"]
+    cuts = ([0, 128, 256],) * 3
+    log("256^3 in 2^3 blocks: 2 iterations against the multi-block oracle")
+    B = sip.sip_blocks_factor(dev(A), cuts, cube["alpha"], "fp64")
+    xt = torch.zeros_like(dev(b))
+    hg = B.iterate(dev(b), xt, 2)
+    B.close()
+    xo, _, _, ho = oracle.blocks(A, cube["alpha"], b, np.zeros_like(b), cuts, 2)
+    assert np.abs(xt.cpu().numpy() - xo).max() <= 1e-12 * np.abs(xo).max()
+    assert np.abs(hg - ho).max() <= 1e-12
