@@ -380,8 +380,8 @@ def blocks_run(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is "
-              "described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py: runs on one GPU only; --gpus must be 1 (the library does not shard a solve "
+              "across GPUs)", file=sys.stderr)
         sys.exit(2)
     if args.prof:
         prof_run(args)
