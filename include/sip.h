@@ -280,8 +280,18 @@ sip_status sip_batch_poll(sip_server s, uint64_t ticket, int32_t wait_ms, sip_re
 /* Drops a resident system's factors (no effect while requests use it). */
 sip_status sip_server_release(sip_server s, uint64_t system_id);
 
-/* Server counters: factorisations, evictions, epochs, resident bytes. */
-sip_status sip_server_stats(sip_server s, uint64_t out[8]);
+/* Server counters (HOST array of SIP_SERVER_NSTATS): factorisations,
+ * evictions, epochs, resident bytes, peak bytes, completed, admitted, sweep
+ * launches, pairs formed.  With the environment variable SIP_SERVER_PAIRS=1
+ * (read by sip_server_create), requests of one resident system with FP32
+ * factors (SIP_MIXED, SIP_FP32), the same rtol and max_iter, admitted
+ * together, are swept in pairs (the two-right-hand-side sweeps of
+ * sip_solve_multi; each result is bitwise the one it gets alone).  It is off
+ * by default: among many small concurrent blocks the pair sweeps' larger
+ * register footprint (one workgroup per CU instead of two) costs more than
+ * the shared coefficient traffic saves. */
+#define SIP_SERVER_NSTATS 9
+sip_status sip_server_stats(sip_server s, uint64_t out[SIP_SERVER_NSTATS]);
 
 /* Stops the scheduler; pending requests complete with SIP_ECANCELLED. */
 sip_status sip_server_destroy(sip_server s);

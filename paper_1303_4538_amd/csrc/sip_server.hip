@@ -36,6 +36,7 @@ using namespace sipk;
 namespace {
 
 constexpr int MAX_SLOTS = 4096;
+constexpr int MAX_PAIRS = 1024;   // pairs of requests swept together
 
 struct Resident {
     uint64_t id = 0;
@@ -55,6 +56,24 @@ struct Resident {
     uint64_t last_use = 0;
 };
 
+struct Req;
+
+// Two requests of one resident system swept together (FP32 factors): b and x
+// of both interleaved, their own face words and three control blocks (the
+// sweep's, one per request).  Each request stops at its own tolerance; the
+// pair's buffers go when both have.
+struct Pair {
+    Req *r[2] = {nullptr, nullptr};
+    Resident *sys = nullptr;
+    int idx = -1;             // control blocks pctl[3 idx .. 3 idx + 2]
+    double *bx = nullptr;     // b pairs, then x pairs
+    void *y = nullptr;
+    uint64_t *face = nullptr;
+    double *part = nullptr;
+    bool done[2] = {false, false};
+    size_t held = 0;          // budget bytes of a finished member, released with the pair
+};
+
 struct Req {
     uint64_t ticket = 0;
     sip_request r{};
@@ -72,6 +91,8 @@ struct Req {
     size_t bytes = 0;
     bool fresh = true;       // b / x0 not staged yet
     int factorised = 0;
+    Pair *pair = nullptr;    // swept together with another request
+    int pm = 0;              // which of the pair
 };
 
 size_t slot_bytes(const Geom &g, int fp32, int max_iter)
@@ -102,15 +123,21 @@ struct sip_server_s {
     std::unordered_map<uint64_t, std::unique_ptr<Resident>> systems;
     size_t used = 0, peak = 0;
     uint64_t clock = 0;
-    uint64_t stats[8] = {0};   // factorisations, evictions, epochs, resident, peak, completed, admitted, launches
+    // factorisations, evictions, epochs, resident, peak, completed, admitted, launches, pairs formed
+    uint64_t stats[SIP_SERVER_NSTATS] = {0};
     // device-side scratch for launches
     Ctl *ctl = nullptr;                      // MAX_SLOTS control blocks
     Ctl *h_ctl = nullptr;                    // pinned mirror
     std::vector<int> free_slots;
-    Job *d_jobs[NARITH] = {};                // per launch group (factor storage, or sweep arithmetic)
-    int2 *d_order[NARITH][2] = {};
-    int order_cap[NARITH] = {};
-    int jobs_cap[NARITH] = {};
+    // per launch group: factor storage or sweep arithmetic; NARITH + arith for pairs
+    Job *d_jobs[2 * NARITH] = {};
+    int2 *d_order[2 * NARITH][2] = {};
+    int order_cap[2 * NARITH] = {};
+    int jobs_cap[2 * NARITH] = {};
+    Ctl *pctl = nullptr, *h_pctl = nullptr;   // 3 * MAX_PAIRS control blocks of pairs (device, pinned mirror)
+    std::vector<int> free_pairs;
+    std::vector<Pair *> pairs;                // live pairs
+    bool pairing = false;                     // SIP_SERVER_PAIRS=1 turns pairing on
     LaunchCtl *lc = nullptr;
     unsigned *d_bad = nullptr, *h_bad = nullptr;   // symmetry check counter (device, pinned mirror)
     SweepPlan plan{};
@@ -124,6 +151,8 @@ struct sip_server_s {
     void finish_locked(Req *q, sip_status st, int iters, double rho);
     sip_status run_factor(const std::vector<Resident *> &sys, const std::vector<Req *> &owners);
     sip_status run_epoch(std::vector<Req *> &act);
+    void form_pairs(std::vector<Req *> &ready);
+    void free_pair(Pair *p);
     sip_status ensure_launch_buffers(int grp, int njobs, int ntiles);
 };
 
@@ -284,6 +313,18 @@ void sip_server_s::finish_locked(Req *q, sip_status st, int iters, double rho)
     q->face = nullptr;
     q->part = nullptr;
     q->hist = nullptr;
+    if (Pair *p = q->pair) {
+        // the pair's buffers stand for both members' budget bytes: they are
+        // released when the second member is done
+        p->done[q->pm] = true;
+        p->held += q->bytes;
+        q->bytes = 0;
+        q->pair = nullptr;
+        if (p->done[0] && p->done[1]) {
+            used -= p->held;
+            free_pair(p);
+        }
+    }
     if (q->slot >= 0) {
         free_slots.push_back(q->slot);
         q->slot = -1;
@@ -298,6 +339,97 @@ void sip_server_s::finish_locked(Req *q, sip_status st, int iters, double rho)
     }
     stats[5]++;
     cv_done.notify_all();
+}
+
+void sip_server_s::free_pair(Pair *p)
+{
+    dev_free(p->bx, stream);
+    dev_free(p->y, stream);
+    dev_free(p->face, stream);
+    dev_free(p->part, stream);
+    free_pairs.push_back(p->idx);
+    pairs.erase(std::find(pairs.begin(), pairs.end(), p));
+    delete p;
+}
+
+// x pairs behind the b pairs, in the precision of the sweeps
+static void *pair_x(const Pair *p)
+{
+    const size_t E = (size_t)p->sys->g.elems;
+    return p->sys->arith == ARITH_F32 ? (void *)((float *)p->bx + 2 * E) : (void *)(p->bx + 2 * E);
+}
+
+// Pairs freshly admitted requests of one resident system (FP32 factors, the
+// same rtol and max_iter, start vectors both given or both zero): they share
+// one pass of the sweeps over A and the factors.  The pair's buffers replace
+// the members' own, inside the budget the members were admitted with.
+void sip_server_s::form_pairs(std::vector<Req *> &ready)
+{
+    if (!pairing) return;
+    std::vector<Req *> open;
+    for (Req *q : ready) {
+        const Resident *rs = q->sys;
+        if (rs->arith != ARITH_MIXED && rs->arith != ARITH_F32) continue;
+        Req *mate = nullptr;
+        for (Req *o : open)
+            if (o->sys == rs && o->r.rtol == q->r.rtol && o->r.max_iter == q->r.max_iter &&
+                (o->r.x0 == nullptr) == (q->r.x0 == nullptr)) {
+                mate = o;
+                break;
+            }
+        if (!mate) {
+            open.push_back(q);
+            continue;
+        }
+        open.erase(std::find(open.begin(), open.end(), mate));
+        if (free_pairs.empty()) continue;
+        const Geom &g = rs->g;
+        const size_t E = (size_t)g.elems;
+        const size_t fbytes = (size_t)g.ntiles * g.steps * FACE_WORDS * 8;
+        Pair *p = new Pair();
+        p->sys = q->sys;
+        if (dev_alloc((void **)&p->bx, 4 * E * 8, stream) != SIP_OK || dev_alloc(&p->y, 2 * E * 4, stream) != SIP_OK ||
+            dev_alloc((void **)&p->face, fbytes, stream) != SIP_OK ||
+            dev_alloc((void **)&p->part, (size_t)g.ntiles * 32, stream) != SIP_OK) {
+            dev_free(p->bx, stream);
+            dev_free(p->y, stream);
+            dev_free(p->face, stream);
+            dev_free(p->part, stream);
+            delete p;
+            continue;   // both stay single
+        }
+        p->idx = free_pairs.back();
+        free_pairs.pop_back();
+        p->r[0] = mate;
+        p->r[1] = q;
+        const bool f32 = rs->arith == ARITH_F32;
+        const int sh = f32 ? SHEAR_PAIR_F32 : SHEAR_PAIR_F64;
+        const double *bs[2] = {mate->r.b, q->r.b};
+        (void)hipMemsetAsync(p->face, 0, fbytes, stream);   // fresh tags: the pair's epochs start at 1
+        (void)launch_to_sheared(g, 2, bs, p->bx, g.elems, sh, stream);
+        if (q->r.x0) {
+            const double *xs[2] = {mate->r.x0, q->r.x0};
+            (void)launch_to_sheared(g, 2, xs, pair_x(p), g.elems, sh, stream);
+        } else {
+            (void)hipMemsetAsync(pair_x(p), 0, 2 * E * (f32 ? 4 : 8), stream);
+        }
+        (void)launch_init_ctl(pctl + 3 * p->idx, 3, (uint32_t)q->r.max_iter, q->r.rtol, 1, stream);
+        for (int m = 0; m < 2; m++) {
+            Req *r = p->r[m];
+            dev_free(r->bx, stream);
+            dev_free(r->y, stream);
+            dev_free(r->face, stream);
+            dev_free(r->part, stream);
+            r->bx = nullptr;
+            r->y = nullptr;
+            r->face = nullptr;
+            r->part = nullptr;
+            r->pair = p;
+            r->pm = m;
+        }
+        pairs.push_back(p);
+        stats[8]++;
+    }
 }
 
 sip_status sip_server_s::ensure_launch_buffers(int grp, int njobs, int ntiles)
@@ -407,16 +539,39 @@ sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const st
 // One epoch: epoch_iters (forward, backward) pairs over every running request.
 sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
 {
-    std::vector<Job> jobs[NARITH];
-    std::vector<Geom> gs[NARITH];
+    // groups 0..NARITH-1: single requests by arithmetic; NARITH + arith: pairs
+    constexpr int NG = 2 * NARITH;
+    std::vector<Job> jobs[NG];
+    std::vector<Geom> gs[NG];
     for (Req *q : act) {
+        if (q->pair) continue;
         const int grp = q->sys->arith;
         jobs[grp].push_back(job_of(q->sys, q, ctl, FACE_WORDS_SWEEP));
         gs[grp].push_back(q->sys->g);
     }
-    std::vector<int2> of[NARITH], ob[NARITH];
-    LaunchArgs fa[NARITH], ba[NARITH];
-    for (int grp = 0; grp < NARITH; grp++) {
+    for (Pair *p : pairs) {
+        const Resident *rs = p->sys;
+        Job J{};
+        J.g = rs->g;
+        J.A = rs->A;
+        J.LU = rs->LU;
+        J.b = p->bx;
+        J.x = pair_x(p);
+        J.y = p->y;
+        J.face = p->face;
+        J.part = p->part;
+        J.hist = nullptr;
+        J.ctl = pctl + 3 * p->idx;
+        J.alpha = rs->alpha;
+        J.fw = FACE_WORDS_SWEEP;
+        J.sym = rs->sym;
+        J.m = 2;
+        jobs[NARITH + rs->arith].push_back(J);
+        gs[NARITH + rs->arith].push_back(rs->g);
+    }
+    std::vector<int2> of[NG], ob[NG];
+    LaunchArgs fa[NG], ba[NG];
+    for (int grp = 0; grp < NG; grp++) {
         if (jobs[grp].empty()) continue;
         of[grp] = topo_order(gs[grp], false);
         ob[grp] = topo_order(gs[grp], true);
@@ -432,25 +587,28 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
         ba[grp] = LaunchArgs{d_jobs[grp], d_order[grp][1], lc, (int)ob[grp].size(), timeout_ticks};
     }
     // launch shape of each group: the tuned plan of its largest block (sip_tune)
-    SweepPlan gplan[NARITH];
-    for (int grp = 0; grp < NARITH; grp++) {
+    SweepPlan gplan[NG];
+    for (int grp = 0; grp < NG; grp++) {
         gplan[grp] = plan;
         if (plan_forced || jobs[grp].empty()) continue;
         const Job *big = &jobs[grp][0];
         for (const Job &J : jobs[grp])
             if (J.g.elems > big->g.elems) big = &J;
-        (void)tuned_plan(big->g, grp, big->sym, &gplan[grp]);
+        (void)tuned_plan(big->g, grp % NARITH, big->sym, &gplan[grp]);
     }
     for (int it = 0; it < cfg.epoch_iters; it++) {
-        for (int grp = 0; grp < NARITH; grp++) {
+        for (int grp = 0; grp < NG; grp++) {
             if (jobs[grp].empty()) continue;
-            if (launch_forward(fa[grp], grp, gplan[grp], stream) != hipSuccess ||
-                launch_backward(ba[grp], grp, gplan[grp], stream) != hipSuccess)
+            const int arith = grp % NARITH, nrhs = grp < NARITH ? 1 : 2;
+            if (launch_forward(fa[grp], arith, gplan[grp], stream, nrhs) != hipSuccess ||
+                launch_backward(ba[grp], arith, gplan[grp], stream, nrhs) != hipSuccess)
                 return set_error(SIP_EDEVICE, "sweep launch failed");
             stats[7] += 2;
         }
     }
     if (hipMemcpyAsync(h_ctl, ctl, sizeof(Ctl) * MAX_SLOTS, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        (!pairs.empty() &&
+         hipMemcpyAsync(h_pctl, pctl, sizeof(Ctl) * 3 * MAX_PAIRS, hipMemcpyDeviceToHost, stream) != hipSuccess) ||
         hipStreamSynchronize(stream) != hipSuccess)
         return set_error(SIP_EDEVICE, "epoch failed: %s", hipGetErrorString(hipGetLastError()));
     stats[2]++;
@@ -503,7 +661,9 @@ void sip_server_s::loop()
                 ready.push_back(q);
             }
         }
+        form_pairs(ready);
         for (Req *q : ready) {
+            if (q->pair) continue;   // staged with its partner
             const Geom &g = q->sys->g;
             const double *src[2] = {q->r.b, q->r.x0 ? q->r.x0 : nullptr};
             const bool f32 = q->sys->arith == ARITH_F32;   // the relaxation starts from FP32 copies
@@ -527,6 +687,17 @@ void sip_server_s::loop()
         // retire finished requests: copy x out, then report them done
         std::vector<Req *> fin;
         for (Req *q : act) {
+            if (Pair *p = q->pair) {
+                const Ctl &c = h_pctl[3 * p->idx + 1 + q->pm];
+                const uint32_t js = h_pctl[3 * p->idx].stop;
+                if (st != SIP_OK || c.stop != RUN || js == BREAKDOWN || js == TIMEOUT) {
+                    if (st == SIP_OK)
+                        (void)launch_from_sheared(q->sys->g, pair_x(p), q->sys->arith == ARITH_F32, q->r.x,
+                                                  pctl + 3 * p->idx + 1 + q->pm, stream, 2, q->pm);
+                    fin.push_back(q);
+                }
+                continue;
+            }
             const Ctl &c = h_ctl[q->slot];
             if (st != SIP_OK || c.stop != RUN) {
                 if (st == SIP_OK)
@@ -538,7 +709,13 @@ void sip_server_s::loop()
         if (!fin.empty()) (void)hipStreamSynchronize(stream);
         std::lock_guard<std::mutex> lk(mu);
         for (Req *q : fin) {
-            const Ctl &c = h_ctl[q->slot];
+            Ctl c = h_ctl[q->slot];
+            if (const Pair *p = q->pair) {
+                c = h_pctl[3 * p->idx + 1 + q->pm];
+                const uint32_t js = h_pctl[3 * p->idx].stop;
+                if (js == BREAKDOWN || js == TIMEOUT) c.stop = js;
+                if (c.stop == ZERO_RHS) c.rho = 0.0;
+            }
             sip_status rs = SIP_OK;
             if (st != SIP_OK) rs = st;
             else if (c.stop == MAXITER) rs = SIP_ENOTCONV;
@@ -581,15 +758,25 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
             s->plan_forced = true;
         }
     }
+    if (const char *e = getenv("SIP_SERVER_PAIRS")) s->pairing = atoi(e) != 0;
     s->timeout_ticks = timeout_ticks_for(s->device, 2.0);
     s->t0 = std::chrono::steady_clock::now();
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc((void **)&s->ctl, sizeof(Ctl) * MAX_SLOTS) != hipSuccess ||
         hipHostMalloc((void **)&s->h_ctl, sizeof(Ctl) * MAX_SLOTS, hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void **)&s->lc, sizeof(LaunchCtl)) != hipSuccess ||
+        hipMalloc((void **)&s->pctl, sizeof(Ctl) * 3 * MAX_PAIRS) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_pctl, sizeof(Ctl) * 3 * MAX_PAIRS, hipHostMallocDefault) != hipSuccess ||
+        hipMemsetAsync(s->pctl, 0, sizeof(Ctl) * 3 * MAX_PAIRS, s->stream) != hipSuccess ||
+        launch_init_ctl(s->pctl, 3 * MAX_PAIRS, 0, 0.0, 1, s->stream) != hipSuccess ||
         hipMalloc((void **)&s->d_bad, sizeof(unsigned)) != hipSuccess ||
         hipHostMalloc((void **)&s->h_bad, sizeof(unsigned), hipHostMallocDefault) != hipSuccess ||
-        hipMemset(s->ctl, 0, sizeof(Ctl) * MAX_SLOTS) != hipSuccess || hipMemset(s->lc, 0, sizeof(LaunchCtl)) != hipSuccess ||
+        // on the server's own stream, in order: the stream does not synchronise
+        // with the legacy default stream, so a plain hipMemset could land after
+        // the initialisation and reset the epochs to 0, which the zeroed face
+        // words of a fresh request would then match
+        hipMemsetAsync(s->ctl, 0, sizeof(Ctl) * MAX_SLOTS, s->stream) != hipSuccess ||
+        hipMemsetAsync(s->lc, 0, sizeof(LaunchCtl), s->stream) != hipSuccess ||
         launch_init_ctl(s->ctl, MAX_SLOTS, 0, 0.0, 1, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess) {
         (void)hipGetLastError();
@@ -597,6 +784,7 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
         return set_error(SIP_ENOMEM, "server buffers");
     }
     for (int k = MAX_SLOTS - 1; k >= 0; k--) s->free_slots.push_back(k);
+    for (int k = MAX_PAIRS - 1; k >= 0; k--) s->free_pairs.push_back(k);
     s->thread = std::thread([s] { s->loop(); });
     *out = s;
     return SIP_OK;
@@ -673,7 +861,7 @@ sip_status sip_server_release(sip_server s, uint64_t system_id)
     return SIP_OK;
 }
 
-sip_status sip_server_stats(sip_server s, uint64_t out[8])
+sip_status sip_server_stats(sip_server s, uint64_t out[SIP_SERVER_NSTATS])
 {
     if (!s || !out) return set_error(SIP_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(s->mu);
@@ -698,7 +886,7 @@ sip_status sip_server_destroy(sip_server s)
         for (auto &kv : s->systems) all.push_back(kv.second.get());
         for (Resident *r : all) s->free_resident_locked(r);
     }
-    for (int grp = 0; grp < NARITH; grp++) {
+    for (int grp = 0; grp < 2 * NARITH; grp++) {
         dev_free(s->d_jobs[grp], s->stream);
         dev_free(s->d_order[grp][0], s->stream);
         dev_free(s->d_order[grp][1], s->stream);
@@ -706,6 +894,8 @@ sip_status sip_server_destroy(sip_server s)
     (void)hipStreamSynchronize(s->stream);
     (void)hipFree(s->ctl);
     (void)hipFree(s->lc);
+    (void)hipFree(s->pctl);
+    (void)hipHostFree(s->h_pctl);
     (void)hipHostFree(s->h_ctl);
     (void)hipFree(s->d_bad);
     (void)hipHostFree(s->h_bad);

@@ -176,3 +176,56 @@ def test_arrivals_while_running_join_the_mix(sip):
         xa, ita, _ = alone(sip, A, b, "mixed")
         assert res[q]["status"] == sip.SIP_OK and res[q]["iters"] == ita
         assert np.array_equal(xt[q].cpu().numpy(), xa)
+
+
+@pytest.mark.parametrize("precision,rtol", [("mixed", 1e-8), ("fp32", 1e-4)])
+def test_requests_of_one_system_run_in_pairs(sip, precision, rtol, monkeypatch):
+    """Requests of one system admitted together are swept in pairs; each
+    result is bitwise its solo solve (also a zero right-hand side and one
+    with its own tolerance, which stays single)."""
+    A, _ = block((30, 26, 22), "cd", 400)
+    rng = np.random.default_rng(401)
+    bs = [rng.uniform(-1, 1, A.shape[1:]) for _ in range(5)]
+    bs[3] = np.zeros(A.shape[1:])
+    At = dev(A)
+    bt = [dev(b) for b in bs]
+    tols = [rtol] * 5 + [rtol * 10]
+    bt.append(dev(rng.uniform(-1, 1, A.shape[1:])))
+    xt = [torch.zeros_like(b) for b in bt]
+    monkeypatch.setenv("SIP_SERVER_PAIRS", "1")
+    srv = sip.Server(max_slots=16, epoch_iters=4)
+    tickets = [srv.submit(7, At, bt[q], xt[q], precision=precision, rtol=tols[q], retain=True)
+               for q in range(len(bt))]
+    res = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    log(f"  {precision}: pairs formed {st['pairs']}")
+    assert st["pairs"] >= 2
+    S = sip.sip_factor(At, 0.92, precision)
+    for q in range(len(bt)):
+        xa = torch.zeros_like(bt[q])
+        _, it, rr, _ = sip.sip_solve(S, bt[q], xa, tols[q], 100000)
+        assert res[q]["status"] == sip.SIP_OK, res[q]
+        assert res[q]["iters"] == it and torch.equal(xt[q], xa), f"request {q}"
+    S.close()
+    assert res[3]["iters"] == 0 and float(xt[3].abs().max()) == 0.0
+
+
+def test_pairing_off_gives_the_same_results(sip, monkeypatch):
+    A, _ = block((20, 17, 13), "poisson", 402)
+    rng = np.random.default_rng(403)
+    n = 5   # the first is admitted alone; the others queue up while it factorises
+    bt = [dev(rng.uniform(-1, 1, A.shape[1:])) for _ in range(n)]
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("SIP_SERVER_PAIRS", flag)
+        srv = sip.Server(max_slots=8, epoch_iters=4)
+        xt = [torch.zeros_like(b) for b in bt]
+        tickets = [srv.submit(3, dev(A), bt[q], xt[q]) for q in range(n)]
+        res = [srv.poll(t) for t in tickets]
+        pairs = srv.stats()["pairs"]
+        srv.close()
+        out.append((xt, res, pairs))
+    assert out[0][2] >= 1 and out[1][2] == 0
+    for q in range(n):
+        assert out[0][1][q]["iters"] == out[1][1][q]["iters"] and torch.equal(out[0][0][q], out[1][0][q])
