@@ -55,3 +55,46 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(sip.Info) == 24
     # sip_block_problem: sip_problem, 3 int32 (+pad), 3 pointers
     assert ctypes.sizeof(sip.BlockProblem) == ctypes.sizeof(sip.Problem) + 12 + 4 + 24
+
+
+def test_host_side_argument_checks(libpath):
+    """Bad arguments come back as SIP_EINVAL from host-side checks, before
+    any device call (the coefficient pointers below are never dereferenced)."""
+    from paper_1303_4538_amd import sip
+    L = sip.lib()
+
+    def problem(ni, nj, nk, alpha=0.92, precision=1, storage=0):
+        p = sip.Problem()
+        p.ni, p.nj, p.nk = ni, nj, nk
+        for d in range(7):
+            p.a[d] = 0x100000 + 64 * d
+        p.alpha, p.precision, p.storage = alpha, precision, storage
+        return p
+
+    h = ctypes.c_void_p()
+    cases = [problem(0, 4, 4), problem(4, 4, 4, alpha=1.5), problem(4, 4, 4, precision=3),
+             problem(4, 4, 4, storage=2), problem(4, 4, 4, precision=2, storage=1),
+             problem(1024, 1024, 300)]           # more than 2^28 cells in the tile-sheared layout
+    for p in cases:
+        assert L.sip_factor(ctypes.byref(p), None, ctypes.byref(h)) == sip.SIP_EINVAL
+    p = problem(4, 4, 4)
+    p.a[3] = None
+    assert L.sip_factor(ctypes.byref(p), None, ctypes.byref(h)) == sip.SIP_EINVAL
+    # multi-block domains: cut planes and precision
+    for cuts, prec in ((([0, 4], [0, 4], [0, 3]), 1), (([0, 2, 2, 4], [0, 4], [0, 4]), 1),
+                       (([1, 4], [0, 4], [0, 4]), 1), (([0, 4], [0, 4], [0, 4]), 2)):
+        bp = sip.BlockProblem()
+        bp.domain = problem(4, 4, 4, precision=prec)
+        arrs = [(ctypes.c_int32 * len(c))(*c) for c in cuts]
+        for d in range(3):
+            bp.nb[d] = len(cuts[d]) - 1
+            bp.cuts[d] = ctypes.cast(arrs[d], ctypes.POINTER(ctypes.c_int32))
+        assert L.sip_blocks_factor(ctypes.byref(bp), None, ctypes.byref(h)) == sip.SIP_EINVAL
+    # NULL handles and counts
+    assert L.sip_iterate(None, None, None, 1, None, None) == sip.SIP_EINVAL
+    assert L.sip_solve_multi(None, 2, None, None, 1e-8, 10, None, None) == sip.SIP_EINVAL
+    assert L.sip_blocks_solve(None, None, None, 1e-8, 10, None, None) == sip.SIP_EINVAL
+    cfg = sip.ServerConfig()
+    cfg.max_slots, cfg.epoch_iters, cfg.max_queue = 0, 4, 16
+    assert L.sip_server_create(ctypes.byref(cfg), ctypes.byref(h)) == sip.SIP_EINVAL
+    assert L.sip_last_error() == b"bad server configuration"
