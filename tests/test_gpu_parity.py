@@ -246,3 +246,29 @@ def test_tune_keeps_results_and_records_the_plan(sip):
     _, it3, _, _ = sip.sip_solve(S, dev(b), x3, 1e-8, 5000)
     S.close()
     assert it1 == it2 == it3 and torch.equal(x1, x2) and torch.equal(x1, x3)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
+def test_graph_replays_equal_eager_launches(sip, precision):
+    """sip_iterate replays a captured graph for every 8 iterations; 24
+    iterations that way (three replays, host work in between) equal 24 eager
+    single iterations, each restaging x (exact: x is stored at the
+    precision the sweeps update it in), bitwise, residual history included;
+    the same call twice gives the same bits (deterministic norms)."""
+    A, b = make("cd", (37, 29, 17), 21)
+    S = sip.sip_factor(dev(A), 0.92, precision)
+    bt = dev(b)
+    xg = torch.zeros_like(bt)
+    hg = sip.sip_iterate(S, bt, xg, 24)
+    xg2 = torch.zeros_like(bt)
+    hg2 = sip.sip_iterate(S, bt, xg2, 24)
+    assert torch.equal(xg, xg2) and np.array_equal(hg, hg2)
+    xe = torch.zeros_like(bt)
+    he = []
+    for n in range(24):
+        h = sip.sip_iterate(S, bt, xe, 1)
+        he.append(h[0])
+    he.append(sip.sip_iterate(S, bt, xe, 0)[0])
+    S.close()
+    assert torch.equal(xg, xe)
+    assert np.array_equal(hg, np.array(he))
