@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the all-FP32 relaxation comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the two-right-hand-side and multi-block solves of the same block")
     ap.add_argument("--profile-iters", type=int, default=40)
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--storage", default="full", choices=["full", "symmetric"],
@@ -377,6 +379,51 @@ def blocks_run(args):
     print(json.dumps(line), flush=True)
 
 
+def pair_and_blocks(sip, A, b, alpha, n):
+    """The same block and b: (1) with a second seeded right-hand side, both
+    solved together (sip_solve_multi) against one after the other; (2) cut
+    into 2^3 blocks coupled through boundary values.  Mixed, to RTOL, one solve
+    each (kernels already warm), factorisation untimed."""
+    import numpy as np
+    import torch
+
+    from paper_1303_4538_amd import problems
+
+    cells = n ** 3
+    b2 = torch.from_numpy(problems.rhs_uniform(
+        n, n, n, np.random.default_rng(np.random.SeedSequence(problems.MASTER_SEED).spawn(3)[2]))).to(b.device)
+    S = sip.sip_factor(A, alpha, "mixed")
+    xs = [torch.zeros_like(b), torch.zeros_like(b)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = sip.sip_solve_multi(S, [b, b2], xs, RTOL, 200000)
+    torch.cuda.synchronize()
+    t_pair = time.perf_counter() - t0
+    its = [i[0] for i in info]
+    t0 = time.perf_counter()
+    for rhs in (b, b2):
+        sip.sip_solve(S, rhs, torch.zeros_like(b), RTOL, 200000)
+    torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t0
+    S.close()
+    cuts = [[0, n // 2, n]] * 3
+    B = sip.sip_blocks_factor(A, cuts, alpha, "mixed")
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, itb, rrb, _ = B.solve(b, x, RTOL, 200000)
+    torch.cuda.synchronize()
+    t_blk = time.perf_counter() - t0
+    B.close()
+    return {"two_rhs_iterations": its,
+            "two_rhs_cell_iters_per_s": cells * sum(its) / t_pair,
+            "one_after_the_other_cell_iters_per_s": cells * sum(its) / t_alone,
+            "two_rhs_speedup": t_alone / t_pair,
+            "blocks_2x2x2_iterations": itb, "blocks_2x2x2_rel_res": rrb,
+            "blocks_2x2x2_cell_iters_per_s": cells * itb / t_blk,
+            "blocks_2x2x2_solve_s": round(t_blk, 3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -450,6 +497,8 @@ def main():
         extra["mixed_speedup_vs_fp64"] = (t3 - t2) / (elapsed / args.steps)
     if not args.no_fp32 and args.storage == "full":
         extra["fp32_relaxation"] = fp32_comparison(sip, A, b, c["alpha"], cells)
+    if not args.no_extras and args.storage == "full" and args.workload == "single":
+        extra["two_rhs_and_blocks"] = pair_and_blocks(sip, A, b, c["alpha"], n)
 
     # dominant kernel: the fused residual + forward sweep (events on the launch stream)
     S = sip.sip_factor(A, c["alpha"], "mixed", storage=args.storage)
