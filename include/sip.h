@@ -34,9 +34,11 @@ extern "C" {
 typedef enum {
     SIP_OK = 0,
     SIP_PENDING = 1,        /* sip_batch_poll: request not finished yet            */
-    SIP_EINVAL = -1,        /* bad argument (dims < 1, alpha outside [0,1], NULL)  */
+    SIP_EINVAL = -1,        /* bad argument (dims < 1, alpha outside [0,1], NULL,
+                               non-finite b or start vector)                      */
     SIP_ENOMEM = -2,        /* device allocation or HBM budget exhausted           */
-    SIP_EBREAKDOWN = -3,    /* zero/non-finite pivot or zero denominator           */
+    SIP_EBREAKDOWN = -3,    /* zero/non-finite pivot or zero denominator, or a
+                               non-finite residual after an update (divergence)   */
     SIP_ENOTCONV = -4,      /* iteration limit reached before the tolerance        */
     SIP_EDEVICE = -5,       /* HIP error or a device-side wait timed out           */
     SIP_EBUSY = -6,         /* server queue full                                   */
@@ -111,8 +113,15 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out);
  *   n_iter   >= 0.
  *   rel_res_hist  NULL, or HOST memory of n_iter+1 doubles that receives
  *           rho_n = ||b - A x_n|| / ||b|| for n = 0..n_iter.  With NULL the
- *           call only enqueues work and does not synchronise the stream.
- * b == 0 everywhere gives x = 0.  Errors: SIP_EINVAL, SIP_EDEVICE. */
+ *           call only enqueues work and does not synchronise the stream (and
+ *           so reports none of the stop decisions below).
+ * b == 0 everywhere gives x = 0.  Non-finite values: the device computes
+ * ||b||^2 and the start residual before any update; if either is not finite
+ * (NaN or Inf in b, x or A x), nothing is updated, the history reads NaN and
+ * the call returns SIP_EINVAL.  A residual that becomes non-finite later
+ * stops the iteration there (x holds that iterate, the history reads NaN
+ * from it on) with SIP_EBREAKDOWN.  Errors: SIP_EINVAL, SIP_EBREAKDOWN,
+ * SIP_EDEVICE. */
 sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
                        double *rel_res_hist, void *stream);
 
@@ -121,7 +130,9 @@ sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
  * cheap, Sec. 3.2; here the norm and the stop test run on the device).
  *   rtol > 0, max_iter >= 0; info (nullable, host) receives iterations,
  *   final relative residual and wall time.  Synchronises the stream.
- * Errors: SIP_EINVAL, SIP_ENOTCONV (x holds x_max_iter), SIP_EDEVICE. */
+ * Non-finite values stop the solve as in sip_iterate (info->rel_res NaN).
+ * Errors: SIP_EINVAL (also non-finite b or start vector), SIP_EBREAKDOWN,
+ * SIP_ENOTCONV (x holds x_max_iter), SIP_EDEVICE. */
 sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int32_t max_iter,
                      sip_info *info, void *stream);
 
@@ -142,7 +153,10 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
  *           right-hand side r's history at r * (n_iter + 1).
  *   info    NULL, or HOST memory of nrhs entries.
  * sip_solve_multi, and sip_iterate_multi with a history, synchronise the
- * stream.  Errors: SIP_EINVAL, SIP_ENOMEM (buffers for
+ * stream.  A right-hand side whose norm or residual is not finite stops alone
+ * (as in sip_iterate / sip_solve); the others run to their own end and the
+ * call then returns that right-hand side's SIP_EINVAL or SIP_EBREAKDOWN
+ * (before SIP_ENOTCONV).  Errors: SIP_EINVAL, SIP_ENOMEM (buffers for
  * the pairs are allocated on first use and kept by the handle), SIP_ENOTCONV
  * (sip_solve_multi: some right-hand side reached max_iter; the others are
  * still solved), SIP_EDEVICE. */
@@ -258,7 +272,8 @@ typedef struct {
 } sip_request;
 
 typedef struct {
-    sip_status status;          /* SIP_OK, SIP_ENOTCONV, SIP_EBREAKDOWN ...   */
+    sip_status status;          /* SIP_OK, SIP_ENOTCONV, SIP_EBREAKDOWN, SIP_EINVAL
+                                   (non-finite b or x0) ...                   */
     sip_info info;
     double t_submit, t_admit, t_done;   /* seconds on the server's clock     */
     int32_t factorised;         /* 1 if this request triggered a factorisation */

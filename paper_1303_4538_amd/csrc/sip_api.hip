@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <string>
@@ -242,6 +243,15 @@ static sip_status launch_chunk(sip_system_s *h, hipStream_t s)
     return SIP_OK;
 }
 
+// A solve that stopped on a non-finite norm has no residual from that
+// iteration on: the history reads NaN there.
+static void nan_from(double *hist, uint32_t from, size_t n)
+{
+    for (size_t q = from; q < n; q++) hist[q] = std::numeric_limits<double>::quiet_NaN();
+}
+
+static bool non_finite(uint32_t stop) { return stop == BAD_INPUT || stop == DIVERGED; }
+
 static sip_status stop_status(uint32_t stop)
 {
     switch (stop) {
@@ -253,6 +263,10 @@ static sip_status stop_status(uint32_t stop)
         return SIP_ENOTCONV;
     case BREAKDOWN:
         return set_error(SIP_EBREAKDOWN, "SIP factorisation breakdown (zero or non-finite pivot)");
+    case BAD_INPUT:
+        return set_error(SIP_EINVAL, "non-finite input: ||b|| or the residual of the start vector is not finite");
+    case DIVERGED:
+        return set_error(SIP_EBREAKDOWN, "the iteration diverged (non-finite residual)");
     case TIMEOUT:
     default:
         return set_error(SIP_EDEVICE, "a device-side wait timed out");
@@ -505,6 +519,7 @@ sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
         for (int q = 0; q <= n_iter; q++) rel_res_hist[q] = 0.0;
         return SIP_OK;
     }
+    if (non_finite(stop)) nan_from(rel_res_hist, h->h_ctl->iter, (size_t)n_iter + 1);
     if (stop == MAXITER || stop == RUN) return SIP_OK;
     return stop_status(stop);
 }
@@ -555,7 +570,7 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) {
         info->iters = (int32_t)c.iter;
-        info->rel_res = c.rho;
+        info->rel_res = non_finite(c.stop) ? std::numeric_limits<double>::quiet_NaN() : c.rho;
         info->seconds = secs;
     }
     if (c.stop == RUN) return set_error(SIP_EDEVICE, "solve ended without a stop decision");
@@ -624,6 +639,8 @@ sip_status sip_iterate_multi(sip_system h, int32_t nrhs, const double *const *b,
     hipStream_t s = (hipStream_t)stream;
     const int npair = pairs_ok(h) ? nrhs / 2 : 0;
     const size_t hn = (size_t)n_iter + 1;
+    sip_status bad = SIP_OK;   // first right-hand side with a non-finite norm; the others still run
+    int bad_r = -1;
     if (npair > 0) TRY(ensure_multi(h, n_iter + 1, s));
     for (int pr = 0; pr < npair; pr++) {
         const int r0 = 2 * pr, r1 = r0 + 1;
@@ -640,14 +657,26 @@ sip_status sip_iterate_multi(sip_system h, int32_t nrhs, const double *const *b,
         for (int m = 0; m < 2; m++) {
             double *dst = rel_res_hist + (size_t)(r0 + m) * hn;
             std::memcpy(dst, hb.data() + (size_t)m * h->mhist_cap, hn * 8);
-            if (h->h_mctl[1 + m].stop == ZERO_RHS)
+            const uint32_t sm = h->h_mctl[1 + m].stop;
+            if (sm == ZERO_RHS)
                 for (size_t q = 0; q < hn; q++) dst[q] = 0.0;
+            if (non_finite(sm)) {
+                nan_from(dst, h->h_mctl[1 + m].iter, hn);
+                if (bad == SIP_OK) bad = stop_status(sm), bad_r = r0 + m;
+            }
         }
         const uint32_t stop = h->h_mctl[0].stop;
         if (stop == BREAKDOWN || stop == TIMEOUT) return stop_status(stop);
     }
-    for (int r = 2 * npair; r < nrhs; r++)
-        TRY(sip_iterate(h, b[r], x[r], n_iter, rel_res_hist ? rel_res_hist + (size_t)r * hn : nullptr, stream));
+    for (int r = 2 * npair; r < nrhs; r++) {
+        const sip_status st = sip_iterate(h, b[r], x[r], n_iter, rel_res_hist ? rel_res_hist + (size_t)r * hn : nullptr,
+                                          stream);
+        if (st == SIP_OK) continue;
+        if ((st != SIP_EINVAL && st != SIP_EBREAKDOWN) || !non_finite(h->h_ctl->stop)) return st;
+        if (bad == SIP_OK) bad = st, bad_r = r;
+    }
+    if (bad != SIP_OK) return set_error(bad, "right-hand side %d: non-finite %s", bad_r,
+                                        bad == SIP_EINVAL ? "input" : "residual (diverged)");
     return SIP_OK;
 }
 
@@ -662,6 +691,8 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
     hipStream_t s = (hipStream_t)stream;
     const int npair = pairs_ok(h) ? nrhs / 2 : 0;
     sip_status worst = SIP_OK;
+    sip_status bad = SIP_OK;   // first right-hand side with a non-finite norm; the others are still solved
+    int bad_r = -1;
     // the finaliser records rho_n for n <= max_iter
     if (npair > 0) TRY(ensure_multi(h, max_iter + 1, s));
     for (int pr = 0; pr < npair; pr++) {
@@ -714,16 +745,21 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
         if (c[0].stop == BREAKDOWN || c[0].stop == TIMEOUT) return stop_status(c[0].stop);
         for (int m = 0; m < 2; m++) {
             sip_info one{(int32_t)c[1 + m].iter, c[1 + m].stop == ZERO_RHS ? 0.0 : c[1 + m].rho, secs};
-            if (c[1 + m].stop == RUN) {
+            if (non_finite(c[1 + m].stop)) {
+                one.rel_res = std::numeric_limits<double>::quiet_NaN();
+                if (bad == SIP_OK) bad = stop_status(c[1 + m].stop), bad_r = r0 + m;
+            } else if (c[1 + m].stop == RUN) {
                 // The partner has stopped: this one continues from its iterate
                 // x_N through the one-right-hand-side sweeps, which compute the
                 // same iterates and residuals as the pair sweeps.
                 const int32_t done = (int32_t)c[0].iter;
                 sip_info more{};
                 const sip_status s1 = sip_solve(h, b[r0 + m], x[r0 + m], rtol, max_iter - done, &more, stream);
-                if (s1 != SIP_OK && s1 != SIP_ENOTCONV) return s1;
+                const bool nf = (s1 == SIP_EINVAL || s1 == SIP_EBREAKDOWN) && non_finite(h->h_ctl[2].stop);
+                if (s1 != SIP_OK && s1 != SIP_ENOTCONV && !nf) return s1;
                 one = sip_info{done + more.iters, more.rel_res, secs + more.seconds};
                 if (s1 == SIP_ENOTCONV) worst = SIP_ENOTCONV;
+                if (nf && bad == SIP_OK) bad = s1, bad_r = r0 + m;
             } else if (c[1 + m].stop == MAXITER) {
                 worst = SIP_ENOTCONV;
             }
@@ -733,8 +769,12 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
     for (int r = 2 * npair; r < nrhs; r++) {
         const sip_status st = sip_solve(h, b[r], x[r], rtol, max_iter, info ? info + r : nullptr, stream);
         if (st == SIP_ENOTCONV) worst = SIP_ENOTCONV;
-        else if (st != SIP_OK) return st;
+        else if ((st == SIP_EINVAL || st == SIP_EBREAKDOWN) && non_finite(h->h_ctl[2].stop)) {
+            if (bad == SIP_OK) bad = st, bad_r = r;
+        } else if (st != SIP_OK) return st;
     }
+    if (bad != SIP_OK) return set_error(bad, "right-hand side %d: non-finite %s", bad_r,
+                                        bad == SIP_EINVAL ? "input" : "residual (diverged)");
     if (worst == SIP_ENOTCONV) return set_error(SIP_ENOTCONV, "a right-hand side reached max_iter");
     return SIP_OK;
 }

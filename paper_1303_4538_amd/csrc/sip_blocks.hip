@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -254,6 +255,10 @@ sip_status stop_status(uint32_t stop)
         return SIP_ENOTCONV;
     case BREAKDOWN:
         return set_error(SIP_EBREAKDOWN, "SIP breakdown in a block");
+    case BAD_INPUT:
+        return set_error(SIP_EINVAL, "non-finite input: ||b|| or the residual of the start vector is not finite");
+    case DIVERGED:
+        return set_error(SIP_EBREAKDOWN, "the iteration diverged (non-finite residual)");
     default:
         return set_error(SIP_EDEVICE, "a device-side wait timed out");
     }
@@ -400,6 +405,8 @@ sip_status sip_blocks_iterate(sip_blocks h, const double *b, double *x, int32_t 
         std::memcpy(rel_res_hist, h->h_hist, (size_t)(n_iter + 1) * 8);
         if (stop == ZERO_RHS)
             for (int q = 0; q <= n_iter; q++) rel_res_hist[q] = 0.0;
+        if (stop == BAD_INPUT || stop == DIVERGED)   // no residual from the stopping iteration on
+            for (int q = (int)h->h_gctl->iter; q <= n_iter; q++) rel_res_hist[q] = std::nan("");
     }
     if (stop == MAXITER || stop == RUN) return SIP_OK;
     return stop_status(stop);

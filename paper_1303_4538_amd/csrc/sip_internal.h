@@ -88,6 +88,8 @@ enum Stop : uint32_t {
     ZERO_RHS = 3,
     BREAKDOWN = 4,
     TIMEOUT = 5,
+    BAD_INPUT = 6,   // non-finite ||b|| or residual of the start vector
+    DIVERGED = 7,    // non-finite residual after the first update
 };
 
 struct Geom {

@@ -559,6 +559,9 @@ __device__ __forceinline__ void fwd_issue(FwdLoad<F, R, M> &c, const FwdSrc<F, R
 // stops once every right-hand side has stopped.  A right-hand side that has
 // stopped keeps its x (the backward sweep skips its update), so its result is
 // the iterate at which it stopped, as in a solve of its own.
+// Finite and not NaN (non-finite inputs or a diverging iteration stop the solve).
+__device__ __forceinline__ bool finite_val(double v) { return v <= 1.7976931348623157e308 && v >= -1.7976931348623157e308; }
+
 template <int M>
 __device__ void finalise_multi(const Job &J, const double *sr, const double *sb, uint32_t iter, uint32_t tag)
 {
@@ -572,10 +575,12 @@ __device__ void finalise_multi(const Job &J, const double *sr, const double *sb,
         const double nb2 = iter == 0 ? sb[m] : cr->bnorm2;
         double rho = 0.0;
         if (nb2 != 0.0) rho = sqrt(sr[m]) / sqrt(nb2);
+        if (!finite_val(nb2)) rho = __builtin_nan("");
         if (J.hist) J.hist[m * J.hstride + iter] = rho;
         if (cr->stop != RUN) continue;
         uint32_t st = RUN;
-        if (nb2 == 0.0) st = ZERO_RHS;
+        if (!finite_val(nb2) || !finite_val(rho)) st = (iter == 0 || !finite_val(nb2)) ? BAD_INPUT : DIVERGED;
+        else if (nb2 == 0.0) st = ZERO_RHS;
         else if (c0->rtol > 0.0 && rho <= c0->rtol) st = CONVERGED;
         else if (iter >= c0->max_iter) st = MAXITER;
         cr->rho = rho;
@@ -890,6 +895,10 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                 const uint32_t err = cc->err;
                 if (err) {
                     st = (err & 2u) ? BREAKDOWN : TIMEOUT;
+                } else if (!finite_val(nb2)) {
+                    st = BAD_INPUT;
+                    cc->rho = __builtin_nan("");
+                    if (J.hist) J.hist[iter] = cc->rho;
                 } else if (nb2 == 0.0) {
                     st = ZERO_RHS;
                     cc->rho = 0.0;
@@ -898,7 +907,8 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                     const double rho = sqrt(sr[0]) / sqrt(nb2);
                     cc->rho = rho;
                     if (J.hist) J.hist[iter] = rho;
-                    if (cc->rtol > 0.0 && rho <= cc->rtol) st = CONVERGED;
+                    if (!finite_val(rho)) st = iter == 0 ? BAD_INPUT : DIVERGED;
+                    else if (cc->rtol > 0.0 && rho <= cc->rtol) st = CONVERGED;
                     else if (iter >= cc->max_iter) st = MAXITER;
                 }
                 cc->stop = st;
@@ -1544,11 +1554,15 @@ __global__ void k_blocks_control(BlockPtrs p, int nblk, Ctl *g, double *hist)
     double rho = 0.0;
     if (err) {
         st = (err & 2u) ? BREAKDOWN : TIMEOUT;
+    } else if (!finite_val(nb2)) {
+        st = BAD_INPUT;
+        rho = __builtin_nan("");
     } else if (nb2 == 0.0) {
         st = ZERO_RHS;
     } else {
         rho = sqrt(sr) / sqrt(nb2);
-        if (g->rtol > 0.0 && rho <= g->rtol) st = CONVERGED;
+        if (!finite_val(rho)) st = iter == 0 ? BAD_INPUT : DIVERGED;
+        else if (g->rtol > 0.0 && rho <= g->rtol) st = CONVERGED;
         else if (iter >= g->max_iter) st = MAXITER;
     }
     g->rho = rho;

@@ -719,7 +719,8 @@ void sip_server_s::loop()
             sip_status rs = SIP_OK;
             if (st != SIP_OK) rs = st;
             else if (c.stop == MAXITER) rs = SIP_ENOTCONV;
-            else if (c.stop == BREAKDOWN) rs = SIP_EBREAKDOWN;
+            else if (c.stop == BREAKDOWN || c.stop == DIVERGED) rs = SIP_EBREAKDOWN;
+            else if (c.stop == BAD_INPUT) rs = SIP_EINVAL;   // non-finite b, x0 or A x0
             else if (c.stop == TIMEOUT) rs = SIP_EDEVICE;
             finish_locked(q, rs, (int)c.iter, c.rho);
             running.erase(std::find(running.begin(), running.end(), q));

@@ -199,21 +199,26 @@ def sip_factor(A, alpha=0.92, precision="fp64", stream=None, storage="full"):
     return System(h, (p.ni, p.nj, p.nk), PRECISIONS[precision])
 
 
-def sip_iterate(system, b, x, n_iter, history=True, stream=None):
-    """Apply n_iter SIP updates to x in place; returns rho_0..rho_n (numpy) or None."""
+def sip_iterate(system, b, x, n_iter, history=True, stream=None, accept=()):
+    """Apply n_iter SIP updates to x in place; returns rho_0..rho_n (numpy) or None.
+    Statuses in accept (besides SIP_OK) return instead of raising SipError."""
     pb, px = _grid(b, system.shape, "b"), _grid(x, system.shape, "x")
     hist = np.zeros(int(n_iter) + 1) if history else None
     hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history else None
-    _check(lib().sip_iterate(system._h, pb, px, int(n_iter), hp, _stream(stream)))
+    _check(lib().sip_iterate(system._h, pb, px, int(n_iter), hp, _stream(stream)), (SIP_OK,) + tuple(accept))
     return hist
 
 
-def sip_solve(system, b, x, rtol=1e-8, max_iter=100000, stream=None, raise_on_notconv=True):
+def _ok(raise_on_notconv, accept):
+    return ((SIP_OK,) if raise_on_notconv else (SIP_OK, SIP_ENOTCONV)) + tuple(accept)
+
+
+def sip_solve(system, b, x, rtol=1e-8, max_iter=100000, stream=None, raise_on_notconv=True, accept=()):
     """Iterate until ||b - A x|| <= rtol ||b||; x in/out.  Returns (status, iters, rel_res, seconds)."""
     pb, px = _grid(b, system.shape, "b"), _grid(x, system.shape, "x")
     info = Info()
     st = lib().sip_solve(system._h, pb, px, float(rtol), int(max_iter), ctypes.byref(info), _stream(stream))
-    _check(st, (SIP_OK,) if raise_on_notconv else (SIP_OK, SIP_ENOTCONV))
+    _check(st, _ok(raise_on_notconv, accept))
     return st, info.iters, info.rel_res, info.seconds
 
 
@@ -222,7 +227,7 @@ def _grids(ts, shape, name):
     return (ctypes.c_void_p * len(ptrs))(*ptrs)
 
 
-def sip_iterate_multi(system, bs, xs, n_iter, history=True, stream=None):
+def sip_iterate_multi(system, bs, xs, n_iter, history=True, stream=None, accept=()):
     """n_iter SIP updates of several right-hand sides (pairs share one pass of
     the sweeps); xs updated in place.  Returns hist[r, n] (numpy) or None."""
     if len(bs) != len(xs) or not bs:
@@ -230,11 +235,12 @@ def sip_iterate_multi(system, bs, xs, n_iter, history=True, stream=None):
     pb, px = _grids(bs, system.shape, "b"), _grids(xs, system.shape, "x")
     hist = np.zeros((len(bs), int(n_iter) + 1)) if history else None
     hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history else None
-    _check(lib().sip_iterate_multi(system._h, len(bs), pb, px, int(n_iter), hp, _stream(stream)))
+    _check(lib().sip_iterate_multi(system._h, len(bs), pb, px, int(n_iter), hp, _stream(stream)),
+           (SIP_OK,) + tuple(accept))
     return hist
 
 
-def sip_solve_multi(system, bs, xs, rtol=1e-8, max_iter=100000, stream=None, raise_on_notconv=True):
+def sip_solve_multi(system, bs, xs, rtol=1e-8, max_iter=100000, stream=None, raise_on_notconv=True, accept=()):
     """Solve several right-hand sides (each stops at its own tolerance).
     Returns (status, [(iters, rel_res, seconds) per right-hand side])."""
     if len(bs) != len(xs) or not bs:
@@ -242,7 +248,7 @@ def sip_solve_multi(system, bs, xs, rtol=1e-8, max_iter=100000, stream=None, rai
     pb, px = _grids(bs, system.shape, "b"), _grids(xs, system.shape, "x")
     info = (Info * len(bs))()
     st = lib().sip_solve_multi(system._h, len(bs), pb, px, float(rtol), int(max_iter), info, _stream(stream))
-    _check(st, (SIP_OK,) if raise_on_notconv else (SIP_OK, SIP_ENOTCONV))
+    _check(st, _ok(raise_on_notconv, accept))
     return st, [(i.iters, i.rel_res, i.seconds) for i in info]
 
 
@@ -298,18 +304,18 @@ class Blocks:
     def shape(self):
         return (self.nk, self.nj, self.ni)
 
-    def iterate(self, b, x, n_iter, history=True, stream=None):
+    def iterate(self, b, x, n_iter, history=True, stream=None, accept=()):
         pb, px = _grid(b, self.shape, "b"), _grid(x, self.shape, "x")
         hist = np.zeros(int(n_iter) + 1) if history else None
         hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history else None
-        _check(lib().sip_blocks_iterate(self._h, pb, px, int(n_iter), hp, _stream(stream)))
+        _check(lib().sip_blocks_iterate(self._h, pb, px, int(n_iter), hp, _stream(stream)), (SIP_OK,) + tuple(accept))
         return hist
 
-    def solve(self, b, x, rtol=1e-8, max_iter=100000, stream=None, raise_on_notconv=True):
+    def solve(self, b, x, rtol=1e-8, max_iter=100000, stream=None, raise_on_notconv=True, accept=()):
         pb, px = _grid(b, self.shape, "b"), _grid(x, self.shape, "x")
         info = Info()
         st = lib().sip_blocks_solve(self._h, pb, px, float(rtol), int(max_iter), ctypes.byref(info), _stream(stream))
-        _check(st, (SIP_OK,) if raise_on_notconv else (SIP_OK, SIP_ENOTCONV))
+        _check(st, _ok(raise_on_notconv, accept))
         return st, info.iters, info.rel_res, info.seconds
 
     def info(self):
