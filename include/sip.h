@@ -120,8 +120,9 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out);
  * (NaN or Inf in b, x or A x), nothing is updated, the history reads NaN and
  * the call returns SIP_EINVAL.  A residual that becomes non-finite later
  * stops the iteration there (x holds that iterate, the history reads NaN
- * from it on) with SIP_EBREAKDOWN.  Errors: SIP_EINVAL, SIP_EBREAKDOWN,
- * SIP_EDEVICE. */
+ * from it on) with SIP_EBREAKDOWN.  The squared norms are FP64: entries
+ * above about 1e150 in magnitude overflow them and count as non-finite.
+ * Errors: SIP_EINVAL, SIP_EBREAKDOWN, SIP_EDEVICE. */
 sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
                        double *rel_res_hist, void *stream);
 
