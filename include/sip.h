@@ -240,6 +240,13 @@ sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double
  * Errors: SIP_EINVAL, SIP_EDEVICE. */
 sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phases, void *stream);
 
+/* Race testing: when the environment variable SIP_SCHEDULE_SEED holds a
+ * nonzero integer at sip_factor, sip_blocks_factor or sip_server_create, that
+ * handle takes its tiles in a random order that still respects every tile's
+ * upstream neighbours, and its kernels pause at pseudo-random steps.  The
+ * results do not change (bitwise); only the run time grows.  Unset or 0: the
+ * default schedule, at no cost. */
+
 /* sip_system_info -- dims, precision and device bytes held by a handle. */
 sip_status sip_system_info(sip_system h, int32_t dims[3], int32_t *precision, size_t *device_bytes);
 

@@ -22,6 +22,7 @@
 #include <limits>
 #include <map>
 #include <mutex>
+#include <random>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -51,8 +52,51 @@ uint64_t timeout_ticks_for(int device, double seconds)
     return (uint64_t)(seconds * rate_khz * 1000.0);
 }
 
-std::vector<int2> topo_order(const std::vector<Geom> &gs, bool backward)
+uint32_t schedule_seed()
 {
+    const char *e = getenv("SIP_SCHEDULE_SEED");
+    return e ? (uint32_t)strtoul(e, nullptr, 10) : 0u;
+}
+
+// Random topological order: repeatedly take a random tile whose upstream
+// neighbours have all been listed.
+static std::vector<int2> random_topo_order(const std::vector<Geom> &gs, bool backward, uint32_t seed)
+{
+    std::vector<std::vector<int>> wait(gs.size());
+    std::vector<int2> ready, out;
+    const int step = backward ? -1 : 1;
+    for (size_t jb = 0; jb < gs.size(); jb++) {
+        const Geom &g = gs[jb];
+        wait[jb].resize(g.ntiles);
+        for (int t = 0; t < g.ntiles; t++) {
+            const int ti = t % g.nti, tj = t / g.nti;
+            const int up = backward ? (ti < g.nti - 1) + (tj < g.ntj - 1) : (ti > 0) + (tj > 0);
+            wait[jb][t] = up;
+            if (up == 0) ready.push_back(make_int2((int)jb, t));
+        }
+    }
+    std::mt19937 rng(seed * 2654435761u + (backward ? 1u : 0u));
+    while (!ready.empty()) {
+        const size_t q = rng() % ready.size();
+        const int2 it = ready[q];
+        ready[q] = ready.back();
+        ready.pop_back();
+        out.push_back(it);
+        const Geom &g = gs[it.x];
+        const int ti = it.y % g.nti, tj = it.y / g.nti;
+        const int down[2][2] = {{ti + step, tj}, {ti, tj + step}};
+        for (const auto &d : down)
+            if (d[0] >= 0 && d[0] < g.nti && d[1] >= 0 && d[1] < g.ntj) {
+                const int t = d[1] * g.nti + d[0];
+                if (--wait[it.x][t] == 0) ready.push_back(make_int2(it.x, t));
+            }
+    }
+    return out;
+}
+
+std::vector<int2> topo_order(const std::vector<Geom> &gs, bool backward, uint32_t seed)
+{
+    if (seed) return random_topo_order(gs, backward, seed);
     struct Item {
         long long key;
         int job, tile;
@@ -207,11 +251,11 @@ bool tuned_plan(const Geom &g, int arith, int sym, SweepPlan *out)
 
 LaunchArgs fwd_args(const sip_system_s *h)
 {
-    return LaunchArgs{h->d_job, h->order_f, h->lc, h->g.ntiles, h->timeout_ticks};
+    return LaunchArgs{h->d_job, h->order_f, h->lc, h->g.ntiles, h->timeout_ticks, h->torture};
 }
 LaunchArgs bwd_args(const sip_system_s *h)
 {
-    return LaunchArgs{h->d_job, h->order_b, h->lc, h->g.ntiles, h->timeout_ticks};
+    return LaunchArgs{h->d_job, h->order_b, h->lc, h->g.ntiles, h->timeout_ticks, h->torture};
 }
 
 static sip_status launch_iterations(sip_system_s *h, int n, hipStream_t s)
@@ -329,7 +373,8 @@ static sip_status ensure_multi(sip_system_s *h, int hist_n, hipStream_t s)
 
 static LaunchArgs multi_args(const sip_system_s *h, bool backward)
 {
-    return LaunchArgs{h->d_mjob, backward ? h->order_b : h->order_f, h->lc, h->g.ntiles, h->timeout_ticks};
+    return LaunchArgs{h->d_mjob, backward ? h->order_b : h->order_f, h->lc, h->g.ntiles, h->timeout_ticks,
+                      h->torture};
 }
 
 static sip_status multi_iterations(sip_system_s *h, int n, hipStream_t s)
@@ -417,6 +462,7 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
         return set_error(SIP_EDEVICE, "no HIP device");
     }
     h->timeout_ticks = timeout_ticks_for(h->device, 2.0);
+    h->torture = schedule_seed();
     if (const char *e = getenv("SIP_SWEEP_PHASES")) {   // tuning override
         const int nl = atoi(e);
         if (nl >= 1 && nl <= sipk::MAX_PHASES) h->plan.phases = nl;
@@ -464,7 +510,7 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     J.fw = FACE_WORDS_SWEEP;
     J.sym = h->sym;
     const std::vector<Geom> gs{g};
-    const std::vector<int2> of = topo_order(gs, false), ob = topo_order(gs, true);
+    const std::vector<int2> of = topo_order(gs, false, h->torture), ob = topo_order(gs, true, h->torture);
     if (hipMemcpyAsync(h->d_job, &J, sizeof(Job), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(h->order_f, of.data(), of.size() * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(h->order_b, ob.data(), ob.size() * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess)

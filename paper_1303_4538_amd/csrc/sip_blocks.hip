@@ -51,6 +51,7 @@ struct sip_blocks_s {
     double *tmp = nullptr;   // staging (7 block-sized natural-order arrays)
     size_t bytes = 0;
     uint64_t timeout_ticks = 0;
+    uint32_t torture = 0;      // schedule_seed() at creation
     SweepPlan plan{};
 };
 
@@ -197,7 +198,8 @@ sip_status build_tables(sip_blocks_s *h, const sip_block_problem *p, hipStream_t
 
 LaunchArgs args_of(const sip_blocks_s *h, bool backward)
 {
-    return LaunchArgs{h->d_jobs, backward ? h->d_order_b : h->d_order_f, h->lc, h->total, h->timeout_ticks};
+    return LaunchArgs{h->d_jobs, backward ? h->d_order_b : h->d_order_f, h->lc, h->total, h->timeout_ticks,
+                      h->torture};
 }
 
 sip_status stage_in(sip_blocks_s *h, const double *b, const double *x, uint32_t max_iter, double rtol, hipStream_t s)
@@ -337,6 +339,7 @@ sip_status sip_blocks_factor(const sip_block_problem *p, void *stream, sip_block
         h->bytes += (size_t)h->blk[q]->g.elems * 8;
     }
     h->timeout_ticks = h->blk[0]->timeout_ticks;
+    h->torture = h->blk[0]->torture;
     h->plan = h->blk[0]->plan;
     st = build_tables(h, p, s);
     if (st != SIP_OK) return bail(st);
@@ -355,7 +358,7 @@ sip_status sip_blocks_factor(const sip_block_problem *p, void *stream, sip_block
         xp[q] = bs->bx + bs->g.elems;
         cp[q] = bs->ctl;
     }
-    const std::vector<int2> of = topo_order(gs, false), ob = topo_order(gs, true);
+    const std::vector<int2> of = topo_order(gs, false, h->torture), ob = topo_order(gs, true, h->torture);
     h->total = (int)of.size();
     if ((st = dalloc((void **)&h->d_jobs, jobs.size() * sizeof(Job), "jobs")) != SIP_OK ||
         (st = dalloc((void **)&h->d_order_f, of.size() * sizeof(int2), "order")) != SIP_OK ||

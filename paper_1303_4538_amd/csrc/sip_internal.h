@@ -158,6 +158,7 @@ struct LaunchArgs {
     LaunchCtl *lc;
     int total;                 // number of workgroups = sum of ntiles
     uint64_t timeout_ticks;    // wall-clock ticks before a wait gives up
+    uint32_t jitter;           // 0, or a seed: race testing pauses waves at random steps
 };
 
 // Face records.  At every local step a tile publishes the values its

@@ -227,6 +227,25 @@ __device__ Assign take_ticket(const LaunchArgs &a, int *s_buf)
     return r;
 }
 
+// Race testing (LaunchArgs::jitter != 0): at about one step in four a wave
+// pauses for up to 15 x 1024 clocks, chosen by a hash of the seed, the job,
+// the tile, the step and the wave (all wave-uniform).  Only the timing of the
+// waves changes, never what they compute.
+__device__ __forceinline__ void jitter_pause(uint32_t seed, int job, int tile, int step, int wave)
+{
+    if (seed == 0u) return;
+    uint32_t h = seed ^ ((uint32_t)tile * 0x9e3779b9u) ^ ((uint32_t)step * 0x85ebca6bu) ^
+                 ((uint32_t)(job * 16 + wave) * 0xc2b2ae35u);
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    if ((h & 3u) != 0u) return;
+    const int n = (int)((h >> 2) & 15u);
+    for (int q = 0; q < n; q++) __builtin_amdgcn_s_sleep(16);
+}
+
 // Launch epilogue: the last workgroup of the launch resets the counters.
 __device__ void launch_done(const LaunchArgs &a)
 {
@@ -702,6 +721,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
 #pragma unroll
             for (int q = 0; q < PD; q++) {
                 const int s = s0 + q;
+                jitter_pause(a.jitter, as.job, as.tile, s, 0);
                 if (!aborted && !halo_wait(pv[q], needW[q], fbase + oW[q], needS[q], fbase + oS[q], tag, ctl,
                                            a.timeout_ticks))
                     aborted = true;
@@ -844,7 +864,10 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
         for (int s0 = 0; s0 < U; s0 += PD) {
             for (int k = 0; k < PD; k++) {
                 const int f = s0 + k + 2;
-                if (f % NP == ph) turn(f);
+                if (f % NP == ph) {
+                    jitter_pause(a.jitter, as.job, as.tile, f, wave);
+                    turn(f);
+                }
                 wg_barrier();
             }
             if (s_buf[3]) break;
@@ -1029,6 +1052,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
 #pragma unroll
             for (int q = 0; q < PD; q++) {
                 const int s = s0 + q;
+                jitter_pause(a.jitter, as.job, as.tile, s, 0);
                 if (!aborted && !halo_wait(pv[q], needE[q], fbase + oE[q], needN[q], fbase + oN[q], tag, ctl,
                                            a.timeout_ticks))
                     aborted = true;
@@ -1139,7 +1163,10 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
         for (int s0 = 0; s0 < U; s0 += PD) {
             for (int k = 0; k < PD; k++) {
                 const int f = s0 + k + 2;
-                if (f % NP == ph) turn(f);
+                if (f % NP == ph) {
+                    jitter_pause(a.jitter, as.job, as.tile, f, wave);
+                    turn(f);
+                }
                 wg_barrier();
             }
             if (s_buf[3]) break;
@@ -1273,6 +1300,7 @@ __global__ __launch_bounds__(WAVE) void k_factor(LaunchArgs a)
     bool aborted = false, broke = false;
     const int dW = v.ip > 0 ? 1 : 0, dS = v.jp > 0 ? LI : 0;
     for (int s = 0; s < g.steps && !aborted; s++) {
+        jitter_pause(a.jitter, as.job, as.tile, s, 0);
         load_step(An, s + 1);
         const bool act = v.inq != 0u && v.kin(s, g.nk);
         const bool nW = act && pp.edge_i, nS = act && pp.edge_j;

@@ -13,7 +13,16 @@ constexpr int CHUNK = 8;   // iterations per graph-captured launch chunk
 extern thread_local std::string g_last_error;
 sip_status set_error(sip_status st, const char *fmt, ...);
 uint64_t timeout_ticks_for(int device, double seconds);
-std::vector<int2> topo_order(const std::vector<Geom> &gs, bool backward);
+// Ticket order of a launch over the jobs gs: every tile after its upstream
+// neighbours (W and S; E and N for the backward sweep).  seed 0: by
+// anti-diagonal; otherwise a random order with the same property (race
+// testing, see schedule_seed).
+std::vector<int2> topo_order(const std::vector<Geom> &gs, bool backward, uint32_t seed = 0);
+// Race testing: the environment variable SIP_SCHEDULE_SEED (read when a
+// handle is created), when set to a nonzero integer, gives the handle a
+// random ticket order and pauses the sweep and factorisation waves at
+// pseudo-random steps.  Results must not change.
+uint32_t schedule_seed();
 size_t system_bytes(const Geom &g, int fp32);
 // The sweep plan sip_tune chose for this shape and arithmetic, if any.
 bool tuned_plan(const Geom &g, int arith, int sym, SweepPlan *out);
@@ -28,6 +37,7 @@ struct sip_system_s {
     double alpha = 0.0;
     int device = 0;
     uint64_t timeout_ticks = 0;
+    uint32_t torture = 0;      // schedule_seed() at creation
     size_t bytes = 0;
     double *A = nullptr;            // 7 * elems
     void *LU = nullptr;             // 7 * elems of FP64 or FP32

@@ -111,6 +111,7 @@ struct sip_server_s {
     int device = 0;
     hipStream_t stream = nullptr;
     uint64_t timeout_ticks = 0;
+    uint32_t torture = 0;   // schedule_seed() at creation: a new random order every launch group
     std::chrono::steady_clock::time_point t0;
     std::thread thread;
     std::mutex mu;
@@ -125,6 +126,11 @@ struct sip_server_s {
     uint64_t clock = 0;
     // factorisations, evictions, epochs, resident, peak, completed, admitted, launches, pairs formed
     uint64_t stats[SIP_SERVER_NSTATS] = {0};
+    // race testing: a different random ticket order for every launch group
+    uint32_t order_seed(int grp) const
+    {
+        return torture ? (torture + 7919u * (uint32_t)stats[2] + 104729u * (uint32_t)grp) | 1u : 0u;
+    }
     // device-side scratch for launches
     Ctl *ctl = nullptr;                      // MAX_SLOTS control blocks
     Ctl *h_ctl = nullptr;                    // pinned mirror
@@ -508,14 +514,14 @@ sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const st
             gs.push_back(sys[k]->g);
         }
         if (jobs.empty()) continue;
-        const std::vector<int2> of = topo_order(gs, false);
+        const std::vector<int2> of = topo_order(gs, false, order_seed(grp));
         if (ensure_launch_buffers(grp, (int)jobs.size(), (int)of.size()) != SIP_OK) return SIP_ENOMEM;
         if (hipMemcpyAsync(d_jobs[grp], jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice, stream) !=
                 hipSuccess ||
             hipMemcpyAsync(d_order[grp][0], of.data(), of.size() * sizeof(int2), hipMemcpyHostToDevice, stream) !=
                 hipSuccess)
             return set_error(SIP_EDEVICE, "upload failed");
-        const LaunchArgs la{d_jobs[grp], d_order[grp][0], lc, (int)of.size(), timeout_ticks};
+        const LaunchArgs la{d_jobs[grp], d_order[grp][0], lc, (int)of.size(), timeout_ticks, torture};
         if (launch_factor(la, grp, stream) != hipSuccess) return set_error(SIP_EDEVICE, "factor launch failed");
         // the sweeps of symmetric systems read the symmetric storage, those of
         // the all-FP32 arithmetic FP32 coefficients; either overwrites the full
@@ -573,8 +579,8 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
     LaunchArgs fa[NG], ba[NG];
     for (int grp = 0; grp < NG; grp++) {
         if (jobs[grp].empty()) continue;
-        of[grp] = topo_order(gs[grp], false);
-        ob[grp] = topo_order(gs[grp], true);
+        of[grp] = topo_order(gs[grp], false, order_seed(grp));
+        ob[grp] = topo_order(gs[grp], true, order_seed(grp));
         if (ensure_launch_buffers(grp, (int)jobs[grp].size(), (int)of[grp].size()) != SIP_OK) return SIP_ENOMEM;
         if (hipMemcpyAsync(d_jobs[grp], jobs[grp].data(), jobs[grp].size() * sizeof(Job), hipMemcpyHostToDevice,
                            stream) != hipSuccess ||
@@ -583,8 +589,8 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
             hipMemcpyAsync(d_order[grp][1], ob[grp].data(), ob[grp].size() * sizeof(int2), hipMemcpyHostToDevice,
                            stream) != hipSuccess)
             return set_error(SIP_EDEVICE, "upload failed");
-        fa[grp] = LaunchArgs{d_jobs[grp], d_order[grp][0], lc, (int)of[grp].size(), timeout_ticks};
-        ba[grp] = LaunchArgs{d_jobs[grp], d_order[grp][1], lc, (int)ob[grp].size(), timeout_ticks};
+        fa[grp] = LaunchArgs{d_jobs[grp], d_order[grp][0], lc, (int)of[grp].size(), timeout_ticks, torture};
+        ba[grp] = LaunchArgs{d_jobs[grp], d_order[grp][1], lc, (int)ob[grp].size(), timeout_ticks, torture};
     }
     // launch shape of each group: the tuned plan of its largest block (sip_tune)
     SweepPlan gplan[NG];
@@ -761,6 +767,7 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
     }
     if (const char *e = getenv("SIP_SERVER_PAIRS")) s->pairing = atoi(e) != 0;
     s->timeout_ticks = timeout_ticks_for(s->device, 2.0);
+    s->torture = schedule_seed();
     s->t0 = std::chrono::steady_clock::now();
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc((void **)&s->ctl, sizeof(Ctl) * MAX_SLOTS) != hipSuccess ||
