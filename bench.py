@@ -79,8 +79,8 @@ def parse():
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="server HBM budget")
     ap.add_argument("--prof", action="store_true",
                     help="short run for rocprofv3: factor + a few sweeps of the default workload (mixed, "
-                         "a pair of right-hand sides, all-FP32) and a 512 MiB device copy used to calibrate "
-                         "the HBM byte counters")
+                         "a pair of right-hand sides, all-FP32; with --workload large: the 512x512x256 block, "
+                         "mixed and FP64) and a 512 MiB device copy used to calibrate the HBM byte counters")
     return ap.parse_args()
 
 
@@ -91,13 +91,26 @@ def prof_run(args):
     from paper_1303_4538_amd import problems, sip
 
     sip.lib()
-    c = problems.config2(args.n)
-    A = torch.from_numpy(c["A"]).cuda()
-    b = torch.from_numpy(c["b"]).cuda()
     src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")       # 512 MiB
     dst = torch.empty_like(src)
     dst.copy_(src)                                                         # calibration copy
     torch.cuda.synchronize()
+    del src, dst
+    if args.workload == "large":
+        # 512 x 512 x 256 stretched Poisson: the mixed and the FP64 sweeps
+        c = problems.config4()
+        A = torch.from_numpy(c["A"]).cuda()
+        b = torch.from_numpy(c["b"]).cuda()
+        for precision in ("mixed", "fp64"):
+            S = sip.sip_factor(A, c["alpha"], precision)
+            f, bk = sip.sip_profile_sweeps(S, b, torch.zeros_like(b), 5)
+            print(f"prof: large {precision} forward {f:.4f} ms, backward {bk:.4f} ms per sweep", flush=True)
+            S.close()
+        torch.cuda.synchronize()
+        return
+    c = problems.config2(args.n)
+    A = torch.from_numpy(c["A"]).cuda()
+    b = torch.from_numpy(c["b"]).cuda()
     S = sip.sip_factor(A, c["alpha"], "mixed")
     x = torch.zeros_like(b)
     fwd_ms, bwd_ms = sip.sip_profile_sweeps(S, b, x, 5)

@@ -158,24 +158,31 @@ def test_blocks_bad_input(sip):
     assert np.abs(hg - ho).max() <= 1e-12
 
 
-def test_server_bad_request_alone_fails(sip):
+@pytest.mark.parametrize("pairs", [False, True])
+def test_server_bad_request_alone_fails(sip, monkeypatch, pairs):
     rng = np.random.default_rng(25)
     A, b, x0 = system(rng)
     bn, _ = spoil(b, x0, "b_nan")
-    log("server: one request with NaN in b among good ones")
+    log(f"server: one request with NaN in b among good ones, pairing {pairs}")
+    monkeypatch.setenv("SIP_SERVER_PAIRS", "1" if pairs else "0")
     At = dev(A)
     srv = sip.Server(max_slots=16, epoch_iters=4)
-    xs = [torch.zeros_like(At[0]) for _ in range(3)]
-    bs = [dev(b), dev(bn), dev(b)]
-    tickets = [srv.submit(7, At, bs[q], xs[q], precision="mixed", rtol=1e-8, max_iter=5000) for q in range(3)]
+    # the first request is admitted alone; the others queue up while it
+    # factorises and, with pairing on, are swept in pairs (the bad one too)
+    bad = 2
+    bs = [dev(bn) if q == bad else dev(b) for q in range(5)]
+    xs = [torch.zeros_like(At[0]) for _ in bs]
+    tickets = [srv.submit(7, At, bs[q], xs[q], precision="mixed", rtol=1e-8, max_iter=5000) for q in range(5)]
     res = [srv.poll(t) for t in tickets]
+    paired = srv.stats()["pairs"]
     srv.close()
-    assert res[1]["status"] == sip.SIP_EINVAL and res[1]["iters"] == 0 and math.isnan(res[1]["rel_res"])
+    assert (paired >= 1) == pairs
+    assert res[bad]["status"] == sip.SIP_EINVAL and res[bad]["iters"] == 0 and math.isnan(res[bad]["rel_res"])
     S = sip.sip_factor(At, 0.92, "mixed")
     x = torch.zeros_like(At[0])
     _, it, rr, _ = sip.sip_solve(S, bs[0], x, 1e-8, 5000)
     S.close()
-    for q in (0, 2):
+    for q in (0, 1, 3, 4):
         assert res[q]["status"] == sip.SIP_OK and res[q]["iters"] == it and torch.equal(xs[q], x)
 
 
