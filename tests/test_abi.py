@@ -72,7 +72,8 @@ def test_host_side_argument_checks(libpath):
         return p
 
     h = ctypes.c_void_p()
-    cases = [problem(0, 4, 4), problem(4, 4, 4, alpha=1.5), problem(4, 4, 4, precision=3),
+    cases = [problem(0, 4, 4), problem(4, 4, 4, alpha=1.5), problem(4, 4, 4, alpha=float("nan")),
+             problem(4, 4, 4, alpha=-0.1), problem(4, 4, 4, precision=3),
              problem(4, 4, 4, storage=2), problem(4, 4, 4, precision=2, storage=1),
              problem(1024, 1024, 300)]           # more than 2^28 cells in the tile-sheared layout
     for p in cases:
