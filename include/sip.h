@@ -240,6 +240,21 @@ sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double
  * Errors: SIP_EINVAL, SIP_EDEVICE. */
 sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phases, void *stream);
 
+/* sip_tune_save / sip_tune_load -- the autotuner's table (block shape,
+ * precision, storage -> loader phases, as recorded by sip_tune) as a text
+ * file, so that a later process starts with the plans an earlier one
+ * measured (load it before sip_factor or sip_server_create).  One JSON
+ * object per line:
+ *   {"ni": 256, "nj": 256, "nk": 256, "precision": 1, "symmetric": 0, "phases": 2}
+ * sip_tune_save writes every entry of the process's table (overwriting
+ * path).  sip_tune_load merges the file's entries into the table (the file's
+ * win); blank lines are skipped; a line that is not such an entry (missing
+ * key, dims < 1, unknown precision, phases outside 1..3) fails the whole
+ * load with SIP_EINVAL and merges nothing.  Host only, thread-safe.
+ * Errors: SIP_EINVAL (NULL path, unreadable or unwritable file, bad line). */
+sip_status sip_tune_save(const char *path);
+sip_status sip_tune_load(const char *path);
+
 /* Race testing: when the environment variable SIP_SCHEDULE_SEED holds a
  * nonzero integer at sip_factor, sip_blocks_factor or sip_server_create, that
  * handle takes its tiles in a random order that still respects every tile's

@@ -922,6 +922,78 @@ sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phas
     return SIP_OK;
 }
 
+// The tuning table as text: one JSON object per line, keys in a fixed order.
+sip_status sip_tune_save(const char *path)
+{
+    if (!path) return set_error(SIP_EINVAL, "NULL argument");
+    std::string out;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto &kv : g_tuned) {
+            char line[160];
+            snprintf(line, sizeof line,
+                     "{\"ni\": %d, \"nj\": %d, \"nk\": %d, \"precision\": %d, \"symmetric\": %d, \"phases\": %d}\n",
+                     std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                     std::get<4>(kv.first), kv.second.phases);
+            out += line;
+        }
+    }
+    FILE *f = fopen(path, "w");
+    if (!f) return set_error(SIP_EINVAL, "cannot open %s for writing", path);
+    const bool ok = fwrite(out.data(), 1, out.size(), f) == out.size();
+    if (fclose(f) != 0 || !ok) return set_error(SIP_EINVAL, "cannot write %s", path);
+    return SIP_OK;
+}
+
+// Value of "key": <integer> in a line; false if absent or not an integer.
+static bool json_int(const char *line, const char *key, long *v)
+{
+    char pat[32];
+    snprintf(pat, sizeof pat, "\"%s\"", key);
+    const char *p = strstr(line, pat);
+    if (!p) return false;
+    p += strlen(pat);
+    while (*p == ' ' || *p == '\t') p++;
+    if (*p++ != ':') return false;
+    char *end = nullptr;
+    *v = strtol(p, &end, 10);
+    return end != p;
+}
+
+sip_status sip_tune_load(const char *path)
+{
+    if (!path) return set_error(SIP_EINVAL, "NULL argument");
+    FILE *f = fopen(path, "r");
+    if (!f) return set_error(SIP_EINVAL, "cannot open %s", path);
+    std::vector<std::pair<std::tuple<int, int, int, int, int>, SweepPlan>> got;
+    char line[512];
+    int lineno = 0;
+    sip_status st = SIP_OK;
+    while (st == SIP_OK && fgets(line, sizeof line, f)) {
+        lineno++;
+        const char *q = line;
+        while (*q == ' ' || *q == '\t' || *q == '\r' || *q == '\n') q++;
+        if (!*q) continue;   // blank line
+        long ni, nj, nk, prec, sym, ph;
+        if (!json_int(line, "ni", &ni) || !json_int(line, "nj", &nj) || !json_int(line, "nk", &nk) ||
+            !json_int(line, "precision", &prec) || !json_int(line, "symmetric", &sym) ||
+            !json_int(line, "phases", &ph) || ni < 1 || nj < 1 || nk < 1 || ni > INT32_MAX || nj > INT32_MAX ||
+            nk > INT32_MAX || prec < SIP_FP64 || prec > SIP_FP32 || sym < 0 || sym > 1 || ph < 1 ||
+            ph > MAX_PHASES) {
+            st = set_error(SIP_EINVAL, "%s:%d: not a tuning entry", path, lineno);
+            break;
+        }
+        SweepPlan pl;
+        pl.phases = (int)ph;
+        got.push_back({std::make_tuple((int)ni, (int)nj, (int)nk, (int)prec, (int)sym), pl});
+    }
+    fclose(f);
+    if (st != SIP_OK) return st;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &e : got) g_tuned[e.first] = e.second;
+    return SIP_OK;
+}
+
 sip_status sip_system_info(sip_system h, int32_t dims[3], int32_t *precision, size_t *device_bytes)
 {
     if (!h) return set_error(SIP_EINVAL, "NULL handle");

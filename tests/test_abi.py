@@ -99,3 +99,42 @@ def test_host_side_argument_checks(libpath):
     cfg.max_slots, cfg.epoch_iters, cfg.max_queue = 0, 4, 16
     assert L.sip_server_create(ctypes.byref(cfg), ctypes.byref(h)) == sip.SIP_EINVAL
     assert L.sip_last_error() == b"bad server configuration"
+
+
+def test_tuning_table_round_trip(libpath, tmp_path):
+    """sip_tune_load / sip_tune_save are host only: a table written by hand
+    loads, saves back entry for entry, and a malformed file merges nothing."""
+    import json
+    from paper_1303_4538_amd import sip
+    entries = [dict(ni=256, nj=256, nk=256, precision=1, symmetric=0, phases=2),
+               dict(ni=17, nj=9, nk=5, precision=2, symmetric=0, phases=3),
+               dict(ni=512, nj=512, nk=256, precision=0, symmetric=1, phases=1)]
+    src = tmp_path / "tune.jsonl"
+    src.write_text("\n".join(json.dumps(e) for e in entries) + "\n\n")
+    sip.sip_tune_load(src)
+    out = tmp_path / "saved.jsonl"
+    sip.sip_tune_save(out)
+    saved = [json.loads(line) for line in out.read_text().splitlines() if line.strip()]
+    for e in entries:
+        assert e in saved
+    # a later entry for the same key wins
+    src.write_text(json.dumps(dict(entries[0], phases=3)) + "\n")
+    sip.sip_tune_load(src)
+    sip.sip_tune_save(out)
+    saved = [json.loads(line) for line in out.read_text().splitlines()]
+    assert dict(entries[0], phases=3) in saved and entries[0] not in saved
+    # bad lines: nothing of the file is merged
+    for bad in ('{"ni": 8, "nj": 8, "nk": 8, "precision": 1, "symmetric": 0, "phases": 4}',
+                '{"ni": 0, "nj": 8, "nk": 8, "precision": 1, "symmetric": 0, "phases": 2}',
+                '{"ni": 8, "nj": 8, "nk": 8, "precision": 5, "symmetric": 0, "phases": 2}',
+                '{"ni": 8, "nj": 8, "nk": 8, "precision": 1, "phases": 2}',
+                'not json'):
+        f = tmp_path / "bad.jsonl"
+        f.write_text(json.dumps(dict(ni=9, nj=9, nk=9, precision=1, symmetric=0, phases=2)) + "\n" + bad + "\n")
+        with pytest.raises(sip.SipError) as e:
+            sip.sip_tune_load(f)
+        assert e.value.status == sip.SIP_EINVAL
+    sip.sip_tune_save(out)
+    assert all(e["ni"] != 9 for e in map(json.loads, out.read_text().splitlines()))
+    with pytest.raises(sip.SipError):
+        sip.sip_tune_load(tmp_path / "missing.jsonl")

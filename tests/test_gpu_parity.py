@@ -228,16 +228,20 @@ def test_config2_full_size(sip):
     assert r_cpu <= 1e-8 * (1 + 1e-9)
 
 
-def test_tune_keeps_results_and_records_the_plan(sip):
+def test_tune_keeps_results_and_records_the_plan(sip, tmp_path):
     """The autotuner picks a launch shape; solves before and after it, and on
     a new system of the same shape (which starts with the tuned plan), are
-    bitwise the same."""
+    bitwise the same; the plan is in the saved tuning table."""
+    import json
     A, b = make("cd", (40, 33, 21), 17)
     S = sip.sip_factor(dev(A), 0.92, "mixed")
     x1 = torch.zeros_like(dev(b))
     _, it1, _, _ = sip.sip_solve(S, dev(b), x1, 1e-8, 5000)
     ph = sip.sip_tune(S, dev(b), 3)
     assert 1 <= ph <= 3
+    sip.sip_tune_save(tmp_path / "tune.jsonl")
+    saved = [json.loads(line) for line in (tmp_path / "tune.jsonl").read_text().splitlines()]
+    assert dict(ni=40, nj=33, nk=21, precision=1, symmetric=0, phases=ph) in saved
     x2 = torch.zeros_like(dev(b))
     _, it2, _, _ = sip.sip_solve(S, dev(b), x2, 1e-8, 5000)
     S.close()
