@@ -26,7 +26,8 @@ def hipcc():
 def build(verbose=False):
     srcs = [os.path.join(HERE, "csrc", s) for s in SOURCES]
     tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + FLAGS + ["-I" + os.path.join(ROOT, "include"), "-o", tmp] + srcs + ["-lpthread"]
+    cmd = [hipcc()] + FLAGS + ["-I" + os.path.join(ROOT, "include"), "-o", tmp] + srcs + [
+        "-lpthread", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

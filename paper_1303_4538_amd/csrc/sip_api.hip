@@ -435,6 +435,7 @@ const char *sip_status_str(sip_status st)
 
 sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
 {
+    const Range range("sip_factor");
     if (!p || !out) return set_error(SIP_EINVAL, "NULL argument");
     if (p->ni < 1 || p->nj < 1 || p->nk < 1) return set_error(SIP_EINVAL, "dims must be >= 1");
     if ((long long)p->ni * p->nj * p->nk > (1ll << 34)) return set_error(SIP_EINVAL, "block too large");
@@ -541,6 +542,7 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
 
 sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter, double *rel_res_hist, void *stream)
 {
+    const Range range("sip_iterate");
     if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
     if (n_iter < 0) return set_error(SIP_EINVAL, "n_iter must be >= 0");
     hipStream_t s = (hipStream_t)stream;
@@ -573,6 +575,7 @@ sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
 sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int32_t max_iter, sip_info *info,
                      void *stream)
 {
+    const Range range("sip_solve");
     if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
     if (!(rtol > 0.0) || max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
     hipStream_t s = (hipStream_t)stream;
@@ -678,6 +681,7 @@ static bool pairs_ok(const sip_system_s *h) { return h->precision == SIP_MIXED |
 sip_status sip_iterate_multi(sip_system h, int32_t nrhs, const double *const *b, double *const *x, int32_t n_iter,
                              double *rel_res_hist, void *stream)
 {
+    const Range range("sip_iterate_multi");
     if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
     if (nrhs < 1 || n_iter < 0) return set_error(SIP_EINVAL, "need nrhs >= 1 and n_iter >= 0");
     for (int r = 0; r < nrhs; r++)
@@ -729,6 +733,7 @@ sip_status sip_iterate_multi(sip_system h, int32_t nrhs, const double *const *b,
 sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, double *const *x, double rtol,
                            int32_t max_iter, sip_info *info, void *stream)
 {
+    const Range range("sip_solve_multi");
     if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
     if (nrhs < 1) return set_error(SIP_EINVAL, "need nrhs >= 1");
     if (!(rtol > 0.0) || max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
@@ -867,6 +872,7 @@ sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double
 
 sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phases, void *stream)
 {
+    const Range range("sip_tune");
     if (!h || !b) return set_error(SIP_EINVAL, "NULL argument");
     if (n_iter < 1) return set_error(SIP_EINVAL, "n_iter must be >= 1");
     hipStream_t s = (hipStream_t)stream;

@@ -272,6 +272,7 @@ extern "C" {
 
 sip_status sip_blocks_factor(const sip_block_problem *p, void *stream, sip_blocks *out)
 {
+    const Range range("sip_blocks_factor");
     if (!p || !out) return set_error(SIP_EINVAL, "NULL argument");
     const sip_problem &dp = p->domain;
     if (dp.ni < 1 || dp.nj < 1 || dp.nk < 1) return set_error(SIP_EINVAL, "dims must be >= 1");
@@ -392,6 +393,7 @@ sip_status sip_blocks_factor(const sip_block_problem *p, void *stream, sip_block
 sip_status sip_blocks_iterate(sip_blocks h, const double *b, double *x, int32_t n_iter, double *rel_res_hist,
                               void *stream)
 {
+    const Range range("sip_blocks_iterate");
     if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
     if (n_iter < 0) return set_error(SIP_EINVAL, "n_iter must be >= 0");
     hipStream_t s = (hipStream_t)stream;
@@ -418,6 +420,7 @@ sip_status sip_blocks_iterate(sip_blocks h, const double *b, double *x, int32_t 
 sip_status sip_blocks_solve(sip_blocks h, const double *b, double *x, double rtol, int32_t max_iter, sip_info *info,
                             void *stream)
 {
+    const Range range("sip_blocks_solve");
     if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
     if (!(rtol > 0.0) || max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
     hipStream_t s = (hipStream_t)stream;

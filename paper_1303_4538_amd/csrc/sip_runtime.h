@@ -3,10 +3,21 @@
 #include "../../include/sip.h"
 #include "sip_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <string>
 #include <vector>
 
 namespace sipk {
+
+// Named host range around a library call (rocprofv3 --marker-trace shows it
+// beside the kernels it launched); costs a function call when no tool listens.
+struct Range {
+    explicit Range(const char *name) { roctxRangePush(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 constexpr int CHUNK = 8;   // iterations per graph-captured launch chunk
 

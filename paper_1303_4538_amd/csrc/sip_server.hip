@@ -487,6 +487,7 @@ static Job job_of(const Resident *s, const Req *q, Ctl *ctl, int fw)
 // precision; each uses the face words of the request that brought it in.
 sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const std::vector<Req *> &owners)
 {
+    const Range range("server factorisations");
     for (int grp = 0; grp < 2; grp++) {
         std::vector<Job> jobs;
         std::vector<Geom> gs;
@@ -545,6 +546,7 @@ sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const st
 // One epoch: epoch_iters (forward, backward) pairs over every running request.
 sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
 {
+    const Range range("server epoch");
     // groups 0..NARITH-1: single requests by arithmetic; NARITH + arith: pairs
     constexpr int NG = 2 * NARITH;
     std::vector<Job> jobs[NG];
