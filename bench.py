@@ -45,6 +45,18 @@ MEASURED = {"kernels_sha256": "3286a2b7c62b54182e8fb7d0c41a3557261c07008850fff44
             "n": 256, "fwd_bytes": 1770713941, "bwd_bytes": 602381858}
 
 
+def host_cpu():
+    """CPU model of the host that timed the oracle."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def kernels_sha256():
     import hashlib
     with open(os.path.join(ROOT, "paper_1303_4538_amd", "csrc", "sip_kernels.hip"), "rb") as f:
@@ -542,7 +554,8 @@ def main():
         cpu = {"value": cells * args.cpu_iters / (t5 - t4), "unit": "cell-iterations/s", "cores": 1,
                "kind": "oracle",
                "sample": f"{label}, first {args.cpu_iters} mixed-form SIP iterations "
-                         f"(FP64 residual, FP32 sweeps), single-threaded C oracle, factorisation untimed"}
+                         f"(FP64 residual, FP32 sweeps), single-threaded C oracle, factorisation untimed",
+               "host_cpu": host_cpu(), "host_cpus": os.cpu_count()}
 
     mean_it = sum(iters) / len(iters)
     line = {
