@@ -331,7 +331,17 @@ sip_status sip_server_release(sip_server s, uint64_t system_id);
 #define SIP_SERVER_NSTATS 9
 sip_status sip_server_stats(sip_server s, uint64_t out[SIP_SERVER_NSTATS]);
 
-/* Stops the scheduler; pending requests complete with SIP_ECANCELLED. */
+/* sip_server_shutdown -- stops the scheduler: the step in flight finishes,
+ * then every request not yet done completes with status SIP_ECANCELLED (its
+ * x is not written) and sip_batch_submit returns SIP_ECANCELLED.  Pollers
+ * waiting on such requests wake up; every result stays pollable until
+ * sip_server_destroy.  Returns once the server's kernels no longer touch any
+ * request's arrays.  Thread-safe; later calls do nothing. */
+sip_status sip_server_shutdown(sip_server s);
+
+/* sip_server_destroy -- shuts the server down (if not yet) and frees it and
+ * every resident factorisation.  No other call on s may run concurrently with
+ * it or follow it. */
 sip_status sip_server_destroy(sip_server s);
 
 const char *sip_status_str(sip_status st);

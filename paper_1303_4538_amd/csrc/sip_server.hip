@@ -114,6 +114,7 @@ struct sip_server_s {
     uint32_t torture = 0;   // schedule_seed() at creation: a new random order every launch group
     std::chrono::steady_clock::time_point t0;
     std::thread thread;
+    std::once_flag stop_once;   // sip_server_shutdown / sip_server_destroy stop the thread once
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     bool quit = false;
@@ -807,6 +808,7 @@ sip_status sip_batch_submit(sip_server s, const sip_request *r, uint64_t *ticket
     if (!(r->rtol > 0.0) || r->max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
     const sip_problem &p = r->problem;
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->quit) return set_error(SIP_ECANCELLED, "the server is shut down");
     auto f = s->systems.find(r->system_id);
     const bool resident = f != s->systems.end();
     bool queued_same = false;
@@ -881,15 +883,32 @@ sip_status sip_server_stats(sip_server s, uint64_t out[SIP_SERVER_NSTATS])
     return SIP_OK;
 }
 
+// Ends the scheduler thread after its current step; it cancels what is not
+// done.  Afterwards no kernel of the server touches a request's arrays.
+static void stop_server(sip_server s)
+{
+    std::call_once(s->stop_once, [s] {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->quit = true;
+        }
+        s->cv_work.notify_all();
+        if (s->thread.joinable()) s->thread.join();
+        (void)hipStreamSynchronize(s->stream);
+    });
+}
+
+sip_status sip_server_shutdown(sip_server s)
+{
+    if (!s) return set_error(SIP_EINVAL, "NULL argument");
+    stop_server(s);
+    return SIP_OK;
+}
+
 sip_status sip_server_destroy(sip_server s)
 {
     if (!s) return set_error(SIP_EINVAL, "NULL argument");
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->quit = true;
-    }
-    s->cv_work.notify_all();
-    if (s->thread.joinable()) s->thread.join();
+    stop_server(s);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         std::vector<Resident *> all;

@@ -31,7 +31,7 @@ EXPORTS = ("sip_factor", "sip_iterate", "sip_solve", "sip_iterate_multi", "sip_s
            "sip_system_info",
            "sip_system_destroy", "sip_blocks_factor", "sip_blocks_iterate", "sip_blocks_solve", "sip_blocks_info",
            "sip_blocks_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
-           "sip_server_release", "sip_server_stats", "sip_server_destroy", "sip_status_str",
+           "sip_server_release", "sip_server_stats", "sip_server_shutdown", "sip_server_destroy", "sip_status_str",
            "sip_last_error", "sip_abi_version")
 
 
@@ -106,12 +106,13 @@ def lib():
     L.sip_batch_poll.argtypes = [vp, ctypes.c_uint64, i32, ctypes.POINTER(Result)]
     L.sip_server_release.argtypes = [vp, ctypes.c_uint64]
     L.sip_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.sip_server_shutdown.argtypes = [vp]
     L.sip_server_destroy.argtypes = [vp]
     for f in ("sip_factor", "sip_iterate", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
               "sip_profile_sweeps", "sip_profile_sweeps_multi", "sip_tune", "sip_tune_save", "sip_tune_load",
               "sip_system_info", "sip_system_destroy", "sip_blocks_factor", "sip_blocks_iterate", "sip_blocks_solve", "sip_blocks_info",
               "sip_blocks_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
-              "sip_server_release", "sip_server_stats", "sip_server_destroy"):
+              "sip_server_release", "sip_server_stats", "sip_server_shutdown", "sip_server_destroy"):
         getattr(L, f).restype = ctypes.c_int32
     L.sip_status_str.argtypes = [ctypes.c_int32]
     L.sip_status_str.restype = ctypes.c_char_p
@@ -420,6 +421,11 @@ class Server:
         keys = ("factorisations", "evictions", "epochs", "resident_bytes", "peak_bytes", "completed",
                 "admitted", "launches", "pairs")
         return dict(zip(keys, [int(v) for v in out]))
+
+    def shutdown(self):
+        """Stop scheduling: requests not done complete with SIP_ECANCELLED and
+        stay pollable; later submissions are refused."""
+        _check(lib().sip_server_shutdown(self._h))
 
     def close(self):
         if self._h:

@@ -229,3 +229,38 @@ def test_pairing_off_gives_the_same_results(sip, monkeypatch):
     assert out[0][2] >= 1 and out[1][2] == 0
     for q in range(n):
         assert out[0][1][q]["iters"] == out[1][1][q]["iters"] and torch.equal(out[0][0][q], out[1][0][q])
+
+
+def test_shutdown_cancels_what_is_not_done(sip):
+    """sip_server_shutdown: requests still queued or running complete with
+    SIP_ECANCELLED and their x is not written, a poller blocked on one wakes
+    up, finished ones keep their results (equal to the solo solve), and later
+    submissions are refused with SIP_ECANCELLED."""
+    import threading
+    data = [block((40, 36, 30), "cd", 600 + q) for q in range(12)]
+    keep = [(dev(A), dev(b)) for A, b in data]
+    xs = [torch.full_like(b, 7.0) for _, b in keep]
+    srv = sip.Server(max_slots=1, epoch_iters=4)   # one request at a time: the others queue
+    tickets = [srv.submit(q, A, b, xs[q], rtol=1e-10, max_iter=100000) for q, (A, b) in enumerate(keep)]
+    got = {}
+    waiter = threading.Thread(target=lambda: got.setdefault("last", srv.poll(tickets[-1])))
+    waiter.start()
+    srv.shutdown()
+    waiter.join(timeout=60)
+    assert not waiter.is_alive()
+    res = [srv.poll(t) for t in tickets[:-1]] + [got["last"]]
+    with pytest.raises(sip.SipError) as e:
+        srv.submit(99, keep[0][0], keep[0][1], torch.zeros_like(keep[0][1]))
+    assert e.value.status == sip.SIP_ECANCELLED
+    srv.shutdown()   # a second call does nothing
+    srv.close()
+    status = [r["status"] for r in res]
+    log(f"  statuses after shutdown: {status}")
+    assert set(status) <= {sip.SIP_OK, sip.SIP_ECANCELLED}
+    assert status.count(sip.SIP_ECANCELLED) >= 6 and status[-1] == sip.SIP_ECANCELLED
+    for q, (A, b) in enumerate(data):
+        if status[q] == sip.SIP_ECANCELLED:
+            assert bool((xs[q] == 7.0).all()), f"request {q}: cancelled, x written"
+        else:
+            xa, it, _ = alone(sip, A, b, "mixed", rtol=1e-10)
+            assert res[q]["iters"] == it and np.array_equal(xs[q].cpu().numpy(), xa)
