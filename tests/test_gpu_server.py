@@ -264,3 +264,27 @@ def test_shutdown_cancels_what_is_not_done(sip):
         else:
             xa, it, _ = alone(sip, A, b, "mixed", rtol=1e-10)
             assert res[q]["iters"] == it and np.array_equal(xs[q].cpu().numpy(), xa)
+
+
+def test_full_queue_refuses_with_busy(sip):
+    """max_queue bounds the requests waiting for admission: with one slot and
+    room for three in the queue, a burst of six gets SIP_EBUSY for some; the
+    accepted ones finish with their solo results."""
+    data = [block((40, 36, 30), "cd", 700 + q) for q in range(6)]
+    keep = [(dev(A), dev(b)) for A, b in data]
+    xs = [torch.zeros_like(b) for _, b in keep]
+    srv = sip.Server(max_slots=1, epoch_iters=4, max_queue=3)
+    accepted, busy = [], 0
+    for q, (A, b) in enumerate(keep):
+        try:
+            accepted.append((q, srv.submit(q, A, b, xs[q], rtol=1e-8)))
+        except sip.SipError as e:
+            assert e.status == sip.SIP_EBUSY
+            busy += 1
+    res = [(q, srv.poll(t)) for q, t in accepted]
+    srv.close()
+    log(f"  accepted {len(accepted)}, busy {busy}")
+    assert busy >= 1 and len(accepted) >= 3
+    for q, r in res:
+        xa, it, _ = alone(sip, *data[q], "mixed")
+        assert r["status"] == sip.SIP_OK and r["iters"] == it and np.array_equal(xs[q].cpu().numpy(), xa)
