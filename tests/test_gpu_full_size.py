@@ -11,6 +11,8 @@ benchmark times.
 * 256^3 with the all-FP32 relaxation, a pair of right-hand sides and the
   domain cut into 2^3 blocks: first iterates against the oracle (all-FP32,
   multi-block) or against the solo solves (pair, bitwise).
+* The largest block the layout takes at a 1024^2 cross-section
+  (1024 x 1024 x 239): FP64 factors and iterates against the oracle.
 """
 import numpy as np
 import pytest
@@ -66,6 +68,37 @@ def test_config4_large_block(sip):
     r = oracle.norm2(oracle.residual(A, b, xt.cpu().numpy())) / oracle.norm2(b)
     assert abs(r - hg[-1]) <= 1e-12
     assert hg[-1] < hg[0]
+
+
+@pytest.mark.timeout(600)
+def test_largest_block(sip):
+    """The largest block the tile-sheared layout takes at a 1024 x 1024 cross
+    section: 1024 x 1024 x 239 (250.6 M cells, just under 2^28 sheared
+    elements, where the byte offsets of the 16-byte coefficient pairs come
+    within 0.4 % of 2^32).  FP64 factors and two iterates elementwise against
+    the oracle."""
+    A = problems.poisson(1024, 1024, 239)
+    b = np.random.default_rng(239).uniform(-1, 1, A.shape[1:])
+    log("1024x1024x239 Poisson: factor fp64 + 2 iterations")
+    At, bt = dev(A), dev(b)
+    S = sip.sip_factor(At, 0.92, "fp64")
+    del At
+    Lg = sip.sip_export_factors(S).cpu().numpy()
+    xt = torch.zeros_like(bt)
+    hg = sip.sip_iterate(S, bt, xt, 2)
+    S.close()
+    xg = xt.cpu().numpy()
+    del xt, bt
+    log("  oracle factor")
+    LU = oracle.factor(A, 0.92)
+    zero = LU == 0
+    rel = np.where(zero, np.abs(Lg), np.abs(Lg - LU) / np.maximum(np.abs(LU), 1e-300))
+    assert float(rel.max()) <= 1e-13
+    del Lg, rel, zero
+    log("  oracle iterations")
+    xo, ho = oracle.iterate(A, LU, b, np.zeros_like(b), 2)
+    assert np.abs(xg - xo).max() <= 1e-12 * np.abs(xo).max()
+    assert np.abs(hg - ho).max() <= 1e-12
 
 
 def test_config3_batched_blocks(sip):
