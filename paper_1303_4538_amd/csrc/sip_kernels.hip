@@ -10,8 +10,13 @@
 // In the sweeps, "loader" waves stream coefficient / factor / vector planes
 // from HBM a few steps ahead, do all work that does not depend on the
 // recurrence (the residual, the update of x; FP64 except in the all-FP32
-// arithmetic) and stage operands in an LDS ring.  Recurrence and loader waves meet at one workgroup barrier per
-// step; the barrier waits on LDS traffic only, so loads stay in flight.
+// arithmetic) and stage operands in an LDS ring.  Recurrence and loader
+// waves meet at one workgroup barrier per step; the barrier waits on LDS
+// traffic only, so loads stay in flight.
+//
+// The forward sweep's last workgroup of a job reduces the per-tile partial
+// norms in tile order and takes the stop decision on the device (converged,
+// iteration limit, zero right-hand side, non-finite input or residual).
 //
 // Face records: a value crossing a tile edge is written as 64-bit words
 // (sweep tag << 32 | 32 payload bits) with agent-scope relaxed atomic stores;
