@@ -188,7 +188,7 @@ def batched_run(args):
                                "convection-diffusion, one solve server, factor + mixed solve to 1e-8",
                    "cells": cells, "max_iters": max(r["iters"] for r in res),
                    "all_ok": all(r["status"] == 0 for r in res), "epochs": st["epochs"],
-                   "launches": st["launches"],
+                   "graph_epochs": st["graph_epochs"], "launches": st["launches"],
                    "hbm_gbps_algorithmic": value * (FWD_BYTES["mixed"] + BWD_BYTES["mixed"]) / 1e9},
     }
     print(json.dumps(line), flush=True)
@@ -249,7 +249,7 @@ def serving_run(args):
                    "run_p99_ms": float(np.percentile(run, 99) * 1e3),
                    "all_ok": all(r["status"] == 0 for r in res),
                    "factorisations": st["factorisations"], "evictions": st["evictions"],
-                   "epochs": st["epochs"], "peak_bytes": st["peak_bytes"],
+                   "epochs": st["epochs"], "graph_epochs": st["graph_epochs"], "peak_bytes": st["peak_bytes"],
                    "mean_cells": float(cells.mean()), "mean_iters": float(iters.mean())},
     }
     print(json.dumps(line), flush=True)

@@ -320,7 +320,10 @@ sip_status sip_server_release(sip_server s, uint64_t system_id);
 
 /* Server counters (HOST array of SIP_SERVER_NSTATS): factorisations,
  * evictions, epochs, resident bytes, peak bytes, completed, admitted, sweep
- * launches, pairs formed.  With the environment variable SIP_SERVER_PAIRS=1
+ * launches, pairs formed, epochs replayed from a captured graph (an epoch's
+ * sweeps are captured once the same launch parameters come up twice in a
+ * row, i.e. while no request joins or leaves, and replayed until they
+ * change).  With the environment variable SIP_SERVER_PAIRS=1
  * (read by sip_server_create), requests of one resident system with FP32
  * factors (SIP_MIXED, SIP_FP32), the same rtol and max_iter, admitted
  * together, are swept in pairs (the two-right-hand-side sweeps of
@@ -328,7 +331,7 @@ sip_status sip_server_release(sip_server s, uint64_t system_id);
  * by default: among many small concurrent blocks the pair sweeps' larger
  * register footprint (one workgroup per CU instead of two) costs more than
  * the shared coefficient traffic saves. */
-#define SIP_SERVER_NSTATS 9
+#define SIP_SERVER_NSTATS 10
 sip_status sip_server_stats(sip_server s, uint64_t out[SIP_SERVER_NSTATS]);
 
 /* sip_server_shutdown -- stops the scheduler: the step in flight finishes,

@@ -125,8 +125,17 @@ struct sip_server_s {
     std::unordered_map<uint64_t, std::unique_ptr<Resident>> systems;
     size_t used = 0, peak = 0;
     uint64_t clock = 0;
-    // factorisations, evictions, epochs, resident, peak, completed, admitted, launches, pairs formed
+    // factorisations, evictions, epochs, resident, peak, completed, admitted, launches, pairs formed,
+    // epochs replayed from a graph
     uint64_t stats[SIP_SERVER_NSTATS] = {0};
+    // The sweeps of an epoch as a captured graph.  Its kernels read the job
+    // list and ticket orders from device buffers uploaded before every epoch,
+    // so the graph stays valid while the launch parameters (buffer addresses,
+    // tile counts, plans, epoch length) stay the same; it is captured the
+    // second time in a row the same parameters come up and replayed from then on.
+    hipGraphExec_t epoch_exec = nullptr;
+    std::vector<uint64_t> epoch_key;
+    bool graphs = true;   // SIP_SERVER_GRAPHS=0 launches every epoch eagerly
     // race testing: a different random ticket order for every launch group
     uint32_t order_seed(int grp) const
     {
@@ -605,15 +614,52 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
             if (J.g.elems > big->g.elems) big = &J;
         (void)tuned_plan(big->g, grp % NARITH, big->sym, &gplan[grp]);
     }
-    for (int it = 0; it < cfg.epoch_iters; it++) {
-        for (int grp = 0; grp < NG; grp++) {
-            if (jobs[grp].empty()) continue;
-            const int arith = grp % NARITH, nrhs = grp < NARITH ? 1 : 2;
-            if (launch_forward(fa[grp], arith, gplan[grp], stream, nrhs) != hipSuccess ||
-                launch_backward(ba[grp], arith, gplan[grp], stream, nrhs) != hipSuccess)
-                return set_error(SIP_EDEVICE, "sweep launch failed");
-            stats[7] += 2;
+    auto launch_all = [&]() -> bool {
+        for (int it = 0; it < cfg.epoch_iters; it++) {
+            for (int grp = 0; grp < NG; grp++) {
+                if (jobs[grp].empty()) continue;
+                const int arith = grp % NARITH, nrhs = grp < NARITH ? 1 : 2;
+                if (launch_forward(fa[grp], arith, gplan[grp], stream, nrhs) != hipSuccess ||
+                    launch_backward(ba[grp], arith, gplan[grp], stream, nrhs) != hipSuccess)
+                    return false;
+            }
         }
+        return true;
+    };
+    std::vector<uint64_t> key{(uint64_t)cfg.epoch_iters};
+    for (int grp = 0; grp < NG; grp++) {
+        if (jobs[grp].empty()) {
+            key.push_back(0);
+            continue;
+        }
+        key.insert(key.end(), {1, (uint64_t)gplan[grp].phases, (uint64_t)(uintptr_t)fa[grp].jobs,
+                               (uint64_t)(uintptr_t)fa[grp].order, (uint64_t)(uintptr_t)ba[grp].order,
+                               (uint64_t)(uintptr_t)fa[grp].lc, (uint64_t)fa[grp].total, (uint64_t)ba[grp].total,
+                               fa[grp].timeout_ticks, (uint64_t)fa[grp].jitter});
+        stats[7] += 2 * (uint64_t)cfg.epoch_iters;
+    }
+    const bool same = key == epoch_key;
+    epoch_key = key;
+    if (!same && epoch_exec) {
+        (void)hipGraphExecDestroy(epoch_exec);
+        epoch_exec = nullptr;
+    }
+    if (same && !epoch_exec && graphs) {
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            const bool ok = launch_all();
+            if (hipStreamEndCapture(stream, &graph) == hipSuccess && ok && graph &&
+                hipGraphInstantiate(&epoch_exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                epoch_exec = nullptr;
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+        (void)hipGetLastError();   // a failed capture leaves the eager launches below
+    }
+    if (epoch_exec) {
+        if (hipGraphLaunch(epoch_exec, stream) != hipSuccess) return set_error(SIP_EDEVICE, "epoch graph launch failed");
+        stats[9]++;
+    } else if (!launch_all()) {
+        return set_error(SIP_EDEVICE, "sweep launch failed");
     }
     if (hipMemcpyAsync(h_ctl, ctl, sizeof(Ctl) * MAX_SLOTS, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         (!pairs.empty() &&
@@ -769,6 +815,7 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
         }
     }
     if (const char *e = getenv("SIP_SERVER_PAIRS")) s->pairing = atoi(e) != 0;
+    if (const char *e = getenv("SIP_SERVER_GRAPHS")) s->graphs = atoi(e) != 0;
     s->timeout_ticks = timeout_ticks_for(s->device, 2.0);
     s->torture = schedule_seed();
     s->t0 = std::chrono::steady_clock::now();
@@ -921,6 +968,7 @@ sip_status sip_server_destroy(sip_server s)
         dev_free(s->d_order[grp][1], s->stream);
     }
     (void)hipStreamSynchronize(s->stream);
+    if (s->epoch_exec) (void)hipGraphExecDestroy(s->epoch_exec);
     (void)hipFree(s->ctl);
     (void)hipFree(s->lc);
     (void)hipFree(s->pctl);

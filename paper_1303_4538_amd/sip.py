@@ -416,10 +416,10 @@ class Server:
         _check(lib().sip_server_release(self._h, ctypes.c_uint64(int(system_id))))
 
     def stats(self):
-        out = (ctypes.c_uint64 * 9)()
+        out = (ctypes.c_uint64 * 10)()
         _check(lib().sip_server_stats(self._h, out))
         keys = ("factorisations", "evictions", "epochs", "resident_bytes", "peak_bytes", "completed",
-                "admitted", "launches", "pairs")
+                "admitted", "launches", "pairs", "graph_epochs")
         return dict(zip(keys, [int(v) for v in out]))
 
     def shutdown(self):

@@ -138,3 +138,12 @@ def test_tuning_table_round_trip(libpath, tmp_path):
     assert all(e["ni"] != 9 for e in map(json.loads, out.read_text().splitlines()))
     with pytest.raises(sip.SipError):
         sip.sip_tune_load(tmp_path / "missing.jsonl")
+
+
+def test_server_stats_length_matches_header():
+    import re
+    from paper_1303_4538_amd import sip
+    hdr = open(os.path.join(ROOT, "include", "sip.h")).read()
+    n = int(re.search(r"#define SIP_SERVER_NSTATS (\d+)", hdr).group(1))
+    src = open(sip.__file__).read()
+    assert f"(ctypes.c_uint64 * {n})()" in src

@@ -288,3 +288,30 @@ def test_full_queue_refuses_with_busy(sip):
     for q, r in res:
         xa, it, _ = alone(sip, *data[q], "mixed")
         assert r["status"] == sip.SIP_OK and r["iters"] == it and np.array_equal(xs[q].cpu().numpy(), xa)
+
+
+@pytest.mark.parametrize("pairs", ["0", "1"])
+def test_epochs_replayed_from_a_graph(sip, monkeypatch, pairs):
+    """While no request joins or leaves, the server replays its epoch's sweeps
+    from a captured graph (the job lists and ticket orders are uploaded before
+    every replay, with the host's own bookkeeping in between); results stay
+    bitwise the solo solves."""
+    monkeypatch.setenv("SIP_SERVER_PAIRS", pairs)
+    data = [block(d, k, 800 + q) for q, (d, k) in enumerate(BLOCKS[:4])]
+    A0, _ = data[0]
+    data += [(A0, np.random.default_rng(900 + q).uniform(-1, 1, A0.shape[1:])) for q in range(2)]
+    keep = [(dev(A), dev(b)) for A, b in data]
+    xs = [torch.zeros_like(b) for _, b in keep]
+    srv = sip.Server(max_slots=16, epoch_iters=2)
+    ids = [0, 1, 2, 3, 0, 0]   # the last two share the first system (pairs when on)
+    tickets = [srv.submit(ids[q], A, b, xs[q], rtol=1e-10, max_iter=100000, retain=True)
+               for q, (A, b) in enumerate(keep)]
+    res = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    log(f"  pairs {pairs}: epochs {st['epochs']}, replayed from a graph {st['graph_epochs']}")
+    assert st["graph_epochs"] >= 1
+    for q, (A, b) in enumerate(data):
+        xa, it, _ = alone(sip, A, b, "mixed", rtol=1e-10)
+        assert res[q]["status"] == sip.SIP_OK and res[q]["iters"] == it, f"request {q}"
+        assert np.array_equal(xs[q].cpu().numpy(), xa), f"request {q}"
