@@ -323,7 +323,8 @@ sip_status sip_server_release(sip_server s, uint64_t system_id);
  * launches, pairs formed, epochs replayed from a captured graph (an epoch's
  * sweeps are captured once the same launch parameters come up twice in a
  * row, i.e. while no request joins or leaves, and replayed until they
- * change).  With the environment variable SIP_SERVER_PAIRS=1
+ * change; SIP_SERVER_GRAPHS=0, read by sip_server_create, launches every
+ * epoch eagerly instead, with the same results).  With the environment variable SIP_SERVER_PAIRS=1
  * (read by sip_server_create), requests of one resident system with FP32
  * factors (SIP_MIXED, SIP_FP32), the same rtol and max_iter, admitted
  * together, are swept in pairs (the two-right-hand-side sweeps of
