@@ -76,6 +76,7 @@ def parse():
                     help="skip the two-right-hand-side and multi-block solves of the same block")
     ap.add_argument("--profile-iters", type=int, default=40)
     ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--cpu-iters-batched", type=int, default=3, help="oracle iterations per block (batched)")
     ap.add_argument("--storage", default="full", choices=["full", "symmetric"],
                     help="coefficient storage of the sweeps (symmetric: Poisson workloads only)")
     ap.add_argument("--workload", default="single",
@@ -155,11 +156,11 @@ def batched_run(args):
         blocks.append((dims, torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda()))
     torch.cuda.synchronize()
 
-    def step(tag):
+    def step(tag, precision="mixed"):
         srv = sip.Server(max_slots=256, epoch_iters=8)
         xs = [torch.zeros_like(b) for _, _, b in blocks]
         t0 = time.perf_counter()
-        tickets = [srv.submit(tag * 1000 + q, A, b, xs[q], precision="mixed", rtol=RTOL, max_iter=200000)
+        tickets = [srv.submit(tag * 1000 + q, A, b, xs[q], precision=precision, rtol=RTOL, max_iter=200000)
                    for q, (_, A, b) in enumerate(blocks)]
         res = [srv.poll(t) for t in tickets]
         t1 = time.perf_counter()
@@ -179,6 +180,27 @@ def batched_run(args):
     res, st = last
     cells = sum(d[0] * d[1] * d[2] for d, _, _ in blocks)
     value = tot_ci / tot_t
+    extra, cpu = {}, None
+    if not args.no_extras:
+        # the same 64 blocks solved one after the other (factor + mixed solve each)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ci1 = 0
+        for dims, A, b in blocks:
+            S = sip.sip_factor(A, problems.ALPHA, "mixed")
+            x = torch.zeros_like(b)
+            _, it, _, _ = sip.sip_solve(S, b, x, RTOL, 200000)
+            S.close()
+            ci1 += dims[0] * dims[1] * dims[2] * it
+        torch.cuda.synchronize()
+        extra["one_at_a_time_cell_iters_per_s"] = ci1 / (time.perf_counter() - t0)
+        # plain FP64 through the same server
+        dt64, ci64, res64, _ = step(500, "fp64")
+        extra["fp64_batched_cell_iters_per_s"] = ci64 / dt64
+        extra["fp64_all_ok"] = all(r["status"] == 0 for r in res64)
+        extra["mixed_speedup_vs_fp64"] = value / (ci64 / dt64)
+    if not args.no_cpu:
+        cpu = batched_cpu_baseline(meta, args.cpu_iters_batched)
     line = {
         "metric": "cell-iterations/s (batched mixed SIP to 1e-8 rel. residual)",
         "value": value, "unit": "cell-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -189,9 +211,48 @@ def batched_run(args):
                    "cells": cells, "max_iters": max(r["iters"] for r in res),
                    "all_ok": all(r["status"] == 0 for r in res), "epochs": st["epochs"],
                    "graph_epochs": st["graph_epochs"], "launches": st["launches"],
-                   "hbm_gbps_algorithmic": value * (FWD_BYTES["mixed"] + BWD_BYTES["mixed"]) / 1e9},
+                   "hbm_gbps_algorithmic": value * (FWD_BYTES["mixed"] + BWD_BYTES["mixed"]) / 1e9, **extra},
+        "roofline": None, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def _oracle_block_sample(job):
+    """One block of the batched workload on one host core: factorisation
+    (untimed), then n mixed-form oracle iterations (timed)."""
+    dims, kind, ss, n = job
+    import numpy as np
+
+    import oracle
+    from paper_1303_4538_amd import problems
+    A, b = problems.make_block(dims, kind, ss)
+    LU = oracle.factor(A, problems.ALPHA)
+    t = time.perf_counter()
+    oracle.iterate(A, LU, b, np.zeros_like(b), n, mixed=True)
+    return dims[0] * dims[1] * dims[2] * n, time.perf_counter() - t
+
+
+def batched_cpu_baseline(meta, n):
+    """The oracle on the batched workload, every block in its own process over
+    all host cores (at most 16): n mixed-form iterations per block; the rate is
+    the total cell-iterations over the summed iteration time spread across the
+    cores."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import oracle
+    oracle.build(force=False)
+    procs = max(1, min(16, os.cpu_count() or 1))
+    # fresh interpreters (no inherited GPU state); a worker that cannot start
+    # fails the pool instead of being restarted
+    with ProcessPoolExecutor(procs, mp_context=mp.get_context("spawn")) as pool:
+        out = list(pool.map(_oracle_block_sample, [(d, k, s, n) for d, k, s in meta]))
+    ci = sum(c for c, _ in out)
+    busy = sum(t for _, t in out)
+    return {"value": ci / (busy / procs), "unit": "cell-iterations/s", "cores": procs, "kind": "oracle",
+            "sample": f"all {len(meta)} blocks, {n} mixed-form SIP iterations each (FP64 residual, FP32 sweeps), "
+                      f"one process per block on {procs} cores, factorisation untimed",
+            "host_cpu": host_cpu(), "host_cpus": os.cpu_count()}
 
 
 def serving_run(args):
@@ -199,58 +260,76 @@ def serving_run(args):
     each system (lognormal dims 24..192 per axis, half Poisson / half
     convection-diffusion) receives 8 right-hand sides; requests are shuffled
     and submitted at their arrival times; factors stay resident across a
-    system's requests.  Reports latency percentiles beside throughput."""
+    system's requests.  Reports latency percentiles beside throughput, the
+    offered load (arrival rate over the served rate), and as context the same
+    stream at lower arrival rates."""
     import numpy as np
     import torch
 
     from paper_1303_4538_amd import problems, sip
 
     sip.lib()
-    systems, reqs = problems.serving_stream(n_systems=args.serve_systems, rhs_per_system=8,
-                                            rate_hz=args.serve_rate)
-    As = []
-    for dims, kind, ss in systems:
-        As.append(torch.from_numpy(problems.system_coefficients(dims, kind, ss)).cuda())
-    bs = [torch.from_numpy(problems.request_rhs(systems[s][0], rs)).cuda() for _, s, _, rs in reqs]
-    xs = [torch.zeros_like(b) for b in bs]
-    torch.cuda.synchronize()
-    srv = sip.Server(hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_slots=512, epoch_iters=8)
-    t0 = time.perf_counter()
-    tickets = []
-    for q, (ta, s, m, _) in enumerate(reqs):
-        wait = t0 + ta - time.perf_counter()
-        if wait > 0:
-            time.sleep(wait)
-        tickets.append(srv.submit(s, As[s], bs[q], xs[q], precision="mixed", rtol=RTOL, max_iter=200000,
-                                  retain=True))
-    res = [srv.poll(t) for t in tickets]
-    t1 = time.perf_counter()
-    st = srv.stats()
-    srv.close()
-    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
-    run = np.array([r["t_done"] - r["t_admit"] for r in res])
-    cells = np.array([np.prod(systems[s][0]) for _, s, _, _ in reqs])
-    iters = np.array([r["iters"] for r in res])
-    ci = float((cells * iters).sum())
-    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+
+    def serve(rate):
+        systems, reqs = problems.serving_stream(n_systems=args.serve_systems, rhs_per_system=8, rate_hz=rate)
+        As = [torch.from_numpy(problems.system_coefficients(dims, kind, ss)).cuda() for dims, kind, ss in systems]
+        bs = [torch.from_numpy(problems.request_rhs(systems[s][0], rs)).cuda() for _, s, _, rs in reqs]
+        xs = [torch.zeros_like(b) for b in bs]
+        torch.cuda.synchronize()
+        srv = sip.Server(hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_slots=512, epoch_iters=8)
+        t0 = time.perf_counter()
+        tickets = []
+        for q, (ta, s, m, _) in enumerate(reqs):
+            wait = t0 + ta - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            tickets.append(srv.submit(s, As[s], bs[q], xs[q], precision="mixed", rtol=RTOL, max_iter=200000,
+                                      retain=True))
+        res = [srv.poll(t) for t in tickets]
+        t1 = time.perf_counter()
+        st = srv.stats()
+        srv.close()
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        run = np.array([r["t_done"] - r["t_admit"] for r in res])
+        cells = np.array([np.prod(systems[s][0]) for _, s, _, _ in reqs])
+        iters = np.array([r["iters"] for r in res])
+        span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+        return dict(n=len(reqs), ci=float((cells * iters).sum()), span=span, wall=t1 - t0,
+                    solves_per_s=len(res) / span,
+                    latency_p50_ms=float(np.percentile(lat, 50) * 1e3),
+                    latency_p99_ms=float(np.percentile(lat, 99) * 1e3),
+                    run_p50_ms=float(np.percentile(run, 50) * 1e3), run_p99_ms=float(np.percentile(run, 99) * 1e3),
+                    all_ok=all(r["status"] == 0 for r in res), st=st,
+                    mean_cells=float(cells.mean()), mean_iters=float(iters.mean()))
+
+    m = serve(args.serve_rate)
+    st = m["st"]
+    sweep = []
+    if not args.no_extras:
+        for rate in (args.serve_rate / 8, args.serve_rate / 4, args.serve_rate / 2):
+            r = serve(rate)
+            sweep.append({"offered_per_s": rate, "solves_per_s": r["solves_per_s"],
+                          "latency_p50_ms": r["latency_p50_ms"], "latency_p99_ms": r["latency_p99_ms"],
+                          "cell_iters_per_s": r["ci"] / r["span"], "all_ok": r["all_ok"]})
     line = {
         "metric": "served solves: cell-iterations/s and latency (mixed SIP to 1e-8)",
-        "value": ci / span, "unit": "cell-iterations/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": (t1 - t0) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": m["ci"] / m["span"], "unit": "cell-iterations/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": m["wall"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"{len(reqs)} requests ({args.serve_systems} systems x 8 rhs), Poisson arrivals "
+        "config": {"workload": f"{m['n']} requests ({args.serve_systems} systems x 8 rhs), Poisson arrivals "
                                f"{args.serve_rate:g}/s, lognormal dims 24..192, half Poisson / half CD, "
                                f"HBM budget {args.serve_budget_gb:g} GB",
-                   "solves_per_s": len(res) / span,
+                   "solves_per_s": m["solves_per_s"],
                    "offered_per_s": args.serve_rate,
-                   "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
-                   "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
-                   "run_p50_ms": float(np.percentile(run, 50) * 1e3),
-                   "run_p99_ms": float(np.percentile(run, 99) * 1e3),
-                   "all_ok": all(r["status"] == 0 for r in res),
+                   "offered_load": args.serve_rate / m["solves_per_s"],
+                   "latency_p50_ms": m["latency_p50_ms"], "latency_p99_ms": m["latency_p99_ms"],
+                   "run_p50_ms": m["run_p50_ms"], "run_p99_ms": m["run_p99_ms"],
+                   "all_ok": m["all_ok"],
                    "factorisations": st["factorisations"], "evictions": st["evictions"],
                    "epochs": st["epochs"], "graph_epochs": st["graph_epochs"], "peak_bytes": st["peak_bytes"],
-                   "mean_cells": float(cells.mean()), "mean_iters": float(iters.mean())},
+                   "mean_cells": m["mean_cells"], "mean_iters": m["mean_iters"],
+                   "rate_sweep": sweep},
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 
