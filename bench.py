@@ -45,6 +45,28 @@ MEASURED = {"kernels_sha256": "5243a0238480581a92ff5be7eacaebd4b10ab4a0e8a26d2f8
             "n": 256, "fwd_bytes": 1766380538, "bwd_bytes": 602386513}
 
 
+def copy_gbps():
+    """Read + write bandwidth of a plain 1 GiB stream on this GPU (the better
+    of a device-to-device copy and an elementwise scale), timed with events on
+    the current stream: the bandwidth a simple streaming kernel reaches."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    best = 0.0
+    for op in (lambda: dst.copy_(src), lambda: torch.mul(src, 2.0, out=dst)):
+        for _ in range(3):
+            op()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            op()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        best = max(best, 2 * src.numel() * 8 / (ms * 1e-3) / 1e9)
+    return best
+
+
 def host_cpu():
     """CPU model of the host that timed the oracle."""
     try:
@@ -620,6 +642,10 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
                 "bwd_gbps": round(BWD_BYTES["mixed"] * cells / (bwd_ms * 1e-3) / 1e9, 1)}
+    # what a plain device copy reaches on this GPU, as context for the fraction
+    copy = copy_gbps()
+    roofline["copy_gbps"] = round(copy, 1)
+    roofline["frac_of_copy"] = round(achieved / copy, 4)
 
     cpu = None
     if not args.no_cpu:
