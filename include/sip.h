@@ -184,7 +184,9 @@ typedef struct sip_blocks_s *sip_blocks;
 
 typedef struct {
     sip_problem domain;         /* dims, coefficients (device, read during the call only),
-                                   alpha, precision (SIP_FP64 or SIP_MIXED), storage */
+                                   alpha, precision (SIP_FP64 or SIP_MIXED), storage (the
+                                   symmetric one needs a symmetric domain; results are
+                                   bitwise those of the full storage) */
     int32_t nb[3];              /* blocks along i, j, k (nb[0] * nb[1] * nb[2] <= 4096) */
     const int32_t *cuts[3];     /* HOST arrays of nb[d] + 1 cut planes */
 } sip_block_problem;

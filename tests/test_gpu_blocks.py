@@ -137,3 +137,22 @@ def test_blocks_invalid_arguments(sip):
     with pytest.raises(sip.SipError) as e:
         sip.sip_blocks_factor(dev(A), ([0, 8], [0, 8], [0, 8]), 0.92, "fp32")
     assert e.value.status == sip.SIP_EINVAL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", [1, 5])
+def test_blocks_symmetric_storage_equals_full(sip, case, precision):
+    """A symmetric domain in the symmetric coefficient storage: every block
+    sweeps with A_P, A_E, A_N, A_T only (the couplings between blocks go
+    through the exchange as before), bitwise the full storage's iterates."""
+    dims, cuts = CASES[case]
+    A, b = make("stretched", dims, 40 + case)
+    log(f"blocks symmetric vs full {dims} {precision}")
+    out = []
+    for storage in ("full", "symmetric"):
+        B = sip.sip_blocks_factor(dev(A), cuts, 0.92, precision, storage=storage)
+        x = torch.zeros_like(dev(b))
+        h = B.iterate(dev(b), x, 8)
+        B.close()
+        out.append((x, h))
+    assert torch.equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
