@@ -235,8 +235,10 @@ sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double
  * sweeps support (1 to 3; each phase is a group of loader waves that prefetch
  * for alternate steps), keeps the fastest for this handle and records it for
  * the block shape and precision, so that later sip_factor calls and solve
- * servers in the process start with it.  Results are unchanged bitwise (the
- * launch shape does not change the arithmetic).  *phases (nullable, host)
+ * servers in the process start with it.  The iterates are unchanged bitwise
+ * (the launch shape does not change their arithmetic); the residual norms
+ * can differ in the last bits, since the loader waves of another phase count
+ * group the per-plane sums of squares differently.  *phases (nullable, host)
  * receives the choice.  Synchronises the stream.  The environment variable
  * SIP_SWEEP_PHASES (1..3), read by sip_factor, overrides tuned plans.
  * Errors: SIP_EINVAL, SIP_EDEVICE. */

@@ -464,6 +464,10 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     }
     h->timeout_ticks = timeout_ticks_for(h->device, 2.0);
     h->torture = schedule_seed();
+    // one system per launch: three loader phases (split turns) shorten the
+    // step; a solve server with many blocks per launch keeps two (more
+    // workgroups per compute unit)
+    h->plan.phases = SINGLE_SYSTEM_PHASES;
     if (const char *e = getenv("SIP_SWEEP_PHASES")) {   // tuning override
         const int nl = atoi(e);
         if (nl >= 1 && nl <= sipk::MAX_PHASES) h->plan.phases = nl;

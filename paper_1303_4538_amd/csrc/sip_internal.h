@@ -235,9 +235,14 @@ hipError_t launch_from_sheared(const Geom &g, const void *src, int src_f32, doub
 hipError_t launch_export_factors(const Geom &g, const void *LU, int fp32, double *const *dst, hipStream_t s);
 hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s);
 // Launch shape of the sweeps: loader phases per tile (1 to 3).  Each phase
-// is NQ loader waves (one per quadrant); phases take turns step by step, so
-// a phase's loads have `phases` steps to arrive.
+// is NQ loader waves (one per quadrant); phases take turns step by step.
+// With one or two phases a loader's whole turn falls in one step interval and
+// its loads have `phases` intervals to arrive; with three the turn is split
+// over two intervals (the loads keep two intervals of lead), which shortens
+// the step of a lone tile by about a quarter but costs occupancy.  Single
+// systems default to three, the solve server (many blocks per launch) to two.
 constexpr int MAX_PHASES = 3;
+constexpr int SINGLE_SYSTEM_PHASES = 3;
 struct SweepPlan {
     int phases = 2;
 };

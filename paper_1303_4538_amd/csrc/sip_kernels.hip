@@ -627,6 +627,12 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
     typedef Pk<F, M> FV;   // y of the M right-hand sides
     typedef Pk<R, M> RV;   // b, x of the M right-hand sides
     constexpr int NV = NW<FV>::n;
+    // With three loader phases a loader owns three intervals per turn, and the
+    // turn is split over two of them: staging (and the residual) of plane f in
+    // one, the loads of plane f + NP and the write-back in the next, so that no
+    // interval has to hold a whole turn (the loads keep their two intervals of
+    // lead).
+    constexpr bool SPLIT = NP >= 3;
     constexpr int NL = NQ * NP;
     constexpr bool R64 = std::is_same<R, double>::value;   // the symmetric storage exists in FP64 only
     __shared__ F ring[2][4 + M][NQ][TT];    // r of each right-hand side, then Lb, Lw, Ls, 1/Lp; two steps
@@ -857,14 +863,25 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                 ring[slot][M + 2][q][lane] = c.l[2];
                 ring[slot][M + 3][q][lane] = c.l[3];
             }
+            if constexpr (!SPLIT) {
+                if (f + NP < g.steps) fwd_issue(c, src, v, q, f + NP, g.steps, g.nk, sym);
+                const int p = f - 3;
+                if (p >= 0 && p < g.steps)   // inactive slots rewrite their zero padding
+                    stg(yout, src.e0 + (uint32_t)p * PLANE, ybuf[p & 1][q][lane]);
+            }
+        };
+        // Second half of a split turn, one interval later: the loads of plane
+        // f + NP and the write-back of plane f - 2 (written by the recurrence
+        // in the interval before, rewritten two intervals later).
+        auto turn_b = [&](int f) {
             if (f + NP < g.steps) fwd_issue(c, src, v, q, f + NP, g.steps, g.nk, sym);
-            const int p = f - 3;
-            if (p >= 0 && p < g.steps)   // inactive slots rewrite their zero padding
-                stg(yout, src.e0 + (uint32_t)p * PLANE, ybuf[p & 1][q][lane]);
+            const int p = f - 2;
+            if (p >= 0 && p < g.steps) stg(yout, src.e0 + (uint32_t)p * PLANE, ybuf[p & 1][q][lane]);
         };
         if (ph == 0) turn(0);
         wg_barrier();   // interval -1
         if (1 % NP == ph) turn(1);
+        if constexpr (SPLIT) if (ph == 0) turn_b(0);
         wg_barrier();   // interval 0
         for (int s0 = 0; s0 < U; s0 += PD) {
             for (int k = 0; k < PD; k++) {
@@ -873,6 +890,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                     jitter_pause(a.jitter, as.job, as.tile, f, wave);
                     turn(f);
                 }
+                if constexpr (SPLIT) if ((f - 1) % NP == ph) turn_b(f - 1);
                 wg_barrier();
             }
             if (s_buf[3]) break;
@@ -983,6 +1001,12 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
     typedef Pk<F, M> FV;
     typedef Pk<R, M> RV;
     constexpr int NV = NW<FV>::n;
+    // With three loader phases a loader owns three intervals per turn, and the
+    // turn is split over two of them: staging (and the residual) of plane f in
+    // one, the loads of plane f + NP and the write-back in the next, so that no
+    // interval has to hold a whole turn (the loads keep their two intervals of
+    // lead).
+    constexpr bool SPLIT = NP >= 3;
     __shared__ FV yring[2][NQ][TT];
     __shared__ F ring[2][3][NQ][TT];     // Un, Ue, Ut
     __shared__ RV xring[4][NQ][TT];
@@ -1138,6 +1162,17 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
         for (int m = 0; m < M; m++) frozen[m] = M > 1 && J.ctl[1 + m].stop != RUN;
         BwdLoad<F, R, M> c;
         if (ph < g.steps) bwd_issue(c, src, g.steps, ph);
+        auto update = [&](int p) {   // x += d of plane p (padding slots: 0 + 0)
+            if (p >= 0 && p < g.steps) {
+                const int sp = g.steps - 1 - p;
+                const FV dv = dbuf[p & 1][q][lane];
+                RV xv = xring[p & 3][q][lane];
+#pragma unroll
+                for (int m = 0; m < M; m++)
+                    if (!frozen[m]) set_el(xv, m, el(xv, m) + (R)el(dv, m));
+                stg(src.x, src.e0 + (uint32_t)sp * PLANE, xv);
+            }
+        };
         auto turn = [&](int f) {
             if (f < g.steps) {
                 const int slot = f & 1;
@@ -1147,23 +1182,21 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
                 ring[slot][2][q][lane] = c.u[2];
                 xring[f & 3][q][lane] = c.x;
             }
-            // Issue the next loads before the x store: a load of x behind a
-            // store to x would wait for the store to complete.
-            if (f + NP < g.steps) bwd_issue(c, src, g.steps, f + NP);
-            const int p = f - 3;
-            if (p >= 0 && p < g.steps) {
-                const int sp = g.steps - 1 - p;
-                const FV dv = dbuf[p & 1][q][lane];
-                RV xv = xring[p & 3][q][lane];
-#pragma unroll
-                for (int m = 0; m < M; m++)
-                    if (!frozen[m]) set_el(xv, m, el(xv, m) + (R)el(dv, m));   // padding: 0 + 0
-                stg(src.x, src.e0 + (uint32_t)sp * PLANE, xv);
+            if constexpr (!SPLIT) {
+                // Issue the next loads before the x store: a load of x behind a
+                // store to x would wait for the store to complete.
+                if (f + NP < g.steps) bwd_issue(c, src, g.steps, f + NP);
+                update(f - 3);
             }
+        };
+        auto turn_b = [&](int f) {   // second half of a split turn: loads of f + NP, x of plane f - 2
+            if (f + NP < g.steps) bwd_issue(c, src, g.steps, f + NP);
+            update(f - 2);
         };
         if (ph == 0) turn(0);
         wg_barrier();   // interval -1
         if (1 % NP == ph) turn(1);
+        if constexpr (SPLIT) if (ph == 0) turn_b(0);
         wg_barrier();   // interval 0
         for (int s0 = 0; s0 < U; s0 += PD) {
             for (int k = 0; k < PD; k++) {
@@ -1172,6 +1205,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
                     jitter_pause(a.jitter, as.job, as.tile, f, wave);
                     turn(f);
                 }
+                if constexpr (SPLIT) if ((f - 1) % NP == ph) turn_b(f - 1);
                 wg_barrier();
             }
             if (s_buf[3]) break;
