@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -341,7 +342,13 @@ sip_status sip_blocks_factor(const sip_block_problem *p, void *stream, sip_block
     }
     h->timeout_ticks = h->blk[0]->timeout_ticks;
     h->torture = h->blk[0]->torture;
-    h->plan = h->blk[0]->plan;
+    // all blocks sweep in one launch with many workgroups: the server's two
+    // loader phases (SIP_SWEEP_PHASES overrides)
+    h->plan = SweepPlan{};
+    if (const char *e = getenv("SIP_SWEEP_PHASES")) {
+        const int nl = atoi(e);
+        if (nl >= 1 && nl <= MAX_PHASES) h->plan.phases = nl;
+    }
     st = build_tables(h, p, s);
     if (st != SIP_OK) return bail(st);
     // one launch per sweep over all blocks
