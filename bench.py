@@ -112,6 +112,7 @@ def parse():
     ap.add_argument("--serve-systems", type=int, default=40, help="systems in the serving stream (8 rhs each)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="server HBM budget")
+    ap.add_argument("--epoch-iters", type=int, default=8, help="server iterations per epoch (batched, serving)")
     ap.add_argument("--prof", action="store_true",
                     help="short run for rocprofv3: factor + a few sweeps of the default workload (mixed, "
                          "a pair of right-hand sides, all-FP32; with --workload large: the 512x512x256 block, "
@@ -179,7 +180,7 @@ def batched_run(args):
     torch.cuda.synchronize()
 
     def step(tag, precision="mixed"):
-        srv = sip.Server(max_slots=256, epoch_iters=8)
+        srv = sip.Server(max_slots=256, epoch_iters=args.epoch_iters)
         xs = [torch.zeros_like(b) for _, _, b in blocks]
         t0 = time.perf_counter()
         tickets = [srv.submit(tag * 1000 + q, A, b, xs[q], precision=precision, rtol=RTOL, max_iter=200000)
@@ -298,7 +299,8 @@ def serving_run(args):
         bs = [torch.from_numpy(problems.request_rhs(systems[s][0], rs)).cuda() for _, s, _, rs in reqs]
         xs = [torch.zeros_like(b) for b in bs]
         torch.cuda.synchronize()
-        srv = sip.Server(hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_slots=512, epoch_iters=8)
+        srv = sip.Server(hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_slots=512,
+                         epoch_iters=args.epoch_iters)
         t0 = time.perf_counter()
         tickets = []
         for q, (ta, s, m, _) in enumerate(reqs):
