@@ -240,7 +240,8 @@ hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s);
 // its loads have `phases` intervals to arrive; with three the turn is split
 // over two intervals (the loads keep two intervals of lead), which shortens
 // the step of a lone tile by about a quarter but costs occupancy.  Single
-// systems default to three, the solve server (many blocks per launch) to two.
+// systems default to three; the solve server takes three only for a launch
+// with no more tiles than compute units, else two, like multi-block domains.
 constexpr int MAX_PHASES = 3;
 constexpr int SINGLE_SYSTEM_PHASES = 3;
 struct SweepPlan {

@@ -109,6 +109,7 @@ size_t resident_bytes(const Geom &g, int fp32) { return (size_t)g.elems * (7 * 8
 struct sip_server_s {
     sip_server_config cfg{};
     int device = 0;
+    int num_cu = 256;   // compute units of the device
     hipStream_t stream = nullptr;
     uint64_t timeout_ticks = 0;
     uint32_t torture = 0;   // schedule_seed() at creation: a new random order every launch group
@@ -604,11 +605,15 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
         fa[grp] = LaunchArgs{d_jobs[grp], d_order[grp][0], lc, (int)of[grp].size(), timeout_ticks, torture};
         ba[grp] = LaunchArgs{d_jobs[grp], d_order[grp][1], lc, (int)ob[grp].size(), timeout_ticks, torture};
     }
-    // launch shape of each group: the tuned plan of its largest block (sip_tune)
+    // launch shape of each group: the tuned plan of its largest block
+    // (sip_tune); without one, the split three-phase turns while the group has
+    // no more tiles than compute units (latency-bound, like a single system),
+    // else two phases (two workgroups per compute unit hide more latency)
     SweepPlan gplan[NG];
     for (int grp = 0; grp < NG; grp++) {
         gplan[grp] = plan;
         if (plan_forced || jobs[grp].empty()) continue;
+        if ((int)of[grp].size() <= num_cu) gplan[grp].phases = SINGLE_SYSTEM_PHASES;
         const Job *big = &jobs[grp][0];
         for (const Job &J : jobs[grp])
             if (J.g.elems > big->g.elems) big = &J;
@@ -818,6 +823,11 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
     if (const char *e = getenv("SIP_SERVER_GRAPHS")) s->graphs = atoi(e) != 0;
     s->timeout_ticks = timeout_ticks_for(s->device, 2.0);
     s->torture = schedule_seed();
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device) == hipSuccess && ncu > 0)
+            s->num_cu = ncu;
+    }
     s->t0 = std::chrono::steady_clock::now();
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc((void **)&s->ctl, sizeof(Ctl) * MAX_SLOTS) != hipSuccess ||
