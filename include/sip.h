@@ -207,14 +207,16 @@ sip_status sip_blocks_solve(sip_blocks h, const double *b, double *x, double rto
 sip_status sip_blocks_info(sip_blocks h, int32_t *nblocks, size_t *device_bytes);
 sip_status sip_blocks_destroy(sip_blocks h);
 
-/* sip_export_factors -- write the factors in natural [nk][nj][ni] order as
+/* sip_export_factors -- the incomplete factors L and U of Stone's method
+ * (Sec. 1; computed once, Sec. 4.1), written in natural [nk][nj][ni] order as
  * FP64 into seven device arrays of ni*nj*nk doubles, in the order
  * Lb, Lw, Ls, Lp, Un, Ue, Ut (Lp is the pivot, U has a unit diagonal).
  * In the mixed and FP32 precisions the FP32 factors are widened.
  * Stream-ordered. */
 sip_status sip_export_factors(sip_system h, double *const out[7], void *stream);
 
-/* sip_profile_sweeps -- measurement hook: runs n_iter iterations like
+/* sip_profile_sweeps -- measurement hook (Sec. 3 times the residual +
+ * forward routine and the backward routine separately): runs n_iter iterations like
  * sip_iterate (x updated in place) with a HIP event recorded before and
  * after every sweep launch on `stream`, synchronises, and writes the average
  * device time in milliseconds of one forward sweep (ms[0]) and one backward
@@ -222,7 +224,7 @@ sip_status sip_export_factors(sip_system h, double *const out[7], void *stream);
  * SIP_EDEVICE. */
 sip_status sip_profile_sweeps(sip_system h, const double *b, double *x, int32_t n_iter, double ms[2], void *stream);
 
-/* sip_profile_sweeps_multi -- sip_profile_sweeps for one pair of
+/* sip_profile_sweeps_multi -- (Sec. 3, Sec. 4.1) sip_profile_sweeps for one pair of
  * right-hand sides (b[0], b[1], x[0], x[1]) swept together: the average
  * device time of one pair forward sweep (ms[0]) and one pair backward sweep
  * (ms[1]).  SIP_MIXED and SIP_FP32 only.  Errors: SIP_EINVAL, SIP_ENOMEM,
@@ -230,7 +232,9 @@ sip_status sip_profile_sweeps(sip_system h, const double *b, double *x, int32_t 
 sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double *const *x, int32_t n_iter,
                                     double ms[2], void *stream);
 
-/* sip_tune -- autotuner of the sweep launch shape: times n_iter iterations
+/* sip_tune -- autotuner of the sweep launch shape (Sec. 2 sizes the
+ * paper's blocks from about 12 thousand to 1.5 million control volumes per
+ * process, so no single launch shape suits every block): times n_iter iterations
  * from x = 0 with b (device, read only) for every loader-phase count the
  * sweeps support (1 to 3; each phase is a group of loader waves that prefetch
  * for alternate steps), keeps the fastest for this handle and records it for
@@ -244,7 +248,8 @@ sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double
  * Errors: SIP_EINVAL, SIP_EDEVICE. */
 sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phases, void *stream);
 
-/* sip_tune_save / sip_tune_load -- the autotuner's table (block shape,
+/* sip_tune_save / sip_tune_load -- the autotuner's table (kept across
+ * processes, like the factorisation that Sec. 4.1 computes once in advance) (block shape,
  * precision, storage -> loader phases, as recorded by sip_tune) as a text
  * file, so that a later process starts with the plans an earlier one
  * measured (load it before sip_factor or sip_server_create).  One JSON
@@ -266,19 +271,27 @@ sip_status sip_tune_load(const char *path);
  * results do not change (bitwise); only the run time grows.  Unset or 0: the
  * default schedule, at no cost. */
 
-/* sip_system_info -- dims, precision and device bytes held by a handle. */
+/* sip_system_info -- dims, precision and device bytes held by a handle
+ * (Sec. 4.1: the solver module owns this memory). */
 sip_status sip_system_info(sip_system h, int32_t dims[3], int32_t *precision, size_t *device_bytes);
 
-/* sip_system_destroy -- free every device buffer of the handle.  The caller
- * must not have work in flight on it. */
+/* sip_system_destroy -- free every device buffer of the handle (Sec. 4.1:
+ * the redesigned solver allocates and releases the memory of its
+ * coefficients and factors itself, through its own entry points).  The
+ * caller must not have work in flight on it. */
 sip_status sip_system_destroy(sip_system h);
 
 /* ------------------------------------------------------------------------
- * Batched and served solves.  A server owns a scheduler thread that admits
- * requests while device memory (the HBM budget) and slots allow, keeps SIP
- * factors resident across requests of the same system, and advances all
- * admitted requests together in epochs of device launches (continuous
- * batching).  Requests that arrive while others run join the next epoch.
+ * Batched and served solves.  Sec. 4.1 turns SIP into a module that owns the
+ * memory of its coefficients and factors, computes the factorisation in
+ * advance and reuses it for all later iterations and time steps; Sec. 4.2
+ * runs SIP on every block of a process one after another.  A server carries
+ * both over to many blocks and right-hand sides on one GPU: its scheduler
+ * thread admits requests while device memory (the HBM budget) and slots
+ * allow, keeps SIP factors resident across requests of the same system, and
+ * advances all admitted requests together in epochs of device launches
+ * (continuous batching).  Requests that arrive while others run join the next
+ * epoch.
  * ------------------------------------------------------------------------ */
 typedef struct {
     size_t hbm_budget_bytes;    /* device bytes the server may hold (0 = 3/4 of free memory) */
@@ -295,7 +308,13 @@ typedef struct {
     const double *x0;           /* device start vector or NULL (zeros)        */
     double rtol;
     int32_t max_iter;
-    int32_t retain;             /* 1: keep this system's factors resident after the request */
+    int32_t retain;             /* 1: keep this system's factors resident after the request
+                                   (until evicted for room: least-recently-used first,
+                                   never while a queued request names the system) */
+    void *stream;               /* the caller's hipStream_t on which b, x0 and the
+                                   coefficients were produced (NULL: the legacy default
+                                   stream); the server reads them only after the work
+                                   queued there before sip_batch_submit has run */
 } sip_request;
 
 typedef struct {
@@ -306,23 +325,44 @@ typedef struct {
     int32_t factorised;         /* 1 if this request triggered a factorisation */
 } sip_result;
 
+/* sip_server_create -- start a server on the current HIP device (Sec. 4.1:
+ * the solver module sets up its own memory before the first solve).
+ *   c     configuration (host, read during the call).  hbm_budget_bytes
+ *         bounds the device bytes of resident systems plus running requests.
+ *   out   receives the handle.
+ * Errors: SIP_EINVAL (max_slots outside 1..4096, epoch_iters < 1,
+ * max_queue < 1), SIP_ENOMEM (the server's own buffers), SIP_EDEVICE. */
 sip_status sip_server_create(const sip_server_config *c, sip_server *out);
 
-/* Never blocks.  On success *ticket identifies the request.  The request's
- * device arrays must stay valid until sip_batch_poll reports it done.
+/* sip_batch_submit -- queue one solve (Sec. 4.1: the factorisation of a
+ * system is computed once and reused for every later right-hand side;
+ * requests with the same system_id share it while it stays resident).
+ * Never blocks.  On success *ticket identifies the request.  The request's
+ * device arrays must stay valid until sip_batch_poll reports it done; the
+ * server reads them on its own stream after r->stream's earlier work.  A
+ * resident system that a queued request names is not evicted.
  * Errors: SIP_EINVAL, SIP_EBUSY (queue full), SIP_ENOMEM (the request alone
- * exceeds the HBM budget). */
+ * exceeds the HBM budget), SIP_ECANCELLED (server shut down), SIP_EDEVICE
+ * (the ordering event could not be recorded on r->stream). */
 sip_status sip_batch_submit(sip_server s, const sip_request *r, uint64_t *ticket);
 
-/* Returns SIP_PENDING while the request runs (waits up to wait_ms
- * milliseconds; 0 = do not wait, < 0 = wait until done), else SIP_OK and
- * fills *out (whose status field carries the solve outcome). */
+/* sip_batch_poll -- the result of a request (Sec. 3.2 / 4.1: the residual
+ * norm the solver reports is the global one, here ||b - A x|| / ||b|| of the
+ * returned x).  Returns SIP_PENDING while the request runs (waits up to
+ * wait_ms milliseconds; 0 = do not wait, < 0 = wait until done), else SIP_OK
+ * and fills *out (whose status field carries the solve outcome); x is then
+ * written and visible to every stream.  A ticket can be collected once.
+ * Errors: SIP_EINVAL (NULL, unknown or already collected ticket). */
 sip_status sip_batch_poll(sip_server s, uint64_t ticket, int32_t wait_ms, sip_result *out);
 
-/* Drops a resident system's factors (no effect while requests use it). */
+/* sip_server_release -- drop a resident system's factors (no effect while
+ * requests use it; Sec. 4.1: the module that computed the factorisation in
+ * advance also frees it). */
 sip_status sip_server_release(sip_server s, uint64_t system_id);
 
-/* Server counters (HOST array of SIP_SERVER_NSTATS): factorisations,
+/* sip_server_stats -- counters of the server (Sec. 3: the paper measures
+ * where the solver's time and memory traffic go; these count the work behind
+ * them).  HOST array of SIP_SERVER_NSTATS: factorisations,
  * evictions, epochs, resident bytes, peak bytes, completed, admitted, sweep
  * launches, pairs formed, epochs replayed from a captured graph (an epoch's
  * sweeps are captured once the same launch parameters come up twice in a
@@ -339,7 +379,8 @@ sip_status sip_server_release(sip_server s, uint64_t system_id);
 #define SIP_SERVER_NSTATS 10
 sip_status sip_server_stats(sip_server s, uint64_t out[SIP_SERVER_NSTATS]);
 
-/* sip_server_shutdown -- stops the scheduler: the step in flight finishes,
+/* sip_server_shutdown -- stops the scheduler (Sec. 4.1: the solver module
+ * ends its own work before its memory is released): the step in flight finishes,
  * then every request not yet done completes with status SIP_ECANCELLED (its
  * x is not written) and sip_batch_submit returns SIP_ECANCELLED.  Pollers
  * waiting on such requests wake up; every result stays pollable until
@@ -348,10 +389,13 @@ sip_status sip_server_stats(sip_server s, uint64_t out[SIP_SERVER_NSTATS]);
 sip_status sip_server_shutdown(sip_server s);
 
 /* sip_server_destroy -- shuts the server down (if not yet) and frees it and
- * every resident factorisation.  No other call on s may run concurrently with
- * it or follow it. */
+ * every resident factorisation (Sec. 4.1: the solver module releases the
+ * coefficient and factor memory it allocated).  No other call on s may run
+ * concurrently with it or follow it. */
 sip_status sip_server_destroy(sip_server s);
 
+/* Error reporting of every call above: the name of a status, the calling
+ * thread's detail text of its last error, and the version of this ABI. */
 const char *sip_status_str(sip_status st);
 const char *sip_last_error(void);      /* thread-local detail of the last error */
 int32_t sip_abi_version(void);

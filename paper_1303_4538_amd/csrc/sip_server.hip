@@ -6,8 +6,11 @@
 //   - a request names a system by id; the first request of an id copies and
 //     factorises the coefficients, later requests reuse the resident factors;
 //   - admission is by an HBM budget (resident systems + per-request state);
-//     unreferenced systems are evicted least-recently-used when space is
-//     needed;
+//     when space is needed, resident systems that no running or queued
+//     request names are evicted, least-recently-used first (a system stays
+//     resident after its last request only if a request asked to retain it);
+//   - a request's arrays (coefficients, b, x0) are read on the server's
+//     stream only after an event recorded on the caller's stream at submit;
 //   - all admitted requests advance together: one epoch is `epoch_iters`
 //     iterations, each a batched forward launch and a batched backward launch
 //     whose workgroups take (request, tile) tickets from one merged order;
@@ -93,6 +96,7 @@ struct Req {
     int factorised = 0;
     Pair *pair = nullptr;    // swept together with another request
     int pm = 0;              // which of the pair
+    hipEvent_t ready = nullptr;   // recorded on the caller's stream at submit
 };
 
 size_t slot_bytes(const Geom &g, int fp32, int max_iter)
@@ -124,6 +128,7 @@ struct sip_server_s {
     std::vector<Req *> running;
     std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
     std::unordered_map<uint64_t, std::unique_ptr<Resident>> systems;
+    std::unordered_map<uint64_t, int> queued_ids;   // system id -> queued requests naming it
     size_t used = 0, peak = 0;
     uint64_t clock = 0;
     // factorisations, evictions, epochs, resident, peak, completed, admitted, launches, pairs formed,
@@ -164,6 +169,7 @@ struct sip_server_s {
     void loop();
     bool admit_locked(std::vector<Req *> &admitted, std::vector<Resident *> &to_factor);
     bool make_room_locked(size_t need);
+    void dequeue_locked(Req *q);
     void free_resident_locked(Resident *s);
     void finish_locked(Req *q, sip_status st, int iters, double rho);
     sip_status run_factor(const std::vector<Resident *> &sys, const std::vector<Req *> &owners);
@@ -201,13 +207,23 @@ void sip_server_s::free_resident_locked(Resident *s)
     systems.erase(s->id);
 }
 
+void sip_server_s::dequeue_locked(Req *q)
+{
+    auto f = queued_ids.find(q->r.system_id);
+    if (f != queued_ids.end() && --f->second == 0) queued_ids.erase(f);
+}
+
+// Evicts unreferenced systems, least-recently-used first, until `need` more
+// bytes fit.  A system that a queued request names is kept: that request may
+// carry no coefficients and could not be served once its factors are gone.
 bool sip_server_s::make_room_locked(size_t need)
 {
     while (used + need > cfg.hbm_budget_bytes) {
         Resident *victim = nullptr;
         for (auto &kv : systems) {
             Resident *s = kv.second.get();
-            if (s->refs == 0 && (!victim || s->last_use < victim->last_use)) victim = s;
+            if (s->refs != 0 || queued_ids.count(s->id)) continue;
+            if (!victim || s->last_use < victim->last_use) victim = s;
         }
         if (!victim) return false;
         free_resident_locked(victim);
@@ -243,7 +259,8 @@ bool sip_server_s::admit_locked(std::vector<Req *> &admitted, std::vector<Reside
             for (int d = 0; d < 7; d++) ok = ok && pb.a[d] != nullptr;
             if (!ok) {   // a request that must factorise needs its coefficients
                 finish_locked(q, SIP_EINVAL, 0, 0.0);
-                it = queue.erase(it);
+                dequeue_locked(q);
+            it = queue.erase(it);
                 continue;
             }
             auto rs = std::make_unique<Resident>();
@@ -259,7 +276,8 @@ bool sip_server_s::admit_locked(std::vector<Req *> &admitted, std::vector<Reside
                 dev_free(rs->A, stream);
                 dev_free(rs->LU, stream);
                 finish_locked(q, SIP_ENOMEM, 0, 0.0);
-                it = queue.erase(it);
+                dequeue_locked(q);
+            it = queue.erase(it);
                 continue;
             }
             used += need_sys;
@@ -290,6 +308,7 @@ bool sip_server_s::admit_locked(std::vector<Req *> &admitted, std::vector<Reside
             q->hist = nullptr;
             s->refs--;
             finish_locked(q, SIP_ENOMEM, 0, 0.0);
+            dequeue_locked(q);
             it = queue.erase(it);
             continue;
         }
@@ -302,6 +321,7 @@ bool sip_server_s::admit_locked(std::vector<Req *> &admitted, std::vector<Reside
         q->t_admit = now();
         admitted.push_back(q);
         stats[6]++;
+        dequeue_locked(q);
         it = queue.erase(it);
         any = true;
     }
@@ -330,6 +350,10 @@ void sip_server_s::finish_locked(Req *q, sip_status st, int iters, double rho)
     q->face = nullptr;
     q->part = nullptr;
     q->hist = nullptr;
+    if (q->ready) {   // the server stream's wait on it, if any, is already enqueued
+        (void)hipEventDestroy(q->ready);
+        q->ready = nullptr;
+    }
     if (Pair *p = q->pair) {
         // the pair's buffers stand for both members' budget bytes: they are
         // released when the second member is done
@@ -687,6 +711,10 @@ void sip_server_s::loop()
             if (quit) break;
             admit_locked(admitted, to_factor);
         }
+        // the coefficients, b and x0 were produced on the caller's stream:
+        // everything below that reads them runs after that stream's work
+        for (Req *q : admitted)
+            if (q->ready) (void)hipStreamWaitEvent(stream, q->ready, 0);
         // factorise new systems (owners = the admitted request that brought each in)
         if (!to_factor.empty()) {
             std::vector<Req *> owners;
@@ -790,6 +818,7 @@ void sip_server_s::loop()
     std::lock_guard<std::mutex> lk(mu);
     for (Req *q : queue) finish_locked(q, SIP_ECANCELLED, 0, 0.0);
     queue.clear();
+    queued_ids.clear();
     for (Req *q : running) finish_locked(q, SIP_ECANCELLED, 0, 0.0);
     running.clear();
 }
@@ -864,6 +893,19 @@ sip_status sip_batch_submit(sip_server s, const sip_request *r, uint64_t *ticket
     if (!r->b || !r->x) return set_error(SIP_EINVAL, "b and x are required");
     if (!(r->rtol > 0.0) || r->max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
     const sip_problem &p = r->problem;
+    // orders the server's reads of the request's arrays after the caller's
+    // work on its stream (the event is destroyed when the request finishes)
+    hipEvent_t ready = nullptr;
+    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ready, (hipStream_t)r->stream) != hipSuccess) {
+        if (ready) (void)hipEventDestroy(ready);
+        (void)hipGetLastError();
+        return set_error(SIP_EDEVICE, "could not record the ordering event on the caller's stream");
+    }
+    struct EventGuard {   // destroys the event unless the request takes it
+        hipEvent_t e;
+        ~EventGuard() { if (e) (void)hipEventDestroy(e); }
+    } guard{ready};
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->quit) return set_error(SIP_ECANCELLED, "the server is shut down");
     auto f = s->systems.find(r->system_id);
@@ -894,7 +936,10 @@ sip_status sip_batch_submit(sip_server s, const sip_request *r, uint64_t *ticket
     q->ticket = s->next_ticket++;
     q->r = *r;
     q->t_submit = s->now();
+    q->ready = ready;
+    guard.e = nullptr;
     *ticket = q->ticket;
+    s->queued_ids[r->system_id]++;
     s->queue.push_back(q.get());
     s->reqs[q->ticket] = std::move(q);
     s->cv_work.notify_one();

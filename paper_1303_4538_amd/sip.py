@@ -63,7 +63,7 @@ class ServerConfig(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("system_id", ctypes.c_uint64), ("problem", Problem), ("b", ctypes.c_void_p),
                 ("x", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("rtol", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("retain", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("retain", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -378,8 +378,10 @@ class Server:
         self._keep = {}
 
     def submit(self, system_id, A, b, x, alpha=0.92, precision="mixed", rtol=1e-8, max_iter=100000,
-               x0=None, retain=False, storage="full"):
-        """Submit a solve; returns a ticket.  A may be None when the system is resident."""
+               x0=None, retain=False, storage="full", stream=None):
+        """Submit a solve; returns a ticket.  A may be None when the system is
+        resident.  The server reads A, b and x0 after the work queued on
+        `stream` (default: torch's current stream) before this call."""
         r = Request()
         r.system_id = int(system_id)
         if A is not None:
@@ -395,6 +397,7 @@ class Server:
         r.rtol = float(rtol)
         r.max_iter = int(max_iter)
         r.retain = 1 if retain else 0
+        r.stream = _stream(stream).value
         t = ctypes.c_uint64()
         _check(lib().sip_batch_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
         self._keep[t.value] = (A, b, x, x0)     # device arrays must outlive the request

@@ -55,6 +55,9 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(sip.Info) == 24
     # sip_block_problem: sip_problem, 3 int32 (+pad), 3 pointers
     assert ctypes.sizeof(sip.BlockProblem) == ctypes.sizeof(sip.Problem) + 12 + 4 + 24
+    # sip_request: id, sip_problem, b, x, x0, rtol, max_iter, retain, stream
+    assert ctypes.sizeof(sip.Request) == 8 + ctypes.sizeof(sip.Problem) + 24 + 8 + 8 + 8
+    assert sip.Request.stream.offset == ctypes.sizeof(sip.Request) - 8
 
 
 def test_host_side_argument_checks(libpath):

@@ -11,6 +11,9 @@ benchmark times.
 * 256^3 with the all-FP32 relaxation, a pair of right-hand sides and the
   domain cut into 2^3 blocks: first iterates against the oracle (all-FP32,
   multi-block) or against the solo solves (pair, bitwise).
+* 256^3 convection-diffusion, mixed: the first iterates elementwise against
+  the mixed-form oracle (2 x the CPU-pinned bound), and the 2^3-block domain's
+  mixed iterates against the multi-block oracle.
 * The largest block the layout takes at a 1024^2 cross-section
   (1024 x 1024 x 239): FP64 factors and iterates against the oracle.
 """
@@ -168,3 +171,36 @@ def test_config2_blocks(sip, cube):
     xo, _, _, ho = oracle.blocks(A, cube["alpha"], b, np.zeros_like(b), cuts, 2)
     assert np.abs(xt.cpu().numpy() - xo).max() <= 1e-12 * np.abs(xo).max()
     assert np.abs(hg - ho).max() <= 1e-12
+
+
+def test_config2_mixed_iterates(sip, cube):
+    """Mixed iterates at the benchmark's size, in its launch configuration
+    (single system, default plan): x_1..x_3 elementwise against the mixed
+    oracle within 4e-6 max|x_n| (twice the pinned bound)."""
+    from tests.mixed_check import mixed_iterates_agree
+    A, b, alpha = cube["A"], cube["b"], cube["alpha"]
+    log("256^3 mixed: factor, 3 single iterations against the mixed oracle")
+    S = sip.sip_factor(dev(A), alpha, "mixed")
+    LU = oracle.factor(A, alpha)
+    worst = mixed_iterates_agree(sip, S, A, LU, b, 3, log_every=True)
+    S.close()
+    log(f"  worst {worst:.2e}")
+
+
+def test_config2_blocks_mixed_iterates(sip, cube):
+    """The 256^3 domain in 2^3 blocks, mixed: x_1, x_2 elementwise against the
+    multi-block mixed oracle (same 4e-6 bar)."""
+    A, b, alpha = cube["A"], cube["b"], cube["alpha"]
+    cuts = ([0, 128, 256], [0, 128, 256], [0, 128, 256])
+    log("256^3 in 2^3 blocks, mixed: 2 iterations against the multi-block mixed oracle")
+    D = sip.sip_blocks_factor(dev(A), cuts, alpha, "mixed")
+    bt = dev(b)
+    xt = torch.zeros_like(bt)
+    xo = np.zeros_like(b)
+    for n in (1, 2):
+        D.iterate(bt, xt, 1)
+        xo = oracle.blocks(A, alpha, b, xo, cuts, 1, mixed=True)[0]
+        err = float(np.abs(xt.cpu().numpy() - xo).max() / np.abs(xo).max())
+        log(f"  x_{n}: max rel diff {err:.2e}")
+        assert err <= 4e-6
+    D.close()

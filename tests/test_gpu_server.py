@@ -129,6 +129,63 @@ def test_budget_forces_eviction_and_waiting(sip):
         assert np.array_equal(xt[q].cpu().numpy(), xa)
 
 
+def test_queued_request_keeps_its_resident_system(sip):
+    """A request naming a resident system without coefficients keeps that
+    system from eviction while it waits: here a new system queued ahead of it
+    needs the room, is held back, and is admitted (evicting the first system)
+    once that request is done."""
+    (A, b), (A2, b2) = block((24, 20, 18), "cd", 301), block((24, 20, 18), "poisson", 302)
+    Ar, br = block((12, 10, 9), "cd", 303)
+    At, bt, A2t, b2t, Art, brt = dev(A), dev(b), dev(A2), dev(b2), dev(Ar), dev(br)
+    probe = sip.Server(max_slots=4, epoch_iters=4)
+    probe.poll(probe.submit(1, At, bt, torch.zeros_like(bt), retain=True))
+    sys_and_slot = probe.stats()["peak_bytes"]
+    probe.close()
+    srv = sip.Server(hbm_budget_bytes=int(sys_and_slot * 1.5), max_slots=1, epoch_iters=4)
+    x1 = torch.zeros_like(bt)
+    assert srv.poll(srv.submit(7, At, bt, x1, retain=True))["status"] == sip.SIP_OK
+    # a long request takes the only slot while the next two queue behind it
+    tr = srv.submit(9, Art, brt, torch.zeros_like(brt), rtol=1e-300, max_iter=20000)
+    x2, x3 = torch.zeros_like(b2t), torch.zeros_like(bt)
+    t2 = srv.submit(8, A2t, b2t, x2)              # new system: needs the room system 7 holds
+    t3 = srv.submit(7, None, bt, x3)              # resident system 7, no coefficients
+    assert srv.poll(tr)["status"] == sip.SIP_ENOTCONV
+    r3, r2 = srv.poll(t3), srv.poll(t2)
+    st = srv.stats()
+    srv.close()
+    assert r3["status"] == sip.SIP_OK and r3["factorised"] == 0
+    assert r2["status"] == sip.SIP_OK and r2["factorised"] == 1
+    assert r2["t_admit"] >= r3["t_done"] - 1e-3
+    assert st["evictions"] >= 1 and st["factorisations"] == 3
+    assert torch.equal(x3, x1)
+    xa, _, _ = alone(sip, A2, b2, "mixed")
+    assert np.array_equal(x2.cpu().numpy(), xa)
+
+
+def test_server_reads_inputs_after_the_callers_stream(sip):
+    """b is written on a side stream behind a long queue of work just before
+    submit; the server, told that stream, reads the new b (with no ordering it
+    would see the zeros still there and return x = 0)."""
+    A, b = block((20, 18, 16), "cd", 305)
+    At, bsrc = dev(A), dev(b)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bt = torch.zeros_like(bsrc)
+        m = torch.ones((4096, 4096), dtype=torch.float32, device="cuda") / 4096
+        for _ in range(40):
+            m = m @ m
+        bt.copy_(bsrc)
+    xt = torch.zeros_like(bsrc)
+    srv = sip.Server(max_slots=4, epoch_iters=4)
+    r = srv.poll(srv.submit(3, At, bt, xt, stream=side))
+    srv.close()
+    torch.cuda.synchronize()
+    assert r["status"] == sip.SIP_OK and r["iters"] > 0
+    xa, ita, _ = alone(sip, A, b, "mixed")
+    assert r["iters"] == ita and np.array_equal(xt.cpu().numpy(), xa)
+
+
 def test_breakdown_and_bad_requests(sip):
     A, b = block((10, 9, 8), "poisson", 3)
     A[0, 0, 0, 0] = 0.0
