@@ -13,6 +13,14 @@ inputs resident in HBM before the timed region.  The line also reports the
 same solve in plain FP64, the forward-sweep kernel's achieved bandwidth
 against the HBM peak (timed with HIP events on the launch stream) and the CPU
 oracle on a bounded sample of the same workload.
+
+With the default 256^3 workload the line also carries, under "configs", the
+other configurations at their full sizes, each with its throughput, the
+error of the mixed result against the FP64 result, a roofline and the oracle
+on a bounded sample: the 64 uneven blocks through one solve server, the
+512 x 512 x 256 stretched-grid Poisson block, and the serving stream of 250
+systems x 8 right-hand sides at 200 arrivals per second (--no-configs skips
+them).
 """
 import argparse
 import json
@@ -36,6 +44,7 @@ FP32_RTOL = 1e-5           # the all-FP32 relaxation stalls near 1e-7
 PAIR_FWD_BYTES = 56 + 16 + 2 * (8 + 8 + 4)     # per cell, both right-hand sides
 PAIR_BWD_BYTES = 12 + 2 * (4 + 8 + 8)
 RTOL = 1e-8
+SOLVE_BYTES_MIXED = FWD_BYTES["mixed"] + BWD_BYTES["mixed"]   # one mixed iteration, both sweeps
 # HBM bytes per launch of the sweep kernels on the 256^3 workload, from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes summarised in
 # profiles/sweeps_256cube_cd.md (calibrated against a plain copy), with
@@ -43,6 +52,11 @@ RTOL = 1e-8
 # differs the counters no longer describe the kernel and traffic is null.
 MEASURED = {"kernels_sha256": "aec6a72e026d29a1beea76be21d99d20bb837992ca147327ccbfec1cc984a94f",
             "n": 256, "fwd_bytes": 1766797262, "bwd_bytes": 602316320}
+
+
+def log(msg):
+    """Progress of the phases on stderr (the JSON line goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def copy_gbps():
@@ -99,6 +113,9 @@ def parse():
     ap.add_argument("--profile-iters", type=int, default=40)
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--cpu-iters-batched", type=int, default=3, help="oracle iterations per block (batched)")
+    ap.add_argument("--cpu-iters-large", type=int, default=2, help="oracle iterations of the 512x512x256 block")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="default line without the batched, large and serving configurations")
     ap.add_argument("--storage", default="full", choices=["full", "symmetric"],
                     help="coefficient storage of the sweeps (symmetric: Poisson workloads only)")
     ap.add_argument("--workload", default="single",
@@ -235,7 +252,7 @@ def batched_run(args):
                    "all_ok": all(r["status"] == 0 for r in res), "epochs": st["epochs"],
                    "graph_epochs": st["graph_epochs"], "launches": st["launches"],
                    "hbm_gbps_algorithmic": value * (FWD_BYTES["mixed"] + BWD_BYTES["mixed"]) / 1e9, **extra},
-        "roofline": None, "cpu_baseline": cpu,
+        "roofline": solve_roofline(value), "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
@@ -278,84 +295,293 @@ def batched_cpu_baseline(meta, n):
             "host_cpu": host_cpu(), "host_cpus": os.cpu_count()}
 
 
-def serving_run(args):
-    """Poisson-arrival stream of solves against one continuous-batching server:
+def serve_stream(sip, n_systems, rate, budget_gb, epoch_iters, keep=False):
+    """One Poisson-arrival stream against a fresh continuous-batching server:
     each system (lognormal dims 24..192 per axis, half Poisson / half
     convection-diffusion) receives 8 right-hand sides; requests are shuffled
     and submitted at their arrival times; factors stay resident across a
-    system's requests.  Reports latency percentiles beside throughput, the
-    offered load (arrival rate over the served rate), and as context the same
-    stream at lower arrival rates."""
+    system's requests.  Returns the latency and throughput figures (and, with
+    keep, the systems, requests, coefficients, right-hand sides and results)."""
     import numpy as np
     import torch
 
-    from paper_1303_4538_amd import problems, sip
+    from paper_1303_4538_amd import problems
+
+    systems, reqs = problems.serving_stream(n_systems=n_systems, rhs_per_system=8, rate_hz=rate)
+    As = [torch.from_numpy(problems.system_coefficients(dims, kind, ss)).cuda() for dims, kind, ss in systems]
+    bs = [torch.from_numpy(problems.request_rhs(systems[s][0], rs)).cuda() for _, s, _, rs in reqs]
+    xs = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    srv = sip.Server(hbm_budget_bytes=int(budget_gb * (1 << 30)), max_slots=512, epoch_iters=epoch_iters)
+    t0 = time.perf_counter()
+    tickets = []
+    for q, (ta, s, m, _) in enumerate(reqs):
+        wait = t0 + ta - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(srv.submit(s, As[s], bs[q], xs[q], precision="mixed", rtol=RTOL, max_iter=200000,
+                                  retain=True))
+    res = [srv.poll(t) for t in tickets]
+    t1 = time.perf_counter()
+    st = srv.stats()
+    srv.close()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    run = np.array([r["t_done"] - r["t_admit"] for r in res])
+    cells = np.array([np.prod(systems[s][0]) for _, s, _, _ in reqs])
+    iters = np.array([r["iters"] for r in res])
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    out = dict(n=len(reqs), ci=float((cells * iters).sum()), span=span, wall=t1 - t0,
+               solves_per_s=len(res) / span,
+               latency_p50_ms=float(np.percentile(lat, 50) * 1e3),
+               latency_p99_ms=float(np.percentile(lat, 99) * 1e3),
+               run_p50_ms=float(np.percentile(run, 50) * 1e3), run_p99_ms=float(np.percentile(run, 99) * 1e3),
+               all_ok=all(r["status"] == 0 for r in res), st=st,
+               mean_cells=float(cells.mean()), mean_iters=float(iters.mean()))
+    if keep:
+        out.update(systems=systems, reqs=reqs, As=As, bs=bs, xs=xs, res=res)
+    return out
+
+
+def serving_run(args):
+    """The serving stream (--serve-systems systems x 8 right-hand sides at
+    --serve-rate arrivals per second) against one server: latency
+    percentiles beside throughput, the offered load (arrival rate over the
+    served rate), and as context the same stream at lower arrival rates."""
+    from paper_1303_4538_amd import sip
 
     sip.lib()
-
-    def serve(rate):
-        systems, reqs = problems.serving_stream(n_systems=args.serve_systems, rhs_per_system=8, rate_hz=rate)
-        As = [torch.from_numpy(problems.system_coefficients(dims, kind, ss)).cuda() for dims, kind, ss in systems]
-        bs = [torch.from_numpy(problems.request_rhs(systems[s][0], rs)).cuda() for _, s, _, rs in reqs]
-        xs = [torch.zeros_like(b) for b in bs]
-        torch.cuda.synchronize()
-        srv = sip.Server(hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_slots=512,
-                         epoch_iters=args.epoch_iters)
-        t0 = time.perf_counter()
-        tickets = []
-        for q, (ta, s, m, _) in enumerate(reqs):
-            wait = t0 + ta - time.perf_counter()
-            if wait > 0:
-                time.sleep(wait)
-            tickets.append(srv.submit(s, As[s], bs[q], xs[q], precision="mixed", rtol=RTOL, max_iter=200000,
-                                      retain=True))
-        res = [srv.poll(t) for t in tickets]
-        t1 = time.perf_counter()
-        st = srv.stats()
-        srv.close()
-        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
-        run = np.array([r["t_done"] - r["t_admit"] for r in res])
-        cells = np.array([np.prod(systems[s][0]) for _, s, _, _ in reqs])
-        iters = np.array([r["iters"] for r in res])
-        span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
-        return dict(n=len(reqs), ci=float((cells * iters).sum()), span=span, wall=t1 - t0,
-                    solves_per_s=len(res) / span,
-                    latency_p50_ms=float(np.percentile(lat, 50) * 1e3),
-                    latency_p99_ms=float(np.percentile(lat, 99) * 1e3),
-                    run_p50_ms=float(np.percentile(run, 50) * 1e3), run_p99_ms=float(np.percentile(run, 99) * 1e3),
-                    all_ok=all(r["status"] == 0 for r in res), st=st,
-                    mean_cells=float(cells.mean()), mean_iters=float(iters.mean()))
-
-    m = serve(args.serve_rate)
+    m = serve_stream(sip, args.serve_systems, args.serve_rate, args.serve_budget_gb, args.epoch_iters)
     st = m["st"]
     sweep = []
     if not args.no_extras:
         for rate in (args.serve_rate / 8, args.serve_rate / 4, args.serve_rate / 2):
-            r = serve(rate)
+            r = serve_stream(sip, args.serve_systems, rate, args.serve_budget_gb, args.epoch_iters)
             sweep.append({"offered_per_s": rate, "solves_per_s": r["solves_per_s"],
                           "latency_p50_ms": r["latency_p50_ms"], "latency_p99_ms": r["latency_p99_ms"],
                           "cell_iters_per_s": r["ci"] / r["span"], "all_ok": r["all_ok"]})
+    value = m["ci"] / m["span"]
     line = {
         "metric": "served solves: cell-iterations/s and latency (mixed SIP to 1e-8)",
-        "value": m["ci"] / m["span"], "unit": "cell-iterations/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "value": value, "unit": "cell-iterations/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": m["wall"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{m['n']} requests ({args.serve_systems} systems x 8 rhs), Poisson arrivals "
                                f"{args.serve_rate:g}/s, lognormal dims 24..192, half Poisson / half CD, "
                                f"HBM budget {args.serve_budget_gb:g} GB",
-                   "solves_per_s": m["solves_per_s"],
-                   "offered_per_s": args.serve_rate,
-                   "offered_load": args.serve_rate / m["solves_per_s"],
-                   "latency_p50_ms": m["latency_p50_ms"], "latency_p99_ms": m["latency_p99_ms"],
-                   "run_p50_ms": m["run_p50_ms"], "run_p99_ms": m["run_p99_ms"],
-                   "all_ok": m["all_ok"],
-                   "factorisations": st["factorisations"], "evictions": st["evictions"],
-                   "epochs": st["epochs"], "graph_epochs": st["graph_epochs"], "peak_bytes": st["peak_bytes"],
-                   "mean_cells": m["mean_cells"], "mean_iters": m["mean_iters"],
-                   "rate_sweep": sweep},
-        "roofline": None, "cpu_baseline": None,
+                   **_serving_fields(m, args.serve_rate), "rate_sweep": sweep},
+        "roofline": solve_roofline(value), "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
+
+
+def _serving_fields(m, rate):
+    st = m["st"]
+    return {"solves_per_s": m["solves_per_s"], "offered_per_s": rate, "offered_load": rate / m["solves_per_s"],
+            "latency_p50_ms": m["latency_p50_ms"], "latency_p99_ms": m["latency_p99_ms"],
+            "run_p50_ms": m["run_p50_ms"], "run_p99_ms": m["run_p99_ms"], "all_ok": m["all_ok"],
+            "factorisations": st["factorisations"], "evictions": st["evictions"], "epochs": st["epochs"],
+            "graph_epochs": st["graph_epochs"], "peak_bytes": st["peak_bytes"],
+            "mean_cells": m["mean_cells"], "mean_iters": m["mean_iters"]}
+
+
+def solve_roofline(rate):
+    """Whole-solve bandwidth of a batched or served run: cell-iterations/s times
+    the algorithmic bytes of one mixed iteration (forward + backward sweep), as
+    a fraction of the HBM peak.  It averages over every launch of the run
+    (factorisations, layout copies and idle gaps included), so it bounds the
+    sweeps' own fraction from below."""
+    achieved = rate * SOLVE_BYTES_MIXED / 1e9
+    return {"bound": "hbm", "kernel": "whole solve: k_forward + k_backward over all active blocks (mixed)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+            "basis": f"cell-iterations/s x {SOLVE_BYTES_MIXED} algorithmic B per mixed cell-iteration"}
+
+
+def rel_err(xm, x64):
+    """max |x_mixed - x_fp64| / max |x_fp64| (on the device)."""
+    s = float(x64.abs().max())
+    return float((xm - x64).abs().max()) / s if s > 0 else 0.0
+
+
+def run_batch(sip, blocks, precision, epoch_iters, tag):
+    """All blocks submitted at once to a fresh solve server (factor + solve
+    to RTOL); returns wall time, cell-iterations, results, stats, solutions."""
+    import torch
+    srv = sip.Server(max_slots=256, epoch_iters=epoch_iters)
+    xs = [torch.zeros_like(b) for _, _, b in blocks]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = [srv.submit(tag * 1000 + q, A, b, xs[q], precision=precision, rtol=RTOL, max_iter=200000)
+               for q, (_, A, b) in enumerate(blocks)]
+    res = [srv.poll(t) for t in tickets]
+    t1 = time.perf_counter()
+    st = srv.stats()
+    srv.close()
+    ci = sum(dims[0] * dims[1] * dims[2] * r["iters"] for (dims, _, _), r in zip(blocks, res))
+    return t1 - t0, ci, res, st, xs
+
+
+def config3_summary(args, sip):
+    """64 uneven blocks (dims uniform 32..160 per axis, half Poisson, half
+    convection-diffusion) through one solve server: one mixed and one FP64
+    run, the mixed result's error against the FP64 result per block, the
+    whole-solve roofline and the oracle on all host cores."""
+    import torch
+
+    from paper_1303_4538_amd import problems
+    meta = problems.config3_meta()
+    blocks = []
+    for dims, kind, ss in meta:
+        A, b = problems.make_block(dims, kind, ss)
+        blocks.append((dims, torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda()))
+    log("64 uneven blocks through the solve server: mixed, FP64")
+    run_batch(sip, blocks, "mixed", args.epoch_iters, 1)   # warm-up
+    dt, ci, res, st, xs = run_batch(sip, blocks, "mixed", args.epoch_iters, 2)
+    dt64, ci64, res64, _, xs64 = run_batch(sip, blocks, "fp64", args.epoch_iters, 3)
+    errs = [rel_err(x, y) for x, y in zip(xs, xs64)]
+    value = ci / dt
+    out = {"workload": "64 blocks, dims uniform 32..160 per axis, half Poisson / half upwind convection-diffusion, "
+                       "one solve server, factor + mixed solve to 1e-8",
+           "cells": sum(d[0] * d[1] * d[2] for d, _, _ in blocks), "value": value, "unit": "cell-iterations/s",
+           "seconds": dt, "max_iters": max(r["iters"] for r in res), "max_rel_res": max(r["rel_res"] for r in res),
+           "all_ok": all(r["status"] == 0 for r in res) and all(r["status"] == 0 for r in res64),
+           "epochs": st["epochs"], "fp64_cell_iters_per_s": ci64 / dt64, "mixed_speedup_vs_fp64": value / (ci64 / dt64),
+           "err_vs_fp64_max": max(errs), "err_vs_fp64_median": sorted(errs)[len(errs) // 2],
+           "roofline": solve_roofline(value)}
+    if not args.no_cpu:
+        log("64 uneven blocks: oracle sample on the host cores")
+        out["cpu_baseline"] = batched_cpu_baseline(meta, args.cpu_iters_batched)
+    del blocks, xs, xs64
+    torch.cuda.empty_cache()
+    return out
+
+
+def config4_summary(args, sip):
+    """512 x 512 x 256 stretched-grid Poisson (67 M cells): factor + mixed solve
+    to 1e-8 and the same in FP64, the mixed result's error against the FP64
+    result, the forward sweep's roofline (HIP events on the launch stream) and
+    the oracle on one host core (first iterations)."""
+    import numpy as np
+    import torch
+
+    from paper_1303_4538_amd import problems
+    c = problems.config4()
+    cells = 512 * 512 * 256
+    A = torch.from_numpy(c["A"]).cuda()
+    b = torch.from_numpy(c["b"]).cuda()
+    xs, its, secs = {}, {}, {}
+    for precision in ("mixed", "fp64"):
+        log(f"512x512x256: {precision} solve")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S = sip.sip_factor(A, c["alpha"], precision)
+        x = torch.zeros_like(b)
+        _, it, rr, _ = sip.sip_solve(S, b, x, RTOL, 200000)
+        torch.cuda.synchronize()
+        secs[precision] = time.perf_counter() - t0
+        if precision == "mixed":
+            fwd_ms, bwd_ms = sip.sip_profile_sweeps(S, b, torch.zeros_like(b), args.profile_iters)
+            rr_mixed = rr
+        S.close()
+        xs[precision], its[precision] = x, it
+    value = cells * its["mixed"] / secs["mixed"]
+    achieved = FWD_BYTES["mixed"] * cells / (fwd_ms * 1e-3) / 1e9
+    out = {"workload": "512x512x256 stretched-grid Poisson (z ratio 1.05), alpha 0.92, factor + mixed solve to 1e-8",
+           "cells": cells, "value": value, "unit": "cell-iterations/s", "seconds": secs["mixed"],
+           "iterations": its["mixed"], "final_rel_res": rr_mixed, "fp64_iterations": its["fp64"],
+           "fp64_cell_iters_per_s": cells * its["fp64"] / secs["fp64"],
+           "mixed_speedup_vs_fp64": secs["fp64"] / secs["mixed"] * its["mixed"] / its["fp64"],
+           "err_vs_fp64": rel_err(xs["mixed"], xs["fp64"]),
+           "roofline": {"bound": "hbm", "kernel": "k_forward<float, double, 3, 1> (FP64 residual + FP32 forward sweep)",
+                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                        "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+                        "bwd_gbps": round(BWD_BYTES["mixed"] * cells / (bwd_ms * 1e-3) / 1e9, 1)}}
+    del A, b, xs
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        import oracle
+        oracle.build(force=False)
+        log("512x512x256: oracle sample")
+        LU = oracle.factor(c["A"], c["alpha"])
+        t = time.perf_counter()
+        oracle.iterate(c["A"], LU, c["b"], np.zeros_like(c["b"]), args.cpu_iters_large, mixed=True)
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": cells * args.cpu_iters_large / dt, "unit": "cell-iterations/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"first {args.cpu_iters_large} mixed-form SIP iterations of the 512x512x256 "
+                                         "block, single-threaded C oracle, factorisation untimed"}
+        del LU
+    return out
+
+
+def _oracle_stream_sample(job):
+    """One served system on one host core: factorisation (untimed), then n
+    mixed-form oracle iterations (timed) on one of its right-hand sides."""
+    dims, kind, ss, rs, n = job
+    import numpy as np
+
+    import oracle
+    from paper_1303_4538_amd import problems
+    A = problems.system_coefficients(dims, kind, ss)
+    b = problems.request_rhs(dims, rs)
+    LU = oracle.factor(A, problems.ALPHA)
+    t = time.perf_counter()
+    oracle.iterate(A, LU, b, np.zeros_like(b), n, mixed=True)
+    return dims[0] * dims[1] * dims[2] * n, time.perf_counter() - t
+
+
+def config5_summary(args, sip):
+    """The serving stream at its full size (250 systems x 8 right-hand sides,
+    Poisson arrivals at 200/s): latency percentiles and throughput, the
+    whole-solve roofline, the mixed results' error against FP64 solves of a 5 %
+    sample of the requests, and the oracle on a 5 % sample of the systems over
+    all host cores."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import torch
+    log("serving stream 250 x 8 at %g/s" % args.serve_rate)
+    m = serve_stream(sip, 250, args.serve_rate, args.serve_budget_gb, args.epoch_iters, keep=True)
+    log("serving: FP64 solves of a 5 % sample")
+    value = m["ci"] / m["span"]
+    errs = []
+    for q in range(0, m["n"], 20):
+        _, s, _, _ = m["reqs"][q]
+        S = sip.sip_factor(m["As"][s], 0.92, "fp64")
+        x64 = torch.zeros_like(m["bs"][q])
+        sip.sip_solve(S, m["bs"][q], x64, RTOL, 200000)
+        S.close()
+        errs.append(rel_err(m["xs"][q], x64))
+    out = {"workload": f"{m['n']} requests (250 systems x 8 rhs), Poisson arrivals {args.serve_rate:g}/s, lognormal "
+                       f"dims 24..192, half Poisson / half CD, HBM budget {args.serve_budget_gb:g} GB",
+           "value": value, "unit": "cell-iterations/s", "seconds": m["wall"], **_serving_fields(m, args.serve_rate),
+           "max_rel_res": max(r["rel_res"] for r in m["res"]),
+           "err_vs_fp64_max": max(errs), "err_vs_fp64_median": sorted(errs)[len(errs) // 2],
+           "err_vs_fp64_sample": f"every 20th request ({len(errs)} of {m['n']}), FP64 factor + solve to 1e-8",
+           "roofline": solve_roofline(value)}
+    sample = [m["systems"][s] for s in range(0, len(m["systems"]), 20)]
+    first_rhs = {}
+    for _, s, _, rs in m["reqs"]:
+        first_rhs.setdefault(s, rs)
+    del m
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        import oracle
+        oracle.build(force=False)
+        log("serving: oracle sample on the host cores")
+        procs = max(1, min(16, os.cpu_count() or 1))
+        systems = [(d, k, ss, first_rhs[20 * i], args.cpu_iters_batched) for i, (d, k, ss) in enumerate(sample)]
+        with ProcessPoolExecutor(procs, mp_context=mp.get_context("spawn")) as pool:
+            res = list(pool.map(_oracle_stream_sample, systems))
+        ci = sum(c for c, _ in res)
+        busy = sum(t for _, t in res)
+        out["cpu_baseline"] = {"value": ci / (busy / procs), "unit": "cell-iterations/s", "cores": procs,
+                               "kind": "oracle",
+                               "sample": f"every 20th system ({len(systems)} of 250), {args.cpu_iters_batched} "
+                                         f"mixed-form SIP iterations each on its first right-hand side, one "
+                                         f"process per system on {procs} cores, factorisation untimed"}
+    return out
 
 
 def fp32_comparison(sip, A, b, alpha, cells):
@@ -593,13 +819,17 @@ def main():
     b = torch.from_numpy(c["b"]).to(dev)
     torch.cuda.synchronize()
 
+    xkeep = {}
+
     def step(precision):
         S = sip.sip_factor(A, c["alpha"], precision, storage=args.storage)
         x = torch.zeros_like(b)
         st, it, rr, _ = sip.sip_solve(S, b, x, RTOL, 200000)
         S.close()
+        xkeep[precision] = x
         return it, rr
 
+    log(f"{label}: {args.warmup} warm-up and {args.steps} timed steps")
     for _ in range(args.warmup):
         step("mixed")
     torch.cuda.synchronize()
@@ -613,6 +843,7 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
 
     extra = {}
+    log("timed steps done; FP64, all-FP32, pair and block comparisons")
     if not args.no_fp64:
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -623,6 +854,7 @@ def main():
         extra["fp64_cell_iters_per_s"] = cells * it64 / (t3 - t2)
         extra["fp64_ms_per_solve"] = (t3 - t2) * 1e3
         extra["mixed_speedup_vs_fp64"] = (t3 - t2) / (elapsed / args.steps)
+        extra["err_vs_fp64"] = rel_err(xkeep["mixed"], xkeep["fp64"])
     if not args.no_fp32 and args.storage == "full":
         extra["fp32_relaxation"] = fp32_comparison(sip, A, b, c["alpha"], cells)
     if not args.no_extras and args.storage == "full" and args.workload == "single":
@@ -666,6 +898,14 @@ def main():
                          f"(FP64 residual, FP32 sweeps), single-threaded C oracle, factorisation untimed",
                "host_cpu": host_cpu(), "host_cpus": os.cpu_count()}
 
+    configs = None
+    if not args.no_configs and args.workload == "single" and args.storage == "full" and args.n == 256:
+        del A, b, xkeep
+        torch.cuda.empty_cache()
+        configs = {"batched_64_blocks": config3_summary(args, sip),
+                   "large_512x512x256": config4_summary(args, sip),
+                   "serving_250x8_at_200_per_s": config5_summary(args, sip)}
+
     mean_it = sum(iters) / len(iters)
     line = {
         "metric": "cell-iterations/s (mixed SIP to 1e-8 rel. residual)",
@@ -692,6 +932,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if configs is not None:
+        line["configs"] = configs
     print(json.dumps(line), flush=True)
 
 

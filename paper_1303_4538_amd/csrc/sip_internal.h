@@ -161,6 +161,39 @@ struct LaunchArgs {
     uint32_t jitter;           // 0, or a seed: race testing pauses waves at random steps
 };
 
+// Persistent batched sweeps (k_persist): one launch in which every job runs
+// its own sequence of sweeps (forward, backward, forward, ...) on its own
+// control block, and leaves when it stops or when the host asks for a pause.
+// Workgroups loop over a queue of tile tasks: ticket t lives in slot t % cap
+// and is valid once seq == t + 1; a consumer frees the slot (seq = 0).  The
+// workgroup that finishes a job's sweep runs its finaliser and publishes the
+// job's next sweep as one block of tasks in the job's own topological order,
+// so every task only waits for tasks with earlier tickets, which are held by
+// running workgroups or done (no co-residency assumed).  At most one sweep
+// per job is published and unconsumed at any time, so cap > total tiles of
+// all jobs guarantees a publisher finds its slots free.
+struct Task {
+    int32_t job, tile, kind;   // kind 0: forward sweep, 1: backward sweep
+    uint32_t seq;              // ticket + 1 once published, 0 while free
+};
+struct PersistCtl {
+    uint32_t head;             // tickets taken
+    uint32_t alloc;            // tickets reserved by publishers
+    uint32_t active;           // jobs that will still publish a sweep in this launch
+    uint32_t err;              // sticky: 1 a queue wait timed out
+};
+struct PersistArgs {
+    const Job *jobs;
+    const int *tile_order;     // job j: forward tile order at 2 off[j], backward at 2 off[j] + ntiles
+    const int *off;            // prefix sums of the jobs' tile counts
+    Task *tasks;
+    uint32_t cap;
+    PersistCtl *pc;
+    const uint32_t *pause;     // host-mapped: nonzero asks every job to leave at its next iteration boundary
+    uint32_t *stopped;         // host-mapped: jobs that reached a stop decision (convergence, limit, error)
+    uint64_t timeout_ticks;
+    uint32_t jitter;
+};
 // Face records.  At every local step a tile publishes the values its
 // downstream neighbours need: FACE_ENTRIES entries, entry e < TJ for cell row
 // j = e of the tile column facing the i neighbour, entry TJ + i for cell
@@ -252,5 +285,8 @@ struct SweepPlan {
 constexpr int MAX_SWEEP_RHS = 2;
 hipError_t launch_forward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s, int nrhs = 1);
 hipError_t launch_backward(const LaunchArgs &a, int arith, const SweepPlan &p, hipStream_t s, int nrhs = 1);
+// Launches k_persist with `wgs` persistent workgroups for jobs of one
+// arithmetic and right-hand-side count, `p.phases` loader phases (2 or 3).
+hipError_t launch_persist(const PersistArgs &a, int arith, const SweepPlan &p, int wgs, hipStream_t s, int nrhs = 1);
 
 }  // namespace sipk

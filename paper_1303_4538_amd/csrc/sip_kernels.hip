@@ -620,8 +620,25 @@ __device__ void finalise_multi(const Job &J, const double *sr, const double *sb,
     c0->done = 0u;
 }
 
+// LDS of one forward-sweep workgroup.
+template <typename F, typename R, int M>
+struct FwdLds {
+    static constexpr bool R64 = std::is_same<R, double>::value;
+    F ring[2][4 + M][NQ][TT];             // r of each right-hand side, then Lb, Lw, Ls, 1/Lp; two steps
+    Pk<F, M> ybuf[2][NQ][TT];
+    Pk<R, M> xring[4][NQ][TT];            // x on planes f-1..f+2 (slot = plane & 3)
+    double cring[R64 ? 4 : 1][3][NQ][TT]; // symmetric storage: A_E, A_N, A_T on planes f-1..f+1
+    // sums of r^2 and b^2 per right-hand side, quadrant and lane, added plane
+    // by plane in plane order (whichever loader phase owns the plane), so the
+    // tile's norms do not depend on the number of loader phases
+    double acc[2 * M][NQ][TT];
+};
+
+// One tile of a forward sweep: the whole workgroup works tile as.tile of job
+// J.  Returns (uniformly) true in the workgroup that finished the job's
+// sweep last, after it has run the job's finaliser (norm and stop decision).
 template <typename F, typename R, int NP, int M>
-__global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
+__device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, FwdLds<F, R, M> &L, int *s_buf)
 {
     static_assert(M == 1 || std::is_same<F, float>::value, "several right-hand sides need FP32 factors");
     typedef Pk<F, M> FV;   // y of the M right-hand sides
@@ -635,23 +652,14 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
     constexpr bool SPLIT = NP >= 3;
     constexpr int NL = NQ * NP;
     constexpr bool R64 = std::is_same<R, double>::value;   // the symmetric storage exists in FP64 only
-    __shared__ F ring[2][4 + M][NQ][TT];    // r of each right-hand side, then Lb, Lw, Ls, 1/Lp; two steps
-    __shared__ FV ybuf[2][NQ][TT];
-    __shared__ RV xring[4][NQ][TT];         // x on planes f-1..f+2 (slot = plane & 3)
-    __shared__ double cring[R64 ? 4 : 1][3][NQ][TT];   // symmetric storage: A_E, A_N, A_T on planes f-1..f+1
-    __shared__ int s_buf[4];
-    __shared__ double s_part[NL][2 * M];
+    auto &ring = L.ring;
+    auto &ybuf = L.ybuf;
+    auto &xring = L.xring;
+    auto &cring = L.cring;
+    auto &acc = L.acc;
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    if (threadIdx.x == 0) s_buf[3] = 0;
-    const Assign as = take_ticket(a, s_buf);
-    const Job J = load_job(a, as.job);
-    const uint32_t stop = J.ctl->stop;
-    if (stop != RUN) {
-        launch_done(a);
-        return;
-    }
     const uint32_t tag = J.ctl->epoch;
     const uint32_t iter = J.ctl->iter;
     const Geom g = J.g;
@@ -663,6 +671,8 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
     GLOBAL Ctl *ctl = gp(J.ctl);
 
     for (int x = threadIdx.x; x < 2 * NQ * TT; x += blockDim.x) (&ybuf[0][0][0])[x] = FV(0);
+    for (int x = threadIdx.x; x < 2 * M * NQ * TT; x += blockDim.x) (&acc[0][0][0])[x] = 0.0;
+    if (threadIdx.x == 0) s_buf[3] = 0;
     if (wave >= 1 && wave <= NQ) {   // phase-0 loaders: planes -1 (zero margin), 0 and 1 of the x ring
         const int q = wave - 1;
         const uint32_t e0 = (uint32_t)v.base + (uint32_t)(q * TT);
@@ -810,9 +820,6 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
         FwdLoad<F, R, M> c;
         if (ph < g.steps) fwd_issue(c, src, v, q, ph, g.steps, g.nk, sym);
         GLOBAL FV *yout = gp((FV *)J.y);
-        double rr[M], bb[M];
-#pragma unroll
-        for (int m = 0; m < M; m++) rr[m] = bb[m] = 0.0;
         // In-ring neighbours: the other quadrant column (row) of the same
         // lane on the same plane, or of the neighbouring lane one plane down
         // (W, S) / up (E, N).
@@ -854,8 +861,9 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
                                  aN * el(xN, m) + aB * el(xB, m) + aT * el(xT, m);
                     const R bm = el(c.b, m);
                     const R r = bm - ax;
-                    rr[m] += (double)r * (double)r;
-                    bb[m] += (double)bm * (double)bm;
+                    // plane f of quadrant q is this wave's alone in this interval
+                    acc[2 * m][q][lane] += (double)r * (double)r;
+                    acc[2 * m + 1][q][lane] += (double)bm * (double)bm;
                     ring[slot][m][q][lane] = (F)r;
                 }
                 ring[slot][M][q][lane] = c.l[0];
@@ -895,24 +903,20 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
             }
             if (s_buf[3]) break;
         }
-#pragma unroll
-        for (int m = 0; m < M; m++) {
-            rr[m] = wave_sum(rr[m]);
-            bb[m] = wave_sum(bb[m]);
-            if (lane == 0) {
-                s_part[lw][2 * m] = rr[m];
-                s_part[lw][2 * m + 1] = bb[m];
-            }
-        }
     }
     __syncthreads();
-    if (threadIdx.x < 2 * M) {   // per-tile partials, one thread per sum, fixed order
-        double sum = 0.0;
-        for (int l = 0; l < NL; l++) sum += s_part[l][threadIdx.x];
-        gp(J.part)[2 * M * v.t + threadIdx.x] = sum;
+    if (wave == 0) {   // per-tile partials: quadrants in order, lanes by a fixed butterfly
+#pragma unroll
+        for (int k = 0; k < 2 * M; k++) {
+            double sum = 0.0;
+#pragma unroll
+            for (int c = 0; c < NQ; c++) sum += wave_sum(acc[k][c][lane]);
+            if (lane == 0) gp(J.part)[2 * M * v.t + k] = sum;
+        }
     }
 
-    if (job_last(J, s_buf) && wave == 0) {
+    const bool last = job_last(J, s_buf);
+    if (last && wave == 0) {
         double sr[M], sb[M];
 #pragma unroll
         for (int m = 0; m < M; m++) {
@@ -963,6 +967,17 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
             }
         }
     }
+    return last;
+}
+
+template <typename F, typename R, int NP, int M>
+__global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
+{
+    __shared__ FwdLds<F, R, M> L;
+    __shared__ int s_buf[8];
+    const Assign as = take_ticket(a, s_buf);
+    const Job J = load_job(a, as.job);
+    if (J.ctl->stop == RUN) (void)fwd_tile<F, R, NP, M>(a, as, J, L, s_buf);
     launch_done(a);
 }
 
@@ -995,8 +1010,18 @@ __device__ __forceinline__ void bwd_issue(BwdLoad<F, R, M> &c, const BwdSrc<F, R
     c.x = ldg((const GLOBAL Pk<R, M> *)s.x, e);
 }
 
+// LDS of one backward-sweep workgroup.
+template <typename F, typename R, int M>
+struct BwdLds {
+    Pk<F, M> yring[2][NQ][TT];
+    F ring[2][3][NQ][TT];     // Un, Ue, Ut
+    Pk<R, M> xring[4][NQ][TT];
+    Pk<F, M> dbuf[2][NQ][TT];
+};
+
+// One tile of a backward sweep (as fwd_tile).
 template <typename F, typename R, int NP, int M>
-__global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
+__device__ bool bwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, BwdLds<F, R, M> &L, int *s_buf)
 {
     typedef Pk<F, M> FV;
     typedef Pk<R, M> RV;
@@ -1007,22 +1032,13 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
     // interval has to hold a whole turn (the loads keep their two intervals of
     // lead).
     constexpr bool SPLIT = NP >= 3;
-    __shared__ FV yring[2][NQ][TT];
-    __shared__ F ring[2][3][NQ][TT];     // Un, Ue, Ut
-    __shared__ RV xring[4][NQ][TT];
-    __shared__ FV dbuf[2][NQ][TT];
-    __shared__ int s_buf[4];
+    auto &yring = L.yring;
+    auto &ring = L.ring;
+    auto &xring = L.xring;
+    auto &dbuf = L.dbuf;
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    if (threadIdx.x == 0) s_buf[3] = 0;
-    const Assign as = take_ticket(a, s_buf);
-    const Job J = load_job(a, as.job);
-    const uint32_t stop = J.ctl->stop;
-    if (stop != RUN) {
-        launch_done(a);
-        return;
-    }
     const uint32_t tag = J.ctl->epoch;
     const Geom g = J.g;
     const TileView v = make_view(g, as.tile, lane);
@@ -1032,6 +1048,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
     GLOBAL Ctl *ctl = gp(J.ctl);
 
     for (int x = threadIdx.x; x < 2 * NQ * TT; x += blockDim.x) (&dbuf[0][0][0])[x] = FV(0);
+    if (threadIdx.x == 0) s_buf[3] = 0;
     __syncthreads();
 
     if (wave == 0) {
@@ -1212,14 +1229,141 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
         }
     }
 
-    if (job_last(J, s_buf) && wave == 0 && lane == 0) {
+    const bool last = job_last(J, s_buf);
+    if (last && wave == 0 && lane == 0) {
         Ctl *cc = J.ctl;
         if (cc->err) cc->stop = (cc->err & 2u) ? BREAKDOWN : TIMEOUT;
         cc->iter = cc->iter + 1u;
         cc->epoch = tag + 1u;
         cc->done = 0u;
     }
+    return last;
+}
+
+template <typename F, typename R, int NP, int M>
+__global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
+{
+    __shared__ BwdLds<F, R, M> L;
+    __shared__ int s_buf[8];
+    const Assign as = take_ticket(a, s_buf);
+    const Job J = load_job(a, as.job);
+    if (J.ctl->stop == RUN) (void)bwd_tile<F, R, NP, M>(a, as, J, L, s_buf);
     launch_done(a);
+}
+
+// ------------------------------------------------------ persistent sweeps
+// k_persist: the sweeps of many jobs in one launch, each job at its own pace
+// (the queue protocol is described with Task in sip_internal.h).  A job's
+// forward finaliser decides its stop as in a single solve; when it runs on,
+// the workgroup publishes the job's backward sweep; the backward finaliser
+// publishes the next forward sweep unless the job stopped (a wait timed out)
+// or the host asked for a pause.  A job that publishes nothing leaves the
+// launch; the launch ends when no job is left and every workgroup finds the
+// queue empty.
+
+template <typename F, typename R, int M>
+union PersistLds {
+    FwdLds<F, R, M> f;
+    BwdLds<F, R, M> b;
+};
+
+// Takes the next ticket and waits until its task is published (thread 0;
+// s_buf[4..6] = job, tile, kind; job -1 when no task will come).
+__device__ void take_task(const PersistArgs &e, int *s_buf)
+{
+    int job = -1, tile = 0, kind = 0;
+    const uint32_t t = atomicAdd(&e.pc->head, 1u);
+    Task *slot = e.tasks + (t % e.cap);
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        if (__hip_atomic_load(&slot->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == t + 1u) {
+            job = slot->job;
+            tile = slot->tile;
+            kind = slot->kind;
+            __hip_atomic_store(&slot->seq, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);   // the slot is free
+            break;
+        }
+        // with no job left nothing is published any more: a ticket beyond the
+        // reserved ones will never hold a task
+        if (__hip_atomic_load(&e.pc->active, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u &&
+            t >= __hip_atomic_load(&e.pc->alloc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            break;
+        if (__hip_atomic_load(&e.pc->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (wall_clock64() - t0 > e.timeout_ticks) {
+            __hip_atomic_fetch_or(&e.pc->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+    s_buf[4] = job;
+    s_buf[5] = tile;
+    s_buf[6] = kind;
+}
+
+// After the finaliser of job `job`'s sweep of kind `kind` (whole workgroup):
+// publish the job's next sweep, or let the job leave the launch.
+__device__ void publish_next(const PersistArgs &e, const Job &J, int job, int kind, int *s_buf)
+{
+    if (threadIdx.x == 0) {
+        const uint32_t stop = J.ctl->stop;   // written by this thread in the finaliser
+        int next = -1;
+        if (stop == RUN) {
+            if (kind == 0) next = 1;
+            else if (__hip_atomic_load(e.pause, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == 0u) next = 0;
+        }
+        if (next < 0) {
+            if (stop != RUN) __hip_atomic_store(e.stopped, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_fetch_sub(&e.pc->active, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            s_buf[7] = (int)atomicAdd(&e.pc->alloc, (uint32_t)J.g.ntiles);
+        }
+        s_buf[6] = next;
+    }
+    __syncthreads();
+    const int next = s_buf[6];
+    if (next < 0) return;
+    const uint32_t base = (uint32_t)s_buf[7];
+    const int nt = J.g.ntiles;
+    const int *ord = e.tile_order + 2 * e.off[job] + (next ? nt : 0);
+    for (int k = threadIdx.x; k < nt; k += blockDim.x) {
+        const uint32_t t = base + (uint32_t)k;
+        Task *slot = e.tasks + (t % e.cap);
+        // free by the capacity argument; waited for all the same (bounded)
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(&slot->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            if (wall_clock64() - t0 > e.timeout_ticks) {
+                __hip_atomic_fetch_or(&e.pc->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        slot->job = job;
+        slot->tile = ord[k];
+        slot->kind = next;
+        __hip_atomic_store(&slot->seq, t + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <typename F, typename R, int NP, int M>
+__global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_persist(PersistArgs e)
+{
+    __shared__ PersistLds<F, R, M> L;
+    __shared__ int s_buf[8];
+    const LaunchArgs a{e.jobs, nullptr, nullptr, 0, e.timeout_ticks, e.jitter};
+    for (;;) {
+        if (threadIdx.x == 0) take_task(e, s_buf);
+        __syncthreads();
+        const int job = __builtin_amdgcn_readfirstlane(s_buf[4]);
+        const int tile = __builtin_amdgcn_readfirstlane(s_buf[5]);
+        const int kind = __builtin_amdgcn_readfirstlane(s_buf[6]);
+        if (job < 0) break;
+        const Assign as{job, tile};
+        const Job J = load_job(a, job);
+        const bool last = kind == 0 ? fwd_tile<F, R, NP, M>(a, as, J, L.f, s_buf)
+                                    : bwd_tile<F, R, NP, M>(a, as, J, L.b, s_buf);
+        if (last) publish_next(e, J, job, kind, s_buf);
+        __syncthreads();   // LDS and s_buf are reused by the next task
+    }
 }
 
 // ------------------------------------------------------ factorisation
@@ -1785,6 +1929,42 @@ static hipError_t launch_sweep(const LaunchArgs &a, int arith, int nrhs, int bac
     case 1: return launch_sweep_np<1>(a, arith, nrhs, backward, s);
     case 2: return launch_sweep_np<2>(a, arith, nrhs, backward, s);
     case 3: return launch_sweep_np<3>(a, arith, nrhs, backward, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename F, typename R, int NP, int M>
+static hipError_t launch_persist_t(const PersistArgs &a, int wgs, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_persist<F, R, NP, M>), dim3(wgs), dim3(WAVE * (1 + NQ * NP)), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NP>
+static hipError_t launch_persist_np(const PersistArgs &a, int arith, int nrhs, int wgs, hipStream_t s)
+{
+    if (nrhs == 2) {
+        switch (arith) {
+        case ARITH_MIXED: return launch_persist_t<float, double, NP, 2>(a, wgs, s);
+        case ARITH_F32: return launch_persist_t<float, float, NP, 2>(a, wgs, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (nrhs != 1) return hipErrorInvalidValue;
+    switch (arith) {
+    case ARITH_F64: return launch_persist_t<double, double, NP, 1>(a, wgs, s);
+    case ARITH_MIXED: return launch_persist_t<float, double, NP, 1>(a, wgs, s);
+    case ARITH_F32: return launch_persist_t<float, float, NP, 1>(a, wgs, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_persist(const PersistArgs &a, int arith, const SweepPlan &p, int wgs, hipStream_t s, int nrhs)
+{
+    if (wgs < 1) return hipErrorInvalidValue;
+    switch (p.phases) {
+    case 2: return launch_persist_np<2>(a, arith, nrhs, wgs, s);
+    case 3: return launch_persist_np<3>(a, arith, nrhs, wgs, s);
     default: return hipErrorInvalidValue;
     }
 }

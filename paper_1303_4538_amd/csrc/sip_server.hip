@@ -11,11 +11,19 @@
 //     resident after its last request only if a request asked to retain it);
 //   - a request's arrays (coefficients, b, x0) are read on the server's
 //     stream only after an event recorded on the caller's stream at submit;
-//   - all admitted requests advance together: one epoch is `epoch_iters`
-//     iterations, each a batched forward launch and a batched backward launch
-//     whose workgroups take (request, tile) tickets from one merged order;
-//   - at every epoch boundary converged requests retire (x copied to the
-//     caller's array) and queued requests are admitted (continuous batching).
+//   - all admitted requests of one arithmetic run in one persistent launch
+//     (k_persist): every request iterates at its own pace (its forward and
+//     backward sweeps follow each other as its own finalisers publish them),
+//     so small blocks do not wait for the largest one; a launch ends when
+//     every request in it has stopped or has been asked to pause at its next
+//     iteration boundary, which the host does when queued requests wait, when
+//     a stopped request has waited long enough to be retired, or to give
+//     another launch group its turn;
+//   - between launches converged requests retire (x copied to the caller's
+//     array) and queued requests are admitted (continuous batching).
+//     SIP_SERVER_PERSISTENT=0 instead advances all requests together in
+//     epochs of `epoch_iters` iterations, each a batched forward launch and a
+//     batched backward launch over one merged ticket order.
 // Every request's arithmetic depends only on its own data and tile order, so
 // a result is the same alone and in any mix.
 #include "sip_internal.h"
@@ -162,6 +170,17 @@ struct sip_server_s {
     bool pairing = false;                     // SIP_SERVER_PAIRS=1 turns pairing on
     LaunchCtl *lc = nullptr;
     unsigned *d_bad = nullptr, *h_bad = nullptr;   // symmetry check counter (device, pinned mirror)
+    // persistent launches (k_persist): per launch group the jobs' tile orders,
+    // their offsets and the task queue; one queue control block; two coherent
+    // pinned flags (pause requests from the host, stop reports from the device)
+    bool persistent = true;                   // SIP_SERVER_PERSISTENT=0: epochs of per-iteration launches
+    int *d_torder[2 * NARITH] = {};
+    int *d_off[2 * NARITH] = {};
+    Task *d_tasks[2 * NARITH] = {};
+    int torder_cap[2 * NARITH] = {}, off_cap[2 * NARITH] = {}, tasks_cap[2 * NARITH] = {};
+    PersistCtl *d_pc = nullptr, *h_pc = nullptr;
+    uint32_t *h_pause = nullptr, *h_stopped = nullptr;   // coherent host memory, read / written by the device
+    uint32_t *d_pause = nullptr, *d_stopped = nullptr;   // their device addresses
     SweepPlan plan{};
     bool plan_forced = false;   // SIP_SWEEP_PHASES set: no tuned plans
 
@@ -174,6 +193,9 @@ struct sip_server_s {
     void finish_locked(Req *q, sip_status st, int iters, double rho);
     sip_status run_factor(const std::vector<Resident *> &sys, const std::vector<Req *> &owners);
     sip_status run_epoch(std::vector<Req *> &act);
+    sip_status run_persist(int grp, const std::vector<Job> &jobs, const std::vector<Geom> &gs, const SweepPlan &gp,
+                           bool others_waiting);
+    bool want_pause(double since_launch, bool others_waiting);
     void form_pairs(std::vector<Req *> &ready);
     void free_pair(Pair *p);
     sip_status ensure_launch_buffers(int grp, int njobs, int ntiles);
@@ -643,6 +665,22 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
             if (J.g.elems > big->g.elems) big = &J;
         (void)tuned_plan(big->g, grp % NARITH, big->sym, &gplan[grp]);
     }
+    if (persistent) {
+        int groups = 0;
+        for (int grp = 0; grp < NG; grp++) groups += !jobs[grp].empty();
+        for (int grp = 0; grp < NG; grp++) {
+            if (jobs[grp].empty()) continue;
+            const sip_status st = run_persist(grp, jobs[grp], gs[grp], gplan[grp], groups > 1);
+            if (st != SIP_OK) return st;
+        }
+        if (hipMemcpyAsync(h_ctl, ctl, sizeof(Ctl) * MAX_SLOTS, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            (!pairs.empty() &&
+             hipMemcpyAsync(h_pctl, pctl, sizeof(Ctl) * 3 * MAX_PAIRS, hipMemcpyDeviceToHost, stream) != hipSuccess) ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return set_error(SIP_EDEVICE, "launch failed: %s", hipGetErrorString(hipGetLastError()));
+        stats[2]++;
+        return SIP_OK;
+    }
     auto launch_all = [&]() -> bool {
         for (int it = 0; it < cfg.epoch_iters; it++) {
             for (int grp = 0; grp < NG; grp++) {
@@ -696,6 +734,101 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
         hipStreamSynchronize(stream) != hipSuccess)
         return set_error(SIP_EDEVICE, "epoch failed: %s", hipGetErrorString(hipGetLastError()));
     stats[2]++;
+    return SIP_OK;
+}
+
+// Whether the running persistent launch should let its requests pause: new
+// requests wait for admission (after a short minimum run, so that a queue that
+// cannot be admitted yet does not restart the launch over and over), a request
+// has stopped and waits to be retired, another launch group waits for its
+// turn, or the server is shutting down.
+bool sip_server_s::want_pause(double since_launch, bool others_waiting)
+{
+    constexpr double MIN_RUN = 2e-3, SLICE = 20e-3;
+    if (since_launch >= MIN_RUN && __atomic_load_n(h_stopped, __ATOMIC_ACQUIRE)) return true;
+    if (others_waiting && since_launch >= SLICE) return true;
+    std::lock_guard<std::mutex> lk(mu);
+    if (quit) return true;
+    return since_launch >= MIN_RUN && !queue.empty() && (int)running.size() < cfg.max_slots;
+}
+
+// One persistent launch for the jobs of launch group grp: every job starts at
+// its next forward sweep (an iteration boundary) and runs until it stops or
+// the host asks for a pause.
+sip_status sip_server_s::run_persist(int grp, const std::vector<Job> &jobs, const std::vector<Geom> &gs,
+                                     const SweepPlan &gp, bool others_waiting)
+{
+    const int arith = grp % NARITH, nrhs = grp < NARITH ? 1 : 2;
+    const int nj = (int)jobs.size();
+    std::vector<int> off(nj + 1, 0), tord;
+    for (int j = 0; j < nj; j++) off[j + 1] = off[j] + gs[j].ntiles;
+    const int total = off[nj];
+    tord.reserve(2 * (size_t)total);
+    for (int j = 0; j < nj; j++)
+        for (int b = 0; b < 2; b++)
+            for (const int2 &o : topo_order({gs[j]}, b != 0, order_seed(grp) ? order_seed(grp) + 31u * j : 0u))
+                tord.push_back(o.y);
+    // the first forward sweeps, merged over the jobs (topological per job)
+    const std::vector<int2> first = topo_order(gs, false, order_seed(grp));
+    const uint32_t cap = (uint32_t)total + 64u;   // more than the tiles of all jobs
+    std::vector<Task> tasks(cap, Task{0, 0, 0, 0u});
+    for (size_t t = 0; t < first.size(); t++) tasks[t] = Task{first[t].x, first[t].y, 0, (uint32_t)t + 1u};
+    auto grow = [&](void **p, int &have, int need, size_t elem) -> bool {
+        if (need <= have) return true;
+        dev_free(*p, stream);
+        const int c = std::max(need, 4096);
+        if (dev_alloc(p, (size_t)c * elem, stream) != SIP_OK) return false;
+        have = c;
+        return true;
+    };
+    if (ensure_launch_buffers(grp, nj, (int)first.size()) != SIP_OK ||
+        !grow((void **)&d_torder[grp], torder_cap[grp], 2 * total, sizeof(int)) ||
+        !grow((void **)&d_off[grp], off_cap[grp], nj + 1, sizeof(int)) ||
+        !grow((void **)&d_tasks[grp], tasks_cap[grp], (int)cap, sizeof(Task)))
+        return SIP_ENOMEM;
+    *h_pc = PersistCtl{0u, (uint32_t)first.size(), (uint32_t)nj, 0u};
+    __atomic_store_n(h_pause, 0u, __ATOMIC_RELEASE);
+    __atomic_store_n(h_stopped, 0u, __ATOMIC_RELEASE);
+    if (hipMemcpyAsync(d_jobs[grp], jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(d_torder[grp], tord.data(), tord.size() * sizeof(int), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(d_off[grp], off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(d_tasks[grp], tasks.data(), tasks.size() * sizeof(Task), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(d_pc, h_pc, sizeof(PersistCtl), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return set_error(SIP_EDEVICE, "upload failed");
+    const PersistArgs pa{d_jobs[grp], d_torder[grp], d_off[grp], d_tasks[grp], cap, d_pc, d_pause, d_stopped,
+                         timeout_ticks, torture};
+    // persistent workgroups: as many as fit the compute units (two 9-wave
+    // workgroups per unit with two loader phases, one 13-wave one with three),
+    // never more than the tiles that can be in flight
+    SweepPlan pp = gp;
+    pp.phases = std::max(2, std::min(3, gp.phases));   // the persistent kernel comes with two or three phases
+    const int per_cu = pp.phases >= 3 ? 1 : 2;
+    const int wgs = std::max(1, std::min(total, num_cu * per_cu));
+    const auto tl = std::chrono::steady_clock::now();
+    if (launch_persist(pa, arith, pp, wgs, stream, nrhs) != hipSuccess)
+        return set_error(SIP_EDEVICE, "persistent launch failed");
+    if (hipMemcpyAsync(h_pc, d_pc, sizeof(PersistCtl), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return set_error(SIP_EDEVICE, "status copy failed");
+    stats[7]++;
+    // while it runs: pause requests (the host vectors above stay alive until
+    // the launch is over, so the copies from them have run)
+    bool paused = false;
+    for (;;) {
+        const hipError_t q = hipStreamQuery(stream);
+        if (q == hipSuccess) break;
+        if (q != hipErrorNotReady) return set_error(SIP_EDEVICE, "persistent launch failed: %s", hipGetErrorString(q));
+        if (!paused &&
+            want_pause(std::chrono::duration<double>(std::chrono::steady_clock::now() - tl).count(), others_waiting)) {
+            __atomic_store_n(h_pause, 1u, __ATOMIC_RELEASE);
+            paused = true;
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(paused ? 20 : 100));
+    }
+    if (h_pc->err) return set_error(SIP_EDEVICE, "a device-side queue wait timed out");
     return SIP_OK;
 }
 
@@ -850,6 +983,7 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
     }
     if (const char *e = getenv("SIP_SERVER_PAIRS")) s->pairing = atoi(e) != 0;
     if (const char *e = getenv("SIP_SERVER_GRAPHS")) s->graphs = atoi(e) != 0;
+    if (const char *e = getenv("SIP_SERVER_PERSISTENT")) s->persistent = atoi(e) != 0;
     s->timeout_ticks = timeout_ticks_for(s->device, 2.0);
     s->torture = schedule_seed();
     {
@@ -868,6 +1002,12 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
         launch_init_ctl(s->pctl, 3 * MAX_PAIRS, 0, 0.0, 1, s->stream) != hipSuccess ||
         hipMalloc((void **)&s->d_bad, sizeof(unsigned)) != hipSuccess ||
         hipHostMalloc((void **)&s->h_bad, sizeof(unsigned), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&s->d_pc, sizeof(PersistCtl)) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_pc, sizeof(PersistCtl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_pause, sizeof(uint32_t), hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_stopped, sizeof(uint32_t), hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&s->d_pause, s->h_pause, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&s->d_stopped, s->h_stopped, 0) != hipSuccess ||
         // on the server's own stream, in order: the stream does not synchronise
         // with the legacy default stream, so a plain hipMemset could land after
         // the initialisation and reset the epochs to 0, which the zeroed face
@@ -1021,6 +1161,9 @@ sip_status sip_server_destroy(sip_server s)
         dev_free(s->d_jobs[grp], s->stream);
         dev_free(s->d_order[grp][0], s->stream);
         dev_free(s->d_order[grp][1], s->stream);
+        dev_free(s->d_torder[grp], s->stream);
+        dev_free(s->d_off[grp], s->stream);
+        dev_free(s->d_tasks[grp], s->stream);
     }
     (void)hipStreamSynchronize(s->stream);
     if (s->epoch_exec) (void)hipGraphExecDestroy(s->epoch_exec);
@@ -1031,6 +1174,10 @@ sip_status sip_server_destroy(sip_server s)
     (void)hipHostFree(s->h_ctl);
     (void)hipFree(s->d_bad);
     (void)hipHostFree(s->h_bad);
+    (void)hipFree(s->d_pc);
+    (void)hipHostFree(s->h_pc);
+    (void)hipHostFree(s->h_pause);
+    (void)hipHostFree(s->h_stopped);
     (void)hipStreamDestroy(s->stream);
     delete s;
     return SIP_OK;

@@ -121,9 +121,12 @@ def test_config3_batched_blocks(sip):
         assert res[q]["status"] == sip.SIP_OK and res[q]["rel_res"] <= 1e-8
         S = sip.sip_factor(At, 0.92, "mixed")
         xa = torch.zeros_like(bt)
-        _, it, _, _ = sip.sip_solve(S, bt, xa, 1e-8, 200000)
+        _, it, rr, _ = sip.sip_solve(S, bt, xa, 1e-8, 200000)
         S.close()
         assert res[q]["iters"] == it and torch.equal(xs[q], xa), f"block {q}"
+        # the server's launch (thousands of tiles, two loader phases) and the
+        # solo solve (three phases) sum the residual norms in the same order
+        assert res[q]["rel_res"] == rr, f"block {q}"
         rc = oracle.norm2(oracle.residual(A, b, xs[q].cpu().numpy())) / oracle.norm2(b)
         assert rc <= 1e-8 * (1 + 1e-9), f"block {q}"
 
@@ -204,3 +207,23 @@ def test_config2_blocks_mixed_iterates(sip, cube):
         log(f"  x_{n}: max rel diff {err:.2e}")
         assert err <= 4e-6
     D.close()
+
+
+@pytest.mark.timeout(600)
+def test_config4_mixed_solve(sip):
+    """The 512 x 512 x 256 block solved in the mixed form to 1e-8 (about 15 k
+    iterations); the returned x is re-checked with the oracle's FP64 residual
+    on every cell."""
+    c = problems.config4()
+    A, b = c["A"], c["b"]
+    log("512x512x256 stretched Poisson: mixed solve to 1e-8")
+    At, bt = dev(A), dev(b)
+    S = sip.sip_factor(At, c["alpha"], "mixed")
+    xt = torch.zeros_like(bt)
+    st, it, rr, _ = sip.sip_solve(S, bt, xt, 1e-8, 200000)
+    S.close()
+    log(f"  {it} iterations, rel_res {rr:.3e}; oracle FP64 residual")
+    assert st == sip.SIP_OK and rr <= 1e-8
+    r = oracle.norm2(oracle.residual(A, b, xt.cpu().numpy())) / oracle.norm2(b)
+    assert abs(r - rr) <= 1e-12
+    assert r <= 1e-8 * (1 + 1e-9)

@@ -1,9 +1,14 @@
 """Batched and served solves (sip_batch_submit / sip_batch_poll) on the GPU.
 
 Bar: every request's result equals the same block solved alone through
-sip_solve (bitwise: identical per-block arithmetic and reduction order), its
-final residual re-checked by the oracle in FP64 is <= rtol, and its
-iteration count is within 2 of the mixed-form oracle's.
+sip_solve (bitwise: identical per-block arithmetic and reduction order; the
+per-tile norms are summed plane by plane whatever the launch shape, so the
+residual and the stop iteration are bitwise too), its final residual
+re-checked by the oracle in FP64 is <= rtol, and its iteration count is
+within 2 of the mixed-form oracle's.  The server runs every request at its
+own pace in one persistent launch (default) or, with
+SIP_SERVER_PERSISTENT=0, in epochs of per-iteration launches; the first test
+covers both.
 """
 import numpy as np
 import pytest
@@ -55,10 +60,12 @@ def alone(sip, A, b, precision, rtol=1e-8):
     return x.cpu().numpy(), it, rr
 
 
+@pytest.mark.parametrize("persistent", ["1", "0"])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_batch_equals_alone_and_oracle(sip, precision):
+def test_batch_equals_alone_and_oracle(sip, precision, persistent, monkeypatch):
+    monkeypatch.setenv("SIP_SERVER_PERSISTENT", persistent)
     data = [block(d, k, 100 + q) for q, (d, k) in enumerate(BLOCKS)]
-    log(f"server batch of {len(data)} blocks, {precision}")
+    log(f"server batch of {len(data)} blocks, {precision}, persistent {persistent}")
     srv = sip.Server(max_slots=64, epoch_iters=8)
     At = [dev(A) for A, _ in data]
     bt = [dev(b) for _, b in data]
@@ -74,6 +81,7 @@ def test_batch_equals_alone_and_oracle(sip, precision):
         xg = xt[q].cpu().numpy()
         xa, ita, rra = alone(sip, A, b, precision)
         assert r["iters"] == ita and np.array_equal(xg, xa), f"block {q} differs from its solo solve"
+        assert r["rel_res"] == rra, f"block {q}: residual differs from its solo solve"
         rc = oracle.norm2(oracle.residual(A, b, xg)) / oracle.norm2(b)
         assert rc <= 1e-8 * (1 + 1e-9)
         LU = oracle.factor(A, 0.92)
@@ -352,8 +360,9 @@ def test_epochs_replayed_from_a_graph(sip, monkeypatch, pairs):
     """While no request joins or leaves, the server replays its epoch's sweeps
     from a captured graph (the job lists and ticket orders are uploaded before
     every replay, with the host's own bookkeeping in between); results stay
-    bitwise the solo solves."""
+    bitwise the solo solves.  Epochs exist in the per-iteration launch mode."""
     monkeypatch.setenv("SIP_SERVER_PAIRS", pairs)
+    monkeypatch.setenv("SIP_SERVER_PERSISTENT", "0")
     data = [block(d, k, 800 + q) for q, (d, k) in enumerate(BLOCKS[:4])]
     A0, _ = data[0]
     data += [(A0, np.random.default_rng(900 + q).uniform(-1, 1, A0.shape[1:])) for q in range(2)]
