@@ -126,6 +126,27 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out);
 sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
                        double *rel_res_hist, void *stream);
 
+/* sip_iterate_noalloc -- sip_iterate for callers that cannot allocate device
+ * memory (work captured into a HIP graph, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, iterates, history and statuses as
+ * sip_iterate (bitwise); the call allocates nothing: the per-call state of
+ * its sweeps (job descriptor, control block, launch counters, per-tile
+ * partial norms, the residual history before it is copied out) lives in a
+ * static device array of SIP_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends.  It launches its iterations one by one (no graph of its own).
+ *   Limit: 1024 + 16 * tiles (rounded up to 256) + (rel_res_hist ? 8 *
+ *   (n_iter + 1) : 0) bytes <= SIP_NOALLOC_SCRATCH_BYTES, where tiles =
+ *   ceil(ni / 16) * ceil(nj / 16); beyond it the call returns SIP_EINVAL and
+ *   does nothing.  (1 MiB: e.g. a 512 x 512 block with a history of up to
+ *   about 128 k iterations.)
+ *   The current device must be the system's (SIP_EINVAL otherwise).
+ * Every call on one GPU shares that GPU's array, which keeps the last
+ * call's contents: calls that overlap on one GPU (several streams or threads)
+ * race and must be serialised by the caller. */
+#define SIP_NOALLOC_SCRATCH_BYTES (1 << 20)
+sip_status sip_iterate_noalloc(sip_system h, const double *b, double *x, int32_t n_iter,
+                               double *rel_res_hist, void *stream);
+
 /* sip_solve -- iterate until rho_n <= rtol and return that x_n (the paper
  * evaluates residuals through a global reduction and keeps such evaluations
  * cheap, Sec. 3.2; here the norm and the stop test run on the device).

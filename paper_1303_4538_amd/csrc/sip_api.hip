@@ -407,6 +407,67 @@ static hipError_t multi_stage_out(const sip_system_s *h, double *x0, double *x1,
     return launch_from_sheared(h->g, h->mjob.x, f32, x1, h->mctl + 2, s, 2, 1);
 }
 
+// ------------------------------------------------ no-allocation iterate
+// sip_iterate_noalloc keeps the per-call state of its sweeps -- the job
+// descriptor, the control block, the launch counters, the per-tile partial
+// norms and the residual history -- in this file-scope array instead of the
+// buffers sip_iterate uses, so that a call allocates nothing.  Each GPU holds
+// its own copy for the life of the process; in host code the name is only a
+// stand-in, and every use goes through the device address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[SIP_NOALLOC_SCRATCH_BYTES];
+
+constexpr size_t NA_OFF_JOB = 0, NA_OFF_CTL = 256, NA_OFF_LC = 512, NA_OFF_PART = 1024;
+static_assert(sizeof(Job) <= NA_OFF_CTL - NA_OFF_JOB, "job descriptor slot");
+static_assert(sizeof(Ctl) <= NA_OFF_LC - NA_OFF_CTL, "control block slot");
+static_assert(sizeof(LaunchCtl) <= NA_OFF_PART - NA_OFF_LC, "launch counter slot");
+
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char *> g_scratch_addr;   // device -> its scratch
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device.
+static sip_status noalloc_scratch(int device, unsigned char **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto f = g_scratch_addr.find(device);
+    if (f != g_scratch_addr.end()) {
+        *out = f->second;
+        return SIP_OK;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return set_error(SIP_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                         hipGetErrorString(e));
+    g_scratch_addr[device] = (unsigned char *)ptr;
+    *out = (unsigned char *)ptr;
+    return SIP_OK;
+}
+
+// Start of a call: the job descriptor (passed by value), zeroed launch
+// counters, and a control block for n_iter iterations that continues the
+// system's sweep tags (the tags in the system's face words must never repeat).
+__global__ void k_noalloc_begin(Job j, Job *job, LaunchCtl *lc, Ctl *ctl, const Ctl *sys, uint32_t max_iter)
+{
+    if (threadIdx.x != 0) return;
+    *job = j;
+    lc->ticket = 0u;
+    lc->done = 0u;
+    Ctl c{};
+    c.epoch = sys->epoch;
+    c.max_iter = max_iter;
+    c.stop = RUN;
+    *ctl = c;
+}
+
+// End of a call: the system's control block takes the final state, so later
+// calls on the system go on with fresh tags.
+__global__ void k_noalloc_end(Ctl *sys, const Ctl *ctl)
+{
+    if (threadIdx.x == 0) *sys = *ctl;
+}
+
 }  // namespace sipk
 
 // ================================================================= C ABI
@@ -566,6 +627,59 @@ sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
     HIPTRY(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
     std::memcpy(rel_res_hist, h->h_hist, (size_t)(n_iter + 1) * 8);
+    const uint32_t stop = h->h_ctl->stop;
+    if (stop == ZERO_RHS) {
+        for (int q = 0; q <= n_iter; q++) rel_res_hist[q] = 0.0;
+        return SIP_OK;
+    }
+    if (non_finite(stop)) nan_from(rel_res_hist, h->h_ctl->iter, (size_t)n_iter + 1);
+    if (stop == MAXITER || stop == RUN) return SIP_OK;
+    return stop_status(stop);
+}
+
+sip_status sip_iterate_noalloc(sip_system h, const double *b, double *x, int32_t n_iter, double *rel_res_hist,
+                               void *stream)
+{
+    if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
+    if (n_iter < 0) return set_error(SIP_EINVAL, "n_iter must be >= 0");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != h->device)
+        return set_error(SIP_EINVAL, "the system lives on device %d, the current device is %d", h->device, cur);
+    const Geom &g = h->g;
+    const size_t part = (size_t)2 * g.ntiles * sizeof(double);
+    const size_t off_hist = NA_OFF_PART + ((part + 255) & ~(size_t)255);
+    const size_t need = off_hist + (rel_res_hist ? (size_t)(n_iter + 1) * sizeof(double) : 0);
+    if (need > SIP_NOALLOC_SCRATCH_BYTES)
+        return set_error(SIP_EINVAL,
+                         "sip_iterate_noalloc: %d tiles and %s need %zu bytes of scratch, more than the %d available",
+                         g.ntiles, rel_res_hist ? "the history" : "no history", need, SIP_NOALLOC_SCRATCH_BYTES);
+    unsigned char *base = nullptr;
+    TRY(noalloc_scratch(h->device, &base));
+    hipStream_t s = (hipStream_t)stream;
+    Job J = h->job;
+    J.part = (double *)(base + NA_OFF_PART);
+    J.ctl = (Ctl *)(base + NA_OFF_CTL);
+    J.hist = rel_res_hist ? (double *)(base + off_hist) : nullptr;
+    Job *dj = (Job *)(base + NA_OFF_JOB);
+    LaunchCtl *lc = (LaunchCtl *)(base + NA_OFF_LC);
+    hipLaunchKernelGGL(k_noalloc_begin, dim3(1), dim3(64), 0, s, J, dj, lc, J.ctl, h->ctl, (uint32_t)n_iter);
+    HIPTRY(hipGetLastError());
+    HIPTRY(stage_in(h, b, x, s));
+    const LaunchArgs fa{dj, h->order_f, lc, g.ntiles, h->timeout_ticks, h->torture};
+    const LaunchArgs ba{dj, h->order_b, lc, g.ntiles, h->timeout_ticks, h->torture};
+    for (int q = 0; q < n_iter; q++) {
+        HIPTRY(launch_forward(fa, h->precision, h->plan, s));
+        HIPTRY(launch_backward(ba, h->precision, h->plan, s));
+    }
+    HIPTRY(launch_forward(fa, h->precision, h->plan, s));   // residual of the final iterate
+    HIPTRY(launch_from_sheared(g, x_of(h), h->precision == ARITH_F32, x, J.ctl, s));
+    hipLaunchKernelGGL(k_noalloc_end, dim3(1), dim3(64), 0, s, h->ctl, (const Ctl *)J.ctl);
+    HIPTRY(hipGetLastError());
+    if (!rel_res_hist) return SIP_OK;
+    HIPTRY(hipMemcpyAsync(rel_res_hist, base + off_hist, (size_t)(n_iter + 1) * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(h->h_ctl, J.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
     const uint32_t stop = h->h_ctl->stop;
     if (stop == ZERO_RHS) {
         for (int q = 0; q <= n_iter; q++) rel_res_hist[q] = 0.0;

@@ -26,7 +26,7 @@ PRECISIONS = {"fp64": SIP_FP64, "mixed": SIP_MIXED, "fp32": SIP_FP32,
               SIP_FP64: SIP_FP64, SIP_MIXED: SIP_MIXED, SIP_FP32: SIP_FP32}
 
 # every symbol include/sip.h declares
-EXPORTS = ("sip_factor", "sip_iterate", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
+EXPORTS = ("sip_factor", "sip_iterate", "sip_iterate_noalloc", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
            "sip_profile_sweeps", "sip_profile_sweeps_multi", "sip_tune", "sip_tune_save", "sip_tune_load",
            "sip_system_info",
            "sip_system_destroy", "sip_blocks_factor", "sip_blocks_iterate", "sip_blocks_solve", "sip_blocks_info",
@@ -85,6 +85,7 @@ def lib():
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     L.sip_factor.argtypes = [ctypes.POINTER(Problem), vp, ctypes.POINTER(vp)]
     L.sip_iterate.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
+    L.sip_iterate_noalloc.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
     L.sip_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(Info), vp]
     L.sip_iterate_multi.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, ctypes.POINTER(dbl), vp]
     L.sip_solve_multi.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, i32, ctypes.POINTER(Info), vp]
@@ -108,7 +109,7 @@ def lib():
     L.sip_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
     L.sip_server_shutdown.argtypes = [vp]
     L.sip_server_destroy.argtypes = [vp]
-    for f in ("sip_factor", "sip_iterate", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
+    for f in ("sip_factor", "sip_iterate", "sip_iterate_noalloc", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
               "sip_profile_sweeps", "sip_profile_sweeps_multi", "sip_tune", "sip_tune_save", "sip_tune_load",
               "sip_system_info", "sip_system_destroy", "sip_blocks_factor", "sip_blocks_iterate", "sip_blocks_solve", "sip_blocks_info",
               "sip_blocks_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
@@ -210,6 +211,16 @@ def sip_iterate(system, b, x, n_iter, history=True, stream=None, accept=()):
     hist = np.zeros(int(n_iter) + 1) if history else None
     hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history else None
     _check(lib().sip_iterate(system._h, pb, px, int(n_iter), hp, _stream(stream)), (SIP_OK,) + tuple(accept))
+    return hist
+
+
+def sip_iterate_noalloc(system, b, x, n_iter, history=True, stream=None, accept=()):
+    """sip_iterate through the entry point that allocates no device memory
+    (its per-call state lives in a static per-GPU scratch array)."""
+    pb, px = _grid(b, system.shape, "b"), _grid(x, system.shape, "x")
+    hist = np.zeros(int(n_iter) + 1) if history else None
+    hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history else None
+    _check(lib().sip_iterate_noalloc(system._h, pb, px, int(n_iter), hp, _stream(stream)), (SIP_OK,) + tuple(accept))
     return hist
 
 
