@@ -165,17 +165,23 @@ struct LaunchArgs {
 // its own sequence of sweeps (forward, backward, forward, ...) on its own
 // control block, and leaves when it stops or when the host asks for a pause.
 // Workgroups loop over a queue of tile tasks: ticket t lives in slot t % cap
-// and is valid once seq == t + 1; a consumer frees the slot (seq = 0).  The
+// and is valid once its high half reads t + 1; a consumer frees the slot (0).  The
 // workgroup that finishes a job's sweep runs its finaliser and publishes the
 // job's next sweep as one block of tasks in the job's own topological order,
 // so every task only waits for tasks with earlier tickets, which are held by
 // running workgroups or done (no co-residency assumed).  At most one sweep
 // per job is published and unconsumed at any time, so cap > total tiles of
 // all jobs guarantees a publisher finds its slots free.
-struct Task {
-    int32_t job, tile, kind;   // kind 0: forward sweep, 1: backward sweep
-    uint32_t seq;              // ticket + 1 once published, 0 while free
-};
+// A task is one 64-bit word, written and read whole: ticket + 1 in the high
+// half (0 while the slot is free), then job (12 bits), kind (1 bit: 0 forward,
+// 1 backward sweep) and tile (19 bits).
+typedef uint64_t Task;
+constexpr int TASK_JOB_BITS = 12, TASK_TILE_BITS = 19;
+__host__ __device__ inline Task make_task(uint32_t ticket, int job, int kind, int tile)
+{
+    return ((uint64_t)(ticket + 1u) << 32) | ((uint64_t)job << (TASK_TILE_BITS + 1)) |
+           ((uint64_t)kind << TASK_TILE_BITS) | (uint64_t)tile;
+}
 struct PersistCtl {
     uint32_t head;             // tickets taken
     uint32_t alloc;            // tickets reserved by publishers

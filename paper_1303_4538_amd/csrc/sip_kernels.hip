@@ -469,7 +469,7 @@ struct FwdLoad {
     Pk<R, M> x2;   // x on plane f + 2, staged into the LDS plane ring for the next steps
     Pk<R, M> hx;   // x across the W or E tile edge (edge slots only)
     Pk<R, M> hy;   // x across the S or N tile edge (edge slots only)
-    F l[4];        // Lb, Lw, Ls, 1/Lp
+    typename Grp<F>::V lv[Grp<F>::N];   // Lb, Lw, Ls, 1/Lp as stored (16-byte groups)
 };
 
 // Uniform base pointers and per-lane index deltas of a forward loader.
@@ -563,11 +563,7 @@ __device__ __forceinline__ void fwd_issue(FwdLoad<F, R, M> &c, const FwdSrc<F, R
     }
     c.b = ldg(s.b, e);
 #pragma unroll
-    for (int k = 0; k < Grp<F>::N; k++) {
-        const typename Grp<F>::V lv = ldg(s.L[k], e);
-#pragma unroll
-        for (int w = 0; w < Grp<F>::W; w++) c.l[k * Grp<F>::W + w] = lane_of(lv, w);
-    }
+    for (int k = 0; k < Grp<F>::N; k++) c.lv[k] = ldg(s.L[k], e);
     c.x2 = ldg(s.x, s.e0 + (uint32_t)min(f + 2, steps) * PLANE);   // plane `steps` is the zero margin
     // x across a tile edge, loaded without control flow (a branch would cost
     // the loader exact wait counts): the edge slots of a quadrant read the
@@ -624,7 +620,8 @@ __device__ void finalise_multi(const Job &J, const double *sr, const double *sb,
 template <typename F, typename R, int M>
 struct FwdLds {
     static constexpr bool R64 = std::is_same<R, double>::value;
-    F ring[2][4 + M][NQ][TT];             // r of each right-hand side, then Lb, Lw, Ls, 1/Lp; two steps
+    F ring[2][M][NQ][TT];                 // r of each right-hand side; two steps
+    typename Grp<F>::V lring[2][Grp<F>::N][NQ][TT];   // (Lb, Lw, Ls, 1/Lp) in the stored 16-byte groups
     Pk<F, M> ybuf[2][NQ][TT];
     Pk<R, M> xring[4][NQ][TT];            // x on planes f-1..f+2 (slot = plane & 3)
     double cring[R64 ? 4 : 1][3][NQ][TT]; // symmetric storage: A_E, A_N, A_T on planes f-1..f+1
@@ -653,6 +650,7 @@ __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Fw
     constexpr int NL = NQ * NP;
     constexpr bool R64 = std::is_same<R, double>::value;   // the symmetric storage exists in FP64 only
     auto &ring = L.ring;
+    auto &lring = L.lring;
     auto &ybuf = L.ybuf;
     auto &xring = L.xring;
     auto &cring = L.cring;
@@ -725,10 +723,17 @@ __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Fw
             for (int c = 0; c < NQ; c++) {
 #pragma unroll
                 for (int m = 0; m < M; m++) r[m][c] = ring[slot][m][c][lane];
-                lb[c] = ring[slot][M][c][lane];
-                lw[c] = ring[slot][M + 1][c][lane];
-                ls[c] = ring[slot][M + 2][c][lane];
-                il[c] = ring[slot][M + 3][c][lane];
+                F lf[4];
+#pragma unroll
+                for (int k = 0; k < Grp<F>::N; k++) {
+                    const typename Grp<F>::V gv = lring[slot][k][c][lane];   // one 16-byte read
+#pragma unroll
+                    for (int w = 0; w < Grp<F>::W; w++) lf[k * Grp<F>::W + w] = lane_of(gv, w);
+                }
+                lb[c] = lf[0];
+                lw[c] = lf[1];
+                ls[c] = lf[2];
+                il[c] = lf[3];
             }
             nW1 = ybuf[pr][1][lane - dW];
             nW3 = ybuf[pr][3][lane - dW];
@@ -866,10 +871,8 @@ __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Fw
                     acc[2 * m + 1][q][lane] += (double)bm * (double)bm;
                     ring[slot][m][q][lane] = (F)r;
                 }
-                ring[slot][M][q][lane] = c.l[0];
-                ring[slot][M + 1][q][lane] = c.l[1];
-                ring[slot][M + 2][q][lane] = c.l[2];
-                ring[slot][M + 3][q][lane] = c.l[3];
+#pragma unroll
+                for (int k = 0; k < Grp<F>::N; k++) lring[slot][k][q][lane] = c.lv[k];
             }
             if constexpr (!SPLIT) {
                 if (f + NP < g.steps) fwd_issue(c, src, v, q, f + NP, g.steps, g.nk, sym);
@@ -1268,7 +1271,9 @@ union PersistLds {
 };
 
 // Takes the next ticket and waits until its task is published (thread 0;
-// s_buf[4..6] = job, tile, kind; job -1 when no task will come).
+// s_buf[4..6] = job, tile, kind; job -1 when no task will come).  The polls
+// are relaxed (an acquire would invalidate the caches at every poll); one
+// acquire fence follows a task, before the workgroup reads the job's data.
 __device__ void take_task(const PersistArgs &e, int *s_buf)
 {
     int job = -1, tile = 0, kind = 0;
@@ -1276,16 +1281,18 @@ __device__ void take_task(const PersistArgs &e, int *s_buf)
     Task *slot = e.tasks + (t % e.cap);
     const uint64_t t0 = wall_clock64();
     for (;;) {
-        if (__hip_atomic_load(&slot->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == t + 1u) {
-            job = slot->job;
-            tile = slot->tile;
-            kind = slot->kind;
-            __hip_atomic_store(&slot->seq, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);   // the slot is free
+        const Task w = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(w >> 32) == t + 1u) {
+            tile = (int)(w & ((1u << TASK_TILE_BITS) - 1u));
+            kind = (int)((w >> TASK_TILE_BITS) & 1u);
+            job = (int)((w >> (TASK_TILE_BITS + 1)) & ((1u << TASK_JOB_BITS) - 1u));
+            __hip_atomic_store(slot, (Task)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // the slot is free
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             break;
         }
         // with no job left nothing is published any more: a ticket beyond the
         // reserved ones will never hold a task
-        if (__hip_atomic_load(&e.pc->active, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u &&
+        if (__hip_atomic_load(&e.pc->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u &&
             t >= __hip_atomic_load(&e.pc->alloc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             break;
         if (__hip_atomic_load(&e.pc->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
@@ -1322,6 +1329,9 @@ __device__ void publish_next(const PersistArgs &e, const Job &J, int job, int ki
     __syncthreads();
     const int next = s_buf[6];
     if (next < 0) return;
+    // the sweep's results (every tile's, gathered by this workgroup's
+    // finaliser) are released before any task of the next sweep is visible
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const uint32_t base = (uint32_t)s_buf[7];
     const int nt = J.g.ntiles;
     const int *ord = e.tile_order + 2 * e.off[job] + (next ? nt : 0);
@@ -1330,20 +1340,21 @@ __device__ void publish_next(const PersistArgs &e, const Job &J, int job, int ki
         Task *slot = e.tasks + (t % e.cap);
         // free by the capacity argument; waited for all the same (bounded)
         const uint64_t t0 = wall_clock64();
-        while (__hip_atomic_load(&slot->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        while (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (Task)0) {
             if (wall_clock64() - t0 > e.timeout_ticks) {
                 __hip_atomic_fetch_or(&e.pc->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        slot->job = job;
-        slot->tile = ord[k];
-        slot->kind = next;
-        __hip_atomic_store(&slot->seq, t + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(slot, make_task(t, job, next, ord[k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
+// Both sweeps are inlined into one loop and register-allocated together
+// (mixed form: about 120 VGPRs against 82 for the forward sweep alone), so a
+// compute unit holds one workgroup of either phase count; the server runs it
+// with three phases, which hold one per unit anyway.
 template <typename F, typename R, int NP, int M>
 __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_persist(PersistArgs e)
 {

@@ -11,19 +11,21 @@
 //     resident after its last request only if a request asked to retain it);
 //   - a request's arrays (coefficients, b, x0) are read on the server's
 //     stream only after an event recorded on the caller's stream at submit;
-//   - all admitted requests of one arithmetic run in one persistent launch
-//     (k_persist): every request iterates at its own pace (its forward and
-//     backward sweeps follow each other as its own finalisers publish them),
-//     so small blocks do not wait for the largest one; a launch ends when
-//     every request in it has stopped or has been asked to pause at its next
-//     iteration boundary, which the host does when queued requests wait, when
-//     a stopped request has waited long enough to be retired, or to give
-//     another launch group its turn;
+//   - while no new request arrives, all admitted requests of one arithmetic
+//     run in one persistent launch (k_persist): every request iterates at its
+//     own pace (its forward and backward sweeps follow each other as its own
+//     finalisers publish them), so small blocks do not wait for the largest
+//     one; a launch ends when every request in it has stopped or has been
+//     asked to pause at its next iteration boundary, which the host does when
+//     queued requests wait, when a stopped request has waited long enough to
+//     be retired, or to give another launch group its turn;
+//   - while requests keep arriving, all admitted requests advance together in
+//     epochs of `epoch_iters` iterations, each a batched forward launch and a
+//     batched backward launch over one merged ticket order (an epoch boundary
+//     admits new requests without draining a persistent launch);
+//     SIP_SERVER_PERSISTENT=1 / 0 forces one mode;
 //   - between launches converged requests retire (x copied to the caller's
 //     array) and queued requests are admitted (continuous batching).
-//     SIP_SERVER_PERSISTENT=0 instead advances all requests together in
-//     epochs of `epoch_iters` iterations, each a batched forward launch and a
-//     batched backward launch over one merged ticket order.
 // Every request's arithmetic depends only on its own data and tile order, so
 // a result is the same alone and in any mix.
 #include "sip_internal.h"
@@ -173,7 +175,12 @@ struct sip_server_s {
     // persistent launches (k_persist): per launch group the jobs' tile orders,
     // their offsets and the task queue; one queue control block; two coherent
     // pinned flags (pause requests from the host, stop reports from the device)
-    bool persistent = true;                   // SIP_SERVER_PERSISTENT=0: epochs of per-iteration launches
+    // persistent launches while no request arrives (a batch then runs every
+    // block at its own pace); per-iteration epochs while requests keep
+    // arriving (admission at every epoch boundary costs no drain).
+    // SIP_SERVER_PERSISTENT=1 / 0 forces one of the two.
+    int persistent = -1;                      // -1 adaptive, 1 always, 0 never
+    uint64_t tickets_at_launch = 0;           // next_ticket when the last launch was decided
     int *d_torder[2 * NARITH] = {};
     int *d_off[2 * NARITH] = {};
     Task *d_tasks[2 * NARITH] = {};
@@ -181,6 +188,9 @@ struct sip_server_s {
     PersistCtl *d_pc = nullptr, *h_pc = nullptr;
     uint32_t *h_pause = nullptr, *h_stopped = nullptr;   // coherent host memory, read / written by the device
     uint32_t *d_pause = nullptr, *d_stopped = nullptr;   // their device addresses
+    // forward then backward tile order of a block of nti x ntj tiles (the
+    // default order depends on nothing else)
+    std::map<std::pair<int, int>, std::vector<int>> tile_orders;
     SweepPlan plan{};
     bool plan_forced = false;   // SIP_SWEEP_PHASES set: no tuned plans
 
@@ -665,7 +675,13 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
             if (J.g.elems > big->g.elems) big = &J;
         (void)tuned_plan(big->g, grp % NARITH, big->sym, &gplan[grp]);
     }
-    if (persistent) {
+    bool use_persistent = persistent == 1;
+    if (persistent < 0) {
+        std::lock_guard<std::mutex> lk(mu);
+        use_persistent = next_ticket == tickets_at_launch;   // nothing submitted since the last launch
+        tickets_at_launch = next_ticket;
+    }
+    if (use_persistent) {
         int groups = 0;
         for (int grp = 0; grp < NG; grp++) groups += !jobs[grp].empty();
         for (int grp = 0; grp < NG; grp++) {
@@ -744,12 +760,14 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
 // turn, or the server is shutting down.
 bool sip_server_s::want_pause(double since_launch, bool others_waiting)
 {
-    constexpr double MIN_RUN = 2e-3, SLICE = 20e-3;
-    if (since_launch >= MIN_RUN && __atomic_load_n(h_stopped, __ATOMIC_ACQUIRE)) return true;
+    // a pause drains the launch (every request finishes its iteration), so it
+    // is asked for no more often than these intervals
+    constexpr double ADMIT = 10e-3, RETIRE = 20e-3, SLICE = 20e-3;
+    if (since_launch >= RETIRE && __atomic_load_n(h_stopped, __ATOMIC_ACQUIRE)) return true;
     if (others_waiting && since_launch >= SLICE) return true;
     std::lock_guard<std::mutex> lk(mu);
     if (quit) return true;
-    return since_launch >= MIN_RUN && !queue.empty() && (int)running.size() < cfg.max_slots;
+    return since_launch >= ADMIT && !queue.empty() && (int)running.size() < cfg.max_slots;
 }
 
 // One persistent launch for the jobs of launch group grp: every job starts at
@@ -764,15 +782,25 @@ sip_status sip_server_s::run_persist(int grp, const std::vector<Job> &jobs, cons
     for (int j = 0; j < nj; j++) off[j + 1] = off[j] + gs[j].ntiles;
     const int total = off[nj];
     tord.reserve(2 * (size_t)total);
-    for (int j = 0; j < nj; j++)
-        for (int b = 0; b < 2; b++)
-            for (const int2 &o : topo_order({gs[j]}, b != 0, order_seed(grp) ? order_seed(grp) + 31u * j : 0u))
-                tord.push_back(o.y);
+    for (int j = 0; j < nj; j++) {
+        if (order_seed(grp)) {   // race testing: a random order per job and launch
+            for (int b = 0; b < 2; b++)
+                for (const int2 &o : topo_order({gs[j]}, b != 0, order_seed(grp) + 31u * j)) tord.push_back(o.y);
+            continue;
+        }
+        std::vector<int> &c = tile_orders[{gs[j].nti, gs[j].ntj}];
+        if (c.empty())
+            for (int b = 0; b < 2; b++)
+                for (const int2 &o : topo_order({gs[j]}, b != 0, 0u)) c.push_back(o.y);
+        tord.insert(tord.end(), c.begin(), c.end());
+    }
     // the first forward sweeps, merged over the jobs (topological per job)
     const std::vector<int2> first = topo_order(gs, false, order_seed(grp));
     const uint32_t cap = (uint32_t)total + 64u;   // more than the tiles of all jobs
-    std::vector<Task> tasks(cap, Task{0, 0, 0, 0u});
-    for (size_t t = 0; t < first.size(); t++) tasks[t] = Task{first[t].x, first[t].y, 0, (uint32_t)t + 1u};
+    if (nj > (1 << TASK_JOB_BITS) || total > (1 << TASK_TILE_BITS))
+        return set_error(SIP_EINVAL, "persistent launch of %d jobs / %d tiles exceeds the task encoding", nj, total);
+    std::vector<Task> tasks(cap, (Task)0);
+    for (size_t t = 0; t < first.size(); t++) tasks[t] = make_task((uint32_t)t, first[t].x, 0, first[t].y);
     auto grow = [&](void **p, int &have, int need, size_t elem) -> bool {
         if (need <= have) return true;
         dev_free(*p, stream);
@@ -801,13 +829,13 @@ sip_status sip_server_s::run_persist(int grp, const std::vector<Job> &jobs, cons
         return set_error(SIP_EDEVICE, "upload failed");
     const PersistArgs pa{d_jobs[grp], d_torder[grp], d_off[grp], d_tasks[grp], cap, d_pc, d_pause, d_stopped,
                          timeout_ticks, torture};
-    // persistent workgroups: as many as fit the compute units (two 9-wave
-    // workgroups per unit with two loader phases, one 13-wave one with three),
-    // never more than the tiles that can be in flight
+    // persistent workgroups: one per compute unit (the kernel holds both
+    // sweeps and needs about 120 VGPRs, so a unit fits one workgroup of either
+    // phase count; three phases shorten the step), never more than the tiles
+    // that can be in flight.  SIP_SWEEP_PHASES=2 still selects two phases.
     SweepPlan pp = gp;
-    pp.phases = std::max(2, std::min(3, gp.phases));   // the persistent kernel comes with two or three phases
-    const int per_cu = pp.phases >= 3 ? 1 : 2;
-    const int wgs = std::max(1, std::min(total, num_cu * per_cu));
+    pp.phases = plan_forced ? std::max(2, std::min(3, gp.phases)) : 3;
+    const int wgs = std::max(1, std::min(total, num_cu));
     const auto tl = std::chrono::steady_clock::now();
     if (launch_persist(pa, arith, pp, wgs, stream, nrhs) != hipSuccess)
         return set_error(SIP_EDEVICE, "persistent launch failed");
@@ -965,9 +993,9 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
         return set_error(SIP_EINVAL, "bad server configuration");
     auto *s = new sip_server_s();
     s->cfg = *c;
-    if (hipGetDevice(&s->device) != hipSuccess) {
+    if (const hipError_t e = hipGetDevice(&s->device); e != hipSuccess) {
         delete s;
-        return set_error(SIP_EDEVICE, "no HIP device");
+        return set_error(SIP_EDEVICE, "no HIP device: hipGetDevice: %s", hipGetErrorString(e));
     }
     if (s->cfg.hbm_budget_bytes == 0) {
         size_t fr = 0, tot = 0;
@@ -983,7 +1011,7 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
     }
     if (const char *e = getenv("SIP_SERVER_PAIRS")) s->pairing = atoi(e) != 0;
     if (const char *e = getenv("SIP_SERVER_GRAPHS")) s->graphs = atoi(e) != 0;
-    if (const char *e = getenv("SIP_SERVER_PERSISTENT")) s->persistent = atoi(e) != 0;
+    if (const char *e = getenv("SIP_SERVER_PERSISTENT")) s->persistent = atoi(e) != 0 ? 1 : 0;
     s->timeout_ticks = timeout_ticks_for(s->device, 2.0);
     s->torture = schedule_seed();
     {

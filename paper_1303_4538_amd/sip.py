@@ -81,6 +81,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"SIP HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+    # torch first: the library must bind to the HIP runtime torch has loaded
+    # (loaded before it, it can pull in a second runtime that sees no device)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     L.sip_factor.argtypes = [ctypes.POINTER(Problem), vp, ctypes.POINTER(vp)]
