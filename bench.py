@@ -119,12 +119,14 @@ def parse():
     ap.add_argument("--storage", default="full", choices=["full", "symmetric"],
                     help="coefficient storage of the sweeps (symmetric: Poisson workloads only)")
     ap.add_argument("--workload", default="single",
-                    choices=["single", "batched", "large", "serving", "pair", "blocks"],
+                    choices=["single", "batched", "large", "serving", "pair", "blocks", "tune"],
                     help="single: 256^3 block (default); batched: 64 uneven blocks through the solve "
                          "server; large: 512x512x256 stretched Poisson; serving: Poisson-arrival "
                          "request stream (8 right-hand sides per system); pair: the 256^3 block with "
                          "two right-hand sides swept together; blocks: the 256^3 domain cut into "
-                         "--blocks-per-axis^3 blocks coupled through boundary values")
+                         "--blocks-per-axis^3 blocks coupled through boundary values; tune: every sweep plan "
+                         "(loader phases x poll distance) timed on blocks of 32^3 to 512x512x256, with "
+                         "sip_tune's choice")
     ap.add_argument("--blocks-per-axis", type=int, default=2, help="blocks along each axis (workload blocks)")
     ap.add_argument("--serve-systems", type=int, default=40, help="systems in the serving stream (8 rhs each)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
@@ -733,6 +735,58 @@ def blocks_run(args):
     print(json.dumps(line), flush=True)
 
 
+def tune_run(args):
+    """Every compiled sweep plan (loader phases 1..3 x poll distance 1..3; the
+    distances other than 2 with two or three phases) timed per iteration
+    (forward + backward launch, HIP events) on mixed solves of blocks from
+    32^3 to 512x512x256, and the plan sip_tune picks for each block."""
+    import torch
+
+    from paper_1303_4538_amd import problems, sip
+
+    sip.lib()
+    shapes = [((32, 32, 32), "cd"), ((64, 64, 64), "cd"), ((160, 160, 160), "cd"), ((256, 256, 256), "cd"),
+              ((512, 512, 256), "stretched")]
+    plans = [(ph, pd) for ph in (1, 2, 3) for pd in (1, 2, 3) if pd == 2 or ph >= 2]
+    table = []
+    for dims, kind in shapes:
+        ni, nj, nk = dims
+        if kind == "stretched":
+            c = problems.config4()
+            A, b = c["A"], c["b"]
+        else:
+            A, b = problems.make_block(dims, kind, np_seed(ni))
+        At, bt = torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda()
+        n_iter = max(4, min(40, int(4e8 // (ni * nj * nk))))
+        row = {"dims": list(dims), "kind": kind, "iters_timed": n_iter, "ms_per_iteration": {}}
+        for ph, pd in plans:
+            os.environ["SIP_SWEEP_PHASES"], os.environ["SIP_POLL_DISTANCE"] = str(ph), str(pd)
+            S = sip.sip_factor(At, problems.ALPHA, "mixed")
+            assert sip.sip_system_plan(S) == (ph, pd)
+            f, bk = sip.sip_profile_sweeps(S, bt, torch.zeros_like(bt), n_iter)
+            S.close()
+            row["ms_per_iteration"][f"{ph}x{pd}"] = round(f + bk, 5)
+        del os.environ["SIP_SWEEP_PHASES"], os.environ["SIP_POLL_DISTANCE"]
+        S = sip.sip_factor(At, problems.ALPHA, "mixed")
+        sip.sip_tune(S, bt, n_iter)
+        row["tuned"] = "%dx%d" % sip.sip_system_plan(S)
+        S.close()
+        best = min(row["ms_per_iteration"], key=row["ms_per_iteration"].get)
+        row["fastest"] = best
+        row["default_3x2_vs_fastest"] = round(row["ms_per_iteration"]["3x2"] / row["ms_per_iteration"][best], 4)
+        log(f"tune {dims}: fastest {best}, tuned {row['tuned']}, {row['ms_per_iteration']}")
+        table.append(row)
+        del At, bt
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "sweep plans: ms per mixed iteration (forward + backward launch)",
+                      "plans": [f"{ph}x{pd}" for ph, pd in plans], "table": table}), flush=True)
+
+
+def np_seed(k):
+    import numpy as np
+    return np.random.SeedSequence(1234 + k)
+
+
 def pair_and_blocks(sip, A, b, alpha, n):
     """The same block and b: (1) with a second seeded right-hand side, both
     solved together (sip_solve_multi) against one after the other; (2) cut
@@ -798,6 +852,9 @@ def main():
         return
     if args.workload == "blocks":
         blocks_run(args)
+        return
+    if args.workload == "tune":
+        tune_run(args)
         return
     import numpy as np
     import torch

@@ -253,21 +253,28 @@ sip_status sip_profile_sweeps(sip_system h, const double *b, double *x, int32_t 
 sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double *const *x, int32_t n_iter,
                                     double ms[2], void *stream);
 
-/* sip_tune -- autotuner of the sweep launch shape (Sec. 2 sizes the
- * paper's blocks from about 12 thousand to 1.5 million control volumes per
- * process, so no single launch shape suits every block): times n_iter iterations
- * from x = 0 with b (device, read only) for every loader-phase count the
- * sweeps support (1 to 3; each phase is a group of loader waves that prefetch
- * for alternate steps), keeps the fastest for this handle and records it for
- * the block shape and precision, so that later sip_factor calls and solve
- * servers in the process start with it.  The iterates are unchanged bitwise
- * (the launch shape does not change their arithmetic); the residual norms
- * can differ in the last bits, since the loader waves of another phase count
- * group the per-plane sums of squares differently.  *phases (nullable, host)
- * receives the choice.  Synchronises the stream.  The environment variable
- * SIP_SWEEP_PHASES (1..3), read by sip_factor, overrides tuned plans.
+/* sip_tune -- autotuner of the sweep launch plan (Sec. 2 sizes the paper's
+ * blocks from about 12 thousand to 1.5 million control volumes per process,
+ * so no single plan suits every block): times n_iter iterations from x = 0
+ * with b (device, read only) for every plan the sweeps are compiled for --
+ * the loader-phase count (1 to 3; each phase is a group of loader waves that
+ * prefetch for alternate steps) and the poll distance (1 to 3 steps: how far
+ * ahead a tile polls its upstream neighbours' boundary values, which sets the
+ * lag per tile hop; the distances other than 2 with two or three phases) --
+ * keeps the fastest for this handle and records it for the block shape,
+ * precision and storage, so that later sip_factor calls and solve servers in
+ * the process start with it.  Iterates and residual norms are unchanged
+ * bitwise (the plan does not change the arithmetic).  *phases (nullable,
+ * host) receives the chosen phase count; sip_system_plan reports the whole
+ * plan.  Synchronises the stream.  The environment variables
+ * SIP_SWEEP_PHASES (1..3) and SIP_POLL_DISTANCE (1..3), read by sip_factor
+ * and sip_server_create, override tuned plans.
  * Errors: SIP_EINVAL, SIP_EDEVICE. */
 sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phases, void *stream);
+/* sip_system_plan -- the sweep plan of a handle (Sec. 2; see sip_tune): loader
+ * phases and poll distance (either pointer nullable, host).  Errors:
+ * SIP_EINVAL (NULL handle). */
+sip_status sip_system_plan(sip_system h, int32_t *phases, int32_t *poll);
 
 /* sip_tune_save / sip_tune_load -- the autotuner's table (kept across
  * processes, like the factorisation that Sec. 4.1 computes once in advance) (block shape,

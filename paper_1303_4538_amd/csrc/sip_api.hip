@@ -529,9 +529,11 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     // step; a solve server with many blocks per launch keeps two (more
     // workgroups per compute unit)
     h->plan.phases = SINGLE_SYSTEM_PHASES;
-    if (const char *e = getenv("SIP_SWEEP_PHASES")) {   // tuning override
-        const int nl = atoi(e);
+    const char *env_ph = getenv("SIP_SWEEP_PHASES"), *env_pd = getenv("SIP_POLL_DISTANCE");
+    if (env_ph || env_pd) {   // tuning overrides
+        const int nl = env_ph ? atoi(env_ph) : 0, pd = env_pd ? atoi(env_pd) : 0;
         if (nl >= 1 && nl <= sipk::MAX_PHASES) h->plan.phases = nl;
+        if (pd >= 1 && pd <= sipk::MAX_POLL) h->plan.poll = pd;
     } else {
         (void)tuned_plan(h->g, p->precision, p->storage == SIP_STORAGE_SYMMETRIC, &h->plan);
     }
@@ -1000,12 +1002,18 @@ sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phas
     hipEvent_t e0, e1;
     HIPTRY(hipEventCreate(&e0));
     HIPTRY(hipEventCreate(&e1));
-    int best = h->plan.phases;
+    // candidates: every phase count with the default poll distance, and the
+    // other distances with two and three phases (compiled for one
+    // right-hand side)
+    std::vector<SweepPlan> cand;
+    for (int np = 1; np <= MAX_PHASES; np++)
+        for (int pd = 1; pd <= MAX_POLL; pd++)
+            if (pd == DEFAULT_POLL || np >= 2) cand.push_back(SweepPlan{np, pd});
+    SweepPlan best = h->plan;
     float best_ms = 0.f;
     sip_status st = SIP_OK;
-    for (int np = 1; np <= MAX_PHASES && st == SIP_OK; np++) {
-        SweepPlan pl;
-        pl.phases = np;
+    for (size_t ci = 0; ci < cand.size() && st == SIP_OK; ci++) {
+        const SweepPlan pl = cand[ci];
         // the same iterations from x = 0 for every candidate
         const double *src[1] = {b};
         if (launch_to_sheared(g, 1, src, h->bx, g.elems, h->precision == ARITH_F32 ? SHEAR_F32 : SHEAR_F64, s) !=
@@ -1024,25 +1032,33 @@ sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phas
         if (st == SIP_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
             st = set_error(SIP_EDEVICE, "tuning timing failed");
-        if (st == SIP_OK && (np == 1 || ms < best_ms)) {
-            best = np;
+        if (st == SIP_OK && (ci == 0 || ms < best_ms)) {
+            best = pl;
             best_ms = ms;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != SIP_OK) return st;
-    if (h->plan.phases != best && h->chunk_exec) {   // the captured chunk holds the old kernels
-        HIPTRY(hipStreamSynchronize(s));
+    if ((h->plan.phases != best.phases || h->plan.poll != best.poll) && h->chunk_exec) {
+        HIPTRY(hipStreamSynchronize(s));   // the captured chunk holds the old kernels
         hipGraphExecDestroy(h->chunk_exec);
         h->chunk_exec = nullptr;
     }
-    h->plan.phases = best;
+    h->plan = best;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[std::make_tuple(g.ni, g.nj, g.nk, h->precision, h->sym)] = h->plan;
     }
-    if (phases) *phases = best;
+    if (phases) *phases = best.phases;
+    return SIP_OK;
+}
+
+sip_status sip_system_plan(sip_system h, int32_t *phases, int32_t *poll)
+{
+    if (!h) return set_error(SIP_EINVAL, "NULL argument");
+    if (phases) *phases = h->plan.phases;
+    if (poll) *poll = h->plan.poll;
     return SIP_OK;
 }
 
@@ -1056,9 +1072,10 @@ sip_status sip_tune_save(const char *path)
         for (const auto &kv : g_tuned) {
             char line[160];
             snprintf(line, sizeof line,
-                     "{\"ni\": %d, \"nj\": %d, \"nk\": %d, \"precision\": %d, \"symmetric\": %d, \"phases\": %d}\n",
+                     "{\"ni\": %d, \"nj\": %d, \"nk\": %d, \"precision\": %d, \"symmetric\": %d, \"phases\": %d, "
+                     "\"poll\": %d}\n",
                      std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
-                     std::get<4>(kv.first), kv.second.phases);
+                     std::get<4>(kv.first), kv.second.phases, kv.second.poll);
             out += line;
         }
     }
@@ -1107,8 +1124,14 @@ sip_status sip_tune_load(const char *path)
             st = set_error(SIP_EINVAL, "%s:%d: not a tuning entry", path, lineno);
             break;
         }
+        long pd = DEFAULT_POLL;   // entries written before the poll distance was tuned have none
+        if (strstr(line, "\"poll\"") && (!json_int(line, "poll", &pd) || pd < 1 || pd > MAX_POLL)) {
+            st = set_error(SIP_EINVAL, "%s:%d: not a tuning entry", path, lineno);
+            break;
+        }
         SweepPlan pl;
         pl.phases = (int)ph;
+        pl.poll = (int)pd;
         got.push_back({std::make_tuple((int)ni, (int)nj, (int)nk, (int)prec, (int)sym), pl});
     }
     fclose(f);

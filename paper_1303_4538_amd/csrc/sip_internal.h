@@ -283,8 +283,16 @@ hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s);
 // with no more tiles than compute units, else two, like multi-block domains.
 constexpr int MAX_PHASES = 3;
 constexpr int SINGLE_SYSTEM_PHASES = 3;
+// poll: how many steps ahead the recurrence wave polls the upstream tiles'
+// face records (1 to 3; two or three phases and one right-hand side take any,
+// the others 2).  A poll sees fresh data once the tile runs about 7 + poll
+// steps behind its upstream neighbour, so the distance sets the lag per tile
+// hop; it must also cover the poll's round trip.
+constexpr int MAX_POLL = 3;
+constexpr int DEFAULT_POLL = 2;
 struct SweepPlan {
     int phases = 2;
+    int poll = DEFAULT_POLL;
 };
 // nrhs: right-hand sides per job (1, or 2 with FP32 factors: ARITH_MIXED,
 // ARITH_F32); every job of the launch must have Job::m == nrhs.

@@ -81,7 +81,8 @@ __device__ __forceinline__ Job load_job(const LaunchArgs &a, int job)
 }
 
 constexpr int WAVE = 64;
-constexpr int PD = 2;   // face-record prefetch distance of the recurrence wave (steps)
+// The face-record prefetch distance of the recurrence wave (steps), PD, is a
+// template parameter of the sweeps (SweepPlan::poll).
 
 // ---------------------------------------------------------------- helpers
 
@@ -634,7 +635,7 @@ struct FwdLds {
 // One tile of a forward sweep: the whole workgroup works tile as.tile of job
 // J.  Returns (uniformly) true in the workgroup that finished the job's
 // sweep last, after it has run the job's finaliser (norm and stop decision).
-template <typename F, typename R, int NP, int M>
+template <typename F, typename R, int NP, int M, int PD>
 __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, FwdLds<F, R, M> &L, int *s_buf)
 {
     static_assert(M == 1 || std::is_same<F, float>::value, "several right-hand sides need FP32 factors");
@@ -973,14 +974,14 @@ __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Fw
     return last;
 }
 
-template <typename F, typename R, int NP, int M>
+template <typename F, typename R, int NP, int M, int PD>
 __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
 {
     __shared__ FwdLds<F, R, M> L;
     __shared__ int s_buf[8];
     const Assign as = take_ticket(a, s_buf);
     const Job J = load_job(a, as.job);
-    if (J.ctl->stop == RUN) (void)fwd_tile<F, R, NP, M>(a, as, J, L, s_buf);
+    if (J.ctl->stop == RUN) (void)fwd_tile<F, R, NP, M, PD>(a, as, J, L, s_buf);
     launch_done(a);
 }
 
@@ -1023,7 +1024,7 @@ struct BwdLds {
 };
 
 // One tile of a backward sweep (as fwd_tile).
-template <typename F, typename R, int NP, int M>
+template <typename F, typename R, int NP, int M, int PD>
 __device__ bool bwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, BwdLds<F, R, M> &L, int *s_buf)
 {
     typedef Pk<F, M> FV;
@@ -1243,14 +1244,14 @@ __device__ bool bwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Bw
     return last;
 }
 
-template <typename F, typename R, int NP, int M>
+template <typename F, typename R, int NP, int M, int PD>
 __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_backward(LaunchArgs a)
 {
     __shared__ BwdLds<F, R, M> L;
     __shared__ int s_buf[8];
     const Assign as = take_ticket(a, s_buf);
     const Job J = load_job(a, as.job);
-    if (J.ctl->stop == RUN) (void)bwd_tile<F, R, NP, M>(a, as, J, L, s_buf);
+    if (J.ctl->stop == RUN) (void)bwd_tile<F, R, NP, M, PD>(a, as, J, L, s_buf);
     launch_done(a);
 }
 
@@ -1370,8 +1371,8 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_persist(PersistArgs e)
         if (job < 0) break;
         const Assign as{job, tile};
         const Job J = load_job(a, job);
-        const bool last = kind == 0 ? fwd_tile<F, R, NP, M>(a, as, J, L.f, s_buf)
-                                    : bwd_tile<F, R, NP, M>(a, as, J, L.b, s_buf);
+        const bool last = kind == 0 ? fwd_tile<F, R, NP, M, 2>(a, as, J, L.f, s_buf)
+                                    : bwd_tile<F, R, NP, M, 2>(a, as, J, L.b, s_buf);
         if (last) publish_next(e, J, job, kind, s_buf);
         __syncthreads();   // LDS and s_buf are reused by the next task
     }
@@ -1903,32 +1904,47 @@ hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename F, typename R, int NP, int M>
+template <typename F, typename R, int NP, int M, int PD>
 static hipError_t launch_sweep_t(const LaunchArgs &a, int backward, hipStream_t s)
 {
     const dim3 block(WAVE * (1 + NQ * NP));
     if (backward)
-        hipLaunchKernelGGL((k_backward<F, R, NP, M>), dim3(a.total), block, 0, s, a);
+        hipLaunchKernelGGL((k_backward<F, R, NP, M, PD>), dim3(a.total), block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_forward<F, R, NP, M>), dim3(a.total), block, 0, s, a);
+        hipLaunchKernelGGL((k_forward<F, R, NP, M, PD>), dim3(a.total), block, 0, s, a);
     return hipGetLastError();
 }
 
+// One right-hand side: every poll distance with two or three phases; one
+// phase and two right-hand sides come with the default distance only.
+template <typename F, typename R, int NP>
+static hipError_t launch_sweep_pd(const LaunchArgs &a, int poll, int backward, hipStream_t s)
+{
+    if constexpr (NP >= 2) {
+        switch (poll) {
+        case 1: return launch_sweep_t<F, R, NP, 1, 1>(a, backward, s);
+        case 3: return launch_sweep_t<F, R, NP, 1, 3>(a, backward, s);
+        default: break;
+        }
+    }
+    return launch_sweep_t<F, R, NP, 1, 2>(a, backward, s);
+}
+
 template <int NP>
-static hipError_t launch_sweep_np(const LaunchArgs &a, int arith, int nrhs, int backward, hipStream_t s)
+static hipError_t launch_sweep_np(const LaunchArgs &a, int arith, int nrhs, int poll, int backward, hipStream_t s)
 {
     if (nrhs == 2) {   // FP32 factors only: a pair of FP32 values fills a face record entry
         switch (arith) {
-        case ARITH_MIXED: return launch_sweep_t<float, double, NP, 2>(a, backward, s);
-        case ARITH_F32: return launch_sweep_t<float, float, NP, 2>(a, backward, s);
+        case ARITH_MIXED: return launch_sweep_t<float, double, NP, 2, 2>(a, backward, s);
+        case ARITH_F32: return launch_sweep_t<float, float, NP, 2, 2>(a, backward, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (nrhs != 1) return hipErrorInvalidValue;
     switch (arith) {
-    case ARITH_F64: return launch_sweep_t<double, double, NP, 1>(a, backward, s);
-    case ARITH_MIXED: return launch_sweep_t<float, double, NP, 1>(a, backward, s);
-    case ARITH_F32: return launch_sweep_t<float, float, NP, 1>(a, backward, s);
+    case ARITH_F64: return launch_sweep_pd<double, double, NP>(a, poll, backward, s);
+    case ARITH_MIXED: return launch_sweep_pd<float, double, NP>(a, poll, backward, s);
+    case ARITH_F32: return launch_sweep_pd<float, float, NP>(a, poll, backward, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1936,10 +1952,11 @@ static hipError_t launch_sweep_np(const LaunchArgs &a, int arith, int nrhs, int 
 static hipError_t launch_sweep(const LaunchArgs &a, int arith, int nrhs, int backward, const SweepPlan &p,
                                hipStream_t s)
 {
+    if (p.poll < 1 || p.poll > MAX_POLL) return hipErrorInvalidValue;
     switch (p.phases) {
-    case 1: return launch_sweep_np<1>(a, arith, nrhs, backward, s);
-    case 2: return launch_sweep_np<2>(a, arith, nrhs, backward, s);
-    case 3: return launch_sweep_np<3>(a, arith, nrhs, backward, s);
+    case 1: return launch_sweep_np<1>(a, arith, nrhs, p.poll, backward, s);
+    case 2: return launch_sweep_np<2>(a, arith, nrhs, p.poll, backward, s);
+    case 3: return launch_sweep_np<3>(a, arith, nrhs, p.poll, backward, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1970,6 +1987,7 @@ static hipError_t launch_persist_np(const PersistArgs &a, int arith, int nrhs, i
     }
 }
 
+// The persistent sweeps poll two steps ahead whatever the plan says.
 hipError_t launch_persist(const PersistArgs &a, int arith, const SweepPlan &p, int wgs, hipStream_t s, int nrhs)
 {
     if (wgs < 1) return hipErrorInvalidValue;

@@ -1009,6 +1009,13 @@ sip_status sip_server_create(const sip_server_config *c, sip_server *out)
             s->plan_forced = true;
         }
     }
+    if (const char *e = getenv("SIP_POLL_DISTANCE")) {
+        const int pd = atoi(e);
+        if (pd >= 1 && pd <= sipk::MAX_POLL) {
+            s->plan.poll = pd;
+            s->plan_forced = true;
+        }
+    }
     if (const char *e = getenv("SIP_SERVER_PAIRS")) s->pairing = atoi(e) != 0;
     if (const char *e = getenv("SIP_SERVER_GRAPHS")) s->graphs = atoi(e) != 0;
     if (const char *e = getenv("SIP_SERVER_PERSISTENT")) s->persistent = atoi(e) != 0 ? 1 : 0;

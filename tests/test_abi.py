@@ -109,16 +109,18 @@ def test_tuning_table_round_trip(libpath, tmp_path):
     loads, saves back entry for entry, and a malformed file merges nothing."""
     import json
     from paper_1303_4538_amd import sip
-    entries = [dict(ni=256, nj=256, nk=256, precision=1, symmetric=0, phases=2),
-               dict(ni=17, nj=9, nk=5, precision=2, symmetric=0, phases=3),
-               dict(ni=512, nj=512, nk=256, precision=0, symmetric=1, phases=1)]
+    entries = [dict(ni=256, nj=256, nk=256, precision=1, symmetric=0, phases=2, poll=2),
+               dict(ni=17, nj=9, nk=5, precision=2, symmetric=0, phases=3, poll=1),
+               dict(ni=512, nj=512, nk=256, precision=0, symmetric=1, phases=1, poll=2),
+               dict(ni=40, nj=40, nk=40, precision=1, symmetric=0, phases=2, poll=3)]
+    old_format = dict(ni=24, nj=24, nk=24, precision=1, symmetric=0, phases=3)   # no poll: the default 2
     src = tmp_path / "tune.jsonl"
-    src.write_text("\n".join(json.dumps(e) for e in entries) + "\n\n")
+    src.write_text("\n".join(json.dumps(e) for e in entries + [old_format]) + "\n\n")
     sip.sip_tune_load(src)
     out = tmp_path / "saved.jsonl"
     sip.sip_tune_save(out)
     saved = [json.loads(line) for line in out.read_text().splitlines() if line.strip()]
-    for e in entries:
+    for e in entries + [dict(old_format, poll=2)]:
         assert e in saved
     # a later entry for the same key wins
     src.write_text(json.dumps(dict(entries[0], phases=3)) + "\n")
@@ -131,6 +133,8 @@ def test_tuning_table_round_trip(libpath, tmp_path):
                 '{"ni": 0, "nj": 8, "nk": 8, "precision": 1, "symmetric": 0, "phases": 2}',
                 '{"ni": 8, "nj": 8, "nk": 8, "precision": 5, "symmetric": 0, "phases": 2}',
                 '{"ni": 8, "nj": 8, "nk": 8, "precision": 1, "phases": 2}',
+                '{"ni": 8, "nj": 8, "nk": 8, "precision": 1, "symmetric": 0, "phases": 2, "poll": 4}',
+                '{"ni": 8, "nj": 8, "nk": 8, "precision": 1, "symmetric": 0, "phases": 2, "poll": 0}',
                 'not json'):
         f = tmp_path / "bad.jsonl"
         f.write_text(json.dumps(dict(ni=9, nj=9, nk=9, precision=1, symmetric=0, phases=2)) + "\n" + bad + "\n")

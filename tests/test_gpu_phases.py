@@ -1,7 +1,8 @@
-"""Every loader-phase count of the sweeps (SIP_SWEEP_PHASES = 1, 2, 3; with
-three the loader turns are split over two intervals) computes bitwise the
-same iterates, residual norms and stop decisions: the launch shape does not
-change the arithmetic (the squares of the residual are summed per quadrant
+"""Every compiled sweep plan -- loader-phase count (SIP_SWEEP_PHASES = 1, 2,
+3; with three the loader turns are split over two intervals) and poll
+distance (SIP_POLL_DISTANCE = 1, 2, 3 with two or three phases) -- computes
+bitwise the same iterates, residual norms and stop decisions: the launch
+shape does not change the arithmetic (the squares of the residual are summed per quadrant
 and lane plane by plane, in plane order, whichever loader wave stages a
 plane).  Covered: the three precisions, a pair of right-hand sides, the
 symmetric storage, a multi-block domain and a server batch, on shapes with
@@ -15,7 +16,8 @@ from paper_1303_4538_amd import problems
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-PHASES = ["2", "1", "3"]   # the default first: the reference
+# (phases, poll distance); the first is the reference
+PLANS = [("2", "2"), ("1", "2"), ("3", "2"), ("2", "1"), ("2", "3"), ("3", "1"), ("3", "3")]
 
 
 def log(msg):
@@ -40,8 +42,9 @@ def close(h, ref):
 
 def each_phase(monkeypatch, run):
     out = []
-    for ph in PHASES:
+    for ph, pd in PLANS:
         monkeypatch.setenv("SIP_SWEEP_PHASES", ph)
+        monkeypatch.setenv("SIP_POLL_DISTANCE", pd)
         out.append(run())
     return out
 
