@@ -494,7 +494,7 @@ def config4_summary(args, sip):
            "fp64_cell_iters_per_s": cells * its["fp64"] / secs["fp64"],
            "mixed_speedup_vs_fp64": secs["fp64"] / secs["mixed"] * its["mixed"] / its["fp64"],
            "err_vs_fp64": rel_err(xs["mixed"], xs["fp64"]),
-           "roofline": {"bound": "hbm", "kernel": "k_forward<float, double, 3, 1> (FP64 residual + FP32 forward sweep)",
+           "roofline": {"bound": "hbm", "kernel": "k_forward<float, double, 3, 1, 2> (FP64 residual + FP32 forward sweep)",
                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                         "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
@@ -675,7 +675,7 @@ def pair_run(args):
                                f"alpha 0.92, factor + sip_solve_multi to {RTOL:g}",
                    "cells": cells, "iterations": its[-1], "one_after_the_other_cell_iters_per_s": alone,
                    "speedup_vs_one_after_the_other": value / alone},
-        "roofline": {"bound": "hbm", "kernel": "k_forward<float, double, 3, 2> (pair forward sweep)",
+        "roofline": {"bound": "hbm", "kernel": "k_forward<float, double, 3, 2, 2> (pair forward sweep)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                      "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
@@ -929,8 +929,9 @@ def main():
             and kernels_sha256() == MEASURED["kernels_sha256"]):
         traffic = round(MEASURED["fwd_bytes"] / (fwd_ms * 1e-3) / 1e9, 1)
     phases = int(os.environ.get("SIP_SWEEP_PHASES", "3"))   # the single-system default: 3 loader phases
+    poll = int(os.environ.get("SIP_POLL_DISTANCE", "2"))    # and polls 2 steps ahead
     roofline = {"bound": "hbm",
-                "kernel": f"k_forward<float, double, {phases}, 1> (FP64 residual + FP32 forward sweep)",
+                "kernel": f"k_forward<float, double, {phases}, 1, {poll}> (FP64 residual + FP32 forward sweep)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),

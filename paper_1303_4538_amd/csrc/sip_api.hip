@@ -31,19 +31,6 @@ using namespace sipk;
 
 namespace sipk {
 
-thread_local std::string g_last_error;
-
-sip_status set_error(sip_status st, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return st;
-}
-
 uint64_t timeout_ticks_for(int device, double seconds)
 {
     int rate_khz = 0;
@@ -135,7 +122,8 @@ static void free_system(sip_system_s *h)
     for (void *p : {(void *)h->A, h->LU, (void *)h->bx, h->y, (void *)h->face, (void *)h->part, (void *)h->ctl,
                     (void *)h->hist, (void *)h->d_job, (void *)h->d_job_factor, (void *)h->order_f, (void *)h->order_b,
                     (void *)h->lc, (void *)h->mbx, h->my, (void *)h->mface, (void *)h->mpart, (void *)h->mctl,
-                    (void *)h->mhist, (void *)h->d_mjob})
+                    (void *)h->mhist, (void *)h->d_mjob, (void *)h->p_tord, (void *)h->p_off, (void *)h->p_tasks,
+                    (void *)h->p_pc, (void *)h->p_flags})
         if (p) hipFree(p);
     if (h->h_ctl) hipHostFree(h->h_ctl);
     if (h->h_mctl) hipHostFree(h->h_mctl);
@@ -407,6 +395,65 @@ static hipError_t multi_stage_out(const sip_system_s *h, double *x0, double *x1,
     return launch_from_sheared(h->g, h->mjob.x, f32, x1, h->mctl + 2, s, 2, 1);
 }
 
+// ------------------------------------------------ persistent solve
+// sip_solve runs the whole solve as one persistent launch (k_persist with a
+// single job): the finalisers publish the sweeps one after the other and
+// decide the stop on the device, so no launch gap separates two sweeps and
+// the host only waits.  The chunked graph replay remains for plans the
+// persistent kernel is not compiled for (one loader phase, poll distances
+// other than 2) and with SIP_SOLVE_PERSISTENT=0.
+static bool solve_persistent(const sip_system_s *h)
+{
+    const char *e = getenv("SIP_SOLVE_PERSISTENT");
+    return (!e || atoi(e) != 0) && h->plan.phases >= 2 && h->plan.poll == DEFAULT_POLL;
+}
+
+static sip_status ensure_persist(sip_system_s *h, hipStream_t s)
+{
+    if (h->p_tasks) return SIP_OK;
+    const Geom &g = h->g;
+    h->p_cap = (uint32_t)g.ntiles + 64u;
+    if (h->num_cu <= 0) {
+        int ncu = 0;
+        h->num_cu = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+                            ncu > 0
+                        ? ncu
+                        : 256;
+    }
+    TRY(alloc_dev((void **)&h->p_tord, 2 * (size_t)g.ntiles * sizeof(int), "tile orders"));
+    TRY(alloc_dev((void **)&h->p_off, 2 * sizeof(int), "tile order offsets"));
+    TRY(alloc_dev((void **)&h->p_tasks, (size_t)h->p_cap * sizeof(Task), "task queue"));
+    TRY(alloc_dev((void **)&h->p_pc, sizeof(PersistCtl), "queue control"));
+    TRY(alloc_dev((void **)&h->p_flags, 2 * sizeof(uint32_t), "queue flags"));
+    std::vector<int> tord;
+    for (int b = 0; b < 2; b++)
+        for (const int2 &o : topo_order({g}, b != 0, h->torture ? h->torture + 17u * b : 0u)) tord.push_back(o.y);
+    const int off[2] = {0, g.ntiles};
+    h->p_host_tasks.assign(h->p_cap, (Task)0);
+    for (int k = 0; k < g.ntiles; k++) h->p_host_tasks[k] = make_task((uint32_t)k, 0, 0, tord[k]);
+    HIPTRY(hipMemcpyAsync(h->p_tord, tord.data(), tord.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPTRY(hipMemcpyAsync(h->p_off, off, sizeof off, hipMemcpyHostToDevice, s));
+    HIPTRY(hipStreamSynchronize(s));   // the host copies above are locals
+    return SIP_OK;
+}
+
+// Enqueues one persistent launch that runs the job until its stop decision.
+static sip_status launch_solve_persistent(sip_system_s *h, hipStream_t s)
+{
+    TRY(ensure_persist(h, s));
+    const Geom &g = h->g;
+    h->p_host_pc = PersistCtl{0u, (uint32_t)g.ntiles, 1u, 0u};
+    HIPTRY(hipMemcpyAsync(h->p_tasks, h->p_host_tasks.data(), h->p_host_tasks.size() * sizeof(Task),
+                          hipMemcpyHostToDevice, s));
+    HIPTRY(hipMemcpyAsync(h->p_pc, &h->p_host_pc, sizeof(PersistCtl), hipMemcpyHostToDevice, s));
+    HIPTRY(launch_init_flags(h->p_flags, s));
+    const PersistArgs pa{h->d_job, h->p_tord, h->p_off, h->p_tasks, h->p_cap, h->p_pc, h->p_flags, h->p_flags + 1,
+                         h->timeout_ticks, h->torture};
+    const int wgs = std::max(1, std::min(g.ntiles, h->num_cu * (h->plan.phases >= 3 ? 1 : 2)));
+    HIPTRY(launch_persist(pa, h->precision, h->plan, wgs, s));
+    return SIP_OK;
+}
+
 // ------------------------------------------------ no-allocation iterate
 // sip_iterate_noalloc keeps the per-call state of its sweeps -- the job
 // descriptor, the control block, the launch counters, the per-tile partial
@@ -475,24 +522,6 @@ __global__ void k_noalloc_end(Ctl *sys, const Ctl *ctl)
 extern "C" {
 
 int32_t sip_abi_version(void) { return 1; }
-
-const char *sip_last_error(void) { return sipk::g_last_error.c_str(); }
-
-const char *sip_status_str(sip_status st)
-{
-    switch (st) {
-    case SIP_OK: return "SIP_OK";
-    case SIP_PENDING: return "SIP_PENDING";
-    case SIP_EINVAL: return "SIP_EINVAL";
-    case SIP_ENOMEM: return "SIP_ENOMEM";
-    case SIP_EBREAKDOWN: return "SIP_EBREAKDOWN";
-    case SIP_ENOTCONV: return "SIP_ENOTCONV";
-    case SIP_EDEVICE: return "SIP_EDEVICE";
-    case SIP_EBUSY: return "SIP_EBUSY";
-    case SIP_ECANCELLED: return "SIP_ECANCELLED";
-    }
-    return "SIP_UNKNOWN";
-}
 
 sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
 {
@@ -703,6 +732,23 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
     TRY(ensure_hist(h, max_iter + 1, s));
     HIPTRY(stage_in(h, b, x, s));
     HIPTRY(launch_init_ctl(h->ctl, 1, (uint32_t)max_iter, rtol, 0, s));
+    if (solve_persistent(h)) {
+        TRY(launch_solve_persistent(h, s));
+        HIPTRY(stage_out(h, x, s));
+        HIPTRY(hipMemcpyAsync(&h->h_ctl[2], h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPTRY(hipMemcpyAsync(&h->p_host_pc, h->p_pc, sizeof(PersistCtl), hipMemcpyDeviceToHost, s));
+        HIPTRY(hipStreamSynchronize(s));
+        const Ctl &c = h->h_ctl[2];
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (info) {
+            info->iters = (int32_t)c.iter;
+            info->rel_res = non_finite(c.stop) ? std::numeric_limits<double>::quiet_NaN() : c.rho;
+            info->seconds = secs;
+        }
+        if (h->p_host_pc.err) return set_error(SIP_EDEVICE, "a device-side queue wait timed out");
+        if (c.stop == RUN) return set_error(SIP_EDEVICE, "solve ended without a stop decision");
+        return stop_status(c.stop);
+    }
     hipEvent_t ev[2];
     HIPTRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     HIPTRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));

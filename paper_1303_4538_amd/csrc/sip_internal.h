@@ -253,6 +253,8 @@ hipError_t launch_blocks_control(BlockPtrs p, int nblk, Ctl *domain, double *his
 
 // Kernel launchers (sip_kernels.hip).  All are asynchronous on `s`.
 hipError_t launch_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int reset_epoch, hipStream_t s);
+// Zeroes the two flags of a persistent launch without a host (pause, stopped).
+hipError_t launch_init_flags(uint32_t *flags, hipStream_t s);
 // Layouts written by launch_to_sheared: plain FP64 or FP32 arrays (array a
 // at dst + a * dst_stride elements), or the 7 coefficient arrays (masked at
 // the block boundary) in the interleaved FP64, symmetric FP64 or FP32 group

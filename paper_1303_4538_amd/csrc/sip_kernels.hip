@@ -338,6 +338,7 @@ __device__ __forceinline__ void from_words(const uint64_t *w, flt2 &v)
     v.y = __uint_as_float((uint32_t)w[1]);
 }
 __device__ __forceinline__ void keep(flt2 &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void keep(dbl2 &x) { asm volatile("" : "+v"(x)); }
 template <typename F> struct Grp;
 template <> struct Grp<float> {
     typedef flt4 V;
@@ -841,10 +842,19 @@ __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Fw
                 const RV xP = xring[f & 3][q][lane];
                 const RV xB = xring[(f - 1) & 3][q][lane];
                 const RV xT = xring[(f + 1) & 3][q][lane];
-                const RV xW = inW ? xring[(f - 1 + qa) & 3][q ^ 1][lane - dW] : c.hx;
-                const RV xE = inE ? xring[(f + qa) & 3][q ^ 1][lane + dE] : c.hx;
-                const RV xS = inS ? xring[(f - 1 + qb) & 3][q ^ 2][lane - dS] : c.hy;
-                const RV xN = inN ? xring[(f + qb) & 3][q ^ 2][lane + dN] : c.hy;
+                // every lane reads the ring (an edge lane its own slot: dW .. dN are
+                // 0 there) and then selects: read only where needed, the reads
+                // became exec-masked branches around the LDS accesses
+                RV rW = xring[(f - 1 + qa) & 3][q ^ 1][lane - dW], rE = xring[(f + qa) & 3][q ^ 1][lane + dE];
+                RV rS = xring[(f - 1 + qb) & 3][q ^ 2][lane - dS], rN = xring[(f + qb) & 3][q ^ 2][lane + dN];
+                keep(rW);
+                keep(rE);
+                keep(rS);
+                keep(rN);
+                const RV xW = inW ? rW : c.hx;
+                const RV xE = inE ? rE : c.hx;
+                const RV xS = inS ? rS : c.hy;
+                const RV xN = inN ? rN : c.hy;
                 R aP = c.a[0], aW = c.a[1], aE = c.a[2], aS = c.a[3], aN = c.a[4], aB = c.a[5], aT = c.a[6];
                 if constexpr (R64) if (sym) {
                     // A_W = A_E of the W cell, A_S = A_N of the S cell, A_B = A_T of the B
@@ -857,8 +867,12 @@ __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Fw
                     aN = cring[f & 3][1][q][lane];
                     aT = cring[f & 3][2][q][lane];
                     aB = cring[(f - 1) & 3][2][q][lane];
-                    aW = inW ? cring[(f - 1 + qa) & 3][0][q ^ 1][lane - dW] : (wall_w ? 0.0 : c.a[1]);
-                    aS = inS ? cring[(f - 1 + qb) & 3][1][q ^ 2][lane - dS] : (wall_s ? 0.0 : c.a[3]);
+                    double cW = cring[(f - 1 + qa) & 3][0][q ^ 1][lane - dW];
+                    double cS = cring[(f - 1 + qb) & 3][1][q ^ 2][lane - dS];
+                    keep(cW);
+                    keep(cS);
+                    aW = inW ? cW : (wall_w ? 0.0 : c.a[1]);
+                    aS = inS ? cS : (wall_s ? 0.0 : c.a[3]);
                 }
                 const int slot = f & 1;
 #pragma unroll
@@ -1682,6 +1696,11 @@ __global__ void k_export_factors(Geom g, const F *LU, DstPtrs out)
     }
 }
 
+__global__ void k_init_flags(uint32_t *f)
+{
+    if (threadIdx.x < 2) f[threadIdx.x] = 0u;
+}
+
 __global__ void k_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int reset_epoch)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1840,6 +1859,12 @@ hipError_t launch_sumsq(const double *v, long long n, double *part, Ctl *domain,
 hipError_t launch_blocks_control(BlockPtrs p, int nblk, Ctl *domain, double *hist, hipStream_t s)
 {
     hipLaunchKernelGGL(k_blocks_control, dim3(1), dim3(64), 0, s, p, nblk, domain, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_flags(uint32_t *flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, s, flags);
     return hipGetLastError();
 }
 

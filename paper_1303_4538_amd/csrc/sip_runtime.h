@@ -1,6 +1,7 @@
 // Host-side runtime structures of the SIP library.
 #pragma once
 #include "../../include/sip.h"
+#include "sip_host.h"
 #include "sip_internal.h"
 
 #include <rocprofiler-sdk-roctx/roctx.h>
@@ -21,8 +22,6 @@ struct Range {
 
 constexpr int CHUNK = 8;   // iterations per graph-captured launch chunk
 
-extern thread_local std::string g_last_error;
-sip_status set_error(sip_status st, const char *fmt, ...);
 uint64_t timeout_ticks_for(int device, double seconds);
 // Ticket order of a launch over the jobs gs: every tile after its upstream
 // neighbours (W and S; E and N for the backward sweep).  seed 0: by
@@ -81,5 +80,15 @@ struct sip_system_s {
     sipk::Ctl *h_mctl = nullptr;    // pinned, 3 slots of 3
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t chunk_exec = nullptr;
+    // persistent solves (allocated on first use): the tile orders, the task
+    // queue and its control block with two device flags (pause, stopped)
+    int num_cu = 0;
+    int *p_tord = nullptr, *p_off = nullptr;
+    sipk::Task *p_tasks = nullptr;
+    sipk::PersistCtl *p_pc = nullptr;
+    uint32_t *p_flags = nullptr;
+    uint32_t p_cap = 0;
+    std::vector<sipk::Task> p_host_tasks;   // host image of the queue uploaded before every solve
+    sipk::PersistCtl p_host_pc{};
     sipk::SweepPlan plan{};
 };

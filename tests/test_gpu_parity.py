@@ -254,13 +254,16 @@ def test_tune_keeps_results_and_records_the_plan(sip, tmp_path):
     _, it1, _, _ = sip.sip_solve(S, dev(b), x1, 1e-8, 5000)
     ph = sip.sip_tune(S, dev(b), 3)
     assert 1 <= ph <= 3
+    tuned = sip.sip_system_plan(S)
+    assert tuned[0] == ph and 1 <= tuned[1] <= 3
     sip.sip_tune_save(tmp_path / "tune.jsonl")
     saved = [json.loads(line) for line in (tmp_path / "tune.jsonl").read_text().splitlines()]
-    assert dict(ni=40, nj=33, nk=21, precision=1, symmetric=0, phases=ph) in saved
+    assert dict(ni=40, nj=33, nk=21, precision=1, symmetric=0, phases=ph, poll=tuned[1]) in saved
     x2 = torch.zeros_like(dev(b))
     _, it2, _, _ = sip.sip_solve(S, dev(b), x2, 1e-8, 5000)
     S.close()
     S = sip.sip_factor(dev(A), 0.92, "mixed")
+    assert sip.sip_system_plan(S) == tuned   # a new system of the shape starts with the tuned plan
     x3 = torch.zeros_like(dev(b))
     _, it3, _, _ = sip.sip_solve(S, dev(b), x3, 1e-8, 5000)
     S.close()

@@ -1,0 +1,61 @@
+"""sip_solve runs a single system as one persistent launch (the finalisers
+publish the sweeps one after the other and stop on the device); with
+SIP_SOLVE_PERSISTENT=0 it replays chunks of iterations from a captured graph.
+Both must give bitwise the same x, iteration count and residual, in every
+precision and storage, on blocks with ragged tiles, a single tile, a thin
+block, and with a limit reached before the tolerance."""
+import numpy as np
+import pytest
+
+from paper_1303_4538_amd import problems
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sip():
+    from paper_1303_4538_amd import sip as s
+    s.lib()
+    assert torch.cuda.is_available()
+    return s
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def solve(sip, A, b, precision, rtol, max_iter, storage="full"):
+    S = sip.sip_factor(dev(A), 0.92, precision, storage=storage)
+    x = torch.zeros_like(dev(b))
+    st, it, rr, _ = sip.sip_solve(S, dev(b), x, rtol, max_iter, raise_on_notconv=False)
+    S.close()
+    return st, it, rr, x.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision,rtol", [("mixed", 1e-8), ("fp64", 1e-8), ("fp32", 1e-5)])
+@pytest.mark.parametrize("dims,kind", [((53, 37, 29), "cd"), ((16, 16, 40), "poisson"), ((33, 17, 3), "cd"),
+                                       ((70, 9, 31), "stretched")])
+def test_persistent_equals_chunked(sip, monkeypatch, precision, rtol, dims, kind):
+    A, b = problems.make_block(dims, kind, np.random.SeedSequence(sum(dims)))
+    print(f"persistent solve {dims} {kind} {precision}", flush=True)
+    out = []
+    for mode in ("1", "0"):
+        monkeypatch.setenv("SIP_SOLVE_PERSISTENT", mode)
+        out.append(solve(sip, A, b, precision, rtol, 5000))
+    (st1, it1, rr1, x1), (st0, it0, rr0, x0) = out
+    assert st1 == st0 == sip.SIP_OK
+    assert it1 == it0 and rr1 == rr0 and np.array_equal(x1, x0)
+    assert rr1 <= rtol
+
+
+def test_persistent_limit_and_symmetric(sip, monkeypatch):
+    A, b = problems.make_block((40, 36, 20), "poisson", np.random.SeedSequence(5))
+    out = []
+    for mode in ("1", "0"):
+        monkeypatch.setenv("SIP_SOLVE_PERSISTENT", mode)
+        out.append(solve(sip, A, b, "mixed", 1e-12, 7))                       # the limit comes first
+        out.append(solve(sip, A, b, "mixed", 1e-8, 5000, storage="symmetric"))
+    assert out[0][0] == out[2][0] == sip.SIP_ENOTCONV and out[0][1] == out[2][1] == 7
+    for a, c in ((out[0], out[2]), (out[1], out[3])):
+        assert a[1] == c[1] and a[2] == c[2] and np.array_equal(a[3], c[3])
