@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["sip_kernels.hip", "sip_api.hip", "sip_server.hip", "sip_blocks.hip", "sip_host.cpp"]
+SOURCES = ["sip_kernels.hip", "sip_api.hip", "sip_server.hip", "sip_blocks.hip", "sip_sched.cpp", "sip_host.cpp"]
 OUT = os.path.join(HERE, "libsip.so")
 
 FLAGS = [

@@ -1,16 +1,16 @@
-// Batched and served SIP solves (sip_server_* / sip_batch_* in include/sip.h).
+// The GPU backend of the SIP server (sip_server_* / sip_batch_* in
+// include/sip.h; the request scheduler is sip_sched.cpp).
 //
 // The paper's redesigned solver owns its coefficients and reuses one
-// factorisation "for all iterations and time steps" (Sec. 4.1); a server
-// generalises that to many blocks and many right-hand sides on one GPU:
-//   - a request names a system by id; the first request of an id copies and
-//     factorises the coefficients, later requests reuse the resident factors;
-//   - admission is by an HBM budget (resident systems + per-request state);
-//     when space is needed, resident systems that no running or queued
-//     request names are evicted, least-recently-used first (a system stays
-//     resident after its last request only if a request asked to retain it);
+// factorisation for every later iteration and time step (Sec. 4.1); the
+// server generalises that to many blocks and many right-hand sides on one
+// GPU.  This backend keeps, in device memory, each resident system's
+// coefficients and factors and each running request's b, x, y, face words
+// and partial sums, and runs the scheduler's steps as kernel launches on the
+// server's own stream:
 //   - a request's arrays (coefficients, b, x0) are read on the server's
 //     stream only after an event recorded on the caller's stream at submit;
+//   - new systems are factorised in one batched launch per factor precision;
 //   - while no new request arrives, all admitted requests of one arithmetic
 //     run in one persistent launch (k_persist): every request iterates at its
 //     own pace (its forward and backward sweeps follow each other as its own
@@ -23,61 +23,47 @@
 //     epochs of `epoch_iters` iterations, each a batched forward launch and a
 //     batched backward launch over one merged ticket order (an epoch boundary
 //     admits new requests without draining a persistent launch);
-//     SIP_SERVER_PERSISTENT=1 / 0 forces one mode;
-//   - between launches converged requests retire (x copied to the caller's
-//     array) and queued requests are admitted (continuous batching).
+//     SIP_SERVER_PERSISTENT=1 / 0 forces one mode.
 // Every request's arithmetic depends only on its own data and tile order, so
 // a result is the same alone and in any mix.
 #include "sip_internal.h"
 #include "sip_runtime.h"
+#include "sip_sched.h"
 
 #include <algorithm>
 #include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
-#include <list>
 #include <map>
 #include <memory>
-#include <mutex>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 using namespace sipk;
 
 namespace {
 
-constexpr int MAX_SLOTS = 4096;
+constexpr int MAX_SLOTS = SERVER_MAX_SLOTS;
 constexpr int MAX_PAIRS = 1024;   // pairs of requests swept together
 
-struct Resident {
-    uint64_t id = 0;
+struct GpuResident final : Resident {
     Geom g{};
     int fp32 = 0;          // factors stored in FP32
     int arith = 0;         // sweep arithmetic (sip_precision)
     double alpha = 0.92;
+    int sym = 0;           // sweeps read the symmetric coefficient storage
     double *A = nullptr;
     void *LU = nullptr;
-    size_t bytes = 0;
-    int refs = 0;
-    bool factored = false;
-    bool retain = false;
-    bool broken = false;
-    int sym = 0;           // sweeps read the symmetric coefficient storage
-    bool asym = false;     // symmetric storage requested for a non-symmetric A
-    uint64_t last_use = 0;
 };
 
-struct Req;
+struct GpuReq;
 
 // Two requests of one resident system swept together (FP32 factors): b and x
 // of both interleaved, their own face words and three control blocks (the
 // sweep's, one per request).  Each request stops at its own tolerance; the
 // pair's buffers go when both have.
 struct Pair {
-    Req *r[2] = {nullptr, nullptr};
-    Resident *sys = nullptr;
+    GpuReq *r[2] = {nullptr, nullptr};
+    GpuResident *sys = nullptr;
     int idx = -1;             // control blocks pctl[3 idx .. 3 idx + 2]
     double *bx = nullptr;     // b pairs, then x pairs
     void *y = nullptr;
@@ -87,63 +73,88 @@ struct Pair {
     size_t held = 0;          // budget bytes of a finished member, released with the pair
 };
 
-struct Req {
-    uint64_t ticket = 0;
-    sip_request r{};
-    double t_submit = 0, t_admit = 0, t_done = 0;
-    int state = 0;   // 0 queued, 1 running, 2 done
-    sip_result res{};
-    // running state
-    Resident *sys = nullptr;
-    int slot = -1;
+struct GpuReq final : Req {
     double *bx = nullptr;
     void *y = nullptr;
     uint64_t *face = nullptr;
     double *part = nullptr;
-    double *hist = nullptr;
-    size_t bytes = 0;
-    bool fresh = true;       // b / x0 not staged yet
-    int factorised = 0;
     Pair *pair = nullptr;    // swept together with another request
     int pm = 0;              // which of the pair
     hipEvent_t ready = nullptr;   // recorded on the caller's stream at submit
+    ~GpuReq() override
+    {
+        if (ready) (void)hipEventDestroy(ready);
+    }
 };
 
-size_t slot_bytes(const Geom &g, int fp32, int max_iter)
+GpuResident *gsys(const Req *q) { return static_cast<GpuResident *>(q->sys); }
+
+size_t slot_bytes(const Geom &g, int fp32)
 {
     const size_t E = (size_t)g.elems;
-    (void)max_iter;   // served requests keep no residual history
     return E * (2 * 8 + (fp32 ? 4 : 8)) + (size_t)g.ntiles * g.steps * FACE_WORDS * 8 + (size_t)g.ntiles * 16;
 }
 
 size_t resident_bytes(const Geom &g, int fp32) { return (size_t)g.elems * (7 * 8 + 7 * (fp32 ? 4 : 8)); }
 
-}  // namespace
+sip_status dev_alloc(void **p, size_t n, hipStream_t s)
+{
+    hipError_t e = hipMallocAsync(p, n ? n : 1, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return set_error(SIP_ENOMEM, "device allocation of %zu bytes failed", n);
+    }
+    return SIP_OK;
+}
 
-struct sip_server_s {
+void dev_free(void *p, hipStream_t s)
+{
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+// x behind b in the request's buffer, in the precision of the sweeps
+void *x_of(const GpuResident *s, const GpuReq *q)
+{
+    return s->arith == ARITH_F32 ? (void *)((float *)q->bx + s->g.elems) : (void *)(q->bx + s->g.elems);
+}
+
+// x pairs behind the b pairs, in the precision of the sweeps
+void *pair_x(const Pair *p)
+{
+    const size_t E = (size_t)p->sys->g.elems;
+    return p->sys->arith == ARITH_F32 ? (void *)((float *)p->bx + 2 * E) : (void *)(p->bx + 2 * E);
+}
+
+Job job_of(const GpuResident *s, const GpuReq *q, Ctl *ctl, int fw)
+{
+    Job J{};
+    J.g = s->g;
+    J.A = s->A;
+    J.LU = s->LU;
+    J.b = q->bx;
+    J.x = x_of(s, q);
+    J.y = q->y;
+    J.face = q->face;
+    J.part = q->part;
+    J.hist = nullptr;   // served requests keep no residual history
+    J.ctl = ctl + q->slot;
+    J.alpha = s->alpha;
+    J.fw = fw;
+    J.sym = fw == FACE_WORDS ? 0 : s->sym;   // the factorisation reads the full coefficients
+    return J;
+}
+
+class GpuBackend final : public Backend {
+public:
     sip_server_config cfg{};
     int device = 0;
     int num_cu = 256;   // compute units of the device
     hipStream_t stream = nullptr;
     uint64_t timeout_ticks = 0;
     uint32_t torture = 0;   // schedule_seed() at creation: a new random order every launch group
+    uint64_t steps = 0;     // steps run (varies the race-testing orders)
     std::chrono::steady_clock::time_point t0;
-    std::thread thread;
-    std::once_flag stop_once;   // sip_server_shutdown / sip_server_destroy stop the thread once
-    std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    bool quit = false;
-    uint64_t next_ticket = 1;
-    std::deque<Req *> queue;
-    std::vector<Req *> running;
-    std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
-    std::unordered_map<uint64_t, std::unique_ptr<Resident>> systems;
-    std::unordered_map<uint64_t, int> queued_ids;   // system id -> queued requests naming it
-    size_t used = 0, peak = 0;
-    uint64_t clock = 0;
-    // factorisations, evictions, epochs, resident, peak, completed, admitted, launches, pairs formed,
-    // epochs replayed from a graph
-    uint64_t stats[SIP_SERVER_NSTATS] = {0};
     // The sweeps of an epoch as a captured graph.  Its kernels read the job
     // list and ticket orders from device buffers uploaded before every epoch,
     // so the graph stays valid while the launch parameters (buffer addresses,
@@ -152,15 +163,9 @@ struct sip_server_s {
     hipGraphExec_t epoch_exec = nullptr;
     std::vector<uint64_t> epoch_key;
     bool graphs = true;   // SIP_SERVER_GRAPHS=0 launches every epoch eagerly
-    // race testing: a different random ticket order for every launch group
-    uint32_t order_seed(int grp) const
-    {
-        return torture ? (torture + 7919u * (uint32_t)stats[2] + 104729u * (uint32_t)grp) | 1u : 0u;
-    }
     // device-side scratch for launches
     Ctl *ctl = nullptr;                      // MAX_SLOTS control blocks
     Ctl *h_ctl = nullptr;                    // pinned mirror
-    std::vector<int> free_slots;
     // per launch group: factor storage or sweep arithmetic; NARITH + arith for pairs
     Job *d_jobs[2 * NARITH] = {};
     int2 *d_order[2 * NARITH][2] = {};
@@ -180,7 +185,6 @@ struct sip_server_s {
     // arriving (admission at every epoch boundary costs no drain).
     // SIP_SERVER_PERSISTENT=1 / 0 forces one of the two.
     int persistent = -1;                      // -1 adaptive, 1 always, 0 never
-    uint64_t tickets_at_launch = 0;           // next_ticket when the last launch was decided
     int *d_torder[2 * NARITH] = {};
     int *d_off[2 * NARITH] = {};
     Task *d_tasks[2 * NARITH] = {};
@@ -194,227 +198,152 @@ struct sip_server_s {
     SweepPlan plan{};
     bool plan_forced = false;   // SIP_SWEEP_PHASES set: no tuned plans
 
-    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
-    void loop();
-    bool admit_locked(std::vector<Req *> &admitted, std::vector<Resident *> &to_factor);
-    bool make_room_locked(size_t need);
-    void dequeue_locked(Req *q);
-    void free_resident_locked(Resident *s);
-    void finish_locked(Req *q, sip_status st, int iters, double rho);
-    sip_status run_factor(const std::vector<Resident *> &sys, const std::vector<Req *> &owners);
-    sip_status run_epoch(std::vector<Req *> &act);
+    // race testing: a different random ticket order for every launch group
+    uint32_t order_seed(int grp) const
+    {
+        return torture ? (torture + 7919u * (uint32_t)steps + 104729u * (uint32_t)grp) | 1u : 0u;
+    }
+
+    sip_status init(sip_server_config &c);
+    ~GpuBackend() override;
+
+    double now() override
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    void thread_start() override { (void)hipSetDevice(device); }
+    sip_status check_problem(const sip_problem &p) override
+    {
+        // kernels address every array with 32-bit byte offsets
+        if (make_geom(p.ni, p.nj, p.nk).elems >= MAX_ELEMS) return set_error(SIP_EINVAL, "block too large");
+        return SIP_OK;
+    }
+    size_t system_bytes(const sip_problem &p) override
+    {
+        return resident_bytes(make_geom(p.ni, p.nj, p.nk), p.precision != SIP_FP64);
+    }
+    size_t request_bytes(const sip_problem &p, const Resident *res) override
+    {
+        if (res) return slot_bytes(static_cast<const GpuResident *>(res)->g, static_cast<const GpuResident *>(res)->fp32);
+        return slot_bytes(make_geom(p.ni, p.nj, p.nk), p.precision != SIP_FP64);
+    }
+    sip_status new_request(const sip_request &r, std::unique_ptr<Req> *out) override;
+    sip_status new_system(const Req &q, std::unique_ptr<Resident> *out) override;
+    void free_system(Resident *s) override
+    {
+        auto *gs = static_cast<GpuResident *>(s);
+        dev_free(gs->A, stream);
+        dev_free(gs->LU, stream);
+        gs->A = nullptr;
+        gs->LU = nullptr;
+    }
+    sip_status alloc_request(Req *q) override;
+    size_t release_request(Req *q) override;
+    void wait_for_callers(const std::vector<Req *> &admitted) override
+    {
+        // the coefficients, b and x0 were produced on the caller's stream:
+        // everything after this that reads them runs after that stream's work
+        for (Req *q : admitted)
+            if (hipEvent_t e = static_cast<GpuReq *>(q)->ready) (void)hipStreamWaitEvent(stream, e, 0);
+    }
+    void factor(const std::vector<Resident *> &sys, const std::vector<Req *> &owners,
+                std::vector<sip_status> &result) override;
+    void stage(std::vector<Req *> &ready) override;
+    sip_status step(std::vector<Req *> &act) override;
+    Outcome outcome(const Req *q, sip_status st) override;
+    void retire(const std::vector<Req *> &fin, sip_status st) override;
+    void drain() override { (void)hipStreamSynchronize(stream); }
+
+private:
+    sip_status run_factor(const std::vector<GpuResident *> &sys, const std::vector<GpuReq *> &owners,
+                          std::vector<sip_status> &result);
     sip_status run_persist(int grp, const std::vector<Job> &jobs, const std::vector<Geom> &gs, const SweepPlan &gp,
                            bool others_waiting);
     bool want_pause(double since_launch, bool others_waiting);
-    void form_pairs(std::vector<Req *> &ready);
+    void form_pairs(std::vector<GpuReq *> &ready);
     void free_pair(Pair *p);
     sip_status ensure_launch_buffers(int grp, int njobs, int ntiles);
 };
 
-namespace {
-
-sip_status dev_alloc(void **p, size_t n, hipStream_t s)
+sip_status GpuBackend::new_request(const sip_request &r, std::unique_ptr<Req> *out)
 {
-    hipError_t e = hipMallocAsync(p, n ? n : 1, s);
-    if (e != hipSuccess) {
+    // orders the server's reads of the request's arrays after the caller's
+    // work on its stream (the event is destroyed with the request object)
+    auto q = std::make_unique<GpuReq>();
+    if (hipEventCreateWithFlags(&q->ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(q->ready, (hipStream_t)r.stream) != hipSuccess) {
         (void)hipGetLastError();
-        *p = nullptr;
-        return set_error(SIP_ENOMEM, "device allocation of %zu bytes failed", n);
+        return set_error(SIP_EDEVICE, "could not record the ordering event on the caller's stream");
     }
+    *out = std::move(q);
     return SIP_OK;
 }
 
-void dev_free(void *p, hipStream_t s)
+sip_status GpuBackend::new_system(const Req &q, std::unique_ptr<Resident> *out)
 {
-    if (p) (void)hipFreeAsync(p, s);
-}
-
-}  // namespace
-
-void sip_server_s::free_resident_locked(Resident *s)
-{
-    dev_free(s->A, stream);
-    dev_free(s->LU, stream);
-    used -= s->bytes;
-    systems.erase(s->id);
-}
-
-void sip_server_s::dequeue_locked(Req *q)
-{
-    auto f = queued_ids.find(q->r.system_id);
-    if (f != queued_ids.end() && --f->second == 0) queued_ids.erase(f);
-}
-
-// Evicts unreferenced systems, least-recently-used first, until `need` more
-// bytes fit.  A system that a queued request names is kept: that request may
-// carry no coefficients and could not be served once its factors are gone.
-bool sip_server_s::make_room_locked(size_t need)
-{
-    while (used + need > cfg.hbm_budget_bytes) {
-        Resident *victim = nullptr;
-        for (auto &kv : systems) {
-            Resident *s = kv.second.get();
-            if (s->refs != 0 || queued_ids.count(s->id)) continue;
-            if (!victim || s->last_use < victim->last_use) victim = s;
-        }
-        if (!victim) return false;
-        free_resident_locked(victim);
-        stats[1]++;
+    const sip_problem &pb = q.r.problem;
+    auto rs = std::make_unique<GpuResident>();
+    rs->g = make_geom(pb.ni, pb.nj, pb.nk);
+    rs->arith = pb.precision;
+    rs->fp32 = pb.precision != SIP_FP64;
+    rs->alpha = pb.alpha;
+    rs->sym = pb.storage == SIP_STORAGE_SYMMETRIC;
+    if (dev_alloc((void **)&rs->A, 7 * (size_t)rs->g.elems * 8, stream) != SIP_OK ||
+        dev_alloc(&rs->LU, 7 * (size_t)rs->g.elems * (rs->fp32 ? 4 : 8), stream) != SIP_OK) {
+        free_system(rs.get());
+        return SIP_ENOMEM;
     }
-    return true;
+    *out = std::move(rs);
+    return SIP_OK;
 }
 
-bool sip_server_s::admit_locked(std::vector<Req *> &admitted, std::vector<Resident *> &to_factor)
+sip_status GpuBackend::alloc_request(Req *rq)
 {
-    bool any = false;
-    for (auto it = queue.begin(); it != queue.end();) {
-        Req *q = *it;
-        if ((int)running.size() + (int)admitted.size() >= cfg.max_slots || free_slots.empty()) break;
-        const sip_problem &pb = q->r.problem;
-        Resident *s = nullptr;
-        auto f = systems.find(q->r.system_id);
-        if (f != systems.end()) s = f->second.get();
-        const Geom g = s ? s->g : make_geom(pb.ni, pb.nj, pb.nk);
-        const int arith = s ? s->arith : pb.precision;
-        const int fp32 = arith != SIP_FP64;
-        const size_t need_slot = slot_bytes(g, fp32, q->r.max_iter);
-        const size_t need_sys = s ? 0 : resident_bytes(g, fp32);
-        if (s) s->refs++;   // pin while making room
-        const bool fits = make_room_locked(need_slot + need_sys);
-        if (s) s->refs--;
-        if (!fits) {
-            ++it;           // first fit: a smaller request behind may still fit
-            continue;
-        }
-        if (!s) {
-            bool ok = pb.ni == g.ni && pb.alpha >= 0.0 && pb.alpha <= 1.0;
-            for (int d = 0; d < 7; d++) ok = ok && pb.a[d] != nullptr;
-            if (!ok) {   // a request that must factorise needs its coefficients
-                finish_locked(q, SIP_EINVAL, 0, 0.0);
-                dequeue_locked(q);
-            it = queue.erase(it);
-                continue;
-            }
-            auto rs = std::make_unique<Resident>();
-            rs->id = q->r.system_id;
-            rs->g = g;
-            rs->fp32 = fp32;
-            rs->arith = arith;
-            rs->alpha = pb.alpha;
-            rs->sym = pb.storage == SIP_STORAGE_SYMMETRIC;
-            rs->bytes = need_sys;
-            if (dev_alloc((void **)&rs->A, 7 * (size_t)g.elems * 8, stream) != SIP_OK ||
-                dev_alloc(&rs->LU, 7 * (size_t)g.elems * (fp32 ? 4 : 8), stream) != SIP_OK) {
-                dev_free(rs->A, stream);
-                dev_free(rs->LU, stream);
-                finish_locked(q, SIP_ENOMEM, 0, 0.0);
-                dequeue_locked(q);
-            it = queue.erase(it);
-                continue;
-            }
-            used += need_sys;
-            s = rs.get();
-            systems[rs->id] = std::move(rs);
-            to_factor.push_back(s);
-            q->factorised = 1;
-        }
-        q->sys = s;
-        s->refs++;
-        s->retain = s->retain || q->r.retain;
-        s->last_use = ++clock;
-        q->bytes = need_slot;
-        const size_t E = (size_t)g.elems;
-        if (dev_alloc((void **)&q->bx, 2 * E * 8, stream) != SIP_OK ||
-            dev_alloc(&q->y, E * (fp32 ? 4 : 8), stream) != SIP_OK ||
-            dev_alloc((void **)&q->face, (size_t)g.ntiles * g.steps * FACE_WORDS * 8, stream) != SIP_OK ||
-            dev_alloc((void **)&q->part, (size_t)g.ntiles * 16, stream) != SIP_OK) {
-            dev_free(q->bx, stream);
-            dev_free(q->y, stream);
-            dev_free(q->face, stream);
-            dev_free(q->part, stream);
-            dev_free(q->hist, stream);
-            q->bx = nullptr;
-            q->y = nullptr;
-            q->face = nullptr;
-            q->part = nullptr;
-            q->hist = nullptr;
-            s->refs--;
-            finish_locked(q, SIP_ENOMEM, 0, 0.0);
-            dequeue_locked(q);
-            it = queue.erase(it);
-            continue;
-        }
-        (void)hipMemsetAsync(q->face, 0, (size_t)g.ntiles * g.steps * FACE_WORDS * 8, stream);
-        used += need_slot;
-        peak = std::max(peak, used);
-        q->slot = free_slots.back();
-        free_slots.pop_back();
-        q->state = 1;
-        q->t_admit = now();
-        admitted.push_back(q);
-        stats[6]++;
-        dequeue_locked(q);
-        it = queue.erase(it);
-        any = true;
-    }
-    return any;
+    auto *q = static_cast<GpuReq *>(rq);
+    const Geom &g = gsys(q)->g;
+    const size_t E = (size_t)g.elems;
+    const size_t fbytes = (size_t)g.ntiles * g.steps * FACE_WORDS * 8;
+    if (dev_alloc((void **)&q->bx, 2 * E * 8, stream) != SIP_OK ||
+        dev_alloc(&q->y, E * (gsys(q)->fp32 ? 4 : 8), stream) != SIP_OK ||
+        dev_alloc((void **)&q->face, fbytes, stream) != SIP_OK ||
+        dev_alloc((void **)&q->part, (size_t)g.ntiles * 16, stream) != SIP_OK)
+        return SIP_ENOMEM;   // release_request frees what was allocated
+    (void)hipMemsetAsync(q->face, 0, fbytes, stream);
+    return SIP_OK;
 }
 
-void sip_server_s::finish_locked(Req *q, sip_status st, int iters, double rho)
+size_t GpuBackend::release_request(Req *rq)
 {
-    q->state = 2;
-    q->t_done = now();
-    q->res.status = st;
-    q->res.info.iters = iters;
-    q->res.info.rel_res = rho;
-    q->res.info.seconds = q->t_done - q->t_submit;
-    q->res.t_submit = q->t_submit;
-    q->res.t_admit = q->t_admit;
-    q->res.t_done = q->t_done;
-    q->res.factorised = q->factorised;
+    auto *q = static_cast<GpuReq *>(rq);
     dev_free(q->bx, stream);
     dev_free(q->y, stream);
     dev_free(q->face, stream);
     dev_free(q->part, stream);
-    dev_free(q->hist, stream);
     q->bx = nullptr;
     q->y = nullptr;
     q->face = nullptr;
     q->part = nullptr;
-    q->hist = nullptr;
     if (q->ready) {   // the server stream's wait on it, if any, is already enqueued
         (void)hipEventDestroy(q->ready);
         q->ready = nullptr;
     }
+    size_t give = q->bytes;
     if (Pair *p = q->pair) {
         // the pair's buffers stand for both members' budget bytes: they are
         // released when the second member is done
         p->done[q->pm] = true;
         p->held += q->bytes;
-        q->bytes = 0;
+        give = 0;
         q->pair = nullptr;
         if (p->done[0] && p->done[1]) {
-            used -= p->held;
+            give = p->held;
             free_pair(p);
         }
     }
-    if (q->slot >= 0) {
-        free_slots.push_back(q->slot);
-        q->slot = -1;
-        used -= q->bytes;
-    }
-    if (q->sys) {
-        Resident *s = q->sys;
-        q->sys = nullptr;
-        s->refs--;
-        s->last_use = ++clock;
-        if (s->refs == 0 && (!s->retain || s->broken)) free_resident_locked(s);
-    }
-    stats[5]++;
-    cv_done.notify_all();
+    return give;
 }
 
-void sip_server_s::free_pair(Pair *p)
+void GpuBackend::free_pair(Pair *p)
 {
     dev_free(p->bx, stream);
     dev_free(p->y, stream);
@@ -425,26 +354,19 @@ void sip_server_s::free_pair(Pair *p)
     delete p;
 }
 
-// x pairs behind the b pairs, in the precision of the sweeps
-static void *pair_x(const Pair *p)
-{
-    const size_t E = (size_t)p->sys->g.elems;
-    return p->sys->arith == ARITH_F32 ? (void *)((float *)p->bx + 2 * E) : (void *)(p->bx + 2 * E);
-}
-
 // Pairs freshly admitted requests of one resident system (FP32 factors, the
 // same rtol and max_iter, start vectors both given or both zero): they share
 // one pass of the sweeps over A and the factors.  The pair's buffers replace
 // the members' own, inside the budget the members were admitted with.
-void sip_server_s::form_pairs(std::vector<Req *> &ready)
+void GpuBackend::form_pairs(std::vector<GpuReq *> &ready)
 {
     if (!pairing) return;
-    std::vector<Req *> open;
-    for (Req *q : ready) {
-        const Resident *rs = q->sys;
+    std::vector<GpuReq *> open;
+    for (GpuReq *q : ready) {
+        const GpuResident *rs = gsys(q);
         if (rs->arith != ARITH_MIXED && rs->arith != ARITH_F32) continue;
-        Req *mate = nullptr;
-        for (Req *o : open)
+        GpuReq *mate = nullptr;
+        for (GpuReq *o : open)
             if (o->sys == rs && o->r.rtol == q->r.rtol && o->r.max_iter == q->r.max_iter &&
                 (o->r.x0 == nullptr) == (q->r.x0 == nullptr)) {
                 mate = o;
@@ -460,7 +382,7 @@ void sip_server_s::form_pairs(std::vector<Req *> &ready)
         const size_t E = (size_t)g.elems;
         const size_t fbytes = (size_t)g.ntiles * g.steps * FACE_WORDS * 8;
         Pair *p = new Pair();
-        p->sys = q->sys;
+        p->sys = gsys(q);
         if (dev_alloc((void **)&p->bx, 4 * E * 8, stream) != SIP_OK || dev_alloc(&p->y, 2 * E * 4, stream) != SIP_OK ||
             dev_alloc((void **)&p->face, fbytes, stream) != SIP_OK ||
             dev_alloc((void **)&p->part, (size_t)g.ntiles * 32, stream) != SIP_OK) {
@@ -488,7 +410,7 @@ void sip_server_s::form_pairs(std::vector<Req *> &ready)
         }
         (void)launch_init_ctl(pctl + 3 * p->idx, 3, (uint32_t)q->r.max_iter, q->r.rtol, 1, stream);
         for (int m = 0; m < 2; m++) {
-            Req *r = p->r[m];
+            GpuReq *r = p->r[m];
             dev_free(r->bx, stream);
             dev_free(r->y, stream);
             dev_free(r->face, stream);
@@ -501,11 +423,11 @@ void sip_server_s::form_pairs(std::vector<Req *> &ready)
             r->pm = m;
         }
         pairs.push_back(p);
-        stats[8]++;
+        host->count(STAT_PAIRS, 1);
     }
 }
 
-sip_status sip_server_s::ensure_launch_buffers(int grp, int njobs, int ntiles)
+sip_status GpuBackend::ensure_launch_buffers(int grp, int njobs, int ntiles)
 {
     if (njobs > jobs_cap[grp]) {
         dev_free(d_jobs[grp], stream);
@@ -525,34 +447,26 @@ sip_status sip_server_s::ensure_launch_buffers(int grp, int njobs, int ntiles)
     return SIP_OK;
 }
 
-// x behind b in the request's buffer, in the precision of the sweeps
-static void *x_of(const Resident *s, const Req *q)
+void GpuBackend::factor(const std::vector<Resident *> &sys, const std::vector<Req *> &owners,
+                        std::vector<sip_status> &result)
 {
-    return s->arith == ARITH_F32 ? (void *)((float *)q->bx + s->g.elems) : (void *)(q->bx + s->g.elems);
-}
-
-static Job job_of(const Resident *s, const Req *q, Ctl *ctl, int fw)
-{
-    Job J{};
-    J.g = s->g;
-    J.A = s->A;
-    J.LU = s->LU;
-    J.b = q->bx;
-    J.x = x_of(s, q);
-    J.y = q->y;
-    J.face = q->face;
-    J.part = q->part;
-    J.hist = q->hist;
-    J.ctl = ctl + q->slot;
-    J.alpha = s->alpha;
-    J.fw = fw;
-    J.sym = fw == FACE_WORDS ? 0 : s->sym;   // the factorisation reads the full coefficients
-    return J;
+    std::vector<GpuResident *> gs;
+    std::vector<GpuReq *> go;
+    for (size_t k = 0; k < sys.size(); k++) {
+        gs.push_back(static_cast<GpuResident *>(sys[k]));
+        go.push_back(static_cast<GpuReq *>(owners[k]));
+    }
+    if (run_factor(gs, go, result) != SIP_OK)
+        for (sip_status &r : result)
+            if (r == SIP_OK) r = SIP_EBREAKDOWN;
 }
 
 // Factorise newly resident systems, all of them in one batched launch per
 // precision; each uses the face words of the request that brought it in.
-sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const std::vector<Req *> &owners)
+// A symmetric-storage request whose A is not symmetric fails with SIP_EINVAL,
+// a factorisation that breaks down with SIP_EBREAKDOWN.
+sip_status GpuBackend::run_factor(const std::vector<GpuResident *> &sys, const std::vector<GpuReq *> &owners,
+                                  std::vector<sip_status> &result)
 {
     const Range range("server factorisations");
     for (int grp = 0; grp < 2; grp++) {
@@ -568,7 +482,7 @@ sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const st
                     hipStreamSynchronize(stream) != hipSuccess)
                     return set_error(SIP_EDEVICE, "symmetry check failed");
                 if (*h_bad) {
-                    sys[k]->asym = true;
+                    result[k] = SIP_EINVAL;
                     continue;
                 }
             }
@@ -595,7 +509,7 @@ sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const st
         // the all-FP32 arithmetic FP32 coefficients; either overwrites the full
         // FP64 storage once the factorisation is done
         for (size_t k = 0; k < sys.size(); k++) {
-            if (sys[k]->fp32 != grp || sys[k]->asym) continue;
+            if (sys[k]->fp32 != grp || result[k] != SIP_OK) continue;
             const int sc = sys[k]->sym ? SHEAR_SYM : sys[k]->arith == ARITH_F32 ? SHEAR_COEF32 : SHEAR_COEF;
             if (sc != SHEAR_COEF &&
                 launch_to_sheared(sys[k]->g, 7, owners[k]->r.problem.a, sys[k]->A, sys[k]->g.elems, sc, stream) !=
@@ -604,28 +518,58 @@ sip_status sip_server_s::run_factor(const std::vector<Resident *> &sys, const st
         }
         // the host copies of jobs/orders must live until the copies ran
         if (hipStreamSynchronize(stream) != hipSuccess) return set_error(SIP_EDEVICE, "factorisation failed");
-        stats[7]++;
+        host->count(STAT_LAUNCHES, 1);
     }
-    stats[0] += sys.size();
+    if (hipMemcpyAsync(h_ctl, ctl, sizeof(Ctl) * MAX_SLOTS, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return set_error(SIP_EDEVICE, "factorisation status copy failed");
+    for (size_t k = 0; k < sys.size(); k++)
+        if (result[k] == SIP_OK && h_ctl[owners[k]->slot].stop != RUN) result[k] = SIP_EBREAKDOWN;
     return SIP_OK;
 }
 
-// One epoch: epoch_iters (forward, backward) pairs over every running request.
-sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
+// Stages b and x0 of newly admitted requests (pairs with their partner).
+void GpuBackend::stage(std::vector<Req *> &ready_reqs)
+{
+    std::vector<GpuReq *> ready;
+    for (Req *q : ready_reqs) ready.push_back(static_cast<GpuReq *>(q));
+    form_pairs(ready);
+    for (GpuReq *q : ready) {
+        if (q->pair) continue;   // staged with its partner
+        const GpuResident *rs = gsys(q);
+        const Geom &g = rs->g;
+        const double *src[2] = {q->r.b, q->r.x0 ? q->r.x0 : nullptr};
+        const bool f32 = rs->arith == ARITH_F32;   // the relaxation starts from FP32 copies
+        const int sh = f32 ? SHEAR_F32 : SHEAR_F64;
+        if (q->r.x0) {
+            (void)launch_to_sheared(g, 2, src, q->bx, g.elems, sh, stream);
+        } else {
+            (void)launch_to_sheared(g, 1, src, q->bx, g.elems, sh, stream);
+            (void)hipMemsetAsync(x_of(rs, q), 0, (size_t)g.elems * (f32 ? 4 : 8), stream);
+        }
+        (void)launch_init_ctl(ctl + q->slot, 1, (uint32_t)q->r.max_iter, q->r.rtol, 0, stream);
+    }
+}
+
+// One step: epoch_iters (forward, backward) pairs over every running request,
+// or one persistent launch.
+sip_status GpuBackend::step(std::vector<Req *> &act)
 {
     const Range range("server epoch");
+    steps++;
     // groups 0..NARITH-1: single requests by arithmetic; NARITH + arith: pairs
     constexpr int NG = 2 * NARITH;
     std::vector<Job> jobs[NG];
     std::vector<Geom> gs[NG];
-    for (Req *q : act) {
+    for (Req *rq : act) {
+        const auto *q = static_cast<const GpuReq *>(rq);
         if (q->pair) continue;
-        const int grp = q->sys->arith;
-        jobs[grp].push_back(job_of(q->sys, q, ctl, FACE_WORDS_SWEEP));
-        gs[grp].push_back(q->sys->g);
+        const int grp = gsys(q)->arith;
+        jobs[grp].push_back(job_of(gsys(q), q, ctl, FACE_WORDS_SWEEP));
+        gs[grp].push_back(gsys(q)->g);
     }
     for (Pair *p : pairs) {
-        const Resident *rs = p->sys;
+        const GpuResident *rs = p->sys;
         Job J{};
         J.g = rs->g;
         J.A = rs->A;
@@ -675,12 +619,8 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
             if (J.g.elems > big->g.elems) big = &J;
         (void)tuned_plan(big->g, grp % NARITH, big->sym, &gplan[grp]);
     }
-    bool use_persistent = persistent == 1;
-    if (persistent < 0) {
-        std::lock_guard<std::mutex> lk(mu);
-        use_persistent = next_ticket == tickets_at_launch;   // nothing submitted since the last launch
-        tickets_at_launch = next_ticket;
-    }
+    // persistent while nothing was submitted since the last step
+    const bool use_persistent = persistent < 0 ? !host->arrivals_since_last_step() : persistent == 1;
     if (use_persistent) {
         int groups = 0;
         for (int grp = 0; grp < NG; grp++) groups += !jobs[grp].empty();
@@ -694,7 +634,7 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
              hipMemcpyAsync(h_pctl, pctl, sizeof(Ctl) * 3 * MAX_PAIRS, hipMemcpyDeviceToHost, stream) != hipSuccess) ||
             hipStreamSynchronize(stream) != hipSuccess)
             return set_error(SIP_EDEVICE, "launch failed: %s", hipGetErrorString(hipGetLastError()));
-        stats[2]++;
+        host->count(STAT_EPOCHS, 1);
         return SIP_OK;
     }
     auto launch_all = [&]() -> bool {
@@ -715,11 +655,12 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
             key.push_back(0);
             continue;
         }
-        key.insert(key.end(), {1, (uint64_t)gplan[grp].phases, (uint64_t)(uintptr_t)fa[grp].jobs,
-                               (uint64_t)(uintptr_t)fa[grp].order, (uint64_t)(uintptr_t)ba[grp].order,
-                               (uint64_t)(uintptr_t)fa[grp].lc, (uint64_t)fa[grp].total, (uint64_t)ba[grp].total,
-                               fa[grp].timeout_ticks, (uint64_t)fa[grp].jitter});
-        stats[7] += 2 * (uint64_t)cfg.epoch_iters;
+        key.insert(key.end(), {1, (uint64_t)gplan[grp].phases, (uint64_t)gplan[grp].poll,
+                               (uint64_t)(uintptr_t)fa[grp].jobs, (uint64_t)(uintptr_t)fa[grp].order,
+                               (uint64_t)(uintptr_t)ba[grp].order, (uint64_t)(uintptr_t)fa[grp].lc,
+                               (uint64_t)fa[grp].total, (uint64_t)ba[grp].total, fa[grp].timeout_ticks,
+                               (uint64_t)fa[grp].jitter});
+        host->count(STAT_LAUNCHES, 2 * (uint64_t)cfg.epoch_iters);
     }
     const bool same = key == epoch_key;
     epoch_key = key;
@@ -740,7 +681,7 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
     }
     if (epoch_exec) {
         if (hipGraphLaunch(epoch_exec, stream) != hipSuccess) return set_error(SIP_EDEVICE, "epoch graph launch failed");
-        stats[9]++;
+        host->count(STAT_GRAPH_EPOCHS, 1);
     } else if (!launch_all()) {
         return set_error(SIP_EDEVICE, "sweep launch failed");
     }
@@ -749,7 +690,7 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
          hipMemcpyAsync(h_pctl, pctl, sizeof(Ctl) * 3 * MAX_PAIRS, hipMemcpyDeviceToHost, stream) != hipSuccess) ||
         hipStreamSynchronize(stream) != hipSuccess)
         return set_error(SIP_EDEVICE, "epoch failed: %s", hipGetErrorString(hipGetLastError()));
-    stats[2]++;
+    host->count(STAT_EPOCHS, 1);
     return SIP_OK;
 }
 
@@ -758,23 +699,22 @@ sip_status sip_server_s::run_epoch(std::vector<Req *> &act)
 // cannot be admitted yet does not restart the launch over and over), a request
 // has stopped and waits to be retired, another launch group waits for its
 // turn, or the server is shutting down.
-bool sip_server_s::want_pause(double since_launch, bool others_waiting)
+bool GpuBackend::want_pause(double since_launch, bool others_waiting)
 {
     // a pause drains the launch (every request finishes its iteration), so it
     // is asked for no more often than these intervals
     constexpr double ADMIT = 10e-3, RETIRE = 20e-3, SLICE = 20e-3;
     if (since_launch >= RETIRE && __atomic_load_n(h_stopped, __ATOMIC_ACQUIRE)) return true;
     if (others_waiting && since_launch >= SLICE) return true;
-    std::lock_guard<std::mutex> lk(mu);
-    if (quit) return true;
-    return since_launch >= ADMIT && !queue.empty() && (int)running.size() < cfg.max_slots;
+    if (host->quitting()) return true;
+    return since_launch >= ADMIT && host->admission_waiting();
 }
 
 // One persistent launch for the jobs of launch group grp: every job starts at
 // its next forward sweep (an iteration boundary) and runs until it stops or
 // the host asks for a pause.
-sip_status sip_server_s::run_persist(int grp, const std::vector<Job> &jobs, const std::vector<Geom> &gs,
-                                     const SweepPlan &gp, bool others_waiting)
+sip_status GpuBackend::run_persist(int grp, const std::vector<Job> &jobs, const std::vector<Geom> &gs,
+                                   const SweepPlan &gp, bool others_waiting)
 {
     const int arith = grp % NARITH, nrhs = grp < NARITH ? 1 : 2;
     const int nj = (int)jobs.size();
@@ -841,7 +781,7 @@ sip_status sip_server_s::run_persist(int grp, const std::vector<Job> &jobs, cons
         return set_error(SIP_EDEVICE, "persistent launch failed");
     if (hipMemcpyAsync(h_pc, d_pc, sizeof(PersistCtl), hipMemcpyDeviceToHost, stream) != hipSuccess)
         return set_error(SIP_EDEVICE, "status copy failed");
-    stats[7]++;
+    host->count(STAT_LAUNCHES, 1);
     // while it runs: pause requests (the host vectors above stay alive until
     // the launch is over, so the copies from them have run)
     bool paused = false;
@@ -860,362 +800,147 @@ sip_status sip_server_s::run_persist(int grp, const std::vector<Job> &jobs, cons
     return SIP_OK;
 }
 
-void sip_server_s::loop()
+// Where a request stands after the step: its control block (a pair member's
+// own, with the pair's sweep failures) as copied back at the step's end.
+Outcome GpuBackend::outcome(const Req *rq, sip_status st)
 {
-    (void)hipSetDevice(device);
-    for (;;) {
-        std::vector<Req *> admitted;
-        std::vector<Resident *> to_factor;
-        {
-            std::unique_lock<std::mutex> lk(mu);
-            cv_work.wait(lk, [&] { return quit || !queue.empty() || !running.empty(); });
-            if (quit) break;
-            admit_locked(admitted, to_factor);
-        }
-        // the coefficients, b and x0 were produced on the caller's stream:
-        // everything below that reads them runs after that stream's work
-        for (Req *q : admitted)
-            if (q->ready) (void)hipStreamWaitEvent(stream, q->ready, 0);
-        // factorise new systems (owners = the admitted request that brought each in)
-        if (!to_factor.empty()) {
-            std::vector<Req *> owners;
-            for (Resident *s : to_factor)
-                for (Req *q : admitted)
-                    if (q->sys == s) {
-                        owners.push_back(q);
-                        break;
-                    }
-            const sip_status st = run_factor(to_factor, owners);
-            (void)hipMemcpyAsync(h_ctl, ctl, sizeof(Ctl) * MAX_SLOTS, hipMemcpyDeviceToHost, stream);
-            (void)hipStreamSynchronize(stream);
-            std::lock_guard<std::mutex> lk(mu);
-            for (size_t k = 0; k < to_factor.size(); k++) {
-                const uint32_t stop = st == SIP_OK ? h_ctl[owners[k]->slot].stop : TIMEOUT;
-                if (stop == RUN && !to_factor[k]->asym) {
-                    to_factor[k]->factored = true;
-                } else {
-                    to_factor[k]->broken = true;
-                }
-            }
-        }
-        // stage b and x0 of newly admitted requests; fail those whose system broke down
-        std::vector<Req *> ready;
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            for (Req *q : admitted) {
-                if (q->sys->broken) {
-                    finish_locked(q, q->sys->asym ? SIP_EINVAL : SIP_EBREAKDOWN, 0, 0.0);
-                    continue;
-                }
-                ready.push_back(q);
-            }
-        }
-        form_pairs(ready);
-        for (Req *q : ready) {
-            if (q->pair) continue;   // staged with its partner
-            const Geom &g = q->sys->g;
-            const double *src[2] = {q->r.b, q->r.x0 ? q->r.x0 : nullptr};
-            const bool f32 = q->sys->arith == ARITH_F32;   // the relaxation starts from FP32 copies
-            const int sh = f32 ? SHEAR_F32 : SHEAR_F64;
-            if (q->r.x0) {
-                (void)launch_to_sheared(g, 2, src, q->bx, g.elems, sh, stream);
-            } else {
-                (void)launch_to_sheared(g, 1, src, q->bx, g.elems, sh, stream);
-                (void)hipMemsetAsync(x_of(q->sys, q), 0, (size_t)g.elems * (f32 ? 4 : 8), stream);
-            }
-            (void)launch_init_ctl(ctl + q->slot, 1, (uint32_t)q->r.max_iter, q->r.rtol, 0, stream);
-        }
-        std::vector<Req *> act;
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            for (Req *q : ready) running.push_back(q);
-            act = running;
-        }
-        if (act.empty()) continue;
-        const sip_status st = run_epoch(act);
-        // retire finished requests: copy x out, then report them done
-        std::vector<Req *> fin;
-        for (Req *q : act) {
-            if (Pair *p = q->pair) {
-                const Ctl &c = h_pctl[3 * p->idx + 1 + q->pm];
-                const uint32_t js = h_pctl[3 * p->idx].stop;
-                if (st != SIP_OK || c.stop != RUN || js == BREAKDOWN || js == TIMEOUT) {
-                    if (st == SIP_OK)
-                        (void)launch_from_sheared(q->sys->g, pair_x(p), q->sys->arith == ARITH_F32, q->r.x,
-                                                  pctl + 3 * p->idx + 1 + q->pm, stream, 2, q->pm);
-                    fin.push_back(q);
-                }
-                continue;
-            }
-            const Ctl &c = h_ctl[q->slot];
-            if (st != SIP_OK || c.stop != RUN) {
-                if (st == SIP_OK)
-                    (void)launch_from_sheared(q->sys->g, x_of(q->sys, q), q->sys->arith == ARITH_F32, q->r.x,
-                                              ctl + q->slot, stream);
-                fin.push_back(q);
-            }
-        }
-        if (!fin.empty()) (void)hipStreamSynchronize(stream);
-        std::lock_guard<std::mutex> lk(mu);
-        for (Req *q : fin) {
-            Ctl c = h_ctl[q->slot];
-            if (const Pair *p = q->pair) {
-                c = h_pctl[3 * p->idx + 1 + q->pm];
-                const uint32_t js = h_pctl[3 * p->idx].stop;
-                if (js == BREAKDOWN || js == TIMEOUT) c.stop = js;
-                if (c.stop == ZERO_RHS) c.rho = 0.0;
-            }
-            sip_status rs = SIP_OK;
-            if (st != SIP_OK) rs = st;
-            else if (c.stop == MAXITER) rs = SIP_ENOTCONV;
-            else if (c.stop == BREAKDOWN || c.stop == DIVERGED) rs = SIP_EBREAKDOWN;
-            else if (c.stop == BAD_INPUT) rs = SIP_EINVAL;   // non-finite b, x0 or A x0
-            else if (c.stop == TIMEOUT) rs = SIP_EDEVICE;
-            finish_locked(q, rs, (int)c.iter, c.rho);
-            running.erase(std::find(running.begin(), running.end(), q));
-        }
+    const auto *q = static_cast<const GpuReq *>(rq);
+    Outcome o;
+    Ctl c = h_ctl[q->slot];
+    if (const Pair *p = q->pair) {
+        c = h_pctl[3 * p->idx + 1 + q->pm];
+        const uint32_t js = h_pctl[3 * p->idx].stop;
+        if (js == BREAKDOWN || js == TIMEOUT) c.stop = js;
+        if (c.stop == ZERO_RHS) c.rho = 0.0;
     }
-    // cancel everything still queued or running
-    std::lock_guard<std::mutex> lk(mu);
-    for (Req *q : queue) finish_locked(q, SIP_ECANCELLED, 0, 0.0);
-    queue.clear();
-    queued_ids.clear();
-    for (Req *q : running) finish_locked(q, SIP_ECANCELLED, 0, 0.0);
-    running.clear();
+    o.done = st != SIP_OK || c.stop != RUN;
+    if (!o.done) return o;
+    o.iters = (int)c.iter;
+    o.rho = c.rho;
+    if (st != SIP_OK) o.status = st;
+    else if (c.stop == MAXITER) o.status = SIP_ENOTCONV;
+    else if (c.stop == BREAKDOWN || c.stop == DIVERGED) o.status = SIP_EBREAKDOWN;
+    else if (c.stop == BAD_INPUT) o.status = SIP_EINVAL;   // non-finite b, x0 or A x0
+    else if (c.stop == TIMEOUT) o.status = SIP_EDEVICE;
+    return o;
 }
 
-extern "C" {
-
-sip_status sip_server_create(const sip_server_config *c, sip_server *out)
+// Copies x of the stopped requests out (after a failed step, nothing).
+void GpuBackend::retire(const std::vector<Req *> &fin, sip_status st)
 {
-    if (!c || !out) return set_error(SIP_EINVAL, "NULL argument");
-    if (c->max_slots < 1 || c->max_slots > MAX_SLOTS || c->epoch_iters < 1 || c->max_queue < 1)
-        return set_error(SIP_EINVAL, "bad server configuration");
-    auto *s = new sip_server_s();
-    s->cfg = *c;
-    if (const hipError_t e = hipGetDevice(&s->device); e != hipSuccess) {
-        delete s;
+    if (st == SIP_OK)
+        for (Req *rq : fin) {
+            const auto *q = static_cast<const GpuReq *>(rq);
+            const GpuResident *rs = gsys(q);
+            if (const Pair *p = q->pair)
+                (void)launch_from_sheared(rs->g, pair_x(p), rs->arith == ARITH_F32, q->r.x,
+                                          pctl + 3 * p->idx + 1 + q->pm, stream, 2, q->pm);
+            else
+                (void)launch_from_sheared(rs->g, x_of(rs, q), rs->arith == ARITH_F32, q->r.x, ctl + q->slot, stream);
+        }
+    (void)hipStreamSynchronize(stream);
+}
+
+sip_status GpuBackend::init(sip_server_config &c)
+{
+    cfg = c;
+    if (const hipError_t e = hipGetDevice(&device); e != hipSuccess)
         return set_error(SIP_EDEVICE, "no HIP device: hipGetDevice: %s", hipGetErrorString(e));
-    }
-    if (s->cfg.hbm_budget_bytes == 0) {
+    if (c.hbm_budget_bytes == 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)8 << 30;
-        s->cfg.hbm_budget_bytes = fr / 4 * 3;
+        c.hbm_budget_bytes = fr / 4 * 3;
     }
     if (const char *e = getenv("SIP_SWEEP_PHASES")) {
         const int nl = atoi(e);
         if (nl >= 1 && nl <= sipk::MAX_PHASES) {
-            s->plan.phases = nl;
-            s->plan_forced = true;
+            plan.phases = nl;
+            plan_forced = true;
         }
     }
     if (const char *e = getenv("SIP_POLL_DISTANCE")) {
         const int pd = atoi(e);
         if (pd >= 1 && pd <= sipk::MAX_POLL) {
-            s->plan.poll = pd;
-            s->plan_forced = true;
+            plan.poll = pd;
+            plan_forced = true;
         }
     }
-    if (const char *e = getenv("SIP_SERVER_PAIRS")) s->pairing = atoi(e) != 0;
-    if (const char *e = getenv("SIP_SERVER_GRAPHS")) s->graphs = atoi(e) != 0;
-    if (const char *e = getenv("SIP_SERVER_PERSISTENT")) s->persistent = atoi(e) != 0 ? 1 : 0;
-    s->timeout_ticks = timeout_ticks_for(s->device, 2.0);
-    s->torture = schedule_seed();
+    if (const char *e = getenv("SIP_SERVER_PAIRS")) pairing = atoi(e) != 0;
+    if (const char *e = getenv("SIP_SERVER_GRAPHS")) graphs = atoi(e) != 0;
+    if (const char *e = getenv("SIP_SERVER_PERSISTENT")) persistent = atoi(e) != 0 ? 1 : 0;
+    timeout_ticks = timeout_ticks_for(device, 2.0);
+    torture = schedule_seed();
     {
         int ncu = 0;
-        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device) == hipSuccess && ncu > 0)
-            s->num_cu = ncu;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+            num_cu = ncu;
     }
-    s->t0 = std::chrono::steady_clock::now();
-    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
-        hipMalloc((void **)&s->ctl, sizeof(Ctl) * MAX_SLOTS) != hipSuccess ||
-        hipHostMalloc((void **)&s->h_ctl, sizeof(Ctl) * MAX_SLOTS, hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void **)&s->lc, sizeof(LaunchCtl)) != hipSuccess ||
-        hipMalloc((void **)&s->pctl, sizeof(Ctl) * 3 * MAX_PAIRS) != hipSuccess ||
-        hipHostMalloc((void **)&s->h_pctl, sizeof(Ctl) * 3 * MAX_PAIRS, hipHostMallocDefault) != hipSuccess ||
-        hipMemsetAsync(s->pctl, 0, sizeof(Ctl) * 3 * MAX_PAIRS, s->stream) != hipSuccess ||
-        launch_init_ctl(s->pctl, 3 * MAX_PAIRS, 0, 0.0, 1, s->stream) != hipSuccess ||
-        hipMalloc((void **)&s->d_bad, sizeof(unsigned)) != hipSuccess ||
-        hipHostMalloc((void **)&s->h_bad, sizeof(unsigned), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void **)&s->d_pc, sizeof(PersistCtl)) != hipSuccess ||
-        hipHostMalloc((void **)&s->h_pc, sizeof(PersistCtl), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&s->h_pause, sizeof(uint32_t), hipHostMallocCoherent) != hipSuccess ||
-        hipHostMalloc((void **)&s->h_stopped, sizeof(uint32_t), hipHostMallocCoherent) != hipSuccess ||
-        hipHostGetDevicePointer((void **)&s->d_pause, s->h_pause, 0) != hipSuccess ||
-        hipHostGetDevicePointer((void **)&s->d_stopped, s->h_stopped, 0) != hipSuccess ||
+    t0 = std::chrono::steady_clock::now();
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc((void **)&ctl, sizeof(Ctl) * MAX_SLOTS) != hipSuccess ||
+        hipHostMalloc((void **)&h_ctl, sizeof(Ctl) * MAX_SLOTS, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&lc, sizeof(LaunchCtl)) != hipSuccess ||
+        hipMalloc((void **)&pctl, sizeof(Ctl) * 3 * MAX_PAIRS) != hipSuccess ||
+        hipHostMalloc((void **)&h_pctl, sizeof(Ctl) * 3 * MAX_PAIRS, hipHostMallocDefault) != hipSuccess ||
+        hipMemsetAsync(pctl, 0, sizeof(Ctl) * 3 * MAX_PAIRS, stream) != hipSuccess ||
+        launch_init_ctl(pctl, 3 * MAX_PAIRS, 0, 0.0, 1, stream) != hipSuccess ||
+        hipMalloc((void **)&d_bad, sizeof(unsigned)) != hipSuccess ||
+        hipHostMalloc((void **)&h_bad, sizeof(unsigned), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&d_pc, sizeof(PersistCtl)) != hipSuccess ||
+        hipHostMalloc((void **)&h_pc, sizeof(PersistCtl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&h_pause, sizeof(uint32_t), hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc((void **)&h_stopped, sizeof(uint32_t), hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&d_pause, h_pause, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&d_stopped, h_stopped, 0) != hipSuccess ||
         // on the server's own stream, in order: the stream does not synchronise
         // with the legacy default stream, so a plain hipMemset could land after
         // the initialisation and reset the epochs to 0, which the zeroed face
         // words of a fresh request would then match
-        hipMemsetAsync(s->ctl, 0, sizeof(Ctl) * MAX_SLOTS, s->stream) != hipSuccess ||
-        hipMemsetAsync(s->lc, 0, sizeof(LaunchCtl), s->stream) != hipSuccess ||
-        launch_init_ctl(s->ctl, MAX_SLOTS, 0, 0.0, 1, s->stream) != hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess) {
+        hipMemsetAsync(ctl, 0, sizeof(Ctl) * MAX_SLOTS, stream) != hipSuccess ||
+        hipMemsetAsync(lc, 0, sizeof(LaunchCtl), stream) != hipSuccess ||
+        launch_init_ctl(ctl, MAX_SLOTS, 0, 0.0, 1, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
         (void)hipGetLastError();
-        delete s;
         return set_error(SIP_ENOMEM, "server buffers");
     }
-    for (int k = MAX_SLOTS - 1; k >= 0; k--) s->free_slots.push_back(k);
-    for (int k = MAX_PAIRS - 1; k >= 0; k--) s->free_pairs.push_back(k);
-    s->thread = std::thread([s] { s->loop(); });
-    *out = s;
+    for (int k = MAX_PAIRS - 1; k >= 0; k--) free_pairs.push_back(k);
     return SIP_OK;
 }
 
-sip_status sip_batch_submit(sip_server s, const sip_request *r, uint64_t *ticket)
+GpuBackend::~GpuBackend()
 {
-    if (!s || !r || !ticket) return set_error(SIP_EINVAL, "NULL argument");
-    if (!r->b || !r->x) return set_error(SIP_EINVAL, "b and x are required");
-    if (!(r->rtol > 0.0) || r->max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
-    const sip_problem &p = r->problem;
-    // orders the server's reads of the request's arrays after the caller's
-    // work on its stream (the event is destroyed when the request finishes)
-    hipEvent_t ready = nullptr;
-    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(ready, (hipStream_t)r->stream) != hipSuccess) {
-        if (ready) (void)hipEventDestroy(ready);
-        (void)hipGetLastError();
-        return set_error(SIP_EDEVICE, "could not record the ordering event on the caller's stream");
-    }
-    struct EventGuard {   // destroys the event unless the request takes it
-        hipEvent_t e;
-        ~EventGuard() { if (e) (void)hipEventDestroy(e); }
-    } guard{ready};
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->quit) return set_error(SIP_ECANCELLED, "the server is shut down");
-    auto f = s->systems.find(r->system_id);
-    const bool resident = f != s->systems.end();
-    bool queued_same = false;
-    for (Req *q : s->queue) queued_same = queued_same || q->r.system_id == r->system_id;
-    if (!resident && !queued_same) {
-        if (p.ni < 1 || p.nj < 1 || p.nk < 1) return set_error(SIP_EINVAL, "dims must be >= 1");
-        if (!(p.alpha >= 0.0 && p.alpha <= 1.0)) return set_error(SIP_EINVAL, "alpha must be in [0, 1]");
-        if (p.precision != SIP_FP64 && p.precision != SIP_MIXED && p.precision != SIP_FP32)
-            return set_error(SIP_EINVAL, "unknown precision");
-        if (p.storage != SIP_STORAGE_FULL && p.storage != SIP_STORAGE_SYMMETRIC)
-            return set_error(SIP_EINVAL, "unknown storage");
-        if (p.storage == SIP_STORAGE_SYMMETRIC && p.precision == SIP_FP32)
-            return set_error(SIP_EINVAL, "the symmetric storage is available with SIP_FP64 and SIP_MIXED only");
-        for (int d = 0; d < 7; d++)
-            if (!p.a[d]) return set_error(SIP_EINVAL, "coefficient pointer %d is NULL", d);
-    }
-    const Geom g = resident ? f->second->g : make_geom(p.ni, p.nj, p.nk);
-    if (g.elems >= sipk::MAX_ELEMS) return set_error(SIP_EINVAL, "block too large");
-    if (resident && (p.ni != g.ni || p.nj != g.nj || p.nk != g.nk))
-        return set_error(SIP_EINVAL, "dims differ from the resident system");
-    const int fp32 = resident ? f->second->fp32 : p.precision != SIP_FP64;
-    const size_t need = slot_bytes(g, fp32, r->max_iter) + (resident ? 0 : resident_bytes(g, fp32));
-    if (need > s->cfg.hbm_budget_bytes) return set_error(SIP_ENOMEM, "request needs %zu bytes, budget %zu", need, s->cfg.hbm_budget_bytes);
-    if ((int)s->queue.size() >= s->cfg.max_queue) return set_error(SIP_EBUSY, "queue full");
-    auto q = std::make_unique<Req>();
-    q->ticket = s->next_ticket++;
-    q->r = *r;
-    q->t_submit = s->now();
-    q->ready = ready;
-    guard.e = nullptr;
-    *ticket = q->ticket;
-    s->queued_ids[r->system_id]++;
-    s->queue.push_back(q.get());
-    s->reqs[q->ticket] = std::move(q);
-    s->cv_work.notify_one();
-    return SIP_OK;
-}
-
-sip_status sip_batch_poll(sip_server s, uint64_t ticket, int32_t wait_ms, sip_result *out)
-{
-    if (!s || !out) return set_error(SIP_EINVAL, "NULL argument");
-    std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return set_error(SIP_EINVAL, "unknown ticket");
-    Req *q = it->second.get();
-    auto done = [&] { return q->state == 2; };
-    if (!done()) {
-        if (wait_ms < 0) s->cv_done.wait(lk, done);
-        else if (wait_ms > 0) s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), done);
-    }
-    if (!done()) return SIP_PENDING;
-    *out = q->res;
-    s->reqs.erase(it);
-    return SIP_OK;
-}
-
-sip_status sip_server_release(sip_server s, uint64_t system_id)
-{
-    if (!s) return set_error(SIP_EINVAL, "NULL argument");
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto f = s->systems.find(system_id);
-    if (f == s->systems.end()) return SIP_OK;
-    f->second->retain = false;
-    if (f->second->refs == 0) s->free_resident_locked(f->second.get());
-    return SIP_OK;
-}
-
-sip_status sip_server_stats(sip_server s, uint64_t out[SIP_SERVER_NSTATS])
-{
-    if (!s || !out) return set_error(SIP_EINVAL, "NULL argument");
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stats[3] = s->used;
-    s->stats[4] = s->peak;
-    std::memcpy(out, s->stats, sizeof s->stats);
-    return SIP_OK;
-}
-
-// Ends the scheduler thread after its current step; it cancels what is not
-// done.  Afterwards no kernel of the server touches a request's arrays.
-static void stop_server(sip_server s)
-{
-    std::call_once(s->stop_once, [s] {
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->quit = true;
-        }
-        s->cv_work.notify_all();
-        if (s->thread.joinable()) s->thread.join();
-        (void)hipStreamSynchronize(s->stream);
-    });
-}
-
-sip_status sip_server_shutdown(sip_server s)
-{
-    if (!s) return set_error(SIP_EINVAL, "NULL argument");
-    stop_server(s);
-    return SIP_OK;
-}
-
-sip_status sip_server_destroy(sip_server s)
-{
-    if (!s) return set_error(SIP_EINVAL, "NULL argument");
-    stop_server(s);
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        std::vector<Resident *> all;
-        for (auto &kv : s->systems) all.push_back(kv.second.get());
-        for (Resident *r : all) s->free_resident_locked(r);
-    }
+    if (!stream) return;
+    for (Pair *p : std::vector<Pair *>(pairs)) free_pair(p);
     for (int grp = 0; grp < 2 * NARITH; grp++) {
-        dev_free(s->d_jobs[grp], s->stream);
-        dev_free(s->d_order[grp][0], s->stream);
-        dev_free(s->d_order[grp][1], s->stream);
-        dev_free(s->d_torder[grp], s->stream);
-        dev_free(s->d_off[grp], s->stream);
-        dev_free(s->d_tasks[grp], s->stream);
+        dev_free(d_jobs[grp], stream);
+        dev_free(d_order[grp][0], stream);
+        dev_free(d_order[grp][1], stream);
+        dev_free(d_torder[grp], stream);
+        dev_free(d_off[grp], stream);
+        dev_free(d_tasks[grp], stream);
     }
-    (void)hipStreamSynchronize(s->stream);
-    if (s->epoch_exec) (void)hipGraphExecDestroy(s->epoch_exec);
-    (void)hipFree(s->ctl);
-    (void)hipFree(s->lc);
-    (void)hipFree(s->pctl);
-    (void)hipHostFree(s->h_pctl);
-    (void)hipHostFree(s->h_ctl);
-    (void)hipFree(s->d_bad);
-    (void)hipHostFree(s->h_bad);
-    (void)hipFree(s->d_pc);
-    (void)hipHostFree(s->h_pc);
-    (void)hipHostFree(s->h_pause);
-    (void)hipHostFree(s->h_stopped);
-    (void)hipStreamDestroy(s->stream);
-    delete s;
-    return SIP_OK;
+    (void)hipStreamSynchronize(stream);
+    if (epoch_exec) (void)hipGraphExecDestroy(epoch_exec);
+    (void)hipFree(ctl);
+    (void)hipFree(lc);
+    (void)hipFree(pctl);
+    (void)hipHostFree(h_pctl);
+    (void)hipHostFree(h_ctl);
+    (void)hipFree(d_bad);
+    (void)hipHostFree(h_bad);
+    (void)hipFree(d_pc);
+    (void)hipHostFree(h_pc);
+    (void)hipHostFree(h_pause);
+    (void)hipHostFree(h_stopped);
+    (void)hipStreamDestroy(stream);
 }
 
-}  // extern "C"
+}  // namespace
+
+sip_status sipk::make_backend(sip_server_config &cfg, std::unique_ptr<Backend> *out)
+{
+    auto be = std::make_unique<GpuBackend>();
+    if (const sip_status e = be->init(cfg); e != SIP_OK) return e;
+    *out = std::move(be);
+    return SIP_OK;
+}
