@@ -10,9 +10,10 @@ update) to a relative residual of 1e-8.
 
 value = cells * iterations / wall time of the timed steps (cell-iterations/s),
 inputs resident in HBM before the timed region.  The line also reports the
-same solve in plain FP64, the forward-sweep kernel's achieved bandwidth
-against the HBM peak (timed with HIP events on the launch stream) and the CPU
-oracle on a bounded sample of the same workload.
+same solve in plain FP64, the achieved bandwidth of the persistent solve
+kernel (one launch runs every sweep of a solve; timed with HIP events on the
+launch stream) against the HBM peak, the two sweeps launched one at a time
+for comparison, and the CPU oracle on a bounded sample of the same workload.
 
 With the default 256^3 workload the line also carries, under "configs", the
 other configurations at their full sizes, each with its throughput, the
@@ -45,13 +46,16 @@ PAIR_FWD_BYTES = 56 + 16 + 2 * (8 + 8 + 4)     # per cell, both right-hand sides
 PAIR_BWD_BYTES = 12 + 2 * (4 + 8 + 8)
 RTOL = 1e-8
 SOLVE_BYTES_MIXED = FWD_BYTES["mixed"] + BWD_BYTES["mixed"]   # one mixed iteration, both sweeps
-# HBM bytes per launch of the sweep kernels on the 256^3 workload, from the
-# rocprofv3 FETCH_SIZE / WRITE_SIZE passes summarised in
-# profiles/sweeps_256cube_cd.md (calibrated against a plain copy), with
-# the SHA-256 of the kernel source they were taken with.  Once the source
-# differs the counters no longer describe the kernel and traffic is null.
-MEASURED = {"kernels_sha256": "aec6a72e026d29a1beea76be21d99d20bb837992ca147327ccbfec1cc984a94f",
-            "n": 256, "fwd_bytes": 1766797262, "bwd_bytes": 602316320}
+# HBM bytes per launch of the persistent solve kernel (one launch = one whole
+# mixed solve) on the 256^3 and the 512x512x256 workloads, from the rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes summarised in profiles/solve_256cube_cd.md and
+# profiles/solve_512x512x256_stretched.md (calibrated against a plain copy),
+# with the iterations of that solve and the SHA-256 of the kernel
+# source they were taken with.  Once the source differs the counters no
+# longer describe the kernel and traffic is null.
+MEASURED = {"kernels_sha256": "d6445c5003a043c36bc47604e65713924b915504316770ac5c1372014dd90dd1",
+            "single": {"iterations": 4069, "persist_bytes": 9764153166720},
+            "large": {"iterations": 15239, "persist_bytes": 147522399636580}}
 
 
 def log(msg):
@@ -119,23 +123,25 @@ def parse():
     ap.add_argument("--storage", default="full", choices=["full", "symmetric"],
                     help="coefficient storage of the sweeps (symmetric: Poisson workloads only)")
     ap.add_argument("--workload", default="single",
-                    choices=["single", "batched", "large", "serving", "pair", "blocks", "tune"],
+                    choices=["single", "batched", "large", "serving", "pair", "blocks", "tune", "steps"],
                     help="single: 256^3 block (default); batched: 64 uneven blocks through the solve "
                          "server; large: 512x512x256 stretched Poisson; serving: Poisson-arrival "
                          "request stream (8 right-hand sides per system); pair: the 256^3 block with "
                          "two right-hand sides swept together; blocks: the 256^3 domain cut into "
                          "--blocks-per-axis^3 blocks coupled through boundary values; tune: every sweep plan "
                          "(loader phases x poll distance) timed on blocks of 32^3 to 512x512x256, with "
-                         "sip_tune's choice")
+                         "sip_tune's choice; steps: the sweeps' time per tile step on shapes that separate "
+                         "the step time from the hop lag")
     ap.add_argument("--blocks-per-axis", type=int, default=2, help="blocks along each axis (workload blocks)")
     ap.add_argument("--serve-systems", type=int, default=40, help="systems in the serving stream (8 rhs each)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="server HBM budget")
     ap.add_argument("--epoch-iters", type=int, default=8, help="server iterations per epoch (batched, serving)")
     ap.add_argument("--prof", action="store_true",
-                    help="short run for rocprofv3: factor + a few sweeps of the default workload (mixed, "
-                         "a pair of right-hand sides, all-FP32; with --workload large: the 512x512x256 block, "
-                         "mixed and FP64) and a 512 MiB device copy used to calibrate the HBM byte counters")
+                    help="short run for rocprofv3: factor, a few sweeps and one persistent mixed solve of the "
+                         "default workload (sweeps: mixed, a pair of right-hand sides, all-FP32; with --workload "
+                         "large: the 512x512x256 block, mixed and FP64) and a 512 MiB device copy used to "
+                         "calibrate the HBM byte counters")
     return ap.parse_args()
 
 
@@ -160,6 +166,9 @@ def prof_run(args):
             S = sip.sip_factor(A, c["alpha"], precision)
             f, bk = sip.sip_profile_sweeps(S, b, torch.zeros_like(b), 5)
             print(f"prof: large {precision} forward {f:.4f} ms, backward {bk:.4f} ms per sweep", flush=True)
+            if precision == "mixed":
+                _, it, _, sec = sip.sip_solve(S, b, torch.zeros_like(b), RTOL, 200000)
+                print(f"prof: large mixed solve, {it} iterations in one persistent launch, {sec:.3f} s", flush=True)
             S.close()
         torch.cuda.synchronize()
         return
@@ -170,6 +179,8 @@ def prof_run(args):
     x = torch.zeros_like(b)
     fwd_ms, bwd_ms = sip.sip_profile_sweeps(S, b, x, 5)
     print(f"prof: mixed forward {fwd_ms:.4f} ms, backward {bwd_ms:.4f} ms per sweep", flush=True)
+    _, it, _, sec = sip.sip_solve(S, b, torch.zeros_like(b), RTOL, 200000)
+    print(f"prof: mixed solve, {it} iterations in one persistent launch, {sec:.3f} s", flush=True)
     # the same block with two right-hand sides swept together
     bs = [b, torch.flip(b, dims=(0,)).contiguous()]
     f2, b2 = sip.sip_profile_sweeps_multi(S, bs, [torch.zeros_like(b), torch.zeros_like(b)], 5)
@@ -386,6 +397,38 @@ def _serving_fields(m, rate):
             "mean_cells": m["mean_cells"], "mean_iters": m["mean_iters"]}
 
 
+def persist_roofline(cells, iters, solve_ms, storage="full", workload=None):
+    """Roofline of the persistent solve kernel k_persist, which runs every
+    sweep of one mixed solve in one launch: iters + 1 fused residual + forward
+    sweeps (the last one finds the residual below the tolerance) and iters
+    backward sweeps, each streaming its arrays once.  solve_ms is the
+    launch's device time from HIP events recorded just before and after it on
+    its stream (sip_system_solve_ms)."""
+    fwd_b = FWD_BYTES["mixed"] - (A_SYM_SAVING if storage == "symmetric" else 0)
+    alg = ((iters + 1) * fwd_b + iters * BWD_BYTES["mixed"]) * cells
+    achieved = alg / (solve_ms * 1e-3) / 1e9
+    traffic = None
+    m = MEASURED.get(workload) if workload else None
+    if m and storage == "full" and kernels_sha256() == MEASURED["kernels_sha256"] and m["iterations"] == iters:
+        traffic = round(m["persist_bytes"] / (solve_ms * 1e-3) / 1e9, 1)
+    return {"bound": "hbm",
+            "kernel": "k_persist<float, double, 3, 1> (whole mixed solve in one launch: FP64 residual + FP32 "
+                      "forward sweep, FP32 backward sweep + FP64 update, every iteration)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+            "launch_ms": round(solve_ms, 3),
+            "basis": f"({iters} + 1) x {fwd_b} + {iters} x {BWD_BYTES['mixed']} algorithmic B per cell per launch"}
+
+
+def sweep_detail(fwd_ms, bwd_ms, cells, storage="full"):
+    """The two sweep kernels launched one at a time (HIP events around each
+    launch): the per-sweep view of the same work."""
+    fwd_b = FWD_BYTES["mixed"] - (A_SYM_SAVING if storage == "symmetric" else 0)
+    return {"fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+            "fwd_gbps": round(fwd_b * cells / (fwd_ms * 1e-3) / 1e9, 1),
+            "bwd_gbps": round(BWD_BYTES["mixed"] * cells / (bwd_ms * 1e-3) / 1e9, 1)}
+
+
 def solve_roofline(rate):
     """Whole-solve bandwidth of a batched or served run: cell-iterations/s times
     the algorithmic bytes of one mixed iteration (forward + backward sweep), as
@@ -393,7 +436,8 @@ def solve_roofline(rate):
     (factorisations, layout copies and idle gaps included), so it bounds the
     sweeps' own fraction from below."""
     achieved = rate * SOLVE_BYTES_MIXED / 1e9
-    return {"bound": "hbm", "kernel": "whole solve: k_forward + k_backward over all active blocks (mixed)",
+    return {"bound": "hbm", "kernel": "whole solve: every sweep launch (persistent or per-epoch) over all active "
+                                      "blocks (mixed)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
             "basis": f"cell-iterations/s x {SOLVE_BYTES_MIXED} algorithmic B per mixed cell-iteration"}
@@ -461,8 +505,8 @@ def config3_summary(args, sip):
 def config4_summary(args, sip):
     """512 x 512 x 256 stretched-grid Poisson (67 M cells): factor + mixed solve
     to 1e-8 and the same in FP64, the mixed result's error against the FP64
-    result, the forward sweep's roofline (HIP events on the launch stream) and
-    the oracle on one host core (first iterations)."""
+    result, the persistent solve kernel's roofline (HIP events on the launch
+    stream) and the oracle on one host core (first iterations)."""
     import numpy as np
     import torch
 
@@ -482,23 +526,29 @@ def config4_summary(args, sip):
         torch.cuda.synchronize()
         secs[precision] = time.perf_counter() - t0
         if precision == "mixed":
+            if os.environ.get("SIP_SOLVE_PERSISTENT", "1") != "0":
+                solve_ms = sip.sip_system_solve_ms(S)   # HIP events around the launch, on its stream
             fwd_ms, bwd_ms = sip.sip_profile_sweeps(S, b, torch.zeros_like(b), args.profile_iters)
             rr_mixed = rr
         S.close()
         xs[precision], its[precision] = x, it
     value = cells * its["mixed"] / secs["mixed"]
-    achieved = FWD_BYTES["mixed"] * cells / (fwd_ms * 1e-3) / 1e9
+    if os.environ.get("SIP_SOLVE_PERSISTENT", "1") != "0":
+        roofline = persist_roofline(cells, its["mixed"], solve_ms, workload="large")
+        roofline["sweeps_one_launch_each"] = sweep_detail(fwd_ms, bwd_ms, cells)
+    else:
+        achieved = FWD_BYTES["mixed"] * cells / (fwd_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": "k_forward<float, double, 3, 1, 2> (FP64 residual + FP32 forward sweep)",
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                    **sweep_detail(fwd_ms, bwd_ms, cells)}
     out = {"workload": "512x512x256 stretched-grid Poisson (z ratio 1.05), alpha 0.92, factor + mixed solve to 1e-8",
            "cells": cells, "value": value, "unit": "cell-iterations/s", "seconds": secs["mixed"],
            "iterations": its["mixed"], "final_rel_res": rr_mixed, "fp64_iterations": its["fp64"],
            "fp64_cell_iters_per_s": cells * its["fp64"] / secs["fp64"],
            "mixed_speedup_vs_fp64": secs["fp64"] / secs["mixed"] * its["mixed"] / its["fp64"],
            "err_vs_fp64": rel_err(xs["mixed"], xs["fp64"]),
-           "roofline": {"bound": "hbm", "kernel": "k_forward<float, double, 3, 1, 2> (FP64 residual + FP32 forward sweep)",
-                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                        "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
-                        "bwd_gbps": round(BWD_BYTES["mixed"] * cells / (bwd_ms * 1e-3) / 1e9, 1)}}
+           "roofline": roofline}
     del A, b, xs
     torch.cuda.empty_cache()
     if not args.no_cpu:
@@ -782,6 +832,39 @@ def tune_run(args):
                       "plans": [f"{ph}x{pd}" for ph, pd in plans], "table": table}), flush=True)
 
 
+def steps_run(args):
+    """Step time and hop lag of the sweeps, separated: sip_profile_sweeps (HIP
+    events around each launch) on mixed convection-diffusion blocks whose
+    shapes isolate them -- one tile (no exchange, no contention), a row and a
+    column of 16 tiles (15 hops in a row), 8 x 8 tiles and the 256^3 block.
+    A launch of nk planes takes nk + 14 steps of its last tile (the shear of
+    the 8-lane tile edge), so us per step = launch time / (nk + 14)."""
+    import torch
+
+    from paper_1303_4538_amd import problems, sip
+
+    sip.lib()
+    shapes = [(16, 16, 256), (16, 16, 1024), (256, 16, 256), (16, 256, 256), (128, 128, 256), (256, 256, 256)]
+    rows = []
+    for dims in shapes:
+        ni, nj, nk = dims
+        A, b = problems.make_block(dims, "cd", np_seed(ni + 3 * nj + 7 * nk))
+        At, bt = torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda()
+        S = sip.sip_factor(At, problems.ALPHA, "mixed")
+        f, bk = sip.sip_profile_sweeps(S, bt, torch.zeros_like(bt), args.profile_iters)
+        plan = "%dx%d" % sip.sip_system_plan(S)
+        S.close()
+        row = {"dims": list(dims), "tiles": (ni // 16) * (nj // 16), "plan": plan, "fwd_ms": round(f, 4),
+               "bwd_ms": round(bk, 4), "fwd_us_per_step": round(f * 1e3 / (nk + 14), 3),
+               "bwd_us_per_step": round(bk * 1e3 / (nk + 14), 3)}
+        log(f"steps {dims}: {row}")
+        rows.append(row)
+        del At, bt
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "sweep step time: us per tile step (launch time / (nk + 14))", "table": rows}),
+          flush=True)
+
+
 def np_seed(k):
     import numpy as np
     return np.random.SeedSequence(1234 + k)
@@ -856,6 +939,9 @@ def main():
     if args.workload == "tune":
         tune_run(args)
         return
+    if args.workload == "steps":
+        steps_run(args)
+        return
     import numpy as np
     import torch
 
@@ -877,11 +963,21 @@ def main():
     torch.cuda.synchronize()
 
     xkeep = {}
+    persistent = os.environ.get("SIP_SOLVE_PERSISTENT", "1") != "0"
+    launch_ms, call_ms = [], []   # per timed solve: the persistent launch, the whole sip_solve call
 
-    def step(precision):
+    def step(precision, timed=False):
         S = sip.sip_factor(A, c["alpha"], precision, storage=args.storage)
         x = torch.zeros_like(b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         st, it, rr, _ = sip.sip_solve(S, b, x, RTOL, 200000)
+        e1.record()
+        if timed:
+            e1.synchronize()
+            call_ms.append(e0.elapsed_time(e1))
+            if persistent:   # HIP events around the launch, on its stream
+                launch_ms.append(sip.sip_system_solve_ms(S))
         S.close()
         xkeep[precision] = x
         return it, rr
@@ -891,7 +987,7 @@ def main():
         step("mixed")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results = [step("mixed") for _ in range(args.steps)]
+    results = [step("mixed", timed=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -917,25 +1013,30 @@ def main():
     if not args.no_extras and args.storage == "full" and args.workload == "single":
         extra["two_rhs_and_blocks"] = pair_and_blocks(sip, A, b, c["alpha"], n)
 
-    # dominant kernel: the fused residual + forward sweep (events on the launch stream)
+    # the sweeps launched one at a time (events around each launch)
     S = sip.sip_factor(A, c["alpha"], "mixed", storage=args.storage)
     x = torch.zeros_like(b)
     fwd_ms, bwd_ms = sip.sip_profile_sweeps(S, b, x, args.profile_iters)
     S.close()
     fwd_bytes = FWD_BYTES["mixed"] - (A_SYM_SAVING if args.storage == "symmetric" else 0)
-    achieved = fwd_bytes * cells / (fwd_ms * 1e-3) / 1e9
-    traffic = None
-    if (args.workload == "single" and args.storage == "full" and args.n == MEASURED["n"]
-            and kernels_sha256() == MEASURED["kernels_sha256"]):
-        traffic = round(MEASURED["fwd_bytes"] / (fwd_ms * 1e-3) / 1e9, 1)
-    phases = int(os.environ.get("SIP_SWEEP_PHASES", "3"))   # the single-system default: 3 loader phases
-    poll = int(os.environ.get("SIP_POLL_DISTANCE", "2"))    # and polls 2 steps ahead
-    roofline = {"bound": "hbm",
-                "kernel": f"k_forward<float, double, {phases}, 1, {poll}> (FP64 residual + FP32 forward sweep)",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
-                "bwd_gbps": round(BWD_BYTES["mixed"] * cells / (bwd_ms * 1e-3) / 1e9, 1)}
+    if persistent:
+        # dominant kernel: the persistent solve, one launch per timed solve
+        same_iters = len(set(iters)) == 1
+        wl = ("large" if args.workload == "large" else "single" if args.n == 256 else None) if same_iters else None
+        roofline = persist_roofline(cells, iters[0], sum(launch_ms) / len(launch_ms), args.storage, wl)
+        roofline["solve_call_ms"] = round(sum(call_ms) / len(call_ms), 3)
+        roofline["sweeps_one_launch_each"] = sweep_detail(fwd_ms, bwd_ms, cells, args.storage)
+        achieved = roofline["achieved"]
+    else:
+        # chunked graph replays: the fused residual + forward sweep dominates
+        achieved = fwd_bytes * cells / (fwd_ms * 1e-3) / 1e9
+        phases = int(os.environ.get("SIP_SWEEP_PHASES", "3"))   # the single-system default: 3 loader phases
+        poll = int(os.environ.get("SIP_POLL_DISTANCE", "2"))    # and polls 2 steps ahead
+        roofline = {"bound": "hbm",
+                    "kernel": f"k_forward<float, double, {phases}, 1, {poll}> (FP64 residual + FP32 forward sweep)",
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                    **sweep_detail(fwd_ms, bwd_ms, cells, args.storage)}
     # what a plain device copy reaches on this GPU, as context for the fraction
     copy = copy_gbps()
     roofline["copy_gbps"] = round(copy, 1)

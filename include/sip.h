@@ -276,18 +276,29 @@ sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phas
  * SIP_EINVAL (NULL handle). */
 sip_status sip_system_plan(sip_system h, int32_t *phases, int32_t *poll);
 
+/* sip_system_solve_ms -- device time of the handle's last persistent solve
+ * launch (Sec. 3 measures the solver's kernels one by one; sip_solve runs a
+ * whole solve as one launch): *ms (host) receives the time between HIP
+ * events recorded on the solve's stream just before and just after that
+ * launch; the layout copies, the factorisation and any host work are
+ * outside it.  Waits for the launch to finish.  Errors: SIP_EINVAL (NULL
+ * argument, or no persistent solve has run on the handle: the chunked path
+ * of SIP_SOLVE_PERSISTENT=0 is not timed), SIP_EDEVICE. */
+sip_status sip_system_solve_ms(sip_system h, double *ms);
+
 /* sip_tune_save / sip_tune_load -- the autotuner's table (kept across
  * processes, like the factorisation that Sec. 4.1 computes once in advance) (block shape,
- * precision, storage -> loader phases, as recorded by sip_tune) as a text
+ * precision, storage -> loader phases and poll distance, as recorded by sip_tune) as a text
  * file, so that a later process starts with the plans an earlier one
  * measured (load it before sip_factor or sip_server_create).  One JSON
  * object per line:
- *   {"ni": 256, "nj": 256, "nk": 256, "precision": 1, "symmetric": 0, "phases": 2}
+ *   {"ni": 256, "nj": 256, "nk": 256, "precision": 1, "symmetric": 0, "phases": 3, "poll": 2}
  * sip_tune_save writes every entry of the process's table (overwriting
  * path).  sip_tune_load merges the file's entries into the table (the file's
  * win); blank lines are skipped; a line that is not such an entry (missing
- * key, dims < 1, unknown precision, phases outside 1..3) fails the whole
- * load with SIP_EINVAL and merges nothing.  Host only, thread-safe.
+ * key, dims < 1, unknown precision, phases or poll outside 1..3) fails the
+ * whole load with SIP_EINVAL and merges nothing; a line without "poll" takes
+ * the default distance 2.  Host only, thread-safe.
  * Errors: SIP_EINVAL (NULL path, unreadable or unwritable file, bad line). */
 sip_status sip_tune_save(const char *path);
 sip_status sip_tune_load(const char *path);

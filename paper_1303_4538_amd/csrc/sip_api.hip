@@ -128,6 +128,8 @@ static void free_system(sip_system_s *h)
     if (h->h_ctl) hipHostFree(h->h_ctl);
     if (h->h_mctl) hipHostFree(h->h_mctl);
     if (h->h_hist) hipHostFree(h->h_hist);
+    for (hipEvent_t e : h->p_ev)
+        if (e) hipEventDestroy(e);
     delete h;
 }
 
@@ -425,6 +427,7 @@ static sip_status ensure_persist(sip_system_s *h, hipStream_t s)
     TRY(alloc_dev((void **)&h->p_tasks, (size_t)h->p_cap * sizeof(Task), "task queue"));
     TRY(alloc_dev((void **)&h->p_pc, sizeof(PersistCtl), "queue control"));
     TRY(alloc_dev((void **)&h->p_flags, 2 * sizeof(uint32_t), "queue flags"));
+    for (hipEvent_t &e : h->p_ev) HIPTRY(hipEventCreate(&e));
     std::vector<int> tord;
     for (int b = 0; b < 2; b++)
         for (const int2 &o : topo_order({g}, b != 0, h->torture ? h->torture + 17u * b : 0u)) tord.push_back(o.y);
@@ -450,7 +453,10 @@ static sip_status launch_solve_persistent(sip_system_s *h, hipStream_t s)
     const PersistArgs pa{h->d_job, h->p_tord, h->p_off, h->p_tasks, h->p_cap, h->p_pc, h->p_flags, h->p_flags + 1,
                          h->timeout_ticks, h->torture};
     const int wgs = std::max(1, std::min(g.ntiles, h->num_cu * (h->plan.phases >= 3 ? 1 : 2)));
+    HIPTRY(hipEventRecord(h->p_ev[0], s));
     HIPTRY(launch_persist(pa, h->precision, h->plan, wgs, s));
+    HIPTRY(hipEventRecord(h->p_ev[1], s));
+    h->p_timed = true;
     return SIP_OK;
 }
 
@@ -1105,6 +1111,17 @@ sip_status sip_system_plan(sip_system h, int32_t *phases, int32_t *poll)
     if (!h) return set_error(SIP_EINVAL, "NULL argument");
     if (phases) *phases = h->plan.phases;
     if (poll) *poll = h->plan.poll;
+    return SIP_OK;
+}
+
+sip_status sip_system_solve_ms(sip_system h, double *ms)
+{
+    if (!h || !ms) return set_error(SIP_EINVAL, "NULL argument");
+    if (!h->p_timed) return set_error(SIP_EINVAL, "no persistent solve has run on this handle");
+    float t = 0.0f;
+    HIPTRY(hipEventSynchronize(h->p_ev[1]));
+    HIPTRY(hipEventElapsedTime(&t, h->p_ev[0], h->p_ev[1]));
+    *ms = t;
     return SIP_OK;
 }
 

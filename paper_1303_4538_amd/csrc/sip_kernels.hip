@@ -1595,43 +1595,59 @@ struct DstPtrs {
     double *p[7];
 };
 
-__device__ __forceinline__ bool decode_sheared(const Geom &g, long long e, int &i, int &j, int &k)
-{
-    const int t = (int)(e / g.tile_elems);
-    const long long rem = e - (long long)t * g.tile_elems;
-    const int pl = (int)(rem / PLANE) - 1;
-    const int w = (int)(rem % PLANE);
-    const int q = w / TT, ln = w % TT;
-    const int ip = ln % LI, jp = ln / LI;
-    i = (t % g.nti) * TI + 2 * ip + (q & 1);
-    j = (t / g.nti) * TJ + 2 * jp + (q >> 1);
-    k = pl - ip - jp;
-    return pl >= 0 && pl < g.steps && i < g.ni && j < g.nj && k >= 0 && k < g.nk;
-}
-
+// The layout copies stage one tile column through LDS, so that both the
+// natural-order side (rows of TI cells) and the sheared side (whole local
+// planes of PLANE elements) are read and written in contiguous runs.  Local
+// plane s of a tile holds the cells with k = s - i' - j', i' + j' in
+// [0, SHEAR_SPAN], so a chunk of local planes needs SHEAR_SPAN more natural
+// planes than it has, and a chunk of natural planes as many more local ones.
+constexpr int SHEAR_SPAN = LI + LJ - 2;
+constexpr int TO_KC = 16;     // local planes (margins included) per workgroup of k_to_sheared
+constexpr int FROM_KC = 32;   // natural planes per workgroup of k_from_sheared
 
 // Copies narr natural-order FP64 arrays into the sheared layout `shear`
 // (T = float for SHEAR_F32 and SHEAR_COEF32, rounding to nearest): plain
 // arrays at dst + a * dst_stride, or the 7 coefficient arrays P..T with the
 // couplings that point out of the block zeroed, in the interleaved, symmetric
-// (P, E, N, T only) or FP32 group storage (sip_internal.h).
+// (P, E, N, T only) or FP32 group storage (sip_internal.h).  Workgroup =
+// (tile, chunk of TO_KC local planes); every slot of the chunk is written,
+// margins and padding with zeros.
 template <typename T>
-__global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, T *dst, long long dst_stride, int shear)
+__global__ __launch_bounds__(256) void k_to_sheared(Geom g, int narr, SrcPtrs src, T *dst, long long dst_stride,
+                                                    int shear)
 {
+    __shared__ double st[(TO_KC + SHEAR_SPAN) * TI * TJ];
     const bool coef = shear == SHEAR_COEF || shear == SHEAR_SYM || shear == SHEAR_COEF32;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.elems; e += stride) {
-        int i, j, k;
-        const bool ok = decode_sheared(g, e, i, j, k);
-        const long long n = ok ? ((long long)k * g.nj + j) * g.ni + i : 0;
-        for (int a = 0; a < narr; a++) {
-            double v = ok ? src.p[a][n] : 0.0;
+    const int nch = (g.planes + TO_KC - 1) / TO_KC;
+    const int tile = blockIdx.x / nch, p0 = (blockIdx.x % nch) * TO_KC;
+    const int p1 = min(p0 + TO_KC, g.planes);
+    const int kbase = p0 - 1 - SHEAR_SPAN;              // natural plane of st[0]
+    const int nkl = p1 - p0 + SHEAR_SPAN;               // natural planes staged
+    const int ti = tile % g.nti, tj = tile / g.nti;
+    const int t = threadIdx.x;
+    // this thread's slot in every local plane of the chunk
+    const int q = t / TT, ln = t % TT, ip = ln % LI, jp = ln / LI;
+    const int il = 2 * ip + (q & 1), jl = 2 * jp + (q >> 1);
+    const int i = ti * TI + il, j = tj * TJ + jl;
+    const bool inij = i < g.ni && j < g.nj;
+    for (int a = 0; a < narr; a++) {
+        const double *sa = src.p[a];
+        for (int r = t; r < nkl * TI * TJ; r += 256) {
+            const int k = kbase + r / (TI * TJ), ri = ti * TI + r % TI, rj = tj * TJ + (r / TI) % TJ;
+            st[r] = (k >= 0 && k < g.nk && ri < g.ni && rj < g.nj) ? sa[((long long)k * g.nj + rj) * g.ni + ri] : 0.0;
+        }
+        __syncthreads();
+        for (int p = p0; p < p1; p++) {
+            const int k = p - 1 - ip - jp;
+            const bool ok = inij && k >= 0 && k < g.nk;
+            double v = ok ? st[((k - kbase) * TJ + jl) * TI + il] : 0.0;
             if (coef && ok) {
                 // couplings that point out of the block are ignored
                 if ((a == 1 && i == 0) || (a == 2 && i == g.ni - 1) || (a == 3 && j == 0) ||
                     (a == 4 && j == g.nj - 1) || (a == 5 && k == 0) || (a == 6 && k == g.nk - 1))
                     v = 0.0;
             }
+            const long long e = (long long)tile * g.tile_elems + (long long)p * PLANE + t;
             if (shear == SHEAR_PAIR_F64 || shear == SHEAR_PAIR_F32) {
                 dst[2 * e + a] = (T)v;
             } else if (shear == SHEAR_SYM) {
@@ -1643,6 +1659,7 @@ __global__ void k_to_sheared(Geom g, int narr, SrcPtrs src, T *dst, long long ds
                 dst[coef ? coef_index(a, e, dst_stride) : a * dst_stride + e] = (T)v;
             }
         }
+        __syncthreads();   // st is refilled for the next array
     }
 }
 
@@ -1664,17 +1681,34 @@ __global__ void k_check_symmetric(int ni, int nj, int nk, SrcPtrs a, unsigned *b
     if (cnt) atomicAdd(bad, cnt);
 }
 
+// Copies x out of the sheared layout (element `which` of groups of `comp`)
+// into natural order as FP64; zeros when the solve found a zero right-hand
+// side.  Workgroup = (tile, chunk of FROM_KC natural planes).
 template <typename T>
-__global__ void k_from_sheared(Geom g, const T *src, double *dst, const Ctl *ctl, int comp, int which)
+__global__ __launch_bounds__(256) void k_from_sheared(Geom g, const T *src, double *dst, const Ctl *ctl, int comp,
+                                                      int which)
 {
-    const long long n = (long long)g.ni * g.nj * g.nk;
+    __shared__ double st[FROM_KC * TI * TJ];
     const bool zero = ctl != nullptr && ctl->stop == ZERO_RHS;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += stride) {
-        const int i = (int)(c % g.ni);
-        const int j = (int)((c / g.ni) % g.nj);
-        const int k = (int)(c / ((long long)g.ni * g.nj));
-        dst[c] = zero ? 0.0 : (double)src[comp * sheared_of(g, i, j, k) + which];
+    const int nch = (g.nk + FROM_KC - 1) / FROM_KC;
+    const int tile = blockIdx.x / nch, k0 = (blockIdx.x % nch) * FROM_KC;
+    const int k1 = min(k0 + FROM_KC, g.nk);
+    const int ti = tile % g.nti, tj = tile / g.nti;
+    const int t = threadIdx.x;
+    const int q = t / TT, ln = t % TT, ip = ln % LI, jp = ln / LI;
+    const int il = 2 * ip + (q & 1), jl = 2 * jp + (q >> 1);
+    // local planes k0 .. k1 - 1 + SHEAR_SPAN hold the chunk's cells
+    for (int s = k0; s < k1 + SHEAR_SPAN; s++) {
+        const int k = s - ip - jp;
+        if (k >= k0 && k < k1) {
+            const long long e = (long long)tile * g.tile_elems + (long long)(s + 1) * PLANE + t;
+            st[((k - k0) * TJ + jl) * TI + il] = (double)src[comp * e + which];
+        }
+    }
+    __syncthreads();
+    for (int r = t; r < (k1 - k0) * TI * TJ; r += 256) {
+        const int k = k0 + r / (TI * TJ), i = ti * TI + r % TI, j = tj * TJ + (r / TI) % TJ;
+        if (i < g.ni && j < g.nj) dst[((long long)k * g.nj + j) * g.ni + i] = zero ? 0.0 : st[r];
     }
 }
 
@@ -1879,7 +1913,7 @@ hipError_t launch_to_sheared(const Geom &g, int narr, const double *const *src, 
 {
     SrcPtrs sp{};
     for (int a = 0; a < narr && a < 9; a++) sp.p[a] = src[a];
-    const dim3 grid(grid_for(g.elems));
+    const dim3 grid((unsigned)g.ntiles * (unsigned)((g.planes + TO_KC - 1) / TO_KC));
     if (shear == SHEAR_F32 || shear == SHEAR_COEF32 || shear == SHEAR_PAIR_F32)
         hipLaunchKernelGGL(k_to_sheared<float>, grid, dim3(256), 0, s, g, narr, sp, (float *)dst, dst_stride, shear);
     else
@@ -1899,7 +1933,7 @@ hipError_t launch_check_symmetric(int ni, int nj, int nk, const double *const *a
 hipError_t launch_from_sheared(const Geom &g, const void *src, int src_f32, double *dst, const Ctl *ctl,
                                hipStream_t s, int comp, int which)
 {
-    const dim3 grid(grid_for((long long)g.ni * g.nj * g.nk));
+    const dim3 grid((unsigned)g.ntiles * (unsigned)((g.nk + FROM_KC - 1) / FROM_KC));
     if (src_f32)
         hipLaunchKernelGGL(k_from_sheared<float>, grid, dim3(256), 0, s, g, (const float *)src, dst, ctl, comp, which);
     else

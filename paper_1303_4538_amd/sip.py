@@ -28,7 +28,7 @@ PRECISIONS = {"fp64": SIP_FP64, "mixed": SIP_MIXED, "fp32": SIP_FP32,
 # every symbol include/sip.h declares
 EXPORTS = ("sip_factor", "sip_iterate", "sip_iterate_noalloc", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
            "sip_profile_sweeps", "sip_profile_sweeps_multi", "sip_tune", "sip_tune_save", "sip_tune_load",
-           "sip_system_plan", "sip_system_info",
+           "sip_system_plan", "sip_system_solve_ms", "sip_system_info",
            "sip_system_destroy", "sip_blocks_factor", "sip_blocks_iterate", "sip_blocks_solve", "sip_blocks_info",
            "sip_blocks_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
            "sip_server_release", "sip_server_stats", "sip_server_shutdown", "sip_server_destroy", "sip_status_str",
@@ -95,6 +95,7 @@ def lib():
     L.sip_export_factors.argtypes = [vp, ctypes.POINTER(vp), vp]
     L.sip_tune.argtypes = [vp, vp, i32, ctypes.POINTER(i32), vp]
     L.sip_system_plan.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.sip_system_solve_ms.argtypes = [vp, ctypes.POINTER(dbl)]
     L.sip_tune_save.argtypes = [ctypes.c_char_p]
     L.sip_tune_load.argtypes = [ctypes.c_char_p]
     L.sip_blocks_factor.argtypes = [ctypes.POINTER(BlockProblem), vp, ctypes.POINTER(vp)]
@@ -115,7 +116,7 @@ def lib():
     L.sip_server_destroy.argtypes = [vp]
     for f in ("sip_factor", "sip_iterate", "sip_iterate_noalloc", "sip_solve", "sip_iterate_multi", "sip_solve_multi", "sip_export_factors",
               "sip_profile_sweeps", "sip_profile_sweeps_multi", "sip_tune", "sip_tune_save", "sip_tune_load",
-              "sip_system_plan", "sip_system_info", "sip_system_destroy", "sip_blocks_factor", "sip_blocks_iterate", "sip_blocks_solve", "sip_blocks_info",
+              "sip_system_plan", "sip_system_solve_ms", "sip_system_info", "sip_system_destroy", "sip_blocks_factor", "sip_blocks_iterate", "sip_blocks_solve", "sip_blocks_info",
               "sip_blocks_destroy", "sip_server_create", "sip_batch_submit", "sip_batch_poll",
               "sip_server_release", "sip_server_stats", "sip_server_shutdown", "sip_server_destroy"):
         getattr(L, f).restype = ctypes.c_int32
@@ -303,6 +304,13 @@ def sip_system_plan(system):
     ph, pd = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().sip_system_plan(system._h, ctypes.byref(ph), ctypes.byref(pd)))
     return ph.value, pd.value
+
+
+def sip_system_solve_ms(system):
+    """Device time (ms) of the handle's last persistent solve launch."""
+    ms = ctypes.c_double()
+    _check(lib().sip_system_solve_ms(system._h, ctypes.byref(ms)))
+    return ms.value
 
 
 def sip_tune_save(path):

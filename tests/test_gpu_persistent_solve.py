@@ -59,3 +59,24 @@ def test_persistent_limit_and_symmetric(sip, monkeypatch):
     assert out[0][0] == out[2][0] == sip.SIP_ENOTCONV and out[0][1] == out[2][1] == 7
     for a, c in ((out[0], out[2]), (out[1], out[3])):
         assert a[1] == c[1] and a[2] == c[2] and np.array_equal(a[3], c[3])
+
+
+def test_solve_launch_time(sip, monkeypatch):
+    """sip_system_solve_ms: the device time of the last persistent launch,
+    positive and within the call's wall time; refused before any persistent
+    solve and on the chunked path."""
+    A, b = problems.make_block((48, 40, 24), "cd", np.random.SeedSequence(9))
+    S = sip.sip_factor(dev(A), 0.92, "mixed")
+    with pytest.raises(sip.SipError):
+        sip.sip_system_solve_ms(S)
+    monkeypatch.setenv("SIP_SOLVE_PERSISTENT", "1")
+    _, it, _, secs = sip.sip_solve(S, dev(b), torch.zeros_like(dev(b)), 1e-8, 5000)
+    ms = sip.sip_system_solve_ms(S)
+    assert it > 0 and 0.0 < ms <= secs * 1e3
+    S.close()
+    monkeypatch.setenv("SIP_SOLVE_PERSISTENT", "0")
+    S = sip.sip_factor(dev(A), 0.92, "mixed")
+    sip.sip_solve(S, dev(b), torch.zeros_like(dev(b)), 1e-8, 5000)
+    with pytest.raises(sip.SipError):
+        sip.sip_system_solve_ms(S)
+    S.close()
