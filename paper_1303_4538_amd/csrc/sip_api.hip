@@ -451,7 +451,7 @@ static sip_status launch_solve_persistent(sip_system_s *h, hipStream_t s)
     HIPTRY(hipMemcpyAsync(h->p_pc, &h->p_host_pc, sizeof(PersistCtl), hipMemcpyHostToDevice, s));
     HIPTRY(launch_init_flags(h->p_flags, s));
     const PersistArgs pa{h->d_job, h->p_tord, h->p_off, h->p_tasks, h->p_cap, h->p_pc, h->p_flags, h->p_flags + 1,
-                         h->timeout_ticks, h->torture};
+                         h->timeout_ticks, h->torture, nullptr};
     const int wgs = std::max(1, std::min(g.ntiles, h->num_cu * (h->plan.phases >= 3 ? 1 : 2)));
     HIPTRY(hipEventRecord(h->p_ev[0], s));
     HIPTRY(launch_persist(pa, h->precision, h->plan, wgs, s));

@@ -167,11 +167,14 @@ struct LaunchArgs {
 // Workgroups loop over a queue of tile tasks: ticket t lives in slot t % cap
 // and is valid once its high half reads t + 1; a consumer frees the slot (0).  The
 // workgroup that finishes a job's sweep runs its finaliser and publishes the
-// job's next sweep as one block of tasks in the job's own topological order,
-// so every task only waits for tasks with earlier tickets, which are held by
-// running workgroups or done (no co-residency assumed).  At most one sweep
-// per job is published and unconsumed at any time, so cap > total tiles of
-// all jobs guarantees a publisher finds its slots free.
+// job's next sweep, either as one block of tasks in the job's own topological
+// order, so every task only waits for tasks with earlier tickets, which are
+// held by running workgroups or done (no co-residency assumed), or
+// (dataflow) as the sweep's first tile only, each tile's task then being
+// published when the tiles it depends on have been taken, so every task only
+// waits for tiles that running workgroups hold or have finished.  At most one
+// sweep per job is published and unconsumed at any time, so cap > total
+// tiles of all jobs guarantees a publisher finds its slots free.
 // A task is one 64-bit word, written and read whole: ticket + 1 in the high
 // half (0 while the slot is free), then job (12 bits), kind (1 bit: 0 forward,
 // 1 backward sweep) and tile (19 bits).
@@ -199,6 +202,12 @@ struct PersistArgs {
     uint32_t *stopped;         // host-mapped: jobs that reached a stop decision (convergence, limit, error)
     uint64_t timeout_ticks;
     uint32_t jitter;
+    // Dataflow publication (nonzero dep): a sweep is published tile by tile,
+    // each tile once the tiles it depends on have been taken by workgroups;
+    // dep holds, per job, 2 * ntiles counters (forward then backward) of
+    // upstream tiles taken, zero at launch.  nullptr: every sweep is published
+    // whole, in the job's tile order.
+    uint32_t *dep;
 };
 // Face records.  At every local step a tile publishes the values its
 // downstream neighbours need: FACE_ENTRIES entries, entry e < TJ for cell row

@@ -1289,6 +1289,9 @@ union PersistLds {
 // s_buf[4..6] = job, tile, kind; job -1 when no task will come).  The polls
 // are relaxed (an acquire would invalidate the caches at every poll); one
 // acquire fence follows a task, before the workgroup reads the job's data.
+__device__ void release_downstream(const PersistArgs &e, int job, int kind, int tile);
+
+template <bool DF>
 __device__ void take_task(const PersistArgs &e, int *s_buf)
 {
     int job = -1, tile = 0, kind = 0;
@@ -1303,6 +1306,7 @@ __device__ void take_task(const PersistArgs &e, int *s_buf)
             job = (int)((w >> (TASK_TILE_BITS + 1)) & ((1u << TASK_JOB_BITS) - 1u));
             __hip_atomic_store(slot, (Task)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // the slot is free
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if constexpr (DF) release_downstream(e, job, kind, tile);
             break;
         }
         // with no job left nothing is published any more: a ticket beyond the
@@ -1322,8 +1326,59 @@ __device__ void take_task(const PersistArgs &e, int *s_buf)
     s_buf[6] = kind;
 }
 
+// One task, published alone (thread 0 of a workgroup): reserve a ticket,
+// wait until its slot is free (the capacity argument says it is; the wait is
+// bounded all the same), store the task.
+__device__ void publish_task(const PersistArgs &e, int job, int kind, int tile)
+{
+    const uint32_t t = atomicAdd(&e.pc->alloc, 1u);
+    Task *slot = e.tasks + (t % e.cap);
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (Task)0) {
+        if (wall_clock64() - t0 > e.timeout_ticks) {
+            __hip_atomic_fetch_or(&e.pc->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __hip_atomic_store(slot, make_task(t, job, kind, tile), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Dataflow publication (thread 0, when the workgroup has taken tile `tile` of
+// job `job`'s sweep `kind`): count this tile as taken for each downstream
+// neighbour (E and N in a forward sweep, W and S backward) and publish a
+// neighbour's task once all of its upstream tiles are taken.  The neighbour
+// then waits at most about one tile hop in its polls, instead of holding a
+// compute unit while the sweep's wavefront reaches it.  A tile's own counter
+// is cleared here: every increment of this sweep came before its task was
+// published, and the job's next sweep of this kind starts after this one ends.
+__device__ void release_downstream(const PersistArgs &e, int job, int kind, int tile)
+{
+    const int nti = e.jobs[job].g.nti, ntj = e.jobs[job].g.ntj;
+    uint32_t *cnt = e.dep + 2 * e.off[job] + kind * nti * ntj;
+    __hip_atomic_store(cnt + tile, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int ti = tile % nti, tj = tile / nti;
+    const int step = kind == 0 ? 1 : -1;
+#pragma unroll
+    for (int axis = 0; axis < 2; axis++) {
+        const int di = ti + (axis == 0 ? step : 0), dj = tj + (axis == 1 ? step : 0);
+        if (di < 0 || di >= nti || dj < 0 || dj >= ntj) continue;
+        // upstream tiles of (di, dj) in this sweep's direction
+        const uint32_t nup = kind == 0 ? (uint32_t)(di > 0) + (uint32_t)(dj > 0)
+                                       : (uint32_t)(di < nti - 1) + (uint32_t)(dj < ntj - 1);
+        const int d = dj * nti + di;
+        if (__hip_atomic_fetch_add(cnt + d, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == nup) {
+            // what this workgroup acquired with its task (the previous sweep's
+            // results) is released to the neighbour's workgroup
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            publish_task(e, job, kind, d);
+        }
+    }
+}
+
 // After the finaliser of job `job`'s sweep of kind `kind` (whole workgroup):
 // publish the job's next sweep, or let the job leave the launch.
+template <bool DF>
 __device__ void publish_next(const PersistArgs &e, const Job &J, int job, int kind, int *s_buf)
 {
     if (threadIdx.x == 0) {
@@ -1336,6 +1391,11 @@ __device__ void publish_next(const PersistArgs &e, const Job &J, int job, int ki
         if (next < 0) {
             if (stop != RUN) __hip_atomic_store(e.stopped, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             __hip_atomic_fetch_sub(&e.pc->active, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else if constexpr (DF) {
+            // dataflow: the next sweep's first tile; the others follow as their
+            // upstream tiles are taken.  The sweep's results are released first.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            publish_task(e, job, next, next == 0 ? 0 : J.g.ntiles - 1);
         } else {
             s_buf[7] = (int)atomicAdd(&e.pc->alloc, (uint32_t)J.g.ntiles);
         }
@@ -1343,7 +1403,7 @@ __device__ void publish_next(const PersistArgs &e, const Job &J, int job, int ki
     }
     __syncthreads();
     const int next = s_buf[6];
-    if (next < 0) return;
+    if (next < 0 || DF) return;
     // the sweep's results (every tile's, gathered by this workgroup's
     // finaliser) are released before any task of the next sweep is visible
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1370,14 +1430,14 @@ __device__ void publish_next(const PersistArgs &e, const Job &J, int job, int ki
 // (mixed form: about 120 VGPRs against 82 for the forward sweep alone), so a
 // compute unit holds one workgroup of either phase count; the server runs it
 // with three phases, which hold one per unit anyway.
-template <typename F, typename R, int NP, int M>
+template <typename F, typename R, int NP, int M, bool DF>
 __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_persist(PersistArgs e)
 {
     __shared__ PersistLds<F, R, M> L;
     __shared__ int s_buf[8];
     const LaunchArgs a{e.jobs, nullptr, nullptr, 0, e.timeout_ticks, e.jitter};
     for (;;) {
-        if (threadIdx.x == 0) take_task(e, s_buf);
+        if (threadIdx.x == 0) take_task<DF>(e, s_buf);
         __syncthreads();
         const int job = __builtin_amdgcn_readfirstlane(s_buf[4]);
         const int tile = __builtin_amdgcn_readfirstlane(s_buf[5]);
@@ -1387,7 +1447,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_persist(PersistArgs e)
         const Job J = load_job(a, job);
         const bool last = kind == 0 ? fwd_tile<F, R, NP, M, 2>(a, as, J, L.f, s_buf)
                                     : bwd_tile<F, R, NP, M, 2>(a, as, J, L.b, s_buf);
-        if (last) publish_next(e, J, job, kind, s_buf);
+        if (last) publish_next<DF>(e, J, job, kind, s_buf);
         __syncthreads();   // LDS and s_buf are reused by the next task
     }
 }
@@ -2023,7 +2083,12 @@ static hipError_t launch_sweep(const LaunchArgs &a, int arith, int nrhs, int bac
 template <typename F, typename R, int NP, int M>
 static hipError_t launch_persist_t(const PersistArgs &a, int wgs, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_persist<F, R, NP, M>), dim3(wgs), dim3(WAVE * (1 + NQ * NP)), 0, s, a);
+    // dataflow and whole-sweep publication are separate kernels, so that the
+    // one does not change the other's register allocation
+    if (a.dep)
+        hipLaunchKernelGGL((k_persist<F, R, NP, M, true>), dim3(wgs), dim3(WAVE * (1 + NQ * NP)), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_persist<F, R, NP, M, false>), dim3(wgs), dim3(WAVE * (1 + NQ * NP)), 0, s, a);
     return hipGetLastError();
 }
 

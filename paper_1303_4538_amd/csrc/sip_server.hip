@@ -188,7 +188,11 @@ public:
     int *d_torder[2 * NARITH] = {};
     int *d_off[2 * NARITH] = {};
     Task *d_tasks[2 * NARITH] = {};
-    int torder_cap[2 * NARITH] = {}, off_cap[2 * NARITH] = {}, tasks_cap[2 * NARITH] = {};
+    uint32_t *d_dep[2 * NARITH] = {};         // dataflow counters, 2 per tile
+    int torder_cap[2 * NARITH] = {}, off_cap[2 * NARITH] = {}, tasks_cap[2 * NARITH] = {}, dep_cap[2 * NARITH] = {};
+    // persistent launches publish each sweep tile by tile as upstream tiles are
+    // taken (SIP_SERVER_DATAFLOW=0: whole sweeps in topological order)
+    bool dataflow = true;
     PersistCtl *d_pc = nullptr, *h_pc = nullptr;
     uint32_t *h_pause = nullptr, *h_stopped = nullptr;   // coherent host memory, read / written by the device
     uint32_t *d_pause = nullptr, *d_stopped = nullptr;   // their device addresses
@@ -734,8 +738,13 @@ sip_status GpuBackend::run_persist(int grp, const std::vector<Job> &jobs, const 
                 for (const int2 &o : topo_order({gs[j]}, b != 0, 0u)) c.push_back(o.y);
         tord.insert(tord.end(), c.begin(), c.end());
     }
-    // the first forward sweeps, merged over the jobs (topological per job)
-    const std::vector<int2> first = topo_order(gs, false, order_seed(grp));
+    // the first forward sweeps: every job's first tile (dataflow), or all
+    // tiles merged over the jobs (topological per job)
+    std::vector<int2> first;
+    if (dataflow)
+        for (int j = 0; j < nj; j++) first.push_back(make_int2(j, 0));
+    else
+        first = topo_order(gs, false, order_seed(grp));
     const uint32_t cap = (uint32_t)total + 64u;   // more than the tiles of all jobs
     if (nj > (1 << TASK_JOB_BITS) || total > (1 << TASK_TILE_BITS))
         return set_error(SIP_EINVAL, "persistent launch of %d jobs / %d tiles exceeds the task encoding", nj, total);
@@ -752,7 +761,8 @@ sip_status GpuBackend::run_persist(int grp, const std::vector<Job> &jobs, const 
     if (ensure_launch_buffers(grp, nj, (int)first.size()) != SIP_OK ||
         !grow((void **)&d_torder[grp], torder_cap[grp], 2 * total, sizeof(int)) ||
         !grow((void **)&d_off[grp], off_cap[grp], nj + 1, sizeof(int)) ||
-        !grow((void **)&d_tasks[grp], tasks_cap[grp], (int)cap, sizeof(Task)))
+        !grow((void **)&d_tasks[grp], tasks_cap[grp], (int)cap, sizeof(Task)) ||
+        (dataflow && !grow((void **)&d_dep[grp], dep_cap[grp], 2 * total, sizeof(uint32_t))))
         return SIP_ENOMEM;
     *h_pc = PersistCtl{0u, (uint32_t)first.size(), (uint32_t)nj, 0u};
     __atomic_store_n(h_pause, 0u, __ATOMIC_RELEASE);
@@ -765,10 +775,11 @@ sip_status GpuBackend::run_persist(int grp, const std::vector<Job> &jobs, const 
             hipSuccess ||
         hipMemcpyAsync(d_tasks[grp], tasks.data(), tasks.size() * sizeof(Task), hipMemcpyHostToDevice, stream) !=
             hipSuccess ||
-        hipMemcpyAsync(d_pc, h_pc, sizeof(PersistCtl), hipMemcpyHostToDevice, stream) != hipSuccess)
+        hipMemcpyAsync(d_pc, h_pc, sizeof(PersistCtl), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        (dataflow && hipMemsetAsync(d_dep[grp], 0, 2 * (size_t)total * sizeof(uint32_t), stream) != hipSuccess))
         return set_error(SIP_EDEVICE, "upload failed");
     const PersistArgs pa{d_jobs[grp], d_torder[grp], d_off[grp], d_tasks[grp], cap, d_pc, d_pause, d_stopped,
-                         timeout_ticks, torture};
+                         timeout_ticks, torture, dataflow ? d_dep[grp] : nullptr};
     // persistent workgroups: one per compute unit (the kernel holds both
     // sweeps and needs about 120 VGPRs, so a unit fits one workgroup of either
     // phase count; three phases shorten the step), never more than the tiles
@@ -868,6 +879,7 @@ sip_status GpuBackend::init(sip_server_config &c)
     if (const char *e = getenv("SIP_SERVER_PAIRS")) pairing = atoi(e) != 0;
     if (const char *e = getenv("SIP_SERVER_GRAPHS")) graphs = atoi(e) != 0;
     if (const char *e = getenv("SIP_SERVER_PERSISTENT")) persistent = atoi(e) != 0 ? 1 : 0;
+    if (const char *e = getenv("SIP_SERVER_DATAFLOW")) dataflow = atoi(e) != 0;
     timeout_ticks = timeout_ticks_for(device, 2.0);
     torture = schedule_seed();
     {
@@ -918,6 +930,7 @@ GpuBackend::~GpuBackend()
         dev_free(d_torder[grp], stream);
         dev_free(d_off[grp], stream);
         dev_free(d_tasks[grp], stream);
+        dev_free(d_dep[grp], stream);
     }
     (void)hipStreamSynchronize(stream);
     if (epoch_exec) (void)hipGraphExecDestroy(epoch_exec);

@@ -60,12 +60,16 @@ def alone(sip, A, b, precision, rtol=1e-8):
     return x.cpu().numpy(), it, rr
 
 
-@pytest.mark.parametrize("persistent", ["1", "0"])
+@pytest.mark.parametrize("mode", ["dataflow", "whole", "epochs"])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_batch_equals_alone_and_oracle(sip, precision, persistent, monkeypatch):
-    monkeypatch.setenv("SIP_SERVER_PERSISTENT", persistent)
+def test_batch_equals_alone_and_oracle(sip, precision, mode, monkeypatch):
+    """Persistent launches that publish sweeps tile by tile as upstream tiles
+    are taken, or whole sweeps in tile order, and per-iteration epochs: every
+    result bitwise its solo solve."""
+    monkeypatch.setenv("SIP_SERVER_PERSISTENT", "0" if mode == "epochs" else "1")
+    monkeypatch.setenv("SIP_SERVER_DATAFLOW", "0" if mode == "whole" else "1")
     data = [block(d, k, 100 + q) for q, (d, k) in enumerate(BLOCKS)]
-    log(f"server batch of {len(data)} blocks, {precision}, persistent {persistent}")
+    log(f"server batch of {len(data)} blocks, {precision}, {mode}")
     srv = sip.Server(max_slots=64, epoch_iters=8)
     At = [dev(A) for A, _ in data]
     bt = [dev(b) for _, b in data]
