@@ -153,6 +153,11 @@ sip_status sip_iterate_noalloc(sip_system h, const double *b, double *x, int32_t
  *   rtol > 0, max_iter >= 0; info (nullable, host) receives iterations,
  *   final relative residual and wall time.  Synchronises the stream.
  * Non-finite values stop the solve as in sip_iterate (info->rel_res NaN).
+ * The whole solve runs as one persistent launch (the sweeps follow each
+ * other on the device, which also takes the stop decision); with the
+ * environment variable SIP_SOLVE_PERSISTENT=0 (read at every call), or a
+ * plan with one loader phase or a poll distance other than 2, it replays
+ * graph-captured chunks of 8 iterations instead, with the same results.
  * Errors: SIP_EINVAL (also non-finite b or start vector), SIP_EBREAKDOWN,
  * SIP_ENOTCONV (x holds x_max_iter), SIP_EDEVICE. */
 sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int32_t max_iter,
@@ -369,6 +374,13 @@ typedef struct {
  *   c     configuration (host, read during the call).  hbm_budget_bytes
  *         bounds the device bytes of resident systems plus running requests.
  *   out   receives the handle.
+ * While no new request arrives, the admitted requests run in persistent
+ * launches in which each iterates at its own pace, its sweeps published tile
+ * by tile as the tiles they depend on are taken; while requests keep
+ * arriving, in epochs of epoch_iters iterations.  Environment variables read
+ * here: SIP_SERVER_PERSISTENT=1 / 0 forces one of the two modes;
+ * SIP_SERVER_DATAFLOW=0 publishes whole sweeps in tile order instead; the
+ * results are the same in every mode.
  * Errors: SIP_EINVAL (max_slots outside 1..4096, epoch_iters < 1,
  * max_queue < 1), SIP_ENOMEM (the server's own buffers), SIP_EDEVICE. */
 sip_status sip_server_create(const sip_server_config *c, sip_server *out);
