@@ -115,9 +115,13 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the two-right-hand-side and multi-block solves of the same block")
     ap.add_argument("--profile-iters", type=int, default=40)
-    ap.add_argument("--cpu-iters", type=int, default=12)
-    ap.add_argument("--cpu-iters-batched", type=int, default=3, help="oracle iterations per block (batched)")
-    ap.add_argument("--cpu-iters-large", type=int, default=2, help="oracle iterations of the 512x512x256 block")
+    # oracle samples sized to about 10-30 s of host CPU work each
+    ap.add_argument("--cpu-iters", type=int, default=50, help="oracle iterations of the 256^3 block")
+    ap.add_argument("--cpu-iters-batched", type=int, default=20,
+                    help="oracle iterations per block (batched; 16 processes)")
+    ap.add_argument("--cpu-iters-large", type=int, default=8, help="oracle iterations of the 512x512x256 block")
+    ap.add_argument("--cpu-iters-serving", type=int, default=100,
+                    help="oracle iterations per sampled system (serving; 16 processes)")
     ap.add_argument("--no-configs", action="store_true",
                     help="default line without the batched, large and serving configurations")
     ap.add_argument("--storage", default="full", choices=["full", "symmetric"],
@@ -623,14 +627,14 @@ def config5_summary(args, sip):
         oracle.build(force=False)
         log("serving: oracle sample on the host cores")
         procs = max(1, min(16, os.cpu_count() or 1))
-        systems = [(d, k, ss, first_rhs[20 * i], args.cpu_iters_batched) for i, (d, k, ss) in enumerate(sample)]
+        systems = [(d, k, ss, first_rhs[20 * i], args.cpu_iters_serving) for i, (d, k, ss) in enumerate(sample)]
         with ProcessPoolExecutor(procs, mp_context=mp.get_context("spawn")) as pool:
             res = list(pool.map(_oracle_stream_sample, systems))
         ci = sum(c for c, _ in res)
         busy = sum(t for _, t in res)
         out["cpu_baseline"] = {"value": ci / (busy / procs), "unit": "cell-iterations/s", "cores": procs,
                                "kind": "oracle",
-                               "sample": f"every 20th system ({len(systems)} of 250), {args.cpu_iters_batched} "
+                               "sample": f"every 20th system ({len(systems)} of 250), {args.cpu_iters_serving} "
                                          f"mixed-form SIP iterations each on its first right-hand side, one "
                                          f"process per system on {procs} cores, factorisation untimed"}
     return out
