@@ -53,9 +53,9 @@ SOLVE_BYTES_MIXED = FWD_BYTES["mixed"] + BWD_BYTES["mixed"]   # one mixed iterat
 # with the iterations of that solve and the SHA-256 of the kernel
 # source they were taken with.  Once the source differs the counters no
 # longer describe the kernel and traffic is null.
-MEASURED = {"kernels_sha256": "ef9809a7a84f3783f88dae3c7a7fb539095c298d1b4bc2a5c65789f6468ff8c3",
-            "single": {"iterations": 4069, "persist_bytes": 9743428095316},
-            "large": {"iterations": 15239, "persist_bytes": 147519207059890}}
+MEASURED = {"kernels_sha256": "fbe13dd4b41909e7b8952f6b31e020f2c4f4203543dd6b58b925e150f45071e6",
+            "single": {"iterations": 4069, "persist_bytes": 9749482215394},
+            "large": {"iterations": 15239, "persist_bytes": 147519934339422}}
 
 
 def log(msg):

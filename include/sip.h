@@ -175,7 +175,9 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
  *   stop decision it would get alone (bitwise): in sip_solve_multi each one
  *   stops at its own first n with rho_n <= rtol and keeps that x_n; once one
  *   of a pair has stopped, the other goes on through the one-right-hand-side
- *   path from its current iterate.
+ *   path from its current iterate.  sip_solve_multi runs a pair as one
+ *   persistent launch up to that point when sip_solve does (SIP_SOLVE_PERSISTENT
+ *   unset or not "0"), else in chunks of launches; the results are the same.
  *   rel_res_hist  NULL, or HOST memory of nrhs * (n_iter + 1) doubles,
  *           right-hand side r's history at r * (n_iter + 1).
  *   info    NULL, or HOST memory of nrhs entries.

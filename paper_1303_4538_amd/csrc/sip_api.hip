@@ -361,6 +361,18 @@ static sip_status ensure_multi(sip_system_s *h, int hist_n, hipStream_t s)
     return SIP_OK;
 }
 
+// The pair job's split flag (Job::coupled for m > 1): a solve stops the pair
+// sweeps once one right-hand side has stopped and continues the other alone;
+// a fixed number of iterations keeps both in the pair sweeps throughout.
+static sip_status set_split(sip_system_s *h, int on, hipStream_t s)
+{
+    if (h->mjob.coupled == on) return SIP_OK;
+    h->mjob.coupled = on;
+    HIPTRY(hipMemcpyAsync(h->d_mjob, &h->mjob, sizeof(Job), hipMemcpyHostToDevice, s));
+    HIPTRY(hipStreamSynchronize(s));
+    return SIP_OK;
+}
+
 static LaunchArgs multi_args(const sip_system_s *h, bool backward)
 {
     return LaunchArgs{h->d_mjob, backward ? h->order_b : h->order_f, h->lc, h->g.ntiles, h->timeout_ticks,
@@ -440,8 +452,9 @@ static sip_status ensure_persist(sip_system_s *h, hipStream_t s)
     return SIP_OK;
 }
 
-// Enqueues one persistent launch that runs the job until its stop decision.
-static sip_status launch_solve_persistent(sip_system_s *h, hipStream_t s)
+// Enqueues one persistent launch that runs the job (the handle's own, or
+// its pair job with nrhs = 2) until its stop decision.
+static sip_status launch_solve_persistent(sip_system_s *h, hipStream_t s, const Job *job = nullptr, int nrhs = 1)
 {
     TRY(ensure_persist(h, s));
     const Geom &g = h->g;
@@ -450,11 +463,11 @@ static sip_status launch_solve_persistent(sip_system_s *h, hipStream_t s)
                           hipMemcpyHostToDevice, s));
     HIPTRY(hipMemcpyAsync(h->p_pc, &h->p_host_pc, sizeof(PersistCtl), hipMemcpyHostToDevice, s));
     HIPTRY(launch_init_flags(h->p_flags, s));
-    const PersistArgs pa{h->d_job, h->p_tord, h->p_off, h->p_tasks, h->p_cap, h->p_pc, h->p_flags, h->p_flags + 1,
-                         h->timeout_ticks, h->torture, nullptr};
+    const PersistArgs pa{job ? job : h->d_job, h->p_tord, h->p_off, h->p_tasks, h->p_cap, h->p_pc, h->p_flags,
+                         h->p_flags + 1, h->timeout_ticks, h->torture, nullptr};
     const int wgs = std::max(1, std::min(g.ntiles, h->num_cu * (h->plan.phases >= 3 ? 1 : 2)));
     HIPTRY(hipEventRecord(h->p_ev[0], s));
-    HIPTRY(launch_persist(pa, h->precision, h->plan, wgs, s));
+    HIPTRY(launch_persist(pa, h->precision, h->plan, wgs, s, nrhs));
     HIPTRY(hipEventRecord(h->p_ev[1], s));
     h->p_timed = true;
     return SIP_OK;
@@ -863,7 +876,10 @@ sip_status sip_iterate_multi(sip_system h, int32_t nrhs, const double *const *b,
     const size_t hn = (size_t)n_iter + 1;
     sip_status bad = SIP_OK;   // first right-hand side with a non-finite norm; the others still run
     int bad_r = -1;
-    if (npair > 0) TRY(ensure_multi(h, n_iter + 1, s));
+    if (npair > 0) {
+        TRY(ensure_multi(h, n_iter + 1, s));
+        TRY(set_split(h, 0, s));
+    }
     for (int pr = 0; pr < npair; pr++) {
         const int r0 = 2 * pr, r1 = r0 + 1;
         HIPTRY(multi_stage_in(h, b[r0], b[r1], x[r0], x[r1], s));
@@ -917,7 +933,10 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
     sip_status bad = SIP_OK;   // first right-hand side with a non-finite norm; the others are still solved
     int bad_r = -1;
     // the finaliser records rho_n for n <= max_iter
-    if (npair > 0) TRY(ensure_multi(h, max_iter + 1, s));
+    if (npair > 0) {
+        TRY(ensure_multi(h, max_iter + 1, s));
+        TRY(set_split(h, 1, s));
+    }
     for (int pr = 0; pr < npair; pr++) {
         const auto t0 = std::chrono::steady_clock::now();
         const int r0 = 2 * pr, r1 = r0 + 1;
@@ -929,7 +948,11 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
         hipEvent_t ev[2];
         HIPTRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
         HIPTRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-        for (int c = 0;; c++) {
+        // one persistent launch runs the pair until it stops (both right-hand
+        // sides, or one of them: PARTNER); otherwise chunks of iterations
+        const bool persist = solve_persistent(h);
+        if (persist) st = launch_solve_persistent(h, s, h->d_mjob, 2);
+        for (int c = 0; !persist; c++) {
             st = multi_iterations(h, CHUNK, s);
             if (st != SIP_OK) break;
             launched += CHUNK;
@@ -961,7 +984,9 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
         }
         HIPTRY(multi_stage_out(h, x[r0], x[r1], s));
         HIPTRY(hipMemcpyAsync(&h->h_mctl[6], h->mctl, 3 * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        if (persist) HIPTRY(hipMemcpyAsync(&h->p_host_pc, h->p_pc, sizeof(PersistCtl), hipMemcpyDeviceToHost, s));
         HIPTRY(hipStreamSynchronize(s));
+        if (persist && h->p_host_pc.err) return set_error(SIP_EDEVICE, "a device-side queue wait timed out");
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         const Ctl *c = &h->h_mctl[6];
         if (c[0].stop == RUN && !split) return set_error(SIP_EDEVICE, "solve ended without a stop decision");

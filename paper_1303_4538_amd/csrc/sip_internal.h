@@ -90,6 +90,7 @@ enum Stop : uint32_t {
     TIMEOUT = 5,
     BAD_INPUT = 6,   // non-finite ||b|| or residual of the start vector
     DIVERGED = 7,    // non-finite residual after the first update
+    PARTNER = 8,     // swept right-hand sides with the split flag: one has stopped, the others go on alone
 };
 
 struct Geom {
@@ -141,8 +142,10 @@ struct Job {
     int fw;                    // face words per local step (FACE_WORDS_SWEEP or FACE_WORDS)
     int sym;                   // A in the symmetric storage (sweeps only; the factorisation reads the full one)
     int m;                     // right-hand sides swept together (b, x, y hold m values per cell)
-    int coupled;               // block of a multi-block domain: the forward finaliser leaves the stop
-                               // decision to the domain's control kernel (rho <- sum r^2, bnorm2 <- sum b^2)
+    int coupled;               // m = 1: block of a multi-block domain: the forward finaliser leaves the stop
+                               // decision to the domain's control kernel (rho <- sum r^2, bnorm2 <- sum b^2);
+                               // m > 1 (split flag): the sweeps stop (PARTNER) once any right-hand side
+                               // has stopped while another runs, which then goes on in one-RHS sweeps
     int hstride;               // m > 1: history of right-hand side r at hist + r * hstride
 };
 

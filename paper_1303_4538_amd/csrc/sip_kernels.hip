@@ -589,7 +589,7 @@ __device__ void finalise_multi(const Job &J, const double *sr, const double *sb,
 {
     Ctl *c0 = J.ctl;
     const uint32_t err = c0->err;
-    bool running = false, capped = false;
+    bool running = false, capped = false, stopped = false;
 #pragma unroll
     for (int m = 0; m < M; m++) {
         Ctl *cr = J.ctl + 1 + m;
@@ -599,7 +599,10 @@ __device__ void finalise_multi(const Job &J, const double *sr, const double *sb,
         if (nb2 != 0.0) rho = sqrt(sr[m]) / sqrt(nb2);
         if (!finite_val(nb2)) rho = __builtin_nan("");
         if (J.hist) J.hist[m * J.hstride + iter] = rho;
-        if (cr->stop != RUN) continue;
+        if (cr->stop != RUN) {
+            stopped = true;
+            continue;
+        }
         uint32_t st = RUN;
         if (!finite_val(nb2) || !finite_val(rho)) st = (iter == 0 || !finite_val(nb2)) ? BAD_INPUT : DIVERGED;
         else if (nb2 == 0.0) st = ZERO_RHS;
@@ -609,9 +612,11 @@ __device__ void finalise_multi(const Job &J, const double *sr, const double *sb,
         cr->iter = iter;
         cr->stop = st;
         running = running || st == RUN;
+        stopped = stopped || st != RUN;
         capped = capped || st == MAXITER;
     }
     uint32_t st = running ? RUN : capped ? MAXITER : CONVERGED;
+    if (J.coupled && running && stopped) st = PARTNER;   // the one still running goes on alone
     if (err) st = (err & 2u) ? BREAKDOWN : TIMEOUT;
     c0->stop = st;
     c0->epoch = tag + 1u;

@@ -79,8 +79,13 @@ def test_pair_iterates_equal_solo(sip, dims, kind, precision):
 
 
 # FP32 stalls near u32 |A| |x| / |b|, about 2e-5 for the smooth right-hand side here
+@pytest.mark.parametrize("persistent", ["1", "0"])
 @pytest.mark.parametrize("precision,rtol", [("mixed", 1e-8), ("fp32", 1e-4)])
-def test_pair_solves_stop_independently(sip, precision, rtol):
+def test_pair_solves_stop_independently(sip, precision, rtol, persistent, monkeypatch):
+    """Two right-hand sides solved together (one persistent launch, or
+    chunks of iterations): the pair sweeps stop once one side has stopped and
+    the other goes on alone; each result bitwise its solo solve."""
+    monkeypatch.setenv("SIP_SOLVE_PERSISTENT", persistent)
     dims = (40, 36, 30)
     rng = np.random.default_rng(5)
     A = system("cd", dims, rng)
@@ -107,7 +112,9 @@ def test_pair_solves_stop_independently(sip, precision, rtol):
             assert rc <= rtol * (1 + 1e-9)
 
 
-def test_odd_count_and_zero_rhs(sip):
+@pytest.mark.parametrize("persistent", ["1", "0"])
+def test_odd_count_and_zero_rhs(sip, persistent, monkeypatch):
+    monkeypatch.setenv("SIP_SOLVE_PERSISTENT", persistent)
     dims = (24, 20, 18)
     rng = np.random.default_rng(8)
     A = system("cd", dims, rng)
@@ -129,7 +136,9 @@ def test_odd_count_and_zero_rhs(sip):
     assert np.all(h[1] == 0.0) and h[0][0] == 1.0 and h[2][0] == 1.0
 
 
-def test_max_iter_on_one_side(sip):
+@pytest.mark.parametrize("persistent", ["1", "0"])
+def test_max_iter_on_one_side(sip, persistent, monkeypatch):
+    monkeypatch.setenv("SIP_SOLVE_PERSISTENT", persistent)
     dims = (30, 28, 26)
     rng = np.random.default_rng(9)
     A = system("cd", dims, rng)
