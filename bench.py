@@ -424,6 +424,29 @@ def persist_roofline(cells, iters, solve_ms, storage="full", workload=None):
             "basis": f"({iters} + 1) x {fwd_b} + {iters} x {BWD_BYTES['mixed']} algorithmic B per cell per launch"}
 
 
+def pair_roofline(cells, its, launch_ms):
+    """Roofline of a two-right-hand-side solve's persistent launches: the pair
+    launch k_persist<float, double, 3, 2, false> sweeps both until the first
+    stops at iteration n0 (n0 + 1 pair forward sweeps, n0 pair backward
+    sweeps), then the other continues from x_n0 in a one-RHS launch
+    (n1 - n0 + 1 forward and n1 - n0 backward sweeps; none when both stop
+    together).  launch_ms: the launches' summed device time from HIP events
+    around each (sip_system_solve_ms)."""
+    n0, n1 = min(its), max(its)
+    pair = (n0 + 1) * PAIR_FWD_BYTES + n0 * PAIR_BWD_BYTES
+    m = n1 - n0
+    cont = (m + 1) * FWD_BYTES["mixed"] + m * BWD_BYTES["mixed"] if m > 0 else 0
+    achieved = (pair + cont) * cells / (launch_ms * 1e-3) / 1e9
+    return {"bound": "hbm",
+            "kernel": "k_persist<float, double, 3, 2, false> (both right-hand sides in one launch until the first "
+                      "stops) + k_persist<float, double, 3, 1, false> (the other's continuation)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "launch_ms": round(launch_ms, 3),
+            "basis": f"({n0} + 1) x {PAIR_FWD_BYTES} + {n0} x {PAIR_BWD_BYTES}"
+                     + (f" + ({m} + 1) x {FWD_BYTES['mixed']} + {m} x {BWD_BYTES['mixed']}" if m > 0 else "")
+                     + " algorithmic B per cell"}
+
+
 def sweep_detail(fwd_ms, bwd_ms, cells, storage="full"):
     """The two sweep kernels launched one at a time (HIP events around each
     launch): the per-sweep view of the same work."""
@@ -693,12 +716,17 @@ def pair_run(args):
     bs = [torch.from_numpy(c["b"]).to(dev), torch.from_numpy(b2).to(dev)]
     torch.cuda.synchronize()
 
-    def step(together):
+    persistent = os.environ.get("SIP_SOLVE_PERSISTENT", "1") != "0"
+    launch_ms = []   # per timed two-RHS solve: its persistent launches' device time
+
+    def step(together, timed=False):
         S = sip.sip_factor(A, c["alpha"], "mixed")
         xs = [torch.zeros_like(b) for b in bs]
         if together:
             st, info = sip.sip_solve_multi(S, bs, xs, RTOL, 200000)
             its = [i[0] for i in info]
+            if timed and persistent:
+                launch_ms.append(sip.sip_system_solve_ms(S))
         else:
             its = [sip.sip_solve(S, b, x, RTOL, 200000)[1] for b, x in zip(bs, xs)]
         S.close()
@@ -708,7 +736,7 @@ def pair_run(args):
         step(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    its = [step(True) for _ in range(args.steps)]
+    its = [step(True, timed=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = cells * sum(sum(i) for i in its) / elapsed
@@ -720,6 +748,15 @@ def pair_run(args):
     fwd_ms, bwd_ms = sip.sip_profile_sweeps_multi(S, bs, [torch.zeros_like(b) for b in bs], args.profile_iters)
     S.close()
     achieved = PAIR_FWD_BYTES * cells / (fwd_ms * 1e-3) / 1e9
+    sweeps = {"fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4), "fwd_gbps": round(achieved, 1),
+              "bwd_gbps": round(PAIR_BWD_BYTES * cells / (bwd_ms * 1e-3) / 1e9, 1)}
+    if persistent:
+        roof = pair_roofline(cells, its[-1], sum(launch_ms) / len(launch_ms))
+        roof["sweeps_one_launch_each"] = sweeps
+    else:
+        roof = {"bound": "hbm", "kernel": "k_forward<float, double, 3, 2, 2> (pair forward sweep, one launch)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, **sweeps}
     line = {
         "metric": "right-hand-side cell-iterations/s (two mixed SIP solves swept together, to 1e-8)",
         "value": value, "unit": "cell-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -729,11 +766,7 @@ def pair_run(args):
                                f"alpha 0.92, factor + sip_solve_multi to {RTOL:g}",
                    "cells": cells, "iterations": its[-1], "one_after_the_other_cell_iters_per_s": alone,
                    "speedup_vs_one_after_the_other": value / alone},
-        "roofline": {"bound": "hbm", "kernel": "k_forward<float, double, 3, 2, 2> (pair forward sweep)",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
-                     "bwd_gbps": round(PAIR_BWD_BYTES * cells / (bwd_ms * 1e-3) / 1e9, 1)},
+        "roofline": roof,
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
@@ -895,6 +928,10 @@ def pair_and_blocks(sip, A, b, alpha, n):
     torch.cuda.synchronize()
     t_pair = time.perf_counter() - t0
     its = [i[0] for i in info]
+    pair_roof = None
+    if os.environ.get("SIP_SOLVE_PERSISTENT", "1") != "0":
+        r = pair_roofline(cells, its, sip.sip_system_solve_ms(S))
+        pair_roof = {k: r[k] for k in ("achieved", "frac", "launch_ms")}
     t0 = time.perf_counter()
     for rhs in (b, b2):
         sip.sip_solve(S, rhs, torch.zeros_like(b), RTOL, 200000)
@@ -914,6 +951,7 @@ def pair_and_blocks(sip, A, b, alpha, n):
             "two_rhs_cell_iters_per_s": cells * sum(its) / t_pair,
             "one_after_the_other_cell_iters_per_s": cells * sum(its) / t_alone,
             "two_rhs_speedup": t_alone / t_pair,
+            "two_rhs_persistent_launches": pair_roof,
             "blocks_2x2x2_iterations": itb, "blocks_2x2x2_rel_res": rrb,
             "blocks_2x2x2_cell_iters_per_s": cells * itb / t_blk,
             "blocks_2x2x2_solve_s": round(t_blk, 3)}

@@ -283,14 +283,17 @@ sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phas
  * SIP_EINVAL (NULL handle). */
 sip_status sip_system_plan(sip_system h, int32_t *phases, int32_t *poll);
 
-/* sip_system_solve_ms -- device time of the handle's last persistent solve
- * launch (Sec. 3 measures the solver's kernels one by one; sip_solve runs a
- * whole solve as one launch): *ms (host) receives the time between HIP
- * events recorded on the solve's stream just before and just after that
- * launch; the layout copies, the factorisation and any host work are
- * outside it.  Waits for the launch to finish.  Errors: SIP_EINVAL (NULL
- * argument, or no persistent solve has run on the handle: the chunked path
- * of SIP_SOLVE_PERSISTENT=0 is not timed), SIP_EDEVICE. */
+/* sip_system_solve_ms -- device time of the persistent launches of the
+ * handle's last sip_solve or sip_solve_multi call (Sec. 3 measures the
+ * solver's kernels one by one; sip_solve runs a whole solve as one launch,
+ * sip_solve_multi one per pair of right-hand sides plus one per one-RHS
+ * continuation or odd last right-hand side): *ms (host) receives the sum,
+ * over those launches, of the time between HIP events recorded on the
+ * solve's stream just before and just after each; the layout copies, the
+ * factorisation and any host work are outside it.  Errors: SIP_EINVAL (NULL
+ * argument, or the last solve call ran no persistent launch: none has run
+ * yet, or the chunked path of SIP_SOLVE_PERSISTENT=0 ran, which is not
+ * timed). */
 sip_status sip_system_solve_ms(sip_system h, double *ms);
 
 /* sip_tune_save / sip_tune_load -- the autotuner's table (kept across

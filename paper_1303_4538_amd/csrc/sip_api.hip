@@ -469,6 +469,16 @@ static sip_status launch_solve_persistent(sip_system_s *h, hipStream_t s, const 
     HIPTRY(hipEventRecord(h->p_ev[0], s));
     HIPTRY(launch_persist(pa, h->precision, h->plan, wgs, s, nrhs));
     HIPTRY(hipEventRecord(h->p_ev[1], s));
+    return SIP_OK;
+}
+
+// After the stream has synchronised: adds the launch's device time to the
+// solve call's sum.
+static sip_status count_solve_launch(sip_system_s *h)
+{
+    float t = 0.0f;
+    HIPTRY(hipEventElapsedTime(&t, h->p_ev[0], h->p_ev[1]));
+    h->p_ms += t;
     h->p_timed = true;
     return SIP_OK;
 }
@@ -740,12 +750,11 @@ sip_status sip_iterate_noalloc(sip_system h, const double *b, double *x, int32_t
     return stop_status(stop);
 }
 
-sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int32_t max_iter, sip_info *info,
-                     void *stream)
+// sip_solve without resetting the call's launch time (sip_solve_multi runs
+// it for the continuations of pairs and for an odd last right-hand side).
+static sip_status solve_one(sip_system h, const double *b, double *x, double rtol, int32_t max_iter,
+                            sip_info *info, void *stream)
 {
-    const Range range("sip_solve");
-    if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
-    if (!(rtol > 0.0) || max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
     hipStream_t s = (hipStream_t)stream;
     const auto t0 = std::chrono::steady_clock::now();
     TRY(ensure_hist(h, max_iter + 1, s));
@@ -757,6 +766,7 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
         HIPTRY(hipMemcpyAsync(&h->h_ctl[2], h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIPTRY(hipMemcpyAsync(&h->p_host_pc, h->p_pc, sizeof(PersistCtl), hipMemcpyDeviceToHost, s));
         HIPTRY(hipStreamSynchronize(s));
+        TRY(count_solve_launch(h));
         const Ctl &c = h->h_ctl[2];
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (info) {
@@ -809,6 +819,17 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
     }
     if (c.stop == RUN) return set_error(SIP_EDEVICE, "solve ended without a stop decision");
     return stop_status(c.stop);
+}
+
+sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int32_t max_iter, sip_info *info,
+                     void *stream)
+{
+    const Range range("sip_solve");
+    if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
+    if (!(rtol > 0.0) || max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
+    h->p_timed = false;
+    h->p_ms = 0.0;
+    return solve_one(h, b, x, rtol, max_iter, info, stream);
 }
 
 sip_status sip_export_factors(sip_system h, double *const out[7], void *stream)
@@ -932,6 +953,8 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
     sip_status worst = SIP_OK;
     sip_status bad = SIP_OK;   // first right-hand side with a non-finite norm; the others are still solved
     int bad_r = -1;
+    h->p_timed = false;
+    h->p_ms = 0.0;
     // the finaliser records rho_n for n <= max_iter
     if (npair > 0) {
         TRY(ensure_multi(h, max_iter + 1, s));
@@ -986,6 +1009,7 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
         HIPTRY(hipMemcpyAsync(&h->h_mctl[6], h->mctl, 3 * sizeof(Ctl), hipMemcpyDeviceToHost, s));
         if (persist) HIPTRY(hipMemcpyAsync(&h->p_host_pc, h->p_pc, sizeof(PersistCtl), hipMemcpyDeviceToHost, s));
         HIPTRY(hipStreamSynchronize(s));
+        if (persist) TRY(count_solve_launch(h));
         if (persist && h->p_host_pc.err) return set_error(SIP_EDEVICE, "a device-side queue wait timed out");
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         const Ctl *c = &h->h_mctl[6];
@@ -1002,7 +1026,7 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
                 // same iterates and residuals as the pair sweeps.
                 const int32_t done = (int32_t)c[0].iter;
                 sip_info more{};
-                const sip_status s1 = sip_solve(h, b[r0 + m], x[r0 + m], rtol, max_iter - done, &more, stream);
+                const sip_status s1 = solve_one(h, b[r0 + m], x[r0 + m], rtol, max_iter - done, &more, stream);
                 const bool nf = (s1 == SIP_EINVAL || s1 == SIP_EBREAKDOWN) && non_finite(h->h_ctl[2].stop);
                 if (s1 != SIP_OK && s1 != SIP_ENOTCONV && !nf) return s1;
                 one = sip_info{done + more.iters, more.rel_res, secs + more.seconds};
@@ -1015,7 +1039,7 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
         }
     }
     for (int r = 2 * npair; r < nrhs; r++) {
-        const sip_status st = sip_solve(h, b[r], x[r], rtol, max_iter, info ? info + r : nullptr, stream);
+        const sip_status st = solve_one(h, b[r], x[r], rtol, max_iter, info ? info + r : nullptr, stream);
         if (st == SIP_ENOTCONV) worst = SIP_ENOTCONV;
         else if ((st == SIP_EINVAL || st == SIP_EBREAKDOWN) && non_finite(h->h_ctl[2].stop)) {
             if (bad == SIP_OK) bad = st, bad_r = r;
@@ -1142,11 +1166,8 @@ sip_status sip_system_plan(sip_system h, int32_t *phases, int32_t *poll)
 sip_status sip_system_solve_ms(sip_system h, double *ms)
 {
     if (!h || !ms) return set_error(SIP_EINVAL, "NULL argument");
-    if (!h->p_timed) return set_error(SIP_EINVAL, "no persistent solve has run on this handle");
-    float t = 0.0f;
-    HIPTRY(hipEventSynchronize(h->p_ev[1]));
-    HIPTRY(hipEventElapsedTime(&t, h->p_ev[0], h->p_ev[1]));
-    *ms = t;
+    if (!h->p_timed) return set_error(SIP_EINVAL, "the handle's last solve call ran no persistent launch");
+    *ms = h->p_ms;
     return SIP_OK;
 }
 

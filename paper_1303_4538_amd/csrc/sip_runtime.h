@@ -90,7 +90,8 @@ struct sip_system_s {
     uint32_t p_cap = 0;
     std::vector<sipk::Task> p_host_tasks;   // host image of the queue uploaded before every solve
     sipk::PersistCtl p_host_pc{};
-    hipEvent_t p_ev[2] = {nullptr, nullptr};  // recorded around the last persistent solve launch
-    bool p_timed = false;                     // a persistent solve has been launched
+    hipEvent_t p_ev[2] = {nullptr, nullptr};  // recorded around the latest persistent solve launch
+    bool p_timed = false;                     // the last solve call ran persistent launches
+    double p_ms = 0.0;                        // their summed device time (ms)
     sipk::SweepPlan plan{};
 };

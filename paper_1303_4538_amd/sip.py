@@ -307,7 +307,8 @@ def sip_system_plan(system):
 
 
 def sip_system_solve_ms(system):
-    """Device time (ms) of the handle's last persistent solve launch."""
+    """Device time (ms) of the persistent launches of the handle's last
+    sip_solve / sip_solve_multi call (summed over its launches)."""
     ms = ctypes.c_double()
     _check(lib().sip_system_solve_ms(system._h, ctypes.byref(ms)))
     return ms.value

@@ -62,10 +62,13 @@ def test_persistent_limit_and_symmetric(sip, monkeypatch):
 
 
 def test_solve_launch_time(sip, monkeypatch):
-    """sip_system_solve_ms: the device time of the last persistent launch,
-    positive and within the call's wall time; refused before any persistent
-    solve and on the chunked path."""
+    """sip_system_solve_ms: the device time of the last solve call's
+    persistent launches, positive and within the call's wall time (a pair of
+    right-hand sides: the pair launch plus the continuation of the one that
+    runs longer, about as long as the longer solo solve or more); refused before any persistent solve
+    and after a chunked one."""
     A, b = problems.make_block((48, 40, 24), "cd", np.random.SeedSequence(9))
+    b2 = problems.rhs_uniform(48, 40, 24, np.random.default_rng(5))
     S = sip.sip_factor(dev(A), 0.92, "mixed")
     with pytest.raises(sip.SipError):
         sip.sip_system_solve_ms(S)
@@ -73,6 +76,13 @@ def test_solve_launch_time(sip, monkeypatch):
     _, it, _, secs = sip.sip_solve(S, dev(b), torch.zeros_like(dev(b)), 1e-8, 5000)
     ms = sip.sip_system_solve_ms(S)
     assert it > 0 and 0.0 < ms <= secs * 1e3
+    _, it2, _, secs2 = sip.sip_solve(S, dev(b2), torch.zeros_like(dev(b)), 1e-8, 5000)
+    ms2 = sip.sip_system_solve_ms(S)
+    assert 0.0 < ms2 <= secs2 * 1e3
+    _, info = sip.sip_solve_multi(S, [dev(b), dev(b2)], [torch.zeros_like(dev(b)) for _ in range(2)], 1e-8, 5000)
+    assert [i[0] for i in info] == [it, it2]
+    msp = sip.sip_system_solve_ms(S)
+    assert 0.9 * max(ms, ms2) < msp <= max(i[2] for i in info) * 1e3
     S.close()
     monkeypatch.setenv("SIP_SOLVE_PERSISTENT", "0")
     S = sip.sip_factor(dev(A), 0.92, "mixed")
