@@ -116,10 +116,10 @@ def parse():
                     help="skip the two-right-hand-side and multi-block solves of the same block")
     ap.add_argument("--profile-iters", type=int, default=40)
     # oracle samples sized to about 10-30 s of host CPU work each
-    ap.add_argument("--cpu-iters", type=int, default=50, help="oracle iterations of the 256^3 block")
+    ap.add_argument("--cpu-iters", type=int, default=100, help="oracle iterations of the 256^3 block")
     ap.add_argument("--cpu-iters-batched", type=int, default=20,
                     help="oracle iterations per block (batched; 16 processes)")
-    ap.add_argument("--cpu-iters-large", type=int, default=8, help="oracle iterations of the 512x512x256 block")
+    ap.add_argument("--cpu-iters-large", type=int, default=20, help="oracle iterations of the 512x512x256 block")
     ap.add_argument("--cpu-iters-serving", type=int, default=100,
                     help="oracle iterations per sampled system (serving; 16 processes)")
     ap.add_argument("--no-configs", action="store_true",
@@ -513,12 +513,24 @@ def config3_summary(args, sip):
     dt64, ci64, res64, _, xs64 = run_batch(sip, blocks, "fp64", args.epoch_iters, 3)
     errs = [rel_err(x, y) for x, y in zip(xs, xs64)]
     value = ci / dt
+    log("64 uneven blocks: the same solved one after the other")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ci1 = 0
+    for dims, A, b in blocks:
+        S = sip.sip_factor(A, problems.ALPHA, "mixed")
+        _, it, _, _ = sip.sip_solve(S, b, torch.zeros_like(b), RTOL, 200000)
+        S.close()
+        ci1 += dims[0] * dims[1] * dims[2] * it
+    torch.cuda.synchronize()
+    one_at_a_time = ci1 / (time.perf_counter() - t0)
     out = {"workload": "64 blocks, dims uniform 32..160 per axis, half Poisson / half upwind convection-diffusion, "
                        "one solve server, factor + mixed solve to 1e-8",
            "cells": sum(d[0] * d[1] * d[2] for d, _, _ in blocks), "value": value, "unit": "cell-iterations/s",
            "seconds": dt, "max_iters": max(r["iters"] for r in res), "max_rel_res": max(r["rel_res"] for r in res),
            "all_ok": all(r["status"] == 0 for r in res) and all(r["status"] == 0 for r in res64),
            "epochs": st["epochs"], "fp64_cell_iters_per_s": ci64 / dt64, "mixed_speedup_vs_fp64": value / (ci64 / dt64),
+           "one_at_a_time_cell_iters_per_s": one_at_a_time, "speedup_vs_one_at_a_time": value / one_at_a_time,
            "err_vs_fp64_max": max(errs), "err_vs_fp64_median": sorted(errs)[len(errs) // 2],
            "roofline": solve_roofline(value)}
     if not args.no_cpu:
