@@ -158,6 +158,12 @@ sip_status sip_iterate_noalloc(sip_system h, const double *b, double *x, int32_t
  * environment variable SIP_SOLVE_PERSISTENT=0 (read at every call), or a
  * plan with one loader phase or a poll distance other than 2, it replays
  * graph-captured chunks of 8 iterations instead, with the same results.
+ * Every device-side wait (a tile for its neighbours' face records, a
+ * workgroup for its next task) is bounded, by 2 s of device wall clock or
+ * by SIP_WAIT_LIMIT_MS (read by every iterate, solve, profile and tune call;
+ * 0 makes every wait that is not met at once time out, a hook for testing
+ * the error path): a wait that times out ends the call with SIP_EDEVICE, and
+ * the handle stays usable (later calls use fresh face-record tags).
  * Errors: SIP_EINVAL (also non-finite b or start vector), SIP_EBREAKDOWN,
  * SIP_ENOTCONV (x holds x_max_iter), SIP_EDEVICE. */
 sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int32_t max_iter,

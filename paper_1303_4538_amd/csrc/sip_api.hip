@@ -39,6 +39,15 @@ uint64_t timeout_ticks_for(int device, double seconds)
     return (uint64_t)(seconds * rate_khz * 1000.0);
 }
 
+// Bound of every device-side wait of a handle's sweeps: 2 s, or
+// SIP_WAIT_LIMIT_MS (a test hook: 0 makes every wait that is not met at once
+// time out, which exercises the error paths without a stalled device).
+static void refresh_wait_limit(sip_system_s *h)
+{
+    const char *e = getenv("SIP_WAIT_LIMIT_MS");
+    h->timeout_ticks = timeout_ticks_for(h->device, e ? std::max(0.0, atof(e)) * 1e-3 : 2.0);
+}
+
 uint32_t schedule_seed()
 {
     const char *e = getenv("SIP_SCHEDULE_SEED");
@@ -261,7 +270,12 @@ static sip_status launch_iterations(sip_system_s *h, int n, hipStream_t s)
 // Replays CHUNK iterations as one captured graph.
 static sip_status launch_chunk(sip_system_s *h, hipStream_t s)
 {
+    if (h->chunk_exec && h->chunk_ticks != h->timeout_ticks) {   // the graph holds the wait bound
+        hipGraphExecDestroy(h->chunk_exec);
+        h->chunk_exec = nullptr;
+    }
     if (!h->chunk_exec) {
+        h->chunk_ticks = h->timeout_ticks;
         if (!h->cap_stream) HIPTRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         HIPTRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -472,6 +486,18 @@ static sip_status launch_solve_persistent(sip_system_s *h, hipStream_t s, const 
     return SIP_OK;
 }
 
+// After a persistent launch whose task queue timed out: the sweep then in
+// progress may not have reached its finaliser, so face records tagged with
+// the control block's current epoch can remain; the next sweep on the handle
+// must use a newer tag.  hc: the block as copied back after the launch.
+static sip_status skip_epoch(Ctl *dctl, Ctl *hc, hipStream_t s)
+{
+    hc->epoch += 1u;
+    HIPTRY(hipMemcpyAsync(dctl, hc, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    HIPTRY(hipStreamSynchronize(s));
+    return SIP_OK;
+}
+
 // After the stream has synchronised: adds the launch's device time to the
 // solve call's sum.
 static sip_status count_solve_launch(sip_system_s *h)
@@ -669,6 +695,7 @@ sip_status sip_iterate(sip_system h, const double *b, double *x, int32_t n_iter,
 {
     const Range range("sip_iterate");
     if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
+    refresh_wait_limit(h);
     if (n_iter < 0) return set_error(SIP_EINVAL, "n_iter must be >= 0");
     hipStream_t s = (hipStream_t)stream;
     TRY(ensure_hist(h, n_iter + 1, s));
@@ -701,6 +728,7 @@ sip_status sip_iterate_noalloc(sip_system h, const double *b, double *x, int32_t
                                void *stream)
 {
     if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
+    refresh_wait_limit(h);
     if (n_iter < 0) return set_error(SIP_EINVAL, "n_iter must be >= 0");
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess || cur != h->device)
@@ -774,7 +802,10 @@ static sip_status solve_one(sip_system h, const double *b, double *x, double rto
             info->rel_res = non_finite(c.stop) ? std::numeric_limits<double>::quiet_NaN() : c.rho;
             info->seconds = secs;
         }
-        if (h->p_host_pc.err) return set_error(SIP_EDEVICE, "a device-side queue wait timed out");
+        if (h->p_host_pc.err) {
+            TRY(skip_epoch(h->ctl, &h->h_ctl[2], s));
+            return set_error(SIP_EDEVICE, "a device-side queue wait timed out");
+        }
         if (c.stop == RUN) return set_error(SIP_EDEVICE, "solve ended without a stop decision");
         return stop_status(c.stop);
     }
@@ -827,6 +858,7 @@ sip_status sip_solve(sip_system h, const double *b, double *x, double rtol, int3
     const Range range("sip_solve");
     if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
     if (!(rtol > 0.0) || max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
+    refresh_wait_limit(h);
     h->p_timed = false;
     h->p_ms = 0.0;
     return solve_one(h, b, x, rtol, max_iter, info, stream);
@@ -844,6 +876,7 @@ sip_status sip_export_factors(sip_system h, double *const out[7], void *stream)
 sip_status sip_profile_sweeps(sip_system h, const double *b, double *x, int32_t n_iter, double ms[2], void *stream)
 {
     if (!h || !b || !x || !ms) return set_error(SIP_EINVAL, "NULL argument");
+    refresh_wait_limit(h);
     if (n_iter < 1) return set_error(SIP_EINVAL, "n_iter must be >= 1");
     hipStream_t s = (hipStream_t)stream;
     TRY(ensure_hist(h, n_iter + 1, s));
@@ -892,6 +925,7 @@ sip_status sip_iterate_multi(sip_system h, int32_t nrhs, const double *const *b,
     if (nrhs < 1 || n_iter < 0) return set_error(SIP_EINVAL, "need nrhs >= 1 and n_iter >= 0");
     for (int r = 0; r < nrhs; r++)
         if (!b[r] || !x[r]) return set_error(SIP_EINVAL, "right-hand side %d: NULL b or x", r);
+    refresh_wait_limit(h);
     hipStream_t s = (hipStream_t)stream;
     const int npair = pairs_ok(h) ? nrhs / 2 : 0;
     const size_t hn = (size_t)n_iter + 1;
@@ -953,6 +987,7 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
     sip_status worst = SIP_OK;
     sip_status bad = SIP_OK;   // first right-hand side with a non-finite norm; the others are still solved
     int bad_r = -1;
+    refresh_wait_limit(h);
     h->p_timed = false;
     h->p_ms = 0.0;
     // the finaliser records rho_n for n <= max_iter
@@ -1010,7 +1045,10 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
         if (persist) HIPTRY(hipMemcpyAsync(&h->p_host_pc, h->p_pc, sizeof(PersistCtl), hipMemcpyDeviceToHost, s));
         HIPTRY(hipStreamSynchronize(s));
         if (persist) TRY(count_solve_launch(h));
-        if (persist && h->p_host_pc.err) return set_error(SIP_EDEVICE, "a device-side queue wait timed out");
+        if (persist && h->p_host_pc.err) {
+            TRY(skip_epoch(h->mctl, &h->h_mctl[6], s));
+            return set_error(SIP_EDEVICE, "a device-side queue wait timed out");
+        }
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         const Ctl *c = &h->h_mctl[6];
         if (c[0].stop == RUN && !split) return set_error(SIP_EDEVICE, "solve ended without a stop decision");
@@ -1055,6 +1093,7 @@ sip_status sip_profile_sweeps_multi(sip_system h, const double *const *b, double
                                     double ms[2], void *stream)
 {
     if (!h || !b || !x || !b[0] || !b[1] || !x[0] || !x[1] || !ms) return set_error(SIP_EINVAL, "NULL argument");
+    refresh_wait_limit(h);
     if (n_iter < 1) return set_error(SIP_EINVAL, "n_iter must be >= 1");
     if (!pairs_ok(h)) return set_error(SIP_EINVAL, "pairs of right-hand sides need FP32 factors");
     hipStream_t s = (hipStream_t)stream;
@@ -1095,6 +1134,7 @@ sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phas
 {
     const Range range("sip_tune");
     if (!h || !b) return set_error(SIP_EINVAL, "NULL argument");
+    refresh_wait_limit(h);
     if (n_iter < 1) return set_error(SIP_EINVAL, "n_iter must be >= 1");
     hipStream_t s = (hipStream_t)stream;
     TRY(ensure_hist(h, n_iter + 1, s));

@@ -80,6 +80,7 @@ struct sip_system_s {
     sipk::Ctl *h_mctl = nullptr;    // pinned, 3 slots of 3
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t chunk_exec = nullptr;
+    uint64_t chunk_ticks = 0;                 // the wait bound the chunk graph was captured with
     // persistent solves (allocated on first use): the tile orders, the task
     // queue and its control block with two device flags (pause, stopped)
     int num_cu = 0;

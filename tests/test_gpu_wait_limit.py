@@ -1,0 +1,99 @@
+"""The device-side waits (a tile polling its neighbours' face records, a
+persistent workgroup waiting for its next task) are all bounded.  Forced from
+the host with SIP_WAIT_LIMIT_MS=0, every wait that is not met at once times
+out: the call reports SIP_EDEVICE, every kernel exits, and the handle then
+solves exactly as a fresh handle does (bitwise x, iteration count and
+residual), which needs the face records of the aborted sweep to be told from
+the new ones by their tags.  Covers the persistent and the chunked single
+solve, a pair of right-hand sides and a fixed iteration count."""
+import numpy as np
+import pytest
+
+from paper_1303_4538_amd import problems
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DIMS = (96, 80, 40)   # 6 x 5 tiles: every sweep has tiles that must wait for others
+
+
+@pytest.fixture(scope="module")
+def sip():
+    from paper_1303_4538_amd import sip as s
+    s.lib()
+    assert torch.cuda.is_available()
+    return s
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def system():
+    A, b = problems.make_block(DIMS, "cd", np.random.SeedSequence(21))
+    b2 = problems.rhs_uniform(DIMS[0], DIMS[1], DIMS[2], np.random.default_rng(22))
+    return dev(A), dev(b), dev(b2)
+
+
+def fresh_solve(sip, A, b):
+    S = sip.sip_factor(A, 0.92, "mixed")
+    x = torch.zeros_like(b)
+    _, it, rr, _ = sip.sip_solve(S, b, x, 1e-8, 5000)
+    S.close()
+    return x, it, rr
+
+
+@pytest.mark.parametrize("persistent", ["1", "0"])
+def test_solve_times_out_then_recovers(sip, system, persistent, monkeypatch):
+    A, b, _ = system
+    monkeypatch.setenv("SIP_SOLVE_PERSISTENT", persistent)
+    x_ref, it_ref, rr_ref = fresh_solve(sip, A, b)
+    S = sip.sip_factor(A, 0.92, "mixed")
+    for attempt in range(2):   # twice in a row: the second starts from the first one's leftovers
+        monkeypatch.setenv("SIP_WAIT_LIMIT_MS", "0")
+        with pytest.raises(sip.SipError) as e:
+            sip.sip_solve(S, b, torch.zeros_like(b), 1e-8, 5000)
+        assert e.value.status == sip.SIP_EDEVICE, str(e.value)
+        monkeypatch.delenv("SIP_WAIT_LIMIT_MS")
+        x = torch.zeros_like(b)
+        _, it, rr, _ = sip.sip_solve(S, b, x, 1e-8, 5000)
+        assert it == it_ref and rr == rr_ref, (attempt, it, it_ref, rr, rr_ref)
+        assert torch.equal(x, x_ref), attempt
+    S.close()
+
+
+def test_pair_times_out_then_recovers(sip, system, monkeypatch):
+    A, b, b2 = system
+    monkeypatch.setenv("SIP_SOLVE_PERSISTENT", "1")
+    refs = [fresh_solve(sip, A, r) for r in (b, b2)]
+    S = sip.sip_factor(A, 0.92, "mixed")
+    monkeypatch.setenv("SIP_WAIT_LIMIT_MS", "0")
+    with pytest.raises(sip.SipError) as e:
+        sip.sip_solve_multi(S, [b, b2], [torch.zeros_like(b) for _ in range(2)], 1e-8, 5000)
+    assert e.value.status == sip.SIP_EDEVICE, str(e.value)
+    monkeypatch.delenv("SIP_WAIT_LIMIT_MS")
+    xs = [torch.zeros_like(b) for _ in range(2)]
+    _, info = sip.sip_solve_multi(S, [b, b2], xs, 1e-8, 5000)
+    for (x_ref, it_ref, rr_ref), x, (it, rr, _) in zip(refs, xs, info):
+        assert it == it_ref and rr == rr_ref
+        assert torch.equal(x, x_ref)
+    S.close()
+
+
+def test_iterate_times_out_then_recovers(sip, system, monkeypatch):
+    A, b, _ = system
+    S0 = sip.sip_factor(A, 0.92, "mixed")
+    x_ref = torch.zeros_like(b)
+    h_ref = sip.sip_iterate(S0, b, x_ref, 20)
+    S0.close()
+    S = sip.sip_factor(A, 0.92, "mixed")
+    monkeypatch.setenv("SIP_WAIT_LIMIT_MS", "0")
+    with pytest.raises(sip.SipError) as e:
+        sip.sip_iterate(S, b, torch.zeros_like(b), 20)
+    assert e.value.status == sip.SIP_EDEVICE, str(e.value)
+    monkeypatch.delenv("SIP_WAIT_LIMIT_MS")
+    x = torch.zeros_like(b)
+    h = sip.sip_iterate(S, b, x, 20)
+    assert np.array_equal(h, h_ref) and torch.equal(x, x_ref)
+    S.close()
