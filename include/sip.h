@@ -391,7 +391,10 @@ typedef struct {
  * arriving, in epochs of epoch_iters iterations.  Environment variables read
  * here: SIP_SERVER_PERSISTENT=1 / 0 forces one of the two modes;
  * SIP_SERVER_DATAFLOW=0 publishes whole sweeps in tile order instead; the
- * results are the same in every mode.
+ * results are the same in every mode.  SIP_WAIT_LIMIT_MS (see sip_solve) is
+ * read at every factorisation and step: a wait that times out fails the
+ * requests of that launch with SIP_EDEVICE (a factorisation's with it too),
+ * and the server goes on serving the others.
  * Errors: SIP_EINVAL (max_slots outside 1..4096, epoch_iters < 1,
  * max_queue < 1), SIP_ENOMEM (the server's own buffers), SIP_EDEVICE. */
 sip_status sip_server_create(const sip_server_config *c, sip_server *out);

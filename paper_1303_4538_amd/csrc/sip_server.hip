@@ -32,6 +32,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -264,6 +265,13 @@ private:
     sip_status run_persist(int grp, const std::vector<Job> &jobs, const std::vector<Geom> &gs, const SweepPlan &gp,
                            bool others_waiting);
     bool want_pause(double since_launch, bool others_waiting);
+    // The bound of every device-side wait: 2 s, or SIP_WAIT_LIMIT_MS (read at
+    // every factorisation and step; a test hook, see sip_solve).
+    void refresh_wait_limit()
+    {
+        const char *e = getenv("SIP_WAIT_LIMIT_MS");
+        timeout_ticks = timeout_ticks_for(device, e ? std::max(0.0, atof(e)) * 1e-3 : 2.0);
+    }
     void form_pairs(std::vector<GpuReq *> &ready);
     void free_pair(Pair *p);
     sip_status ensure_launch_buffers(int grp, int njobs, int ntiles);
@@ -460,9 +468,10 @@ void GpuBackend::factor(const std::vector<Resident *> &sys, const std::vector<Re
         gs.push_back(static_cast<GpuResident *>(sys[k]));
         go.push_back(static_cast<GpuReq *>(owners[k]));
     }
-    if (run_factor(gs, go, result) != SIP_OK)
+    refresh_wait_limit();
+    if (const sip_status e = run_factor(gs, go, result); e != SIP_OK)
         for (sip_status &r : result)
-            if (r == SIP_OK) r = SIP_EBREAKDOWN;
+            if (r == SIP_OK) r = e;
 }
 
 // Factorise newly resident systems, all of them in one batched launch per
@@ -527,8 +536,10 @@ sip_status GpuBackend::run_factor(const std::vector<GpuResident *> &sys, const s
     if (hipMemcpyAsync(h_ctl, ctl, sizeof(Ctl) * MAX_SLOTS, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
         return set_error(SIP_EDEVICE, "factorisation status copy failed");
-    for (size_t k = 0; k < sys.size(); k++)
-        if (result[k] == SIP_OK && h_ctl[owners[k]->slot].stop != RUN) result[k] = SIP_EBREAKDOWN;
+    for (size_t k = 0; k < sys.size(); k++) {
+        const uint32_t fs = h_ctl[owners[k]->slot].stop;
+        if (result[k] == SIP_OK && fs != RUN) result[k] = fs == TIMEOUT ? SIP_EDEVICE : SIP_EBREAKDOWN;
+    }
     return SIP_OK;
 }
 
@@ -561,6 +572,7 @@ sip_status GpuBackend::step(std::vector<Req *> &act)
 {
     const Range range("server epoch");
     steps++;
+    refresh_wait_limit();
     // groups 0..NARITH-1: single requests by arithmetic; NARITH + arith: pairs
     constexpr int NG = 2 * NARITH;
     std::vector<Job> jobs[NG];

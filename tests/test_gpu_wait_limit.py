@@ -97,3 +97,36 @@ def test_iterate_times_out_then_recovers(sip, system, monkeypatch):
     h = sip.sip_iterate(S, b, x, 20)
     assert np.array_equal(h, h_ref) and torch.equal(x, x_ref)
     S.close()
+
+
+@pytest.mark.parametrize("persistent", ["1", "0"])
+def test_server_times_out_then_serves(sip, system, persistent, monkeypatch):
+    """The solve server reads the bound at every factorisation and step: a
+    resident system's solve that times out, and a new system's factorisation
+    that does, fail their requests with SIP_EDEVICE; the next requests for
+    both systems are served bitwise as solo solves.  (The variable is only
+    changed while the server has no request, so its thread never reads the
+    environment while it is being changed.)"""
+    A, b, _ = system
+    monkeypatch.setenv("SIP_SOLVE_PERSISTENT", "1")
+    x_ref, it_ref, rr_ref = fresh_solve(sip, A, b)
+    monkeypatch.setenv("SIP_SERVER_PERSISTENT", persistent)
+    srv = sip.Server(max_slots=16)
+
+    def run(system_id):
+        x = torch.zeros_like(b)
+        r = srv.poll(srv.submit(system_id, A, b, x, rtol=1e-8, max_iter=5000, retain=True))
+        return r, x
+
+    def exact(r, x):
+        assert r["status"] == 0 and r["iters"] == it_ref and r["rel_res"] == rr_ref, r
+        assert torch.equal(x, x_ref)
+
+    exact(*run(7))
+    for system_id in (7, 8):   # 7: resident, its solve times out; 8: its factorisation does
+        monkeypatch.setenv("SIP_WAIT_LIMIT_MS", "0")
+        r, _ = run(system_id)
+        assert r["status"] == sip.SIP_EDEVICE, (system_id, r)
+        monkeypatch.delenv("SIP_WAIT_LIMIT_MS")
+        exact(*run(system_id))
+    srv.close()
