@@ -39,14 +39,15 @@ uint64_t timeout_ticks_for(int device, double seconds)
     return (uint64_t)(seconds * rate_khz * 1000.0);
 }
 
-// Bound of every device-side wait of a handle's sweeps: 2 s, or
-// SIP_WAIT_LIMIT_MS (a test hook: 0 makes every wait that is not met at once
-// time out, which exercises the error paths without a stalled device).
-static void refresh_wait_limit(sip_system_s *h)
+double wait_limit_seconds()
 {
     const char *e = getenv("SIP_WAIT_LIMIT_MS");
-    h->timeout_ticks = timeout_ticks_for(h->device, e ? std::max(0.0, atof(e)) * 1e-3 : 2.0);
+    return e ? std::max(0.0, atof(e)) * 1e-3 : 2.0;
 }
+
+// The bound of every device-side wait of a handle's sweeps, read at every
+// call (SIP_WAIT_LIMIT_MS exercises the error paths without a stalled device).
+static void refresh_wait_limit(sip_system_s *h) { h->timeout_ticks = timeout_ticks_for(h->device, wait_limit_seconds()); }
 
 uint32_t schedule_seed()
 {

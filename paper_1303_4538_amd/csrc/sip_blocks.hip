@@ -404,6 +404,7 @@ sip_status sip_blocks_iterate(sip_blocks h, const double *b, double *x, int32_t 
     if (!h || !b || !x) return set_error(SIP_EINVAL, "NULL argument");
     if (n_iter < 0) return set_error(SIP_EINVAL, "n_iter must be >= 0");
     hipStream_t s = (hipStream_t)stream;
+    h->timeout_ticks = timeout_ticks_for(h->blk[0]->device, wait_limit_seconds());
     TRY(ensure_hist(h, n_iter + 1, s));
     TRY(stage_in(h, b, x, (uint32_t)n_iter, 0.0, s));
     for (int q = 0; q < n_iter; q++) TRY(step(h, true, s));
@@ -432,6 +433,7 @@ sip_status sip_blocks_solve(sip_blocks h, const double *b, double *x, double rto
     if (!(rtol > 0.0) || max_iter < 0) return set_error(SIP_EINVAL, "need rtol > 0 and max_iter >= 0");
     hipStream_t s = (hipStream_t)stream;
     const auto t0 = std::chrono::steady_clock::now();
+    h->timeout_ticks = timeout_ticks_for(h->blk[0]->device, wait_limit_seconds());
     TRY(ensure_hist(h, max_iter + 1, s));
     TRY(stage_in(h, b, x, (uint32_t)max_iter, rtol, s));
     hipEvent_t ev[2];

@@ -23,6 +23,9 @@ struct Range {
 constexpr int CHUNK = 8;   // iterations per graph-captured launch chunk
 
 uint64_t timeout_ticks_for(int device, double seconds);
+// Bound of the device-side waits in seconds: 2, or SIP_WAIT_LIMIT_MS (a test
+// hook: 0 makes every wait that is not met at once time out).
+double wait_limit_seconds();
 // Ticket order of a launch over the jobs gs: every tile after its upstream
 // neighbours (W and S; E and N for the backward sweep).  seed 0: by
 // anti-diagonal; otherwise a random order with the same property (race

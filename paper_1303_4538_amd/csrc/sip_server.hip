@@ -32,7 +32,6 @@
 
 #include <algorithm>
 #include <chrono>
-#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -267,11 +266,7 @@ private:
     bool want_pause(double since_launch, bool others_waiting);
     // The bound of every device-side wait: 2 s, or SIP_WAIT_LIMIT_MS (read at
     // every factorisation and step; a test hook, see sip_solve).
-    void refresh_wait_limit()
-    {
-        const char *e = getenv("SIP_WAIT_LIMIT_MS");
-        timeout_ticks = timeout_ticks_for(device, e ? std::max(0.0, atof(e)) * 1e-3 : 2.0);
-    }
+    void refresh_wait_limit() { timeout_ticks = timeout_ticks_for(device, wait_limit_seconds()); }
     void form_pairs(std::vector<GpuReq *> &ready);
     void free_pair(Pair *p);
     sip_status ensure_launch_buffers(int grp, int njobs, int ntiles);

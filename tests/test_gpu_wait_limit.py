@@ -130,3 +130,25 @@ def test_server_times_out_then_serves(sip, system, persistent, monkeypatch):
         monkeypatch.delenv("SIP_WAIT_LIMIT_MS")
         exact(*run(system_id))
     srv.close()
+
+
+def test_blocks_time_out_then_recover(sip, system, monkeypatch):
+    """A multi-block domain (2 x 2 x 2 blocks coupled through boundary
+    values): the blocks' sweeps time out, the domain control stops every block
+    and the solve reports SIP_EDEVICE; the next solve is bitwise a fresh one."""
+    A, b, _ = system
+    cuts = [[0, 48, 96], [0, 32, 80], [0, 16, 40]]
+    B0 = sip.sip_blocks_factor(A, cuts, 0.92, "mixed")
+    x_ref = torch.zeros_like(b)
+    _, it_ref, rr_ref, _ = B0.solve(b, x_ref, 1e-8, 5000)
+    B0.close()
+    B = sip.sip_blocks_factor(A, cuts, 0.92, "mixed")
+    monkeypatch.setenv("SIP_WAIT_LIMIT_MS", "0")
+    with pytest.raises(sip.SipError) as e:
+        B.solve(b, torch.zeros_like(b), 1e-8, 5000)
+    assert e.value.status == sip.SIP_EDEVICE, str(e.value)
+    monkeypatch.delenv("SIP_WAIT_LIMIT_MS")
+    x = torch.zeros_like(b)
+    _, it, rr, _ = B.solve(b, x, 1e-8, 5000)
+    assert it == it_ref and rr == rr_ref and torch.equal(x, x_ref)
+    B.close()
