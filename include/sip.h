@@ -160,8 +160,8 @@ sip_status sip_iterate_noalloc(sip_system h, const double *b, double *x, int32_t
  * graph-captured chunks of 8 iterations instead, with the same results.
  * Every device-side wait (a tile for its neighbours' face records, a
  * workgroup for its next task) is bounded, by 2 s of device wall clock or
- * by SIP_WAIT_LIMIT_MS (read by every iterate, solve, profile and tune call,
- * of a single system or of a multi-block domain;
+ * by SIP_WAIT_LIMIT_MS (read by every factorisation, iterate, solve, profile
+ * and tune call, of a single system or of a multi-block domain;
  * 0 makes every wait that is not met at once time out, a hook for testing
  * the error path): a wait that times out ends the call with SIP_EDEVICE, and
  * the handle stays usable (later calls use fresh face-record tags).

@@ -608,7 +608,7 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
         delete h;
         return set_error(SIP_EDEVICE, "no HIP device");
     }
-    h->timeout_ticks = timeout_ticks_for(h->device, 2.0);
+    h->timeout_ticks = timeout_ticks_for(h->device, wait_limit_seconds());
     h->torture = schedule_seed();
     // one system per launch: three loader phases (split turns) shorten the
     // step; a solve server with many blocks per launch keeps two (more

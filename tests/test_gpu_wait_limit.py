@@ -152,3 +152,17 @@ def test_blocks_time_out_then_recover(sip, system, monkeypatch):
     _, it, rr, _ = B.solve(b, x, 1e-8, 5000)
     assert it == it_ref and rr == rr_ref and torch.equal(x, x_ref)
     B.close()
+
+
+def test_factorisation_times_out(sip, system, monkeypatch):
+    """sip_factor's face-record waits are bounded the same way: SIP_EDEVICE,
+    no handle; the next factorisation gives the same factors (solve bitwise)."""
+    A, b, _ = system
+    x_ref, it_ref, rr_ref = fresh_solve(sip, A, b)
+    monkeypatch.setenv("SIP_WAIT_LIMIT_MS", "0")
+    with pytest.raises(sip.SipError) as e:
+        sip.sip_factor(A, 0.92, "mixed")
+    assert e.value.status == sip.SIP_EDEVICE, str(e.value)
+    monkeypatch.delenv("SIP_WAIT_LIMIT_MS")
+    x, it, rr = fresh_solve(sip, A, b)
+    assert it == it_ref and rr == rr_ref and torch.equal(x, x_ref)
