@@ -47,15 +47,17 @@ PAIR_BWD_BYTES = 12 + 2 * (4 + 8 + 8)
 RTOL = 1e-8
 SOLVE_BYTES_MIXED = FWD_BYTES["mixed"] + BWD_BYTES["mixed"]   # one mixed iteration, both sweeps
 # HBM bytes per launch of the persistent solve kernel (one launch = one whole
-# mixed solve) on the 256^3 and the 512x512x256 workloads, from the rocprofv3
-# FETCH_SIZE / WRITE_SIZE passes summarised in profiles/solve_256cube_cd.md and
-# profiles/solve_512x512x256_stretched.md (calibrated against a plain copy),
-# with the iterations of that solve and the SHA-256 of the kernel
-# source they were taken with.  Once the source differs the counters no
+# mixed solve) on the 256^3 and the 512x512x256 workloads, and of the two
+# launches of the pair workload's two-right-hand-side solve, from the rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes summarised in profiles/solve_256cube_cd.md,
+# profiles/solve_512x512x256_stretched.md and profiles/solve_pair_256cube_cd.md
+# (calibrated against a plain copy), with the iterations of that solve and the
+# SHA-256 of the kernel source they were taken with.  Once the source differs the counters no
 # longer describe the kernel and traffic is null.
 MEASURED = {"kernels_sha256": "fbe13dd4b41909e7b8952f6b31e020f2c4f4203543dd6b58b925e150f45071e6",
             "single": {"iterations": 4069, "persist_bytes": 9749482215394},
-            "large": {"iterations": 15239, "persist_bytes": 147519934339422}}
+            "large": {"iterations": 15239, "persist_bytes": 147519934339422},
+            "pair": {"iterations": [4069, 6023], "persist_bytes": 18050078353724}}
 
 
 def log(msg):
@@ -144,13 +146,15 @@ def parse():
     ap.add_argument("--prof", action="store_true",
                     help="short run for rocprofv3: factor, a few sweeps and one persistent mixed solve of the "
                          "default workload (sweeps: mixed, a pair of right-hand sides, all-FP32; with --workload "
-                         "large: the 512x512x256 block, mixed and FP64) and a 512 MiB device copy used to "
-                         "calibrate the HBM byte counters")
+                         "large: the 512x512x256 block, mixed and FP64; with --workload pair: the two-right-hand-"
+                         "side solve of the pair workload) and a 512 MiB device copy used to calibrate the HBM "
+                         "byte counters")
     return ap.parse_args()
 
 
 def prof_run(args):
     """Minimal GPU work for counter collection (one process, no CPU oracle)."""
+    import numpy as np
     import torch
 
     from paper_1303_4538_amd import problems, sip
@@ -179,6 +183,19 @@ def prof_run(args):
     c = problems.config2(args.n)
     A = torch.from_numpy(c["A"]).cuda()
     b = torch.from_numpy(c["b"]).cuda()
+    if args.workload == "pair":
+        # the two-right-hand-side solve of the pair workload: one pair launch
+        # and the continuation of the right-hand side that runs longer
+        n = args.n
+        b2 = torch.from_numpy(problems.rhs_uniform(
+            n, n, n, np.random.default_rng(np.random.SeedSequence(problems.MASTER_SEED).spawn(3)[2]))).cuda()
+        S = sip.sip_factor(A, c["alpha"], "mixed")
+        _, info = sip.sip_solve_multi(S, [b, b2], [torch.zeros_like(b), torch.zeros_like(b)], RTOL, 200000)
+        print(f"prof: pair solve, iterations {[i[0] for i in info]}, "
+              f"{sip.sip_system_solve_ms(S):.1f} ms in its persistent launches", flush=True)
+        S.close()
+        torch.cuda.synchronize()
+        return
     S = sip.sip_factor(A, c["alpha"], "mixed")
     x = torch.zeros_like(b)
     fwd_ms, bwd_ms = sip.sip_profile_sweeps(S, b, x, 5)
@@ -764,6 +781,9 @@ def pair_run(args):
               "bwd_gbps": round(PAIR_BWD_BYTES * cells / (bwd_ms * 1e-3) / 1e9, 1)}
     if persistent:
         roof = pair_roofline(cells, its[-1], sum(launch_ms) / len(launch_ms))
+        m = MEASURED.get("pair")
+        if m and kernels_sha256() == MEASURED["kernels_sha256"] and m["iterations"] == its[-1]:
+            roof["traffic"] = round(m["persist_bytes"] / (roof["launch_ms"] * 1e-3) / 1e9, 1)
         roof["sweeps_one_launch_each"] = sweeps
     else:
         roof = {"bound": "hbm", "kernel": "k_forward<float, double, 3, 2, 2> (pair forward sweep, one launch)",
