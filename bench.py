@@ -54,10 +54,10 @@ SOLVE_BYTES_MIXED = FWD_BYTES["mixed"] + BWD_BYTES["mixed"]   # one mixed iterat
 # (calibrated against a plain copy), with the iterations of that solve and the
 # SHA-256 of the kernel source they were taken with.  Once the source differs the counters no
 # longer describe the kernel and traffic is null.
-MEASURED = {"kernels_sha256": "fbe13dd4b41909e7b8952f6b31e020f2c4f4203543dd6b58b925e150f45071e6",
-            "single": {"iterations": 4069, "persist_bytes": 9749482215394},
-            "large": {"iterations": 15239, "persist_bytes": 147519934339422},
-            "pair": {"iterations": [4069, 6023], "persist_bytes": 18050078353724}}
+MEASURED = {"kernels_sha256": "b2870e99014f841995aa648012c9f90a4d7f9509a758d332e21f6036b1197ada",
+            "single": {"iterations": 4069, "persist_bytes": 9731795800813},
+            "large": {"iterations": 15239, "persist_bytes": 147047520252700},
+            "pair": {"iterations": [4069, 6023], "persist_bytes": 17930728889985}}
 
 
 def log(msg):

@@ -288,6 +288,15 @@ __device__ __forceinline__ T ldg(const GLOBAL T *base, uint32_t idx)
 {
     return *(const GLOBAL T *)((const GLOBAL char *)base + (size_t)(idx * (uint32_t)sizeof(T)));
 }
+// The same with the non-temporal hint, for streams that no other load of the
+// sweep reads again (coefficients, factors, b): they then do not displace the
+// x planes, which the halo loads of the neighbour tiles and the tile's own
+// slot loads read again shortly after.
+template <typename T>
+__device__ __forceinline__ T ldg_stream(const GLOBAL T *base, uint32_t idx)
+{
+    return __builtin_nontemporal_load((const GLOBAL T *)((const GLOBAL char *)base + (size_t)(idx * (uint32_t)sizeof(T))));
+}
 template <typename T>
 __device__ __forceinline__ void stg(GLOBAL T *base, uint32_t idx, T v)
 {
@@ -534,8 +543,8 @@ __device__ __forceinline__ void fwd_issue(FwdLoad<F, R, M> &c, const FwdSrc<F, R
         // the pad of the second group is not loaded: a dead lane of a load in
         // flight would be reused as soon as the load completes, which makes
         // the compiler wait for every outstanding load
-        const flt4 c0 = ldg(s.A4, e);
-        const flt3 c1 = ldg(s.A3, e);
+        const flt4 c0 = ldg_stream(s.A4, e);
+        const flt3 c1 = ldg_stream(s.A3, e);
         c.a[0] = c0.x;
         c.a[1] = c0.y;
         c.a[2] = c0.z;
@@ -557,15 +566,15 @@ __device__ __forceinline__ void fwd_issue(FwdLoad<F, R, M> &c, const FwdSrc<F, R
     } else {
 #pragma unroll
         for (int p = 0; p < 3; p++) {
-            const dbl2 v2 = ldg(s.AP[p], e);
+            const dbl2 v2 = ldg_stream(s.AP[p], e);
             c.a[2 * p] = v2.x;
             c.a[2 * p + 1] = v2.y;
         }
-        c.a[6] = ldg(s.AT, e);
+        c.a[6] = ldg_stream(s.AT, e);
     }
-    c.b = ldg(s.b, e);
+    c.b = ldg_stream(s.b, e);
 #pragma unroll
-    for (int k = 0; k < Grp<F>::N; k++) c.lv[k] = ldg(s.L[k], e);
+    for (int k = 0; k < Grp<F>::N; k++) c.lv[k] = ldg_stream(s.L[k], e);
     c.x2 = ldg(s.x, s.e0 + (uint32_t)min(f + 2, steps) * PLANE);   // plane `steps` is the zero margin
     // x across a tile edge, loaded without control flow (a branch would cost
     // the loader exact wait counts): the edge slots of a quadrant read the
