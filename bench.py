@@ -45,6 +45,10 @@ FP32_RTOL = 1e-5           # the all-FP32 relaxation stalls near 1e-7
 PAIR_FWD_BYTES = 56 + 16 + 2 * (8 + 8 + 4)     # per cell, both right-hand sides
 PAIR_BWD_BYTES = 12 + 2 * (4 + 8 + 8)
 RTOL = 1e-8
+# Single systems of at least this many cells load the forward sweep's
+# coefficient, factor and b streams non-temporally (the library's own
+# threshold): the last template argument of the persistent kernel's name.
+STREAM_HINT_CELLS = 1 << 22
 SOLVE_BYTES_MIXED = FWD_BYTES["mixed"] + BWD_BYTES["mixed"]   # one mixed iteration, both sweeps
 # HBM bytes per launch of the persistent solve kernel (one launch = one whole
 # mixed solve) on the 256^3 and the 512x512x256 workloads, and of the two
@@ -54,10 +58,10 @@ SOLVE_BYTES_MIXED = FWD_BYTES["mixed"] + BWD_BYTES["mixed"]   # one mixed iterat
 # (calibrated against a plain copy), with the iterations of that solve and the
 # SHA-256 of the kernel source they were taken with.  Once the source differs the counters no
 # longer describe the kernel and traffic is null.
-MEASURED = {"kernels_sha256": "b2870e99014f841995aa648012c9f90a4d7f9509a758d332e21f6036b1197ada",
-            "single": {"iterations": 4069, "persist_bytes": 9731795800813},
-            "large": {"iterations": 15239, "persist_bytes": 147047520252700},
-            "pair": {"iterations": [4069, 6023], "persist_bytes": 17930728889985}}
+MEASURED = {"kernels_sha256": "9301a9dcc7cb9e6a68ca8158838549282692f8490aaa3d4b90c95780e75bcb67",
+            "single": {"iterations": 4069, "persist_bytes": 9722727273959},
+            "large": {"iterations": 15239, "persist_bytes": 147059406083308},
+            "pair": {"iterations": [4069, 6023], "persist_bytes": 17929576910473}}
 
 
 def log(msg):
@@ -432,9 +436,10 @@ def persist_roofline(cells, iters, solve_ms, storage="full", workload=None):
     m = MEASURED.get(workload) if workload else None
     if m and storage == "full" and kernels_sha256() == MEASURED["kernels_sha256"] and m["iterations"] == iters:
         traffic = round(m["persist_bytes"] / (solve_ms * 1e-3) / 1e9, 1)
+    st = "true" if cells >= STREAM_HINT_CELLS else "false"
     return {"bound": "hbm",
-            "kernel": "k_persist<float, double, 3, 1, false> (whole mixed solve in one launch: FP64 residual + FP32 "
-                      "forward sweep, FP32 backward sweep + FP64 update, every iteration)",
+            "kernel": f"k_persist<float, double, 3, 1, false, {st}> (whole mixed solve in one launch: FP64 residual "
+                      "+ FP32 forward sweep, FP32 backward sweep + FP64 update, every iteration)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
             "launch_ms": round(solve_ms, 3),
@@ -443,7 +448,7 @@ def persist_roofline(cells, iters, solve_ms, storage="full", workload=None):
 
 def pair_roofline(cells, its, launch_ms):
     """Roofline of a two-right-hand-side solve's persistent launches: the pair
-    launch k_persist<float, double, 3, 2, false> sweeps both until the first
+    launch k_persist<float, double, 3, 2, false, ...> sweeps both until the first
     stops at iteration n0 (n0 + 1 pair forward sweeps, n0 pair backward
     sweeps), then the other continues from x_n0 in a one-RHS launch
     (n1 - n0 + 1 forward and n1 - n0 backward sweeps; none when both stop
@@ -454,9 +459,10 @@ def pair_roofline(cells, its, launch_ms):
     m = n1 - n0
     cont = (m + 1) * FWD_BYTES["mixed"] + m * BWD_BYTES["mixed"] if m > 0 else 0
     achieved = (pair + cont) * cells / (launch_ms * 1e-3) / 1e9
+    st = "true" if cells >= STREAM_HINT_CELLS else "false"
     return {"bound": "hbm",
-            "kernel": "k_persist<float, double, 3, 2, false> (both right-hand sides in one launch until the first "
-                      "stops) + k_persist<float, double, 3, 1, false> (the other's continuation)",
+            "kernel": f"k_persist<float, double, 3, 2, false, {st}> (both right-hand sides in one launch until the "
+                      f"first stops) + k_persist<float, double, 3, 1, false, {st}> (the other's continuation)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "launch_ms": round(launch_ms, 3),
             "basis": f"({n0} + 1) x {PAIR_FWD_BYTES} + {n0} x {PAIR_BWD_BYTES}"
@@ -594,7 +600,7 @@ def config4_summary(args, sip):
         roofline["sweeps_one_launch_each"] = sweep_detail(fwd_ms, bwd_ms, cells)
     else:
         achieved = FWD_BYTES["mixed"] * cells / (fwd_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": "k_forward<float, double, 3, 1, 2> (FP64 residual + FP32 forward sweep)",
+        roofline = {"bound": "hbm", "kernel": "k_forward<float, double, 3, 1, 2, true> (FP64 residual + FP32 forward sweep)",
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                     **sweep_detail(fwd_ms, bwd_ms, cells)}
@@ -786,7 +792,7 @@ def pair_run(args):
             roof["traffic"] = round(m["persist_bytes"] / (roof["launch_ms"] * 1e-3) / 1e9, 1)
         roof["sweeps_one_launch_each"] = sweeps
     else:
-        roof = {"bound": "hbm", "kernel": "k_forward<float, double, 3, 2, 2> (pair forward sweep, one launch)",
+        roof = {"bound": "hbm", "kernel": "k_forward<float, double, 3, 2, 2, true> (pair forward sweep, one launch)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, **sweeps}
     line = {
@@ -1106,8 +1112,10 @@ def main():
         achieved = fwd_bytes * cells / (fwd_ms * 1e-3) / 1e9
         phases = int(os.environ.get("SIP_SWEEP_PHASES", "3"))   # the single-system default: 3 loader phases
         poll = int(os.environ.get("SIP_POLL_DISTANCE", "2"))    # and polls 2 steps ahead
+        st = "true" if cells >= STREAM_HINT_CELLS and phases == 3 and poll == 2 else "false"
         roofline = {"bound": "hbm",
-                    "kernel": f"k_forward<float, double, {phases}, 1, {poll}> (FP64 residual + FP32 forward sweep)",
+                    "kernel": f"k_forward<float, double, {phases}, 1, {poll}, {st}> (FP64 residual + FP32 forward "
+                              "sweep)",
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                     **sweep_detail(fwd_ms, bwd_ms, cells, args.storage)}

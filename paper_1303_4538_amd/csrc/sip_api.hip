@@ -245,7 +245,8 @@ bool tuned_plan(const Geom &g, int arith, int sym, SweepPlan *out)
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto f = g_tuned.find(std::make_tuple(g.ni, g.nj, g.nk, arith, sym));
     if (f == g_tuned.end()) return false;
-    *out = f->second;
+    out->phases = f->second.phases;   // the caller keeps its own stream choice
+    out->poll = f->second.poll;
     return true;
 }
 
@@ -622,6 +623,10 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
     } else {
         (void)tuned_plan(h->g, p->precision, p->storage == SIP_STORAGE_SYMMETRIC, &h->plan);
     }
+    // non-temporal streams for systems far beyond the caches;
+    // SIP_STREAM_LOADS=0 / 1 forces the choice (the results are the same)
+    const char *env_st = getenv("SIP_STREAM_LOADS");
+    h->plan.stream = env_st ? (atoi(env_st) != 0) : ((long long)p->ni * p->nj * p->nk >= STREAM_HINT_CELLS);
     sip_status st = system_alloc(h, s);
     if (st != SIP_OK) {
         free_system(h);
@@ -1150,7 +1155,7 @@ sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phas
     std::vector<SweepPlan> cand;
     for (int np = 1; np <= MAX_PHASES; np++)
         for (int pd = 1; pd <= MAX_POLL; pd++)
-            if (pd == DEFAULT_POLL || np >= 2) cand.push_back(SweepPlan{np, pd});
+            if (pd == DEFAULT_POLL || np >= 2) cand.push_back(SweepPlan{np, pd, h->plan.stream});
     SweepPlan best = h->plan;
     float best_ms = 0.f;
     sip_status st = SIP_OK;

@@ -304,9 +304,18 @@ constexpr int SINGLE_SYSTEM_PHASES = 3;
 // hop; it must also cover the poll's round trip.
 constexpr int MAX_POLL = 3;
 constexpr int DEFAULT_POLL = 2;
+// stream: the forward sweep loads the coefficients, the factors and b with
+// the non-temporal hint (three phases and the default poll distance only).
+// Single systems of at least STREAM_HINT_CELLS cells take it: their data per
+// iteration (124 B per cell, mixed) is far beyond the caches, so these
+// streams would only displace the x planes that are read again.  Smaller
+// systems, and the solve server's launches of many smaller blocks, measured
+// faster without it.
+constexpr long long STREAM_HINT_CELLS = 1ll << 22;
 struct SweepPlan {
     int phases = 2;
     int poll = DEFAULT_POLL;
+    int stream = 0;
 };
 // nrhs: right-hand sides per job (1, or 2 with FP32 factors: ARITH_MIXED,
 // ARITH_F32); every job of the launch must have Job::m == nrhs.

@@ -289,13 +289,21 @@ __device__ __forceinline__ T ldg(const GLOBAL T *base, uint32_t idx)
     return *(const GLOBAL T *)((const GLOBAL char *)base + (size_t)(idx * (uint32_t)sizeof(T)));
 }
 // The same with the non-temporal hint, for streams that no other load of the
-// sweep reads again (coefficients, factors, b): they then do not displace the
-// x planes, which the halo loads of the neighbour tiles and the tile's own
-// slot loads read again shortly after.
+// sweep reads again (coefficients, factors, b) in systems much larger than the
+// caches: they then do not displace the x planes, which the halo loads of the
+// neighbour tiles and the tile's own slot loads read again shortly after.
+// (Smaller systems, whose data the caches can hold from one iteration to the
+// next, load them as usual: ST = false.)
 template <typename T>
 __device__ __forceinline__ T ldg_stream(const GLOBAL T *base, uint32_t idx)
 {
     return __builtin_nontemporal_load((const GLOBAL T *)((const GLOBAL char *)base + (size_t)(idx * (uint32_t)sizeof(T))));
+}
+template <bool ST, typename T>
+__device__ __forceinline__ T ldg_st(const GLOBAL T *base, uint32_t idx)
+{
+    if constexpr (ST) return ldg_stream(base, idx);
+    else return ldg(base, idx);
 }
 template <typename T>
 __device__ __forceinline__ void stg(GLOBAL T *base, uint32_t idx, T v)
@@ -533,7 +541,7 @@ __device__ __forceinline__ FwdSrc<F, R, M> fwd_src(const Job &J, const TileView 
 
 // Branch-free: inactive slots read their own zero-padded slot (every index
 // stays inside the tile's planes -1..steps for f in [0, steps)).
-template <typename F, typename R, int M>
+template <typename F, typename R, int M, bool ST>
 __device__ __forceinline__ void fwd_issue(FwdLoad<F, R, M> &c, const FwdSrc<F, R, M> &s, const TileView &v, int q,
                                           int f, int steps, int nk, bool sym)
 {
@@ -543,8 +551,8 @@ __device__ __forceinline__ void fwd_issue(FwdLoad<F, R, M> &c, const FwdSrc<F, R
         // the pad of the second group is not loaded: a dead lane of a load in
         // flight would be reused as soon as the load completes, which makes
         // the compiler wait for every outstanding load
-        const flt4 c0 = ldg_stream(s.A4, e);
-        const flt3 c1 = ldg_stream(s.A3, e);
+        const flt4 c0 = ldg_st<ST>(s.A4, e);
+        const flt3 c1 = ldg_st<ST>(s.A3, e);
         c.a[0] = c0.x;
         c.a[1] = c0.y;
         c.a[2] = c0.z;
@@ -566,15 +574,15 @@ __device__ __forceinline__ void fwd_issue(FwdLoad<F, R, M> &c, const FwdSrc<F, R
     } else {
 #pragma unroll
         for (int p = 0; p < 3; p++) {
-            const dbl2 v2 = ldg_stream(s.AP[p], e);
+            const dbl2 v2 = ldg_st<ST>(s.AP[p], e);
             c.a[2 * p] = v2.x;
             c.a[2 * p + 1] = v2.y;
         }
-        c.a[6] = ldg_stream(s.AT, e);
+        c.a[6] = ldg_st<ST>(s.AT, e);
     }
-    c.b = ldg_stream(s.b, e);
+    c.b = ldg_st<ST>(s.b, e);
 #pragma unroll
-    for (int k = 0; k < Grp<F>::N; k++) c.lv[k] = ldg_stream(s.L[k], e);
+    for (int k = 0; k < Grp<F>::N; k++) c.lv[k] = ldg_st<ST>(s.L[k], e);
     c.x2 = ldg(s.x, s.e0 + (uint32_t)min(f + 2, steps) * PLANE);   // plane `steps` is the zero margin
     // x across a tile edge, loaded without control flow (a branch would cost
     // the loader exact wait counts): the edge slots of a quadrant read the
@@ -650,7 +658,7 @@ struct FwdLds {
 // One tile of a forward sweep: the whole workgroup works tile as.tile of job
 // J.  Returns (uniformly) true in the workgroup that finished the job's
 // sweep last, after it has run the job's finaliser (norm and stop decision).
-template <typename F, typename R, int NP, int M, int PD>
+template <typename F, typename R, int NP, int M, int PD, bool ST>
 __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, FwdLds<F, R, M> &L, int *s_buf)
 {
     static_assert(M == 1 || std::is_same<F, float>::value, "several right-hand sides need FP32 factors");
@@ -839,7 +847,7 @@ __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Fw
         const int qa = q & 1, qb = q >> 1;
         const FwdSrc<F, R, M> src = fwd_src<F, R, M>(J, v, q);
         FwdLoad<F, R, M> c;
-        if (ph < g.steps) fwd_issue(c, src, v, q, ph, g.steps, g.nk, sym);
+        if (ph < g.steps) fwd_issue<F, R, M, ST>(c, src, v, q, ph, g.steps, g.nk, sym);
         GLOBAL FV *yout = gp((FV *)J.y);
         // In-ring neighbours: the other quadrant column (row) of the same
         // lane on the same plane, or of the neighbouring lane one plane down
@@ -904,7 +912,7 @@ __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Fw
                 for (int k = 0; k < Grp<F>::N; k++) lring[slot][k][q][lane] = c.lv[k];
             }
             if constexpr (!SPLIT) {
-                if (f + NP < g.steps) fwd_issue(c, src, v, q, f + NP, g.steps, g.nk, sym);
+                if (f + NP < g.steps) fwd_issue<F, R, M, ST>(c, src, v, q, f + NP, g.steps, g.nk, sym);
                 const int p = f - 3;
                 if (p >= 0 && p < g.steps)   // inactive slots rewrite their zero padding
                     stg(yout, src.e0 + (uint32_t)p * PLANE, ybuf[p & 1][q][lane]);
@@ -914,7 +922,7 @@ __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Fw
         // f + NP and the write-back of plane f - 2 (written by the recurrence
         // in the interval before, rewritten two intervals later).
         auto turn_b = [&](int f) {
-            if (f + NP < g.steps) fwd_issue(c, src, v, q, f + NP, g.steps, g.nk, sym);
+            if (f + NP < g.steps) fwd_issue<F, R, M, ST>(c, src, v, q, f + NP, g.steps, g.nk, sym);
             const int p = f - 2;
             if (p >= 0 && p < g.steps) stg(yout, src.e0 + (uint32_t)p * PLANE, ybuf[p & 1][q][lane]);
         };
@@ -1002,14 +1010,14 @@ __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Fw
     return last;
 }
 
-template <typename F, typename R, int NP, int M, int PD>
+template <typename F, typename R, int NP, int M, int PD, bool ST>
 __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_forward(LaunchArgs a)
 {
     __shared__ FwdLds<F, R, M> L;
     __shared__ int s_buf[8];
     const Assign as = take_ticket(a, s_buf);
     const Job J = load_job(a, as.job);
-    if (J.ctl->stop == RUN) (void)fwd_tile<F, R, NP, M, PD>(a, as, J, L, s_buf);
+    if (J.ctl->stop == RUN) (void)fwd_tile<F, R, NP, M, PD, ST>(a, as, J, L, s_buf);
     launch_done(a);
 }
 
@@ -1444,7 +1452,7 @@ __device__ void publish_next(const PersistArgs &e, const Job &J, int job, int ki
 // (mixed form: about 120 VGPRs against 82 for the forward sweep alone), so a
 // compute unit holds one workgroup of either phase count; the server runs it
 // with three phases, which hold one per unit anyway.
-template <typename F, typename R, int NP, int M, bool DF>
+template <typename F, typename R, int NP, int M, bool DF, bool ST>
 __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_persist(PersistArgs e)
 {
     __shared__ PersistLds<F, R, M> L;
@@ -1459,7 +1467,7 @@ __global__ __launch_bounds__(WAVE *(1 + NQ * NP)) void k_persist(PersistArgs e)
         if (job < 0) break;
         const Assign as{job, tile};
         const Job J = load_job(a, job);
-        const bool last = kind == 0 ? fwd_tile<F, R, NP, M, 2>(a, as, J, L.f, s_buf)
+        const bool last = kind == 0 ? fwd_tile<F, R, NP, M, 2, ST>(a, as, J, L.f, s_buf)
                                     : bwd_tile<F, R, NP, M, 2>(a, as, J, L.b, s_buf);
         if (last) publish_next<DF>(e, J, job, kind, s_buf);
         __syncthreads();   // LDS and s_buf are reused by the next task
@@ -2037,14 +2045,14 @@ hipError_t launch_factor(const LaunchArgs &a, int fp32, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename F, typename R, int NP, int M, int PD>
+template <typename F, typename R, int NP, int M, int PD, bool ST = false>
 static hipError_t launch_sweep_t(const LaunchArgs &a, int backward, hipStream_t s)
 {
     const dim3 block(WAVE * (1 + NQ * NP));
     if (backward)
         hipLaunchKernelGGL((k_backward<F, R, NP, M, PD>), dim3(a.total), block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_forward<F, R, NP, M, PD>), dim3(a.total), block, 0, s, a);
+        hipLaunchKernelGGL((k_forward<F, R, NP, M, PD, ST>), dim3(a.total), block, 0, s, a);
     return hipGetLastError();
 }
 
@@ -2082,10 +2090,31 @@ static hipError_t launch_sweep_np(const LaunchArgs &a, int arith, int nrhs, int 
     }
 }
 
+// The default plan of a single large system (three phases, poll distance 2)
+// also comes with the non-temporal streams of the forward sweep.
+static hipError_t launch_sweep_st(const LaunchArgs &a, int arith, int nrhs, int backward, hipStream_t s)
+{
+    if (nrhs == 2) {
+        switch (arith) {
+        case ARITH_MIXED: return launch_sweep_t<float, double, 3, 2, 2, true>(a, backward, s);
+        case ARITH_F32: return launch_sweep_t<float, float, 3, 2, 2, true>(a, backward, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (nrhs != 1) return hipErrorInvalidValue;
+    switch (arith) {
+    case ARITH_F64: return launch_sweep_t<double, double, 3, 1, 2, true>(a, backward, s);
+    case ARITH_MIXED: return launch_sweep_t<float, double, 3, 1, 2, true>(a, backward, s);
+    case ARITH_F32: return launch_sweep_t<float, float, 3, 1, 2, true>(a, backward, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 static hipError_t launch_sweep(const LaunchArgs &a, int arith, int nrhs, int backward, const SweepPlan &p,
                                hipStream_t s)
 {
     if (p.poll < 1 || p.poll > MAX_POLL) return hipErrorInvalidValue;
+    if (p.stream && p.phases == 3 && p.poll == DEFAULT_POLL) return launch_sweep_st(a, arith, nrhs, backward, s);
     switch (p.phases) {
     case 1: return launch_sweep_np<1>(a, arith, nrhs, p.poll, backward, s);
     case 2: return launch_sweep_np<2>(a, arith, nrhs, p.poll, backward, s);
@@ -2094,33 +2123,33 @@ static hipError_t launch_sweep(const LaunchArgs &a, int arith, int nrhs, int bac
     }
 }
 
-template <typename F, typename R, int NP, int M>
+template <typename F, typename R, int NP, int M, bool ST>
 static hipError_t launch_persist_t(const PersistArgs &a, int wgs, hipStream_t s)
 {
     // dataflow and whole-sweep publication are separate kernels, so that the
     // one does not change the other's register allocation
     if (a.dep)
-        hipLaunchKernelGGL((k_persist<F, R, NP, M, true>), dim3(wgs), dim3(WAVE * (1 + NQ * NP)), 0, s, a);
+        hipLaunchKernelGGL((k_persist<F, R, NP, M, true, ST>), dim3(wgs), dim3(WAVE * (1 + NQ * NP)), 0, s, a);
     else
-        hipLaunchKernelGGL((k_persist<F, R, NP, M, false>), dim3(wgs), dim3(WAVE * (1 + NQ * NP)), 0, s, a);
+        hipLaunchKernelGGL((k_persist<F, R, NP, M, false, ST>), dim3(wgs), dim3(WAVE * (1 + NQ * NP)), 0, s, a);
     return hipGetLastError();
 }
 
-template <int NP>
+template <int NP, bool ST>
 static hipError_t launch_persist_np(const PersistArgs &a, int arith, int nrhs, int wgs, hipStream_t s)
 {
     if (nrhs == 2) {
         switch (arith) {
-        case ARITH_MIXED: return launch_persist_t<float, double, NP, 2>(a, wgs, s);
-        case ARITH_F32: return launch_persist_t<float, float, NP, 2>(a, wgs, s);
+        case ARITH_MIXED: return launch_persist_t<float, double, NP, 2, ST>(a, wgs, s);
+        case ARITH_F32: return launch_persist_t<float, float, NP, 2, ST>(a, wgs, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (nrhs != 1) return hipErrorInvalidValue;
     switch (arith) {
-    case ARITH_F64: return launch_persist_t<double, double, NP, 1>(a, wgs, s);
-    case ARITH_MIXED: return launch_persist_t<float, double, NP, 1>(a, wgs, s);
-    case ARITH_F32: return launch_persist_t<float, float, NP, 1>(a, wgs, s);
+    case ARITH_F64: return launch_persist_t<double, double, NP, 1, ST>(a, wgs, s);
+    case ARITH_MIXED: return launch_persist_t<float, double, NP, 1, ST>(a, wgs, s);
+    case ARITH_F32: return launch_persist_t<float, float, NP, 1, ST>(a, wgs, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -2130,8 +2159,9 @@ hipError_t launch_persist(const PersistArgs &a, int arith, const SweepPlan &p, i
 {
     if (wgs < 1) return hipErrorInvalidValue;
     switch (p.phases) {
-    case 2: return launch_persist_np<2>(a, arith, nrhs, wgs, s);
-    case 3: return launch_persist_np<3>(a, arith, nrhs, wgs, s);
+    case 2: return launch_persist_np<2, false>(a, arith, nrhs, wgs, s);
+    case 3: return p.stream ? launch_persist_np<3, true>(a, arith, nrhs, wgs, s)
+                            : launch_persist_np<3, false>(a, arith, nrhs, wgs, s);
     default: return hipErrorInvalidValue;
     }
 }

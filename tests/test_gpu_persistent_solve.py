@@ -90,3 +90,29 @@ def test_solve_launch_time(sip, monkeypatch):
     with pytest.raises(sip.SipError):
         sip.sip_system_solve_ms(S)
     S.close()
+
+
+@pytest.mark.parametrize("persistent", ["1", "0"])
+def test_stream_loads_change_nothing(sip, persistent, monkeypatch):
+    """The forward sweep's non-temporal streams (taken by systems of 4 M
+    cells and more, forced here on a small ragged block) leave x, iteration
+    counts and residuals bitwise unchanged, in every precision, for one
+    right-hand side and for a pair."""
+    monkeypatch.setenv("SIP_SOLVE_PERSISTENT", persistent)
+    dims = (40, 36, 30)
+    A, b = problems.make_block(dims, "cd", np.random.SeedSequence(31))
+    b2 = problems.rhs_uniform(*dims, np.random.default_rng(32))
+    for precision, rtol in (("mixed", 1e-8), ("fp64", 1e-8), ("fp32", 1e-5)):
+        out = {}
+        for st in ("0", "1"):
+            monkeypatch.setenv("SIP_STREAM_LOADS", st)
+            S = sip.sip_factor(dev(A), 0.92, precision)
+            x = torch.zeros_like(dev(b))
+            _, it, rr, _ = sip.sip_solve(S, dev(b), x, rtol, 3000)
+            xs = [torch.zeros_like(dev(b)) for _ in range(2)]
+            _, info = sip.sip_solve_multi(S, [dev(b), dev(b2)], xs, rtol, 3000)
+            S.close()
+            out[st] = (x, it, rr, xs, [i[:2] for i in info])
+        a, c = out["0"], out["1"]
+        assert a[1:3] == c[1:3] and a[4] == c[4], precision
+        assert torch.equal(a[0], c[0]) and all(torch.equal(p, q) for p, q in zip(a[3], c[3])), precision
