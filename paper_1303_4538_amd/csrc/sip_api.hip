@@ -127,19 +127,19 @@ size_t system_bytes(const Geom &g, int fp32)
 static void free_system(sip_system_s *h)
 {
     if (!h) return;
-    if (h->chunk_exec) hipGraphExecDestroy(h->chunk_exec);
-    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    if (h->chunk_exec) (void)hipGraphExecDestroy(h->chunk_exec);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (void *p : {(void *)h->A, h->LU, (void *)h->bx, h->y, (void *)h->face, (void *)h->part, (void *)h->ctl,
                     (void *)h->hist, (void *)h->d_job, (void *)h->d_job_factor, (void *)h->order_f, (void *)h->order_b,
                     (void *)h->lc, (void *)h->mbx, h->my, (void *)h->mface, (void *)h->mpart, (void *)h->mctl,
                     (void *)h->mhist, (void *)h->d_mjob, (void *)h->p_tord, (void *)h->p_off, (void *)h->p_tasks,
                     (void *)h->p_pc, (void *)h->p_flags})
-        if (p) hipFree(p);
-    if (h->h_ctl) hipHostFree(h->h_ctl);
-    if (h->h_mctl) hipHostFree(h->h_mctl);
-    if (h->h_hist) hipHostFree(h->h_hist);
+        if (p) (void)hipFree(p);
+    if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+    if (h->h_mctl) (void)hipHostFree(h->h_mctl);
+    if (h->h_hist) (void)hipHostFree(h->h_hist);
     for (hipEvent_t e : h->p_ev)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     delete h;
 }
 
@@ -195,8 +195,8 @@ sip_status ensure_hist(sip_system_s *h, int n, hipStream_t s)
 {
     if (n <= h->hist_cap) return SIP_OK;
     HIPTRY(hipStreamSynchronize(s));
-    if (h->hist) hipFree(h->hist);
-    if (h->h_hist) hipHostFree(h->h_hist);
+    if (h->hist) (void)hipFree(h->hist);
+    if (h->h_hist) (void)hipHostFree(h->h_hist);
     h->hist = nullptr;
     h->h_hist = nullptr;
     h->hist_cap = 0;
@@ -209,7 +209,7 @@ sip_status ensure_hist(sip_system_s *h, int n, hipStream_t s)
     HIPTRY(hipMemcpyAsync(h->d_job, &h->job, sizeof(Job), hipMemcpyHostToDevice, s));
     HIPTRY(hipStreamSynchronize(s));
     if (h->chunk_exec) {
-        hipGraphExecDestroy(h->chunk_exec);
+        (void)hipGraphExecDestroy(h->chunk_exec);
         h->chunk_exec = nullptr;
     }
     return SIP_OK;
@@ -273,7 +273,7 @@ static sip_status launch_iterations(sip_system_s *h, int n, hipStream_t s)
 static sip_status launch_chunk(sip_system_s *h, hipStream_t s)
 {
     if (h->chunk_exec && h->chunk_ticks != h->timeout_ticks) {   // the graph holds the wait bound
-        hipGraphExecDestroy(h->chunk_exec);
+        (void)hipGraphExecDestroy(h->chunk_exec);
         h->chunk_exec = nullptr;
     }
     if (!h->chunk_exec) {
@@ -286,7 +286,7 @@ static sip_status launch_chunk(sip_system_s *h, hipStream_t s)
         if (st != SIP_OK) return st;
         if (e != hipSuccess) return set_error(SIP_EDEVICE, "graph capture: %s", hipGetErrorString(e));
         e = hipGraphInstantiate(&h->chunk_exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return set_error(SIP_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
     }
     HIPTRY(hipGraphLaunch(h->chunk_exec, s));
@@ -349,7 +349,7 @@ static sip_status ensure_multi(sip_system_s *h, int hist_n, hipStream_t s)
     }
     if (hist_n > h->mhist_cap) {
         HIPTRY(hipStreamSynchronize(s));
-        if (h->mhist) hipFree(h->mhist);
+        if (h->mhist) (void)hipFree(h->mhist);
         h->mhist = nullptr;
         h->mhist_cap = 0;
         const int cap = std::max(hist_n, 64);
@@ -633,7 +633,7 @@ sip_status sip_factor(const sip_problem *p, void *stream, sip_system *out)
         return st;
     }
     auto bail = [&](sip_status e) {
-        hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
         free_system(h);
         return e;
     };
@@ -838,10 +838,10 @@ static sip_status solve_one(sip_system h, const double *b, double *x, double rto
             if (h->h_ctl[(c - 1) & 1].stop != RUN) break;
         }
     }
-    hipEventDestroy(ev[0]);
-    hipEventDestroy(ev[1]);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
     if (st != SIP_OK) {
-        hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
         return st;
     }
     HIPTRY(stage_out(h, x, s));
@@ -1040,10 +1040,10 @@ sip_status sip_solve_multi(sip_system h, int32_t nrhs, const double *const *b, d
                 }
             }
         }
-        hipEventDestroy(ev[0]);
-        hipEventDestroy(ev[1]);
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
         if (st != SIP_OK) {
-            hipStreamSynchronize(s);
+            (void)hipStreamSynchronize(s);
             return st;
         }
         HIPTRY(multi_stage_out(h, x[r0], x[r1], s));
@@ -1189,7 +1189,7 @@ sip_status sip_tune(sip_system h, const double *b, int32_t n_iter, int32_t *phas
     if (st != SIP_OK) return st;
     if ((h->plan.phases != best.phases || h->plan.poll != best.poll) && h->chunk_exec) {
         HIPTRY(hipStreamSynchronize(s));   // the captured chunk holds the old kernels
-        hipGraphExecDestroy(h->chunk_exec);
+        (void)hipGraphExecDestroy(h->chunk_exec);
         h->chunk_exec = nullptr;
     }
     h->plan = best;

@@ -85,13 +85,13 @@ void destroy(sip_blocks_s *h)
     for (sip_system s : h->blk)
         if (s) sip_system_destroy(s);
     for (double *p : h->beff)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     for (void *p : {(void *)h->d_jobs, (void *)h->d_order_f, (void *)h->d_order_b, (void *)h->lc, (void *)h->d_cells,
                     (void *)h->d_terms, (void *)h->d_b, (void *)h->d_beff, (void *)h->d_x, (void *)h->d_ctl,
                     (void *)h->d_gctl, (void *)h->d_hist, (void *)h->tmp})
-        if (p) hipFree(p);
-    if (h->h_gctl) hipHostFree(h->h_gctl);
-    if (h->h_hist) hipHostFree(h->h_hist);
+        if (p) (void)hipFree(p);
+    if (h->h_gctl) (void)hipHostFree(h->h_gctl);
+    if (h->h_hist) (void)hipHostFree(h->h_hist);
     delete h;
 }
 
@@ -115,8 +115,8 @@ sip_status ensure_hist(sip_blocks_s *h, int n, hipStream_t s)
 {
     if (n <= h->hist_cap) return SIP_OK;
     HIPTRY(hipStreamSynchronize(s));
-    if (h->d_hist) hipFree(h->d_hist);
-    if (h->h_hist) hipHostFree(h->h_hist);
+    if (h->d_hist) (void)hipFree(h->d_hist);
+    if (h->h_hist) (void)hipHostFree(h->h_hist);
     h->d_hist = nullptr;
     h->h_hist = nullptr;
     h->hist_cap = 0;
@@ -191,8 +191,8 @@ sip_status build_tables(sip_blocks_s *h, const sip_block_problem *p, hipStream_t
          launch_gather_coef(h->d_terms, h->nterms, d_dir, d_gidx, p->domain.a, s) != hipSuccess ||
          hipStreamSynchronize(s) != hipSuccess))
         st = set_error(SIP_EDEVICE, "exchange table setup failed");
-    if (d_dir) hipFree(d_dir);
-    if (d_gidx) hipFree(d_gidx);
+    if (d_dir) (void)hipFree(d_dir);
+    if (d_gidx) (void)hipFree(d_gidx);
     h->bytes += cells.size() * sizeof(XCell) + terms.size() * sizeof(XTerm);
     return st;
 }
@@ -305,7 +305,7 @@ sip_status sip_blocks_factor(const sip_block_problem *p, void *stream, sip_block
     h->blk.assign(h->nblk, nullptr);
     h->beff.assign(h->nblk, nullptr);
     auto bail = [&](sip_status e) {
-        hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
         destroy(h);
         return e;
     };
@@ -459,10 +459,10 @@ sip_status sip_blocks_solve(sip_blocks h, const double *b, double *x, double rto
             if (h->h_gctl[(c - 1) & 1].stop != RUN) break;
         }
     }
-    hipEventDestroy(ev[0]);
-    hipEventDestroy(ev[1]);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
     if (st != SIP_OK) {
-        hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
         return st;
     }
     TRY(stage_out(h, x, s));

@@ -671,7 +671,6 @@ __device__ bool fwd_tile(const LaunchArgs &a, const Assign &as, const Job &J, Fw
     // interval has to hold a whole turn (the loads keep their two intervals of
     // lead).
     constexpr bool SPLIT = NP >= 3;
-    constexpr int NL = NQ * NP;
     constexpr bool R64 = std::is_same<R, double>::value;   // the symmetric storage exists in FP64 only
     auto &ring = L.ring;
     auto &lring = L.lring;
@@ -1835,7 +1834,8 @@ __global__ void k_init_ctl(Ctl *ctl, int n, uint32_t max_iter, double rtol, int 
 
 // ------------------------------------------------------ multi-block domain
 
-__global__ void k_box_copy(const double *src, double *dst, int ni, int nj, int nk, int i0, int j0, int k0, int bi,
+// (the box lies inside the domain: nk is not needed for the indexing)
+__global__ void k_box_copy(const double *src, double *dst, int ni, int nj, int /*nk*/, int i0, int j0, int k0, int bi,
                            int bj, int bk, int to_block)
 {
     const long long nc = (long long)bi * bj * bk;
