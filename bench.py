@@ -58,10 +58,10 @@ SOLVE_BYTES_MIXED = FWD_BYTES["mixed"] + BWD_BYTES["mixed"]   # one mixed iterat
 # (calibrated against a plain copy), with the iterations of that solve and the
 # SHA-256 of the kernel source they were taken with.  Once the source differs the counters no
 # longer describe the kernel and traffic is null.
-MEASURED = {"kernels_sha256": "9301a9dcc7cb9e6a68ca8158838549282692f8490aaa3d4b90c95780e75bcb67",
-            "single": {"iterations": 4069, "persist_bytes": 9722727273959},
-            "large": {"iterations": 15239, "persist_bytes": 147059406083308},
-            "pair": {"iterations": [4069, 6023], "persist_bytes": 17929576910473}}
+MEASURED = {"kernels_sha256": "5c3497df3e244a4b2c3bcf66754d076ef980a87eaa475b0e66aa594286e91fb6",
+            "single": {"iterations": 4069, "persist_bytes": 9723600658445},
+            "large": {"iterations": 15239, "persist_bytes": 147052406773563},
+            "pair": {"iterations": [4069, 6023], "persist_bytes": 17950146754459}}
 
 
 def log(msg):
