@@ -129,11 +129,16 @@ def test_odd_count_and_zero_rhs(sip, persistent, monkeypatch):
         x = torch.ones_like(bs[r])
         _, it, rr, _ = sip.sip_solve(S, bs[r], x, 1e-8, 5000)
         assert info[r][0] == it and torch.equal(xs[r], x)
-    # histories: the zero right-hand side reports zeros
+    # histories: the zero right-hand side reports zeros; a fixed iteration
+    # count keeps its partner in the pair sweeps to the end (after a solve
+    # on the same handle, whose pairs stop when one side stops)
     xs = [torch.zeros_like(b) for b in bs]
     h = sip.sip_iterate_multi(S, bs, xs, 4)
+    x0 = torch.zeros_like(bs[0])
+    h0 = sip.sip_iterate(S, bs[0], x0, 4)
     S.close()
     assert np.all(h[1] == 0.0) and h[0][0] == 1.0 and h[2][0] == 1.0
+    assert np.array_equal(h[0], h0) and torch.equal(xs[0], x0)
 
 
 @pytest.mark.parametrize("persistent", ["1", "0"])
