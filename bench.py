@@ -49,6 +49,16 @@ RTOL = 1e-8
 # coefficient, factor and b streams non-temporally (the library's own
 # threshold): the last template argument of the persistent kernel's name.
 STREAM_HINT_CELLS = 1 << 22
+# Device bytes a mixed system keeps resident per cell (A 56, FP32 factors 28,
+# b, x and y 20); a workload whose whole working set fits the 256 MiB
+# last-level cache would be a cache measurement, not an HBM one.
+RESIDENT_BYTES_MIXED = 104
+MALL_BYTES = 256 << 20
+
+
+def working_set(cells):
+    ws = cells * RESIDENT_BYTES_MIXED
+    return {"working_set_mib": round(ws / 2 ** 20, 1), "cache_resident": ws <= MALL_BYTES}
 SOLVE_BYTES_MIXED = FWD_BYTES["mixed"] + BWD_BYTES["mixed"]   # one mixed iteration, both sweeps
 # HBM bytes per launch of the persistent solve kernel (one launch = one whole
 # mixed solve) on the 256^3 and the 512x512x256 workloads, and of the two
@@ -549,7 +559,8 @@ def config3_summary(args, sip):
     one_at_a_time = ci1 / (time.perf_counter() - t0)
     out = {"workload": "64 blocks, dims uniform 32..160 per axis, half Poisson / half upwind convection-diffusion, "
                        "one solve server, factor + mixed solve to 1e-8",
-           "cells": sum(d[0] * d[1] * d[2] for d, _, _ in blocks), "value": value, "unit": "cell-iterations/s",
+           "cells": sum(d[0] * d[1] * d[2] for d, _, _ in blocks),
+           **working_set(sum(d[0] * d[1] * d[2] for d, _, _ in blocks)), "value": value, "unit": "cell-iterations/s",
            "seconds": dt, "max_iters": max(r["iters"] for r in res), "max_rel_res": max(r["rel_res"] for r in res),
            "all_ok": all(r["status"] == 0 for r in res) and all(r["status"] == 0 for r in res64),
            "epochs": st["epochs"], "fp64_cell_iters_per_s": ci64 / dt64, "mixed_speedup_vs_fp64": value / (ci64 / dt64),
@@ -605,7 +616,7 @@ def config4_summary(args, sip):
                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                     **sweep_detail(fwd_ms, bwd_ms, cells)}
     out = {"workload": "512x512x256 stretched-grid Poisson (z ratio 1.05), alpha 0.92, factor + mixed solve to 1e-8",
-           "cells": cells, "value": value, "unit": "cell-iterations/s", "seconds": secs["mixed"],
+           "cells": cells, **working_set(cells), "value": value, "unit": "cell-iterations/s", "seconds": secs["mixed"],
            "iterations": its["mixed"], "final_rel_res": rr_mixed, "fp64_iterations": its["fp64"],
            "fp64_cell_iters_per_s": cells * its["fp64"] / secs["fp64"],
            "mixed_speedup_vs_fp64": secs["fp64"] / secs["mixed"] * its["mixed"] / its["fp64"],
@@ -1165,6 +1176,7 @@ def main():
             "workload": f"{label}, alpha 0.92, factor + mixed solve to {RTOL:g}"
                         + (", symmetric coefficient storage" if args.storage == "symmetric" else ""),
             "cells": cells,
+            **working_set(cells),
             "iterations": mean_it,
             "final_rel_res": max(rr for _, rr in results),
             "hbm_gbps_algorithmic": value * (fwd_bytes + BWD_BYTES["mixed"]) / 1e9,

@@ -60,3 +60,9 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120, cwd=ROOT)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def test_working_set_flag():
+    # 256^3 mixed: 104 B per cell resident, far beyond the 256 MiB last-level cache
+    assert bench.working_set(256 ** 3) == {"working_set_mib": 1664.0, "cache_resident": False}
+    assert bench.working_set(64 ** 3)["cache_resident"] is True
