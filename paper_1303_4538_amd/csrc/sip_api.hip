@@ -42,7 +42,10 @@ uint64_t timeout_ticks_for(int device, double seconds)
 double wait_limit_seconds()
 {
     const char *e = getenv("SIP_WAIT_LIMIT_MS");
-    return e ? std::max(0.0, atof(e)) * 1e-3 : 2.0;
+    char *end = nullptr;
+    const double ms = e ? strtod(e, &end) : 0.0;
+    if (!e || end == e || !(ms >= 0.0) || ms > 1e9) return 2.0;   // unset or not a time: the default
+    return ms * 1e-3;
 }
 
 // The bound of every device-side wait of a handle's sweeps, read at every
